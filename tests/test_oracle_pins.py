@@ -1,0 +1,503 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Nothing here compares the oracle with itself: every expected value comes from
+an invariant, a closed form, an independent definition (oracle/definition.py:
+exact polyhedral cuts, ray supersampling, closed-form solid angles) or a
+statement of the paper.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import definition as D
+from paper_2110_09841_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_setups.json")
+
+EX_EC = O.Options(exact=True, ec=True)
+EX = O.Options(exact=True, ec=False)
+REL_EC = O.Options(exact=False, ec=True)
+REL = O.Options(exact=False, ec=False)
+RAW = O.Options(exact=True, ec=False, scaling="none", raw_volume=True)
+RAW_EC = O.Options(exact=True, ec=True, scaling="none", raw_volume=True)
+
+
+def small():
+    return synth.config_small()
+
+
+def cone():
+    return synth.config_cone()
+
+
+# ------------------------------------------------------------------ frames
+
+def test_frame_orthonormal_right_handed():
+    """Sec. II-C: Q is orthogonal; chi2 is opposite to x3 (Sec. III-A)."""
+    g = small()
+    for view in range(0, 32, 5):
+        s, e1, e2, d = O.view_frame(g, view)
+        Q = np.array([e1, e2, d])
+        assert np.allclose(Q @ Q.T, np.eye(3), atol=1e-14)
+        assert abs(np.linalg.det(Q) - 1.0) < 1e-14
+        assert e2[2] == -1.0
+        # the principal ray passes through the isocentre
+        assert np.allclose(np.cross(d, -s), 0, atol=1e-9)
+        assert abs(np.linalg.norm(s) - g["sid_mm"]) < 1e-9
+
+
+def test_isocentre_projects_to_principal_point():
+    g = small()
+    for view in range(0, 32, 7):
+        chi = O.project_point(g, view, [0.0, 0.0, 0.0])
+        assert np.allclose(chi, [(96 - 1) / 2, (96 - 1) / 2], atol=1e-12)
+
+
+def test_point_on_pixel_ray_projects_to_pixel():
+    """A point on the ray from the source through the centre of pixel (u,v)
+    projects back onto (u,v); the detector point is built independently."""
+    g = cone()
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        view = int(rng.integers(0, 360))
+        u, v = rng.uniform(0, 511), rng.uniform(0, 383)
+        P = D.detector_point(g, view, u, v)[0]
+        s = D.frame(g, view)[0]
+        x = s + rng.uniform(0.3, 0.9) * (P - s)
+        chi = O.project_point(g, view, x)
+        assert np.allclose(chi, [u, v], atol=1e-9)
+
+
+def test_column_identity():
+    """eq. columnprojectionidentity: chi1 does not depend on x3."""
+    g = cone()
+    rng = np.random.default_rng(2)
+    for _ in range(20):
+        view = int(rng.integers(0, 360))
+        x = rng.uniform(-60, 60, size=3)
+        c_a = O.project_point(g, view, x)
+        x[2] = rng.uniform(-60, 60)
+        c_b = O.project_point(g, view, x)
+        assert abs(c_a[0] - c_b[0]) < 1e-10
+
+
+# ----------------------------------------------------------- column cuts
+
+def _square_samples(g, i, j, n=1024):
+    a1, a2 = g["voxel_mm"][:2]
+    lo, hi = D.voxel_box(g, i, j, 0)
+    t = (np.arange(n) + 0.5) / n
+    X, Y = np.meshgrid(lo[0] + t * a1, lo[1] + t * a2, indexing="ij")
+    return X.ravel(), Y.ravel()
+
+
+@pytest.mark.parametrize("gname", ["small", "cone"])
+def test_column_areas_partition_and_brute_force(gname):
+    """Sum of A_u over a fully covered column equals a1*a2; each A_u, CM_u
+    and depth variance agree with a point count over the base square."""
+    g = small() if gname == "small" else cone()
+    a1, a2 = g["voxel_mm"][:2]
+    rng = np.random.default_rng(3)
+    n = 1024
+    for _ in range(6):
+        view = int(rng.integers(0, len(g["angles_rad"])))
+        i, j = (int(t) for t in rng.integers(0, g["vol_dims"][0], size=2))
+        pcs = O.column_pieces(g, EX_EC, view, i, j)
+        X, Y = _square_samples(g, i, j, n)
+        s, e1, e2, d = D.frame(g, view)
+        c1 = (g["det_cols"] - 1) / 2
+        f, b1 = g["sdd_mm"], g["pitch_mm"][0]
+        R1, R2 = X - s[0], Y - s[1]
+        chi1 = c1 + (f / b1) * (e1[0] * R1 + e1[1] * R2) / (d[0] * R1 + d[1] * R2)
+        col = np.floor(chi1 + 0.5).astype(int)
+        if col.min() >= 0 and col.max() < g["det_cols"]:
+            assert abs(sum(p["area"] for p in pcs) - a1 * a2) < 1e-12 * a1 * a2
+        for p in pcs:
+            m = col == p["u"]
+            frac = m.mean()
+            assert abs(p["area"] - frac * a1 * a2) < 4.0 / n * a1 * a2
+            if frac > 0.05:
+                assert abs(p["cm1"] - X[m].mean()) < 2.0 / n * a1
+                assert abs(p["cm2"] - Y[m].mean()) < 2.0 / n * a2
+                depth = d[0] * R1[m] + d[1] * R2[m]
+                assert abs(p["depth"] - depth.mean()) < 2.0 / n * max(a1, a2)
+                assert abs(p["h"] - math.sqrt(3 * depth.var())) < 0.02 * max(a1, a2)
+
+
+# ------------------------------------------------------------- row lengths
+
+def test_row_lengths_partition_plain_and_ec():
+    """Sum over rows of d_uv equals a3 for a voxel inside the detector rows,
+    with and without the elevation correction."""
+    g = cone()
+    rng = np.random.default_rng(4)
+    for _ in range(30):
+        depth = rng.uniform(560, 640)
+        h = rng.uniform(0.0, 0.4)
+        z0 = rng.uniform(-50, 50)
+        z1 = z0 + 0.5
+        tot_plain = sum(O.row_length(g, 0.0, v, depth, 0.0, z0, z1) for v in range(384))
+        tot_ec = sum(O.row_length(g, 0.0, v, depth, h, z0, z1) for v in range(384))
+        assert abs(tot_plain - 0.5) < 1e-12
+        assert abs(tot_ec - 0.5) < 1e-12
+
+
+def test_ec_row_length_is_box_average():
+    """Sec. III-B reading: the EC row length is the mean of the plain band
+    length over the depth box [D-h, D+h] (checked by a fine midpoint rule)."""
+    g = cone()
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        depth = rng.uniform(560, 640)
+        h = rng.uniform(0.01, 0.5)
+        z0 = rng.uniform(-50, 50)
+        z1 = z0 + 0.5
+        v = int(np.floor(191.5 - z0 * 900 / (0.388 * depth) + 0.5))
+        n = 20000
+        Dp = depth - h + (np.arange(n) + 0.5) * (2 * h / n)
+        k = 0.388 / 900.0
+        top = -(v - 0.5 - 191.5) * k * Dp
+        bot = -(v + 0.5 - 191.5) * k * Dp
+        ref = np.mean(np.maximum(np.minimum(z1, top) - np.maximum(z0, bot), 0.0))
+        got = O.row_length(g, 0.0, v, depth, h, z0, z1)
+        assert abs(got - ref) < 1e-7
+        assert abs(O.row_length(g, 0.0, v, depth, 1e-12, z0, z1) -
+                   O.row_length(g, 0.0, v, depth, 0.0, z0, z1)) < 1e-9
+
+
+# -------------------------------------------------------------- cut volume
+
+@pytest.mark.parametrize("opts", [RAW, RAW_EC])
+def test_cut_volume_sums_to_voxel_volume_small(opts):
+    """Every voxel of the 64^3 / 96x96 workload is fully projected, so the cut
+    volumes of each voxel-view sum to a1*a2*a3 (eq. cutvolume)."""
+    g = small()
+    rng = np.random.default_rng(6)
+    for _ in range(200):
+        i, j, k = (int(t) for t in rng.integers(0, 64, size=3))
+        view = int(rng.integers(0, 32))
+        us, vs, ws = O.voxel_weights(g, opts, view, i, j, k)
+        assert abs(ws.sum() - 1.0) < 1e-12
+
+
+def test_cut_volume_equals_exact_polyhedron_when_no_row_plane_crosses():
+    """A_u * d_uv equals the exact volume of voxel n pixel pyramid whenever no
+    row plane crosses the top or bottom face of the voxel inside H_u (then the
+    row extent is linear in depth over H_u and the centroid gives its mean)."""
+    g = cone()
+    G = O.Geometry(g)
+    rng = np.random.default_rng(7)
+    checked = 0
+    f, b2 = g["sdd_mm"], g["pitch_mm"][1]
+    c2 = (g["det_rows"] - 1) / 2
+    while checked < 40:
+        i, j, k = (int(t) for t in rng.integers(0, 256, size=3))
+        view = int(rng.integers(0, 360))
+        lo, hi = D.voxel_box(g, i, j, k)
+        us, vs, ws = O.voxel_weights(G, RAW, view, i, j, k)
+        s, e1, e2, d = D.frame(g, view)
+        # depth range of the voxel base
+        cs = [np.array([x, y]) for x in (lo[0], hi[0]) for y in (lo[1], hi[1])]
+        dep = [d[0] * (c[0] - s[0]) + d[1] * (c[1] - s[1]) for c in cs]
+        # chi2 of the top/bottom faces over that depth range
+        spans = [c2 - (z * f / b2) / np.array([min(dep), max(dep)]) for z in (lo[2], hi[2])]
+        crosses = any(np.floor(sp[0] + 0.5) != np.floor(sp[1] + 0.5) for sp in spans)
+        if crosses or len(ws) == 0:
+            continue
+        for u, v, w in zip(us, vs, ws):
+            vol = D.cut_integrals(g, view, (i, j, k), u, v)[0]
+            assert abs(w - vol) < 1e-9 * 0.125, (i, j, k, view, u, v, w, vol)
+        checked += 1
+
+
+def _eprj(g, opts, ijk, view, weighting):
+    G = O.Geometry(g)
+    us, vs, ws = O.voxel_weights(G, EX_EC, view, *ijk)
+    pix = [(u, v) for u in range(us.min() - 1, us.max() + 2) for v in range(vs.min() - 1, vs.max() + 2)
+           if 0 <= u < g["det_cols"] and 0 <= v < g["det_rows"]]
+    sig = O.pixel_scale(G, opts.scaling)
+    u2, v2, w2 = O.voxel_weights(G, opts, view, *ijk)
+    got = {(u, v): w * sig[v, u] for u, v, w in zip(u2, v2, w2)}
+    a = np.array([got.get(p, 0.0) for p in pix])
+    ref = D.voxel_definition(g, view, ijk, pix, weighting)
+    return np.linalg.norm(a - ref) / np.linalg.norm(ref)
+
+
+def _cases(g, n, seed):
+    rng = np.random.default_rng(seed)
+    G = O.Geometry(g)
+    out = []
+    while len(out) < n:
+        ijk = tuple(int(t) for t in rng.integers(0, g["vol_dims"][0], size=3))
+        view = int(rng.integers(0, len(g["angles_rad"])))
+        if len(O.voxel_weights(G, EX_EC, view, *ijk)[0]):
+            out.append((ijk, view))
+    return out
+
+
+def test_projector_error_against_exact_definition():
+    """Relative projector error e_PRJ (Sec. IV-B) of single voxels against the
+    exact pixel-averaged extinction (eq. integub through eq. intcut), on the
+    12-degree cone workload.  The paper claims: the elevation correction
+    removes the worst errors (Sec. V-A) and the relaxed form is less accurate
+    (abstract)."""
+    g = cone()
+    cases = _cases(g, 16, 8)
+    err = {}
+    for name, opts in (("ex_ec", EX_EC), ("ex", EX), ("rel_ec", REL_EC)):
+        err[name] = np.array([_eprj(g, opts, ijk, view, "solid_angle") for ijk, view in cases])
+    assert err["ex_ec"].max() < 1e-3
+    assert err["ex_ec"].max() < err["ex"].max()
+    assert err["ex_ec"].mean() <= err["ex"].mean()
+    assert err["ex_ec"].mean() < err["rel_ec"].mean()
+
+
+def test_cos_scaling_against_area_definition():
+    """The flat-panel formula (eq. cvp) approximates the area average of the
+    chord length (eq. integ).  It takes R and theta at the pixel centre; R^3
+    varies over a pixel by about 3 rho b / f^2 relative (rho: distance of the
+    pixel from the principal point), which does not cancel for pixels the
+    voxel covers only in part.  The bound uses the detector corner."""
+    g = small()
+    cos_opts = O.Options(exact=True, ec=True, scaling="cos")
+    rho = math.hypot(48 * 1.6, 48 * 1.6)
+    bound = 3 * rho * 1.6 / 1200.0 ** 2
+    for ijk, view in _cases(g, 8, 9):
+        assert _eprj(g, cos_opts, ijk, view, "area") < bound
+
+
+def test_supersampling_converges_to_exact_definition():
+    """K x K rays per pixel (Sec. II-D) converge to the exact cut integral
+    (eq. intcut) as K grows; this ties the two definitions together."""
+    g = small()
+    ijk, view = (20, 41, 33), 5
+    G = O.Geometry(g)
+    us, vs, _ = O.voxel_weights(G, EX_EC, view, *ijk)
+    pix = [(u, v) for u in range(us.min() - 1, us.max() + 2) for v in range(vs.min() - 1, vs.max() + 2)]
+    for weighting in ("solid_angle", "area"):
+        exact = D.voxel_definition(g, view, ijk, pix, weighting)
+        errs = [np.linalg.norm(D.supersample_voxel(g, view, ijk, pix, K, weighting) - exact)
+                / np.linalg.norm(exact) for K in (16, 64, 256)]
+        assert errs[2] < errs[0]
+        assert errs[2] < 5e-3
+
+
+def test_isocentre_voxel_cvp_beats_siddon32():
+    """Sec. V-A: with no elevation (a 1x1x5 mm voxel at the isocentre), the
+    32x32-ray SiddonK is worse than unrelaxed CVP from every view angle.
+    Ground truth: the exact area average (the K -> infinity limit)."""
+    setup = json.load(open(GOLDEN))["accuracy_isocentre"]
+    g = synth.geometry((1, 1, 1), setup["voxel_mm"], setup["det_cols"], setup["det_rows"],
+                       setup["pitch_mm"], setup["sid_mm"], setup["sdd_mm"], setup["n_views"])
+    G = O.Geometry(g)
+    opts = O.Options(exact=True, ec=True, scaling="cos")
+    sig = O.pixel_scale(G, "cos")
+    for view in (0, 37, 101):
+        us, vs, ws = O.voxel_weights(G, opts, view, 0, 0, 0)
+        pix = list(zip(us.tolist(), vs.tolist()))
+        # the exact area average over the footprint rows/cols nearest the
+        # top and bottom edges, where the two projectors differ
+        vmin, vmax = vs.min(), vs.max()
+        sel = [n for n, (u, v) in enumerate(pix) if v <= vmin + 1 or v >= vmax - 1 or n % 7 == 0]
+        pix_s = [pix[n] for n in sel]
+        exact = D.voxel_definition(g, view, (0, 0, 0), pix_s, "area")
+        cvp = np.array([ws[n] * sig[pix[n][1], pix[n][0]] for n in sel])
+        sid32 = D.supersample_voxel(g, view, (0, 0, 0), pix_s, 32, "area")
+        e_cvp = np.linalg.norm(cvp - exact) / np.linalg.norm(exact)
+        e_sid = np.linalg.norm(sid32 - exact) / np.linalg.norm(exact)
+        assert e_cvp < e_sid, (view, e_cvp, e_sid)
+
+
+# ------------------------------------------------------------- 1/r^2 term
+
+def test_inverse_square_against_quadrature():
+    """eq. vox: vol/r^2 against the exact integral of 1/r^2 over the cut.
+    Exact form (r at the centroid of the prism H_u x [x3 extent]): for pieces
+    spanning the full voxel height the prism is the cut, so the error is second
+    order, (size/r)^2 < 1e-6.  Pieces bounded by a row plane have a centroid
+    offset of at most slope * extent (slope of the row planes <= (N/2) b2 / f),
+    a first-order error 2 * slope * extent / r.  The relaxed form (r at the
+    voxel centre) is first order everywhere and worse on average."""
+    slope = 192 * 0.388 / 900.0
+    first_order = 2 * slope * 0.5 * math.sqrt(2) / (600.0 - 128 * 0.5 * math.sqrt(2))
+    ex_full, ex_cut, rel_all, ex_all = [], [], [], []
+    # the 12-degree cone workload, and the same with rows 8x taller (most
+    # pieces then span the whole voxel height)
+    tall = cone()
+    tall["pitch_mm"] = (0.388, 8 * 0.388)
+    tall["det_rows"] = 48
+    for g in (cone(), tall):
+      G = O.Geometry(g)
+      rng = np.random.default_rng(10)
+      n = 0
+      while n < 12:
+          ijk = tuple(int(t) for t in rng.integers(0, 256, size=3))
+          view = int(rng.integers(0, 360))
+          uv_raw = O.voxel_weights(G, RAW, view, *ijk)
+          if not len(uv_raw[0]):
+              continue
+          pcs = {p["u"]: p for p in O.column_pieces(G, EX, view, ijk[0], ijk[1])}
+          ue, ve, we = O.voxel_weights(G, EX, view, *ijk)
+          ur, vr, wr = O.voxel_weights(G, REL, view, *ijk)
+          for (u, v, wv, w1, w2) in zip(ue, ve, uv_raw[2], we, wr):
+              vol, isa, _ = D.cut_integrals(g, view, ijk, u, v)
+              if vol < 0.05 * 0.125 or abs(wv - vol) > 1e-9:
+                  continue   # only pieces whose volume is exact
+              e = abs(w1 - isa) / isa
+              full = abs(wv - pcs[u]["area"] * 0.5) < 1e-12
+              (ex_full if full else ex_cut).append(e)
+              ex_all.append(e)
+              rel_all.append(abs(w2 - isa) / isa)
+          n += 1
+    assert len(ex_full) > 3 and len(ex_cut) > 3
+    assert max(ex_full) < 1e-6
+    assert max(ex_cut) < first_order
+    assert np.mean(rel_all) > np.mean(ex_all)
+
+
+# ---------------------------------------------------------- pixel scaling
+
+def test_pixel_solid_angle_three_closed_forms():
+    """The oracle's pixel solid angle equals the rectangle arctan formula and
+    the paper's spherical-quadrilateral formula (Sec. II-E) in FP64."""
+    for setup in ("accuracy_isocentre", "accuracy_large_cone"):
+        s = json.load(open(GOLDEN))[setup]
+        g = synth.geometry(1, 1.0, s["det_cols"], s["det_rows"], s["pitch_mm"], s["sid_mm"],
+                           s["sdd_mm"], 1)
+        rng = np.random.default_rng(11)
+        for _ in range(20):
+            u, v = int(rng.integers(0, s["det_cols"])), int(rng.integers(0, s["det_rows"]))
+            om = O.pixel_solid_angle(g, u, v)
+            x0, x1, y0, y1 = D.pixel_edges_mm(g, u, v)
+            # the arctan form subtracts terms ~|XY|/f^2 larger than Omega
+            # (about 1e5 here), so it keeps ~11 digits in FP64
+            assert abs(om - D.pixel_solid_angle_arctan(s["sdd_mm"], x0, x1, y0, y1)) < 1e-10 * om
+            assert abs(om - D.pixel_solid_angle_paper(s["sdd_mm"], x0, x1, y0, y1)) < 1e-6 * om
+
+
+def test_solid_angles_sum_to_detector():
+    g = small()
+    G = O.Geometry(g)
+    tot = sum(O.pixel_solid_angle(G, u, v) for u in range(96) for v in range(96))
+    h = 48 * 1.6
+    assert abs(tot - D.pixel_solid_angle_arctan(1200.0, -h, h, -h, h)) < 1e-12
+
+
+def test_cos_scale_closed_form():
+    """eq. cvp: f^2 / (a cos^3 theta) with R cos theta = f."""
+    g = small()
+    sig = O.pixel_scale(g, "cos")
+    for (u, v) in ((0, 0), (47, 50), (95, 3)):
+        X, Y = (u - 47.5) * 1.6, (v - 47.5) * 1.6
+        R = math.sqrt(X * X + Y * Y + 1200.0 ** 2)
+        assert abs(sig[v, u] - R ** 3 / (1.6 * 1.6 * 1200.0)) < 1e-12 * sig[v, u]
+    assert np.all(O.pixel_scale(g, "none") == 1.0)
+
+
+# ------------------------------------------------------------ closed forms
+
+@pytest.mark.parametrize("scaling", ["solid_angle", "cos"])
+def test_single_voxel_inside_one_pixel(scaling):
+    """A voxel whose whole footprint lies in one pixel gives
+    E = mu * a1 a2 a3 / (r^2 * Omega) (eq. cvpus) or
+    mu * a1 a2 a3 * f^2 / (a cos^3 theta r^2) (eq. cvp), r to the voxel centre."""
+    g = synth.geometry(3, 0.1, 9, 9, 20.0, 700.0, 1100.0, 4, 360.0)
+    G = O.Geometry(g)
+    opts = O.Options(exact=True, ec=True, scaling=scaling)
+    for view in range(4):
+        us, vs, ws = O.voxel_weights(G, opts, view, 1, 1, 1)
+        assert len(ws) == 1 and (us[0], vs[0]) == (4, 4)
+        sig = O.pixel_scale(G, scaling)[4, 4]
+        s = D.frame(g, view)[0]
+        r2 = float(np.dot(s, s))
+        vol = 0.1 ** 3
+        if scaling == "solid_angle":
+            ref = vol / (r2 * D.pixel_solid_angle_arctan(1100.0, -10, 10, -10, 10))
+        else:
+            ref = vol * 1100.0 ** 2 / (400.0 * r2)
+        assert abs(ws[0] * sig - ref) < 1e-12 * ref
+
+
+@pytest.mark.parametrize("angle_deg", [0.0, 45.0, 30.0])
+def test_parallel_beam_limit(angle_deg):
+    """Source far away, magnification 2, pitch = 2 mm (1 mm in the object):
+    CVP with flat-panel scaling equals the exact pixel-integrated parallel
+    footprint; at 0 deg a box, at 45 deg the box-box convolution (trapezoid)."""
+    lam = math.radians(angle_deg)
+    g = synth.geometry((5, 5, 5), 1.0, 21, 21, 2.0, 1e6, 2e6, 1, 360.0)
+    g["angles_rad"] = np.array([lam])
+    G = O.Geometry(g)
+    for ec in (False, True):
+        opts = O.Options(exact=True, ec=ec, scaling="cos")
+        sig = O.pixel_scale(G, "cos")
+        for (i, j, k) in ((2, 2, 2), (0, 4, 1), (3, 1, 4)):
+            us, vs, ws = O.voxel_weights(G, opts, 0, i, j, k)
+            got = {(u, v): w * sig[v, u] for u, v, w in zip(us, vs, ws)}
+            lo, hi = D.voxel_box(g, i, j, k)
+            c = 0.5 * (lo + hi)
+            e1 = np.array([-math.sin(lam), math.cos(lam)])
+            pc = e1 @ c[:2]                       # footprint centre along chi1 (mm)
+            # chord length through the unit square vs the offset p along e1:
+            # a trapezoid with outer half width (|cos|+|sin|)/2, flat half
+            # width ||cos|-|sin||/2 and height 1/max(|cos|,|sin|)
+            ca, sa = abs(math.cos(lam)), abs(math.sin(lam))
+            half, flat, top = 0.5 * (ca + sa), 0.5 * abs(ca - sa), 1.0 / max(ca, sa)
+
+            def L(p):
+                q = abs(p - pc)
+                if q >= half:
+                    return 0.0
+                return top if q <= flat else top * (half - q) / (half - flat)
+
+            def chord_integral(p0, p1):
+                ks = sorted({p0, p1} | {pc + x for x in (-half, -flat, flat, half) if p0 < pc + x < p1})
+                # midpoint rule per linear piece (exact, also across the jumps
+                # of the box at 0 degrees)
+                return sum((ks[n + 1] - ks[n]) * L(0.5 * (ks[n] + ks[n + 1]))
+                           for n in range(len(ks) - 1))
+
+            for u in range(21):
+                for v in range(21):
+                    # object-space pixel: chi1 -> p = (u - 10) mm, chi2 -> x3 = -(v - 10) mm
+                    area = chord_integral(u - 10 - 0.5, u - 10 + 0.5)
+                    zl = max(lo[2], -(v - 10) - 0.5)
+                    zh = min(hi[2], -(v - 10) + 0.5)
+                    ref = area * max(zh - zl, 0.0)
+                    assert abs(got.get((u, v), 0.0) - ref) < 2e-5, (angle_deg, i, j, k, u, v)
+
+
+# ---------------------------------------------------------------- adjoint
+
+@pytest.mark.parametrize("opts", [EX_EC, EX, REL_EC, REL, O.Options(exact=True, ec=True, scaling="cos")])
+def test_dot_product_test(opts):
+    """Sec. III-D: b.(A x) = x.(A^T b) for random x, b."""
+    g = synth.geometry((12, 10, 8), (1.0, 1.1, 1.3), 24, 20, 1.5, 300.0, 500.0, 7, 200.0)
+    rng = np.random.default_rng(12)
+    x = rng.random((8, 10, 12))
+    b = rng.random((7, 20, 24))
+    Ax = O.project(g, opts, x)
+    Atb = O.backproject(g, opts, b)
+    lhs, rhs = float(np.sum(b * Ax)), float(np.sum(x * Atb))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_explicit_matrix_transpose():
+    """Columns of A from unit volumes equal rows of A^T from unit projections."""
+    g = synth.geometry((3, 4, 2), 2.0, 8, 6, 3.0, 60.0, 100.0, 3, 360.0)
+    nvox, npix = 3 * 4 * 2, 3 * 6 * 8
+    A = np.zeros((npix, nvox))
+    for j in range(nvox):
+        e = np.zeros(nvox); e[j] = 1.0
+        A[:, j] = O.project(g, EX_EC, e).ravel()
+    AT = np.zeros((nvox, npix))
+    for i in range(npix):
+        e = np.zeros(npix); e[i] = 1.0
+        AT[:, i] = O.backproject(g, EX_EC, e).ravel()
+    assert np.abs(A).max() > 0
+    assert np.allclose(A, AT.T, rtol=1e-13, atol=1e-15)
+    idx = np.array([0, 5, 23])
+    assert np.allclose(O.backproject_voxels(g, EX_EC, np.ones(npix), idx), AT[idx].sum(axis=1))
