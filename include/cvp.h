@@ -1,0 +1,149 @@
+/*
+ * cvp.h -- C ABI of the MI355X (gfx950) cutting voxel projector library.
+ *
+ * The operators are those of Kulvait & Rose, "Cutting Voxel Projector a New
+ * Approach to Construct 3D Cone Beam CT Operator" (2021):
+ *
+ *   b = A x    (projection, Sec. I, the operator equation A x = b)
+ *   x = A^T b  (backprojection, its exact adjoint, Sec. III-D)
+ *
+ * with  A[(view,v,u),(i,j,k)] = sigma_uv * |V^(ijk)_(uv)| / r^2 :
+ *   |V^(ijk)_(uv)|  the volume of voxel (i,j,k) cut by the ray pyramid of
+ *                   pixel (u,v), estimated from the column polygons and the x3
+ *                   extents of Sec. III-A (eq. cutvolume), optionally with the
+ *                   elevation correction of Sec. III-B;
+ *   1/r^2           the cut integral of 1/r^2 taken at one point (Sec. II-F,
+ *                   eq. vox): the cut centroid (exact form) or the voxel
+ *                   centre (relaxed form);
+ *   sigma_uv        the per-pixel factor applied after the unscaled sums
+ *                   (eq. cvpsu): 1/solid angle (eq. cvpus) or
+ *                   f^2/(a cos^3 theta) (eq. cvp).
+ *
+ * Geometry: circular trajectory about +x3, source at
+ * (D cos l, D sin l, 0); flat detector at distance f from the source, chi1
+ * along (-sin l, cos l, 0), chi2 along -x3 (Sec. III-A).  Pixel (u,v) covers
+ * [u-1/2,u+1/2] x [v-1/2,v+1/2] in pixel-index units; u is the column (chi1),
+ * v the row (chi2).
+ *
+ * Memory layouts (all float32, contiguous, caller-owned device memory):
+ *   volume       [n3][n2][n1]          (x1 fastest)
+ *   projections  [n_views][rows][cols] (u fastest)
+ *
+ * Conventions for every entry point:
+ *   - all functions are extern "C"; none throws;
+ *   - device pointers are owned by the caller and never freed by the library;
+ *   - outputs are overwritten (every element written; no prior memset needed);
+ *   - operator calls are asynchronous on the given HIP stream (hipStream_t
+ *     passed as void*; NULL = default stream); they allocate no memory;
+ *   - a geometry object is immutable after creation and may be shared across
+ *     streams and threads; distinct outputs may be computed concurrently;
+ *   - on error the call returns a status and leaves a message retrievable by
+ *     cvp_last_error_detail() on the same thread.
+ */
+#ifndef CVP_H
+#define CVP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CVP_OK = 0,
+    CVP_E_INVALID = 1,      /* bad argument; the message names the field */
+    CVP_E_NOMEM = 2,        /* host or device allocation failed */
+    CVP_E_DEVICE = 3,       /* HIP runtime error (no device, launch failure) */
+    CVP_E_UNSUPPORTED = 4,  /* valid but outside what the kernels handle */
+    CVP_E_BREAKDOWN = 5     /* CGLS: zero search direction norm */
+} cvp_status;
+
+typedef enum {
+    CVP_EXACT = 0,          /* r at the centroid of each cut piece */
+    CVP_RELAXED = 1         /* r at the voxel centre (speed-optimised form) */
+} cvp_variant;
+
+typedef enum {
+    CVP_SCALE_SOLID_ANGLE = 0,  /* unit-sphere formula, eq. cvpus (default) */
+    CVP_SCALE_COS = 1,          /* flat-panel formula, eq. cvp */
+    CVP_SCALE_NONE = 2          /* unscaled sums S (eq. cvpsu), for tests */
+} cvp_scaling;
+
+/* Test mode: weight = cut volume |V^(ijk)_(uv)| (no 1/r^2). */
+#define CVP_FLAG_RAW_VOLUME 1u
+
+/* Circular cone-beam geometry.  All lengths in mm, angles in radians. */
+typedef struct {
+    int32_t vol_dims[3];        /* n1, n2, n3 (> 0) */
+    double voxel_mm[3];         /* a1, a2, a3 (> 0) */
+    double vol_offset_mm[3];    /* centre of the volume box; 0 = isocentric */
+    int32_t det_cols, det_rows; /* M (along chi1), N (along chi2), > 0 */
+    double pitch_mm[2];         /* b1, b2 (> 0) */
+    double principal_px[2];     /* principal point (pixel-index units);
+                                   NAN => ((M-1)/2, (N-1)/2) */
+    double source_iso_mm;       /* source-isocentre distance D */
+    double source_det_mm;       /* source-detector distance f > D */
+    int32_t n_views;            /* >= 1 */
+    const double *angles_rad;   /* host pointer, n_views angles; copied */
+} cvp_geometry_desc;
+
+typedef struct {
+    cvp_variant variant;
+    int32_t elevation_correction;   /* 0 off, 1 on (Sec. III-B) */
+    cvp_scaling scaling;
+    uint32_t flags;                 /* CVP_FLAG_* */
+} cvp_options;
+
+typedef struct cvp_geometry cvp_geometry;  /* opaque */
+
+/*
+ * Validate a geometry description and build the per-view tables (FP64 on the
+ * host, uploaded once to the current HIP device) and the pixel factor tables.
+ * Validation: dims > 0, sizes > 0, f > D > half diagonal of the volume box
+ * in the x1x2 plane (the source stays outside the volume), n_views >= 1,
+ * non-null pointers.  On success *out owns host and device memory; release it
+ * with cvp_geometry_destroy.  Errors: CVP_E_INVALID (field named),
+ * CVP_E_UNSUPPORTED (projected voxel or volume too large for the kernels),
+ * CVP_E_NOMEM, CVP_E_DEVICE.
+ */
+cvp_status cvp_geometry_from_views(const cvp_geometry_desc *desc, cvp_geometry **out);
+
+/* Frees the geometry (NULL is ignored).  Not stream-ordered: the caller makes
+ * sure no operator call using it is still running. */
+void cvp_geometry_destroy(cvp_geometry *g);
+
+/*
+ * b = A x.  d_vol: [n3][n2][n1] float32 input; d_proj: [n_views][rows][cols]
+ * float32 output, overwritten.  Projection is voxel driven; each workgroup
+ * owns a band of detector columns of one view and sums into LDS, so there are
+ * no global atomics and results are bitwise reproducible.
+ * Errors: CVP_E_INVALID (null pointer or option), CVP_E_DEVICE (launch).
+ */
+cvp_status cvp_project(const cvp_geometry *g, const cvp_options *opts,
+                       const float *d_vol, float *d_proj, void *hip_stream);
+
+/*
+ * x = A^T b with the same weights (the exact adjoint of cvp_project).
+ * d_proj: [n_views][rows][cols] input; d_vol: [n3][n2][n1] output,
+ * overwritten.  Voxel-driven gather: every voxel is written once.
+ */
+cvp_status cvp_backproject(const cvp_geometry *g, const cvp_options *opts,
+                           const float *d_proj, float *d_vol, void *hip_stream);
+
+/* Geometry queries (host-side, no device work). */
+cvp_status cvp_geometry_sizes(const cvp_geometry *g, int64_t *n_voxels,
+                              int64_t *n_pixels_total);
+
+/* Human-readable status name; never NULL. */
+const char *cvp_status_string(cvp_status s);
+
+/* Copies the calling thread's last error message into buf (NUL-terminated,
+ * truncated to n bytes).  Returns CVP_OK, or CVP_E_INVALID if buf is NULL. */
+cvp_status cvp_last_error_detail(char *buf, size_t n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CVP_H */

@@ -1,0 +1,7 @@
+"""MI355X (gfx950) cutting voxel projector.
+
+Hand-written HIP kernels behind a C ABI (include/cvp.h, libcvp.so); this
+package is the thin Python binding.  Kulvait & Rose, "Cutting Voxel Projector
+a New Approach to Construct 3D Cone Beam CT Operator" (2021).
+"""
+from .cvp import Geometry, Options, backproject, project  # noqa: F401

@@ -1,0 +1,328 @@
+// C ABI of the cutting voxel projector library: argument validation, FP64
+// host geometry, device tables and launch configuration.  See include/cvp.h.
+#include "cvp.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "cvp_internal.h"
+
+namespace cvp {
+hipError_t configure_kernel_lds(size_t max_lds);
+}
+
+struct cvp_geometry {
+    std::vector<double> angles;
+    int device = 0;
+    cvp::ViewGeom *d_views = nullptr;
+    float *d_sigma[2] = {nullptr, nullptr};   // solid angle, cos
+    cvp::DevGeom base{};
+    cvp::ProjLaunch pl{};
+    cvp::BackLaunch bl{};
+    int64_t nvox = 0, npix = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+cvp_status fail(cvp_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+cvp_status ok()
+{
+    g_err.clear();
+    return CVP_OK;
+}
+
+cvp_status device_fail(hipError_t e, const char *what)
+{
+    if (e == hipErrorOutOfMemory) return fail(CVP_E_NOMEM, "%s: %s", what, hipGetErrorString(e));
+    return fail(CVP_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+constexpr size_t kLdsBudget = 78 * 1024;   // two workgroups per CU (160 KB LDS)
+
+// Solid angle of the rectangle [x0,x1] x [y0,y1] on a plane at distance f
+// (pixel edges relative to the principal point): the standard arctan form.
+double rect_solid_angle(double f, double x0, double x1, double y0, double y1)
+{
+    auto F = [f](double X, double Y) { return std::atan(X * Y / (f * std::sqrt(X * X + Y * Y + f * f))); };
+    return F(x1, y1) - F(x0, y1) - F(x1, y0) + F(x0, y0);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *cvp_status_string(cvp_status s)
+{
+    switch (s) {
+    case CVP_OK: return "CVP_OK";
+    case CVP_E_INVALID: return "CVP_E_INVALID";
+    case CVP_E_NOMEM: return "CVP_E_NOMEM";
+    case CVP_E_DEVICE: return "CVP_E_DEVICE";
+    case CVP_E_UNSUPPORTED: return "CVP_E_UNSUPPORTED";
+    case CVP_E_BREAKDOWN: return "CVP_E_BREAKDOWN";
+    }
+    return "CVP_E_UNKNOWN";
+}
+
+cvp_status cvp_last_error_detail(char *buf, size_t n)
+{
+    if (!buf) return CVP_E_INVALID;
+    if (n == 0) return CVP_OK;
+    std::strncpy(buf, g_err.c_str(), n - 1);
+    buf[n - 1] = '\0';
+    return CVP_OK;
+}
+
+void cvp_geometry_destroy(cvp_geometry *g)
+{
+    if (!g) return;
+    if (g->d_views) (void)hipFree(g->d_views);
+    for (float *p : g->d_sigma)
+        if (p) (void)hipFree(p);
+    delete g;
+}
+
+cvp_status cvp_geometry_from_views(const cvp_geometry_desc *d, cvp_geometry **out)
+{
+    if (!out) return fail(CVP_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!d) return fail(CVP_E_INVALID, "desc is NULL");
+    for (int a = 0; a < 3; ++a) {
+        if (d->vol_dims[a] <= 0 || d->vol_dims[a] > 16384)
+            return fail(CVP_E_INVALID, "vol_dims[%d] = %d (must be 1..16384)", a, d->vol_dims[a]);
+        if (!finite_pos(d->voxel_mm[a]))
+            return fail(CVP_E_INVALID, "voxel_mm[%d] must be finite and > 0", a);
+        if (!std::isfinite(d->vol_offset_mm[a]))
+            return fail(CVP_E_INVALID, "vol_offset_mm[%d] must be finite", a);
+    }
+    if (d->det_cols <= 0 || d->det_cols > 16384) return fail(CVP_E_INVALID, "det_cols = %d (must be 1..16384)", d->det_cols);
+    if (d->det_rows <= 0 || d->det_rows > 16384) return fail(CVP_E_INVALID, "det_rows = %d (must be 1..16384)", d->det_rows);
+    if (!finite_pos(d->pitch_mm[0]) || !finite_pos(d->pitch_mm[1]))
+        return fail(CVP_E_INVALID, "pitch_mm must be finite and > 0");
+    if (!finite_pos(d->source_iso_mm)) return fail(CVP_E_INVALID, "source_iso_mm must be finite and > 0");
+    if (!std::isfinite(d->source_det_mm) || !(d->source_det_mm > d->source_iso_mm))
+        return fail(CVP_E_INVALID, "source_det_mm must exceed source_iso_mm");
+    if (d->n_views < 1) return fail(CVP_E_INVALID, "n_views = %d (must be >= 1)", d->n_views);
+    if (!d->angles_rad) return fail(CVP_E_INVALID, "angles_rad is NULL");
+    for (int v = 0; v < d->n_views; ++v)
+        if (!std::isfinite(d->angles_rad[v])) return fail(CVP_E_INVALID, "angles_rad[%d] is not finite", v);
+    double c1 = d->principal_px[0], c2 = d->principal_px[1];
+    if (std::isnan(c1)) c1 = 0.5 * (d->det_cols - 1);
+    if (std::isnan(c2)) c2 = 0.5 * (d->det_rows - 1);
+    if (!std::isfinite(c1) || !std::isfinite(c2)) return fail(CVP_E_INVALID, "principal_px must be finite or NAN");
+
+    const int n1 = d->vol_dims[0], n2 = d->vol_dims[1], n3 = d->vol_dims[2];
+    const double a1 = d->voxel_mm[0], a2 = d->voxel_mm[1], a3 = d->voxel_mm[2];
+    const double x1lo = d->vol_offset_mm[0] - 0.5 * n1 * a1, x2lo = d->vol_offset_mm[1] - 0.5 * n2 * a2;
+    const double x3lo = d->vol_offset_mm[2] - 0.5 * n3 * a3;
+    // farthest point of the volume box from the rotation axis (x1x2 plane)
+    double rmax = 0.0;
+    for (int c = 0; c < 4; ++c) {
+        const double x = (c & 1) ? x1lo + n1 * a1 : x1lo, y = (c & 2) ? x2lo + n2 * a2 : x2lo;
+        rmax = std::max(rmax, std::hypot(x, y));
+    }
+    const double D = d->source_iso_mm, f = d->source_det_mm;
+    if (!(D > rmax * (1.0 + 1e-9)))
+        return fail(CVP_E_INVALID, "source_iso_mm = %g must exceed the volume's distance from the axis (%g): the source would enter the volume", D, rmax);
+    const double b1 = d->pitch_mm[0], b2 = d->pitch_mm[1];
+    const double Dmin = D - rmax;
+    // widest projected voxel base and tallest projected row extent (pixels)
+    const double wmax = std::hypot(a1, a2) * f / (b1 * (Dmin - 0.5 * std::hypot(a1, a2)));
+    const int pieces = (int)std::floor(wmax) + 2;
+    if (!(Dmin > std::hypot(a1, a2)) || pieces > 8)
+        return fail(CVP_E_UNSUPPORTED, "a voxel base projects onto up to %d detector columns (max 8)", pieces);
+    const double zabs = std::max(std::fabs(x3lo), std::fabs(x3lo + n3 * a3));
+    const double ymax = std::fabs(c2) + zabs * f / (b2 * Dmin) + 8.0;
+    if (ymax > 8000.0)
+        return fail(CVP_E_UNSUPPORTED, "the volume projects up to %.0f rows from the detector origin (max 8000)", ymax);
+
+    cvp_geometry *g = new (std::nothrow) cvp_geometry();
+    if (!g) return fail(CVP_E_NOMEM, "host allocation");
+    g->angles.assign(d->angles_rad, d->angles_rad + d->n_views);
+    g->nvox = (int64_t)n1 * n2 * n3;
+    g->npix = (int64_t)d->n_views * d->det_rows * d->det_cols;
+
+    // per-view frames (Sec. II-C), FP64
+    std::vector<cvp::ViewGeom> views(d->n_views);
+    for (int v = 0; v < d->n_views; ++v) {
+        const double l = d->angles_rad[v], cl = std::cos(l), sl = std::sin(l);
+        cvp::ViewGeom &V = views[v];
+        V.s1 = D * cl; V.s2 = D * sl; V.s3 = 0.0;
+        V.e1x = -sl; V.e1y = cl;
+        V.dx = -cl; V.dy = -sl;
+        V.pad = 0.0;
+    }
+    // per-pixel factors of the second phase: 1/solid angle (eq. cvpus) and
+    // f^2 / (a cos^3 theta) = R^3 / (b1 b2 f) (eq. cvp); FP64, stored FP32
+    const int M = d->det_cols, N = d->det_rows;
+    std::vector<float> sig_sa((size_t)M * N), sig_cos((size_t)M * N);
+    for (int v = 0; v < N; ++v) {
+        const double y0 = (v - 0.5 - c2) * b2, y1 = (v + 0.5 - c2) * b2, yc = (v - c2) * b2;
+        for (int u = 0; u < M; ++u) {
+            const double x0 = (u - 0.5 - c1) * b1, x1 = (u + 0.5 - c1) * b1, xc = (u - c1) * b1;
+            sig_sa[(size_t)v * M + u] = (float)(1.0 / rect_solid_angle(f, x0, x1, y0, y1));
+            const double R = std::sqrt(xc * xc + yc * yc + f * f);
+            sig_cos[(size_t)v * M + u] = (float)(R * R * R / (b1 * b2 * f));
+        }
+    }
+
+    hipError_t e = hipGetDevice(&g->device);
+    if (e != hipSuccess) { cvp_geometry_destroy(g); return device_fail(e, "hipGetDevice"); }
+    e = hipMalloc((void **)&g->d_views, views.size() * sizeof(cvp::ViewGeom));
+    if (e == hipSuccess) e = hipMalloc((void **)&g->d_sigma[0], sig_sa.size() * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void **)&g->d_sigma[1], sig_cos.size() * sizeof(float));
+    if (e == hipSuccess) e = hipMemcpy(g->d_views, views.data(), views.size() * sizeof(cvp::ViewGeom), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(g->d_sigma[0], sig_sa.data(), sig_sa.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(g->d_sigma[1], sig_cos.data(), sig_cos.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) { cvp_geometry_destroy(g); return device_fail(e, "device tables"); }
+    static std::once_flag lds_once;
+    static hipError_t lds_err = hipSuccess;
+    std::call_once(lds_once, [] { lds_err = cvp::configure_kernel_lds(kLdsBudget); });
+    if (lds_err != hipSuccess) { cvp_geometry_destroy(g); return device_fail(lds_err, "kernel LDS attribute"); }
+
+    cvp::DevGeom &G = g->base;
+    G.n1 = n1; G.n2 = n2; G.n3 = n3; G.M = M; G.N = N; G.nviews = d->n_views;
+    G.a1 = a1; G.a2 = a2; G.a3 = a3;
+    G.x1lo = x1lo; G.x2lo = x2lo; G.x3lo = x3lo;
+    G.b1 = b1; G.b2 = b2; G.c1 = c1; G.c2 = c2; G.f = f;
+    G.views = g->d_views;
+    G.sigma = nullptr;
+    G.raw_volume = 0;
+
+    const int pmax = pieces <= 4 ? 4 : 8;
+    // projection: bands of U detector columns; LDS = per-wave bins + row
+    // tables + per-wave piece records
+    {
+        cvp::ProjLaunch &L = g->pl;
+        const size_t npad = (size_t)(N | 1);
+        const size_t other = (size_t)(2 * n2 + 1 + cvp::kBlock + 4) * 4 + 16 +
+                             (size_t)cvp::kWaves * (16 * pmax * cvp::kRecFloats + 16) * 4;
+        if (other + cvp::kWaves * npad * 4 > kLdsBudget) {
+            cvp_geometry_destroy(g);
+            return fail(CVP_E_UNSUPPORTED, "detector rows (%d) or volume rows (%d) too large for the projection LDS layout", N, n2);
+        }
+        int U = (int)((kLdsBudget - other) / (cvp::kWaves * npad * 4));
+        U = std::max(1, std::min(U, 32));
+        L.U = U;
+        L.nbands = (M + U - 1) / U;
+        L.items = L.nbands * d->n_views;
+        L.chunk = (L.items + 7) / 8;
+        L.pmax = pmax;
+        L.lds = other + cvp::kWaves * (size_t)U * npad * 4;
+    }
+    // backprojection: stacks of GW columns x 64 voxels; LDS = per-wave piece
+    // records + per-wave detector window (also reused for the final sum)
+    {
+        cvp::BackLaunch &L = g->bl;
+        const double mag = f / Dmin;
+        int gw = 4;
+        int cap = 0;
+        for (int cand : {16, 8, 4}) {
+            const size_t rec = (size_t)cand * pmax * cvp::kRecFloats + cand;
+            const int c = (int)((kLdsBudget / (cvp::kWaves * 4) - rec) / 4 * 4);
+            const double wu = std::hypot(cand * a1, a2) * mag / b1 + pmax + 2;
+            const double zspan = std::hypot(cand * a1, a2);
+            const double wv = 64 * a3 * mag / b2 + zabs * (f / b2) * zspan / (Dmin * Dmin) + 6;
+            gw = cand;
+            cap = c;
+            if (wu * ((int)wv | 1) <= c) break;
+        }
+        L.gw = gw;
+        L.win_cap = cap;
+        L.pmax = pmax;
+        L.ngroups = (n1 + gw - 1) / gw;
+        L.nkchunks = (n3 + 63) / 64;
+        L.items = n2 * L.ngroups * L.nkchunks;
+        L.chunk = (L.items + 7) / 8;
+        const size_t waveFloats = ((size_t)gw * pmax * cvp::kRecFloats + gw + cap + 3) / 4 * 4;
+        L.lds = cvp::kWaves * waveFloats * 4;
+        if (cap < 1024) {
+            cvp_geometry_destroy(g);
+            return fail(CVP_E_UNSUPPORTED, "backprojection LDS window too small");
+        }
+    }
+    *out = g;
+    return ok();
+}
+
+cvp_status cvp_geometry_sizes(const cvp_geometry *g, int64_t *n_voxels, int64_t *n_pixels_total)
+{
+    if (!g) return fail(CVP_E_INVALID, "geometry is NULL");
+    if (n_voxels) *n_voxels = g->nvox;
+    if (n_pixels_total) *n_pixels_total = g->npix;
+    return ok();
+}
+
+static cvp_status prepare(const cvp_geometry *g, const cvp_options *o, const void *in, void *outp,
+                          cvp::DevGeom &G)
+{
+    if (!g) return fail(CVP_E_INVALID, "geometry is NULL");
+    if (!o) return fail(CVP_E_INVALID, "options is NULL");
+    if (!in) return fail(CVP_E_INVALID, "input pointer is NULL");
+    if (!outp) return fail(CVP_E_INVALID, "output pointer is NULL");
+    if (in == outp) return fail(CVP_E_INVALID, "input and output alias");
+    if (o->variant != CVP_EXACT && o->variant != CVP_RELAXED)
+        return fail(CVP_E_INVALID, "options.variant = %d", (int)o->variant);
+    if (o->elevation_correction != 0 && o->elevation_correction != 1)
+        return fail(CVP_E_INVALID, "options.elevation_correction = %d", o->elevation_correction);
+    if (o->scaling != CVP_SCALE_SOLID_ANGLE && o->scaling != CVP_SCALE_COS && o->scaling != CVP_SCALE_NONE)
+        return fail(CVP_E_INVALID, "options.scaling = %d", (int)o->scaling);
+    if (o->flags & ~CVP_FLAG_RAW_VOLUME) return fail(CVP_E_INVALID, "options.flags = 0x%x", o->flags);
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return device_fail(e, "hipGetDevice");
+    if (dev != g->device)
+        return fail(CVP_E_INVALID, "geometry lives on device %d but device %d is current", g->device, dev);
+    G = g->base;
+    G.sigma = o->scaling == CVP_SCALE_NONE ? nullptr : g->d_sigma[o->scaling == CVP_SCALE_COS ? 1 : 0];
+    G.raw_volume = (o->flags & CVP_FLAG_RAW_VOLUME) ? 1 : 0;
+    return CVP_OK;
+}
+
+cvp_status cvp_project(const cvp_geometry *g, const cvp_options *o, const float *d_vol,
+                       float *d_proj, void *stream)
+{
+    cvp::DevGeom G;
+    cvp_status st = prepare(g, o, d_vol, d_proj, G);
+    if (st != CVP_OK) return st;
+    hipError_t e = cvp::launch_project(G, g->pl, o->variant == CVP_EXACT, o->elevation_correction != 0,
+                                       d_vol, d_proj, (hipStream_t)stream);
+    if (e != hipSuccess) return device_fail(e, "projection launch");
+    return ok();
+}
+
+cvp_status cvp_backproject(const cvp_geometry *g, const cvp_options *o, const float *d_proj,
+                           float *d_vol, void *stream)
+{
+    cvp::DevGeom G;
+    cvp_status st = prepare(g, o, d_proj, d_vol, G);
+    if (st != CVP_OK) return st;
+    hipError_t e = cvp::launch_backproject(G, g->bl, o->variant == CVP_EXACT, o->elevation_correction != 0,
+                                           d_proj, d_vol, (hipStream_t)stream);
+    if (e != hipSuccess) return device_fail(e, "backprojection launch");
+    return ok();
+}
+
+}  // extern "C"

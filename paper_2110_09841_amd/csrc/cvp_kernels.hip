@@ -1,0 +1,721 @@
+// Cutting voxel projector kernels for gfx950 (MI355X).
+//
+// Kulvait & Rose, "Cutting Voxel Projector a New Approach to Construct 3D Cone
+// Beam CT Operator" (2021).  Both directions apply the same weights
+//   w = mu * |V^(ijk)_(uv)| / r^2            (Sec. II-F, eq. vox)
+// with the cut volume estimated as A_u * d_uv (Sec. III-A, eq. cutvolume) and
+// the per-pixel factor sigma_uv applied to the unscaled sums (eq. cvpsu).
+//
+// Work split (one launch per direction, no global atomics):
+//  * projection: a workgroup owns one view and a band of U detector columns.
+//    It walks every voxel column whose base meets the band's wedge (by the
+//    column identity of Sec. III-A the wedge is the same for all k), computes
+//    the column cut pieces once per column in FP64, and then, with lanes over
+//    k, scatters each voxel's row pieces into LDS bins with ds_add_f32.  The
+//    band is written once at the end, scaled by sigma.
+//  * backprojection: a workgroup owns a 64-voxel-tall stack of GW columns;
+//    each wave takes every 4th view, stages the pre-scaled detector window of
+//    the stack in LDS and gathers into registers.  Each voxel is written once.
+//
+// Numerics: the column stage (polygon moments, centroid depth) runs in FP64
+// (full rate on CDNA4 VALU); the per-voxel stage runs in FP32 on quantities
+// that are small by construction: detector row positions are split into a
+// 2^-10-quantised high part, whose differences with half-integer row
+// boundaries are exact, plus a small low part.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "cvp_internal.h"
+
+namespace cvp {
+namespace {
+
+// ------------------------------------------------------------ FP64 column stage
+
+// Shoelace sums of a polygon: a2 = 2A, sx = 6A cx, sy = 6A cy,
+// sxx = 12 int x^2, syy = 12 int y^2, sxy = 24 int xy.
+struct Mom {
+    double a2, sx, sy, sxx, sxy, syy;
+};
+
+__device__ __forceinline__ void mom_edge(Mom &m, double x0, double y0, double x1, double y1)
+{
+    const double cr = x0 * y1 - x1 * y0;
+    m.a2 += cr;
+    m.sx += (x0 + x1) * cr;
+    m.sy += (y0 + y1) * cr;
+    m.sxx += (x0 * x0 + x0 * x1 + x1 * x1) * cr;
+    m.syy += (y0 * y0 + y0 * y1 + y1 * y1) * cr;
+    m.sxy += (x0 * y1 + 2.0 * x0 * y0 + 2.0 * x1 * y1 + x1 * y0) * cr;
+}
+
+// Moments of the square [-h1,h1] x [-h2,h2] cut to {q : gx qx + gy qy + c <= 0}
+// by Green's theorem: the inside parts of the square's edges (counter-
+// clockwise) plus the chord along the cutting line from exit to entry.
+__device__ __forceinline__ Mom halfplane_moments(double h1, double h2, double gx, double gy,
+                                                 double c)
+{
+    const double px[4] = {-h1, h1, h1, -h1};
+    const double py[4] = {-h2, -h2, h2, h2};
+    double val[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) val[k] = gx * px[k] + gy * py[k] + c;
+    Mom m = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double ex = 0.0, ey = 0.0, nx = 0.0, ny = 0.0;
+    bool has_exit = false, has_entry = false;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int b = (k + 1) & 3;
+        const double va = val[k], vb = val[b];
+        if (va <= 0.0 && vb <= 0.0) {
+            mom_edge(m, px[k], py[k], px[b], py[b]);
+        } else if (va <= 0.0) {
+            const double t = va / (va - vb);
+            const double xx = px[k] + t * (px[b] - px[k]), yy = py[k] + t * (py[b] - py[k]);
+            mom_edge(m, px[k], py[k], xx, yy);
+            ex = xx; ey = yy; has_exit = true;
+        } else if (vb <= 0.0) {
+            const double t = va / (va - vb);
+            const double xx = px[k] + t * (px[b] - px[k]), yy = py[k] + t * (py[b] - py[k]);
+            mom_edge(m, xx, yy, px[b], py[b]);
+            nx = xx; ny = yy; has_entry = true;
+        }
+    }
+    if (has_exit && has_entry) mom_edge(m, ex, ey, nx, ny);
+    return m;
+}
+
+// One voxel column (i, j) seen from one view.  Local coordinates q are
+// relative to the column centre.  chi1(x) <= t  <=>  G(t).q + chi1c - t <= 0
+// with G(t) = ((f/b1) e1 - (t - c1) d) / Dc: the half-plane of the paper's
+// polygons H- / H+ (Sec. III-A), normalised by the centre depth Dc > 0.
+struct Column {
+    double xc1, xc2;   // centre
+    double Dc;         // depth of the centre, d.(xc - s)
+    double chic;       // chi1 of the centre
+    double chimin, chimax;
+};
+
+__device__ __forceinline__ Column make_column(const DevGeom &G, const ViewGeom &V, int i, int j)
+{
+    Column C;
+    C.xc1 = G.x1lo + (i + 0.5) * G.a1;
+    C.xc2 = G.x2lo + (j + 0.5) * G.a2;
+    const double r1 = C.xc1 - V.s1, r2 = C.xc2 - V.s2;
+    const double P1 = V.e1x * r1 + V.e1y * r2;
+    C.Dc = V.dx * r1 + V.dy * r2;
+    const double fb = G.f / G.b1;
+    C.chic = G.c1 + fb * P1 / C.Dc;
+    double mn = 1e300, mx = -1e300;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double q1 = (k & 1) ? 0.5 * G.a1 : -0.5 * G.a1;
+        const double q2 = (k & 2) ? 0.5 * G.a2 : -0.5 * G.a2;
+        const double ch = G.c1 + fb * (P1 + V.e1x * q1 + V.e1y * q2) / (C.Dc + V.dx * q1 + V.dy * q2);
+        mn = fmin(mn, ch);
+        mx = fmax(mx, ch);
+    }
+    C.chimin = mn;
+    C.chimax = mx;
+    return C;
+}
+
+__device__ __forceinline__ Mom column_prefix(const DevGeom &G, const ViewGeom &V, const Column &C,
+                                             double t)
+{
+    const double fb = G.f / G.b1;
+    const double inv = 1.0 / C.Dc;
+    const double gx = (fb * V.e1x - (t - G.c1) * V.dx) * inv;
+    const double gy = (fb * V.e1y - (t - G.c1) * V.dy) * inv;
+    return halfplane_moments(0.5 * G.a1, 0.5 * G.a2, gx, gy, C.chic - t);
+}
+
+// Record of one cut piece H_u for the FP32 voxel stage (12 floats):
+//  [0] u (int bits)  [1] W = A_u * b2 D_u / f       [2] Y0 hi   [3] Y0 lo
+//  [4] beta hi       [5] beta lo   [6] beta          [7] rho = h/D (EC)
+//  [8] R^2 (x1x2 part of r^2: cut centroid, or column centre if relaxed)
+//  [9] b2 D_u / f (mm of x3 per row)  [10..11] unused
+// Y(k) = Y0 - k beta is chi2 of the top face of voxel k at the centroid depth.
+template <bool EXACT, bool EC>
+__device__ __forceinline__ void piece_record(const DevGeom &G, const ViewGeom &V, const Column &C,
+                                             int u, float *rec)
+{
+    const Mom hi = column_prefix(G, V, C, u + 0.5);
+    const Mom lo = column_prefix(G, V, C, u - 0.5);
+    const double a2 = hi.a2 - lo.a2;
+    const double A = 0.5 * a2;
+    double cx = 0.0, cy = 0.0, var = 0.0;
+    if (A > 1e-12 * G.a1 * G.a2) {
+        cx = (hi.sx - lo.sx) / (3.0 * a2);
+        cy = (hi.sy - lo.sy) / (3.0 * a2);
+        const double cxx = (hi.sxx - lo.sxx) / (12.0 * A) - cx * cx;
+        const double cyy = (hi.syy - lo.syy) / (12.0 * A) - cy * cy;
+        const double cxy = (hi.sxy - lo.sxy) / (24.0 * A) - cx * cy;
+        var = V.dx * V.dx * cxx + 2.0 * V.dx * V.dy * cxy + V.dy * V.dy * cyy;
+        if (!(var > 0.0)) var = 0.0;
+    }
+    const double Du = C.Dc + V.dx * cx + V.dy * cy;
+    const double gmm = G.b2 * Du / G.f;          // x3 mm per detector row at depth Du
+    const double ig = G.f / (G.b2 * Du);
+    const double Y0 = G.c2 - (G.x3lo + G.a3 - V.s3) * ig;
+    const double beta = G.a3 * ig;
+    const double Y0h = rint(Y0 * 1024.0) * (1.0 / 1024.0);
+    const double bh = rint(beta * 1024.0) * (1.0 / 1024.0);
+    double R2;
+    if (EXACT) {
+        const double p1 = C.xc1 + cx - V.s1, p2 = C.xc2 + cy - V.s2;
+        R2 = p1 * p1 + p2 * p2;
+    } else {
+        const double p1 = C.xc1 - V.s1, p2 = C.xc2 - V.s2;
+        R2 = p1 * p1 + p2 * p2;
+    }
+    rec[0] = __int_as_float(u);
+    rec[1] = (A > 1e-12 * G.a1 * G.a2) ? (float)(A * gmm) : 0.0f;
+    rec[2] = (float)Y0h;
+    rec[3] = (float)(Y0 - Y0h);
+    rec[4] = (float)bh;
+    rec[5] = (float)(beta - bh);
+    rec[6] = (float)beta;
+    rec[7] = EC ? (float)(sqrt(3.0 * var) / Du) : 0.0f;
+    rec[8] = (float)R2;
+    rec[9] = (float)gmm;
+    rec[10] = 0.0f;
+    rec[11] = 0.0f;
+}
+
+// ------------------------------------------------------------ FP32 voxel stage
+
+// Box average over the depth box of max(s, 0), where s moves uniformly over
+// [s - e, s + e] (Sec. III-B reading); e = 0 gives max(s, 0).
+__device__ __forceinline__ float tbox(float s, float e, float inv4e)
+{
+    const float a = s + e;
+    const float quad = a * a * inv4e;
+    const float low = (s <= -e) ? 0.0f : quad;
+    return (s >= e) ? s : low;
+}
+
+// C(t): the part of the voxel's chi2 extent [Ytop, Ytop + beta] that lies
+// beyond row boundary t (averaged over the depth box with EC).  s1 = Ytop - t.
+template <bool EC>
+__device__ __forceinline__ float cum(float s1, float beta, float tc, float rho)
+{
+    const float s0 = s1 + beta;
+    if (!EC) return fmaxf(s0, 0.0f) - fmaxf(s1, 0.0f);
+    const float e = fabsf(tc) * rho;
+    const float inv = 0.25f * __builtin_amdgcn_rcpf(e);
+    return tbox(s0, e, inv) - tbox(s1, e, inv);
+}
+
+__device__ __forceinline__ void lds_add(float *p, float v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Rows touched by a piece of voxel k: [vlo, vhi] clipped to the detector.
+template <bool EC>
+__device__ __forceinline__ void row_range(float Ytop, float beta, float rho, float c2f, int N,
+                                          int &vlo, int &vhi)
+{
+    float E = 0.0f;
+    if (EC) E = 1.01f * rho * (fmaxf(fabsf(Ytop - c2f), fabsf(Ytop + beta - c2f)) + 1.0f);
+    vlo = max((int)floorf(Ytop - E + 0.5f - 1e-3f), 0);
+    vhi = min((int)floorf(Ytop + beta + E + 0.5f + 1e-3f), N - 1);
+}
+
+// Record phase shared by both directions: lanes (c, slot) compute the pieces
+// of columns i0 + c of row j whose detector column u lies in [ulo, uhi].
+template <bool EXACT, bool EC, int PMAX, int GW>
+__device__ __forceinline__ void build_records(const DevGeom &G, const ViewGeom &V, int i0, int j,
+                                              int ulo, int uhi, float *rec, int *npc, int lane)
+{
+    constexpr int SLOTS = kWave / GW;
+    const int c = lane % GW;
+    const int slot = lane / GW;
+    const int i = i0 + c;
+    const bool colok = i < G.n1;
+    Column C;
+    int ufirst = 0, n = 0;
+    if (colok) {
+        C = make_column(G, V, i, j);
+        ufirst = max((int)floor(C.chimin + 0.5), ulo);
+        const int ulast = min((int)floor(C.chimax + 0.5), uhi);
+        n = min(max(ulast - ufirst + 1, 0), PMAX);
+    }
+    if (slot == 0) npc[c] = n;
+#pragma unroll
+    for (int pass = 0; pass * SLOTS < PMAX; ++pass) {
+        const int s = slot + pass * SLOTS;
+        if (colok && s < n) piece_record<EXACT, EC>(G, V, C, ufirst + s, rec + (c * PMAX + s) * kRecFloats);
+    }
+}
+
+// ------------------------------------------------------------ projection
+
+template <bool EXACT, bool EC, int PMAX>
+__global__ void __launch_bounds__(kBlock)
+project_kernel(const DevGeom G, const int U, const int items, const int chunk,
+               const float *__restrict__ vol, float *__restrict__ proj)
+{
+    constexpr int GW = 16;
+    extern __shared__ __align__(16) float smem[];
+    const int item = (blockIdx.x & 7) * chunk + (blockIdx.x >> 3);   // XCD-contiguous items
+    if (item >= items) return;
+    const int view = item % G.nviews;
+    const int u0 = (item / G.nviews) * U;
+    const int ub = min(u0 + U, G.M) - 1;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int Npad = G.N | 1;
+    const int ngroups = (G.n1 + GW - 1) / GW;
+
+    // per-wavefront bins (each wave sums into its own band image, so the
+    // order of additions into any pixel is fixed), then row tables, then the
+    // per-wave piece records
+    float *bins = smem;
+    float *wbins = bins + wave * U * Npad;
+    int *rowStart = reinterpret_cast<int *>(bins + kWaves * U * Npad);
+    int *rowQ = rowStart + (G.n2 + 1);
+    int *part = rowQ + G.n2;
+    float *recAll = reinterpret_cast<float *>(part + kBlock + 4);
+    recAll = reinterpret_cast<float *>((reinterpret_cast<uintptr_t>(recAll) + 15) & ~uintptr_t(15));
+    float *rec = recAll + wave * (GW * PMAX * kRecFloats + GW);
+    int *npc = reinterpret_cast<int *>(rec + GW * PMAX * kRecFloats);
+
+    for (int idx = tid; idx < kWaves * U * Npad; idx += kBlock) bins[idx] = 0.0f;
+
+    const ViewGeom V = G.views[view];
+
+    // Column groups of each row j meeting the band's wedge: the chi1 range of
+    // a group's base rectangle (extremes at its corners) must meet
+    // [u0 - 1/2, ub + 1/2].  chi1 is monotone in x1, so the hits are
+    // contiguous in the group index.  FP32 with a margin is conservative.
+    {
+        const float fb = (float)(G.f / G.b1);
+        const float e1x = (float)V.e1x, e1y = (float)V.e1y, dx = (float)V.dx, dy = (float)V.dy;
+        const float lo_t = u0 - 0.5f - 0.02f, hi_t = ub + 0.5f + 0.02f;
+        const int rows_per = (G.n2 + kBlock - 1) / kBlock;
+        int local = 0;
+        for (int r = 0; r < rows_per; ++r) {
+            const int j = tid * rows_per + r;
+            if (j >= G.n2) break;
+            const float y0 = (float)(G.x2lo + j * G.a2 - V.s2), y1 = y0 + (float)G.a2;
+            int qa = -1, qb = -2;
+            for (int q = 0; q < ngroups; ++q) {
+                const float x0 = (float)(G.x1lo + q * GW * G.a1 - V.s1);
+                const float x1 = (float)(G.x1lo + min((q + 1) * GW, G.n1) * G.a1 - V.s1);
+                float mn = 1e30f, mx = -1e30f;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const float px = (k & 1) ? x1 : x0, py = (k & 2) ? y1 : y0;
+                    const float ch = (float)G.c1 + fb * (e1x * px + e1y * py) / (dx * px + dy * py);
+                    mn = fminf(mn, ch);
+                    mx = fmaxf(mx, ch);
+                }
+                if (mx >= lo_t && mn <= hi_t) {
+                    if (qa < 0) qa = q;
+                    qb = q;
+                }
+            }
+            rowQ[j] = qa;
+            const int cnt = qa >= 0 ? qb - qa + 1 : 0;
+            rowStart[j] = cnt;   // counts for now
+            local += cnt;
+        }
+        part[tid] = local;
+        __syncthreads();
+        if (tid == 0) {
+            int acc = 0;
+            for (int t = 0; t < kBlock; ++t) {
+                const int v = part[t];
+                part[t] = acc;
+                acc += v;
+            }
+            rowStart[G.n2] = acc;
+        }
+        __syncthreads();
+        int acc = part[tid];
+        for (int r = 0; r < rows_per; ++r) {
+            const int j = tid * rows_per + r;
+            if (j >= G.n2) break;
+            const int cnt = rowStart[j];
+            rowStart[j] = acc;
+            acc += cnt;
+        }
+        __syncthreads();
+    }
+    const int total = rowStart[G.n2];
+
+    const float c2f = (float)G.c2;
+    const float a3f = (float)G.a3;
+    const float zt0 = (float)(G.x3lo + G.a3 - V.s3);   // x3 of the top of voxel 0, minus s3
+    const bool raw = G.raw_volume != 0;
+    const bool vec_rows = (G.n1 & 3) == 0 && (reinterpret_cast<uintptr_t>(vol) & 15) == 0;
+
+    for (int gi = wave; gi < total; gi += kWaves) {
+        int lo = 0, hi = G.n2;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (rowStart[mid] <= gi) lo = mid; else hi = mid;
+        }
+        const int j = lo;
+        const int i0 = (rowQ[j] + (gi - rowStart[j])) * GW;
+
+        build_records<EXACT, EC, PMAX, GW>(G, V, i0, j, u0, ub, rec, npc, lane);
+        wave_sync();
+        int any = 0;
+#pragma unroll
+        for (int c = 0; c < GW; ++c) any |= npc[c];
+        if (any == 0) {
+            wave_sync();
+            continue;
+        }
+        const bool full = vec_rows && (i0 + GW <= G.n1);
+
+        for (int kc = 0; kc < G.n3; kc += kWave) {
+            const int k = kc + lane;
+            const bool kv = k < G.n3;
+            float mu[GW];
+            const float *rowp = vol + ((size_t)min(k, G.n3 - 1) * G.n2 + j) * G.n1 + i0;
+            if (full) {
+#pragma unroll
+                for (int q = 0; q < GW / 4; ++q) {
+                    const float4 t4 = reinterpret_cast<const float4 *>(rowp)[q];
+                    mu[4 * q] = t4.x; mu[4 * q + 1] = t4.y; mu[4 * q + 2] = t4.z; mu[4 * q + 3] = t4.w;
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < GW; ++c) mu[c] = (i0 + c < G.n1) ? rowp[c] : 0.0f;
+            }
+            const float kf = (float)k;
+            const float zt = fmaf(kf, a3f, zt0);        // top of voxel k, relative to s3
+            const float zc = zt - 0.5f * a3f;           // centre of voxel k
+#pragma unroll
+            for (int c = 0; c < GW; ++c) {
+                const int np = npc[c];
+                if (np == 0) continue;
+                const float m = kv ? mu[c] : 0.0f;
+                if (__ballot(m != 0.0f) == 0) continue;
+                const float *rc = rec + c * PMAX * kRecFloats;
+                float base = m;
+                if (!EXACT && !raw) base = m * __builtin_amdgcn_rcpf(fmaf(zc, zc, rc[8]));
+                for (int p = 0; p < np; ++p) {
+                    const float4 r0 = *reinterpret_cast<const float4 *>(rc + p * kRecFloats);
+                    const float4 r1 = *reinterpret_cast<const float4 *>(rc + p * kRecFloats + 4);
+                    const float4 r2 = *reinterpret_cast<const float4 *>(rc + p * kRecFloats + 8);
+                    const int u = __float_as_int(r0.x);
+                    const float coef = base * r0.y;
+                    const float Yh = fmaf(-kf, r1.x, r0.z);
+                    const float Yl = fmaf(-kf, r1.y, r0.w);
+                    const float beta = r1.z, rho = r1.w;
+                    int vlo, vhi;
+                    row_range<EC>(Yh + Yl, beta, rho, c2f, G.N, vlo, vhi);
+                    float *bcol = wbins + (u - u0) * Npad;
+                    float tb = (float)vlo - 0.5f;
+                    float s1p = (Yh - tb) + Yl;
+                    float Cp = cum<EC>(s1p, beta, tb - c2f, rho);
+                    for (int v = vlo; v <= vhi; ++v) {
+                        tb += 1.0f;
+                        const float s1n = (Yh - tb) + Yl;
+                        const float Cn = cum<EC>(s1n, beta, tb - c2f, rho);
+                        float w = coef * (Cp - Cn);
+                        if (EXACT && !raw) {
+                            float mm = 0.5f * (fmaxf(0.0f, -s1p) + fminf(beta, -s1n));
+                            mm = fminf(fmaxf(mm, 0.0f), beta);
+                            const float zb = fmaf(-mm, r2.y, zt);
+                            w *= __builtin_amdgcn_rcpf(fmaf(zb, zb, r2.x));
+                        }
+                        lds_add(bcol + v, w);
+                        Cp = Cn;
+                        s1p = s1n;
+                    }
+                }
+            }
+        }
+        wave_sync();
+    }
+    __syncthreads();
+
+    // Coalesced flush of the band: the wave images summed in a fixed order,
+    // times the pixel factor (second phase).
+    const int Ub = ub - u0 + 1;
+    for (int idx = tid; idx < Ub * G.N; idx += kBlock) {
+        const int du = idx % Ub, v = idx / Ub;
+        const int u = u0 + du;
+        float s = bins[du * Npad + v];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) s += bins[(w * U + du) * Npad + v];
+        if (G.sigma) s *= G.sigma[(size_t)v * G.M + u];
+        proj[((size_t)view * G.N + v) * G.M + u] = s;
+    }
+}
+
+// ------------------------------------------------------------ backprojection
+
+template <bool EXACT, bool EC, int PMAX, int GW>
+__global__ void __launch_bounds__(kBlock)
+backproject_kernel(const DevGeom G, const int ngroups, const int nkchunks, const int items,
+                   const int chunk, const int winCap, const float *__restrict__ proj,
+                   float *__restrict__ vol)
+{
+    extern __shared__ __align__(16) float smem[];
+    const int item = (blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
+    if (item >= items) return;
+    const int kch = item % nkchunks;
+    const int t = item / nkchunks;
+    const int q = t % ngroups;
+    const int j = t / ngroups;
+    const int i0 = q * GW;
+    const int k0 = kch * kWave;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int k = k0 + lane;
+    const bool kv = k < G.n3;
+    const int kmax = min(k0 + kWave, G.n3) - 1;
+
+    const int recFloats = GW * PMAX * kRecFloats + GW;
+    const int waveFloats = ((recFloats + winCap + 3) / 4) * 4;
+    float *rec = smem + wave * waveFloats;
+    int *npc = reinterpret_cast<int *>(rec + GW * PMAX * kRecFloats);
+    float *win = rec + recFloats;
+
+    const float c2f = (float)G.c2;
+    const float a3f = (float)G.a3;
+    const bool raw = G.raw_volume != 0;
+    const float kf = (float)k;
+
+    float acc[GW];
+#pragma unroll
+    for (int c = 0; c < GW; ++c) acc[c] = 0.0f;
+
+    for (int view = wave; view < G.nviews; view += kWaves) {
+        const ViewGeom V = G.views[view];
+        build_records<EXACT, EC, PMAX, GW>(G, V, i0, j, 0, G.M - 1, rec, npc, lane);
+        wave_sync();
+
+        // detector window of the stack: columns of all pieces, rows of the
+        // chunk's top voxel (smallest chi2) to its bottom voxel
+        int wu0 = 1 << 30, wu1 = -1, wv0 = 1 << 30, wv1 = -1;
+        {
+            const int c = lane % GW, s0 = lane / GW;
+            for (int s = s0; s < PMAX; s += kWave / GW) {
+                if (s < npc[c]) {
+                    const float *r = rec + (c * PMAX + s) * kRecFloats;
+                    const int u = __float_as_int(r[0]);
+                    const float beta = r[6], rho = r[7];
+                    const float Ytop_hi = fmaf(-(float)kmax, r[4], r[2]) + fmaf(-(float)kmax, r[5], r[3]);
+                    const float Ytop_lo = fmaf(-(float)k0, r[4], r[2]) + fmaf(-(float)k0, r[5], r[3]);
+                    int a, b, a2, b2;
+                    row_range<EC>(Ytop_hi, beta, rho, c2f, G.N, a, b);
+                    row_range<EC>(Ytop_lo, beta, rho, c2f, G.N, a2, b2);
+                    wu0 = min(wu0, u); wu1 = max(wu1, u);
+                    wv0 = min(wv0, min(a, a2)); wv1 = max(wv1, max(b, b2));
+                }
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                wu0 = min(wu0, __shfl_xor(wu0, off));
+                wu1 = max(wu1, __shfl_xor(wu1, off));
+                wv0 = min(wv0, __shfl_xor(wv0, off));
+                wv1 = max(wv1, __shfl_xor(wv1, off));
+            }
+        }
+        if (wu1 < wu0 || wv1 < wv0) {
+            wave_sync();
+            continue;
+        }
+        // one spare row each side absorbs FP32 rounding of intermediate k
+        wv0 = max(wv0 - 1, 0);
+        wv1 = min(wv1 + 1, G.N - 1);
+        const int Wd = wu1 - wu0 + 1;
+        const int H = wv1 - wv0 + 1;
+        const int Hp = H | 1;
+        const bool useWin = Wd * Hp <= winCap;
+        const float *pv = proj + (size_t)view * G.N * G.M;
+        if (useWin) {
+            for (int idx = lane; idx < Wd * H; idx += kWave) {
+                const int uu = idx % Wd, vv = idx / Wd;
+                const size_t off = (size_t)(wv0 + vv) * G.M + (wu0 + uu);
+                float val = pv[off];
+                if (G.sigma) val *= G.sigma[off];
+                win[uu * Hp + vv] = val;
+            }
+        }
+        wave_sync();
+
+        const float zt = fmaf(kf, a3f, (float)(G.x3lo + G.a3 - V.s3));
+        const float zc = zt - 0.5f * a3f;
+#pragma unroll
+        for (int c = 0; c < GW; ++c) {
+            const int np = npc[c];
+            if (np == 0) continue;
+            const float *rc = rec + c * PMAX * kRecFloats;
+            float base = 1.0f;
+            if (!EXACT && !raw) base = __builtin_amdgcn_rcpf(fmaf(zc, zc, rc[8]));
+            float a = 0.0f;
+            for (int p = 0; p < np; ++p) {
+                const float4 r0 = *reinterpret_cast<const float4 *>(rc + p * kRecFloats);
+                const float4 r1 = *reinterpret_cast<const float4 *>(rc + p * kRecFloats + 4);
+                const float4 r2 = *reinterpret_cast<const float4 *>(rc + p * kRecFloats + 8);
+                const int u = __float_as_int(r0.x);
+                const float coef = base * r0.y;
+                const float Yh = fmaf(-kf, r1.x, r0.z);
+                const float Yl = fmaf(-kf, r1.y, r0.w);
+                const float beta = r1.z, rho = r1.w;
+                int vlo, vhi;
+                row_range<EC>(Yh + Yl, beta, rho, c2f, G.N, vlo, vhi);
+                vlo = max(vlo, wv0);
+                vhi = min(vhi, wv1);
+                if (!kv) vhi = vlo - 1;
+                const float *wcol = win + (u - wu0) * Hp - wv0;
+                float tb = (float)vlo - 0.5f;
+                float s1p = (Yh - tb) + Yl;
+                float Cp = cum<EC>(s1p, beta, tb - c2f, rho);
+                for (int v = vlo; v <= vhi; ++v) {
+                    tb += 1.0f;
+                    const float s1n = (Yh - tb) + Yl;
+                    const float Cn = cum<EC>(s1n, beta, tb - c2f, rho);
+                    float w = coef * (Cp - Cn);
+                    if (EXACT && !raw) {
+                        float mm = 0.5f * (fmaxf(0.0f, -s1p) + fminf(beta, -s1n));
+                        mm = fminf(fmaxf(mm, 0.0f), beta);
+                        const float zb = fmaf(-mm, r2.y, zt);
+                        w *= __builtin_amdgcn_rcpf(fmaf(zb, zb, r2.x));
+                    }
+                    float val;
+                    if (useWin) {
+                        val = wcol[v];
+                    } else {
+                        const size_t off = (size_t)v * G.M + u;
+                        val = pv[off];
+                        if (G.sigma) val *= G.sigma[off];
+                    }
+                    a = fmaf(w, val, a);
+                    Cp = Cn;
+                    s1p = s1n;
+                }
+            }
+            acc[c] += a;
+        }
+        wave_sync();
+    }
+
+    // Sum the four waves' partial sums in a fixed order; one store per voxel.
+    __syncthreads();
+    float *red = smem;   // [kWaves][GW][kWave], aliases the per-wave areas
+#pragma unroll
+    for (int c = 0; c < GW; ++c) red[(wave * GW + c) * kWave + lane] = acc[c];
+    __syncthreads();
+    for (int c = wave; c < GW; c += kWaves) {
+        const int i = i0 + c;
+        float s = red[(0 * GW + c) * kWave + lane];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) s += red[(w * GW + c) * kWave + lane];
+        if (kv && i < G.n1) vol[((size_t)k * G.n2 + j) * G.n1 + i] = s;
+    }
+}
+
+template <bool EXACT, bool EC>
+hipError_t launch_p(const DevGeom &g, const ProjLaunch &L, const float *vol, float *proj,
+                    hipStream_t s)
+{
+    const dim3 grid(8 * L.chunk), block(kBlock);
+    if (L.pmax <= 4)
+        hipLaunchKernelGGL((project_kernel<EXACT, EC, 4>), grid, block, L.lds, s, g, L.U, L.items,
+                           L.chunk, vol, proj);
+    else
+        hipLaunchKernelGGL((project_kernel<EXACT, EC, 8>), grid, block, L.lds, s, g, L.U, L.items,
+                           L.chunk, vol, proj);
+    return hipGetLastError();
+}
+
+template <bool EXACT, bool EC, int PMAX>
+hipError_t launch_bp_gw(const DevGeom &g, const BackLaunch &L, const float *proj, float *vol,
+                        hipStream_t s)
+{
+    const dim3 grid(8 * L.chunk), block(kBlock);
+    switch (L.gw) {
+    case 16:
+        hipLaunchKernelGGL((backproject_kernel<EXACT, EC, PMAX, 16>), grid, block, L.lds, s, g,
+                           L.ngroups, L.nkchunks, L.items, L.chunk, L.win_cap, proj, vol);
+        break;
+    case 8:
+        hipLaunchKernelGGL((backproject_kernel<EXACT, EC, PMAX, 8>), grid, block, L.lds, s, g,
+                           L.ngroups, L.nkchunks, L.items, L.chunk, L.win_cap, proj, vol);
+        break;
+    default:
+        hipLaunchKernelGGL((backproject_kernel<EXACT, EC, PMAX, 4>), grid, block, L.lds, s, g,
+                           L.ngroups, L.nkchunks, L.items, L.chunk, L.win_cap, proj, vol);
+        break;
+    }
+    return hipGetLastError();
+}
+
+template <bool EXACT, bool EC>
+hipError_t launch_bp(const DevGeom &g, const BackLaunch &L, const float *proj, float *vol,
+                     hipStream_t s)
+{
+    if (L.pmax <= 4) return launch_bp_gw<EXACT, EC, 4>(g, L, proj, vol, s);
+    return launch_bp_gw<EXACT, EC, 8>(g, L, proj, vol, s);
+}
+
+template <bool EXACT, bool EC, int PMAX>
+hipError_t set_lds_one(size_t n)
+{
+    hipError_t e = hipFuncSetAttribute((const void *)project_kernel<EXACT, EC, PMAX>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)backproject_kernel<EXACT, EC, PMAX, 16>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)backproject_kernel<EXACT, EC, PMAX, 8>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)backproject_kernel<EXACT, EC, PMAX, 4>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
+    return e;
+}
+
+}  // namespace
+
+// Allow the dynamic LDS sizes chosen by the host (above the 64 KB default).
+hipError_t configure_kernel_lds(size_t max_lds)
+{
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = set_lds_one<true, true, 4>(max_lds);
+    if (e == hipSuccess) e = set_lds_one<true, false, 4>(max_lds);
+    if (e == hipSuccess) e = set_lds_one<false, true, 4>(max_lds);
+    if (e == hipSuccess) e = set_lds_one<false, false, 4>(max_lds);
+    if (e == hipSuccess) e = set_lds_one<true, true, 8>(max_lds);
+    if (e == hipSuccess) e = set_lds_one<true, false, 8>(max_lds);
+    if (e == hipSuccess) e = set_lds_one<false, true, 8>(max_lds);
+    if (e == hipSuccess) e = set_lds_one<false, false, 8>(max_lds);
+    return e;
+}
+
+hipError_t launch_project(const DevGeom &g, const ProjLaunch &L, bool exact, bool ec,
+                          const float *vol, float *proj, hipStream_t stream)
+{
+    if (exact) return ec ? launch_p<true, true>(g, L, vol, proj, stream)
+                         : launch_p<true, false>(g, L, vol, proj, stream);
+    return ec ? launch_p<false, true>(g, L, vol, proj, stream)
+              : launch_p<false, false>(g, L, vol, proj, stream);
+}
+
+hipError_t launch_backproject(const DevGeom &g, const BackLaunch &L, bool exact, bool ec,
+                              const float *proj, float *vol, hipStream_t stream)
+{
+    if (exact) return ec ? launch_bp<true, true>(g, L, proj, vol, stream)
+                         : launch_bp<true, false>(g, L, proj, vol, stream);
+    return ec ? launch_bp<false, true>(g, L, proj, vol, stream)
+              : launch_bp<false, false>(g, L, proj, vol, stream);
+}
+
+}  // namespace cvp

@@ -1,0 +1,101 @@
+"""Python binding of the cutting voxel projector (argument marshalling only).
+
+Every step runs in the HIP kernels of libcvp.so; PyTorch provides device
+memory and the current stream.  Layouts: volume [n3, n2, n1], projections
+[views, rows, cols], float32, contiguous, on the geometry's device.
+"""
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+
+VARIANTS = {"exact": 0, "relaxed": 1}
+SCALINGS = {"solid_angle": 0, "cos": 1, "none": 2}
+
+
+@dataclass(frozen=True)
+class Options:
+    """variant: 'exact' (r at the cut centroid) or 'relaxed' (r at the voxel
+    centre); ec: elevation correction (Sec. III-B); scaling: 'solid_angle'
+    (eq. cvpus), 'cos' (eq. cvp) or 'none'; raw_volume: weight = cut volume."""
+    variant: str = "exact"
+    ec: bool = True
+    scaling: str = "solid_angle"
+    raw_volume: bool = False
+
+    def c(self):
+        return _lib.OptionsC(VARIANTS[self.variant], int(bool(self.ec)), SCALINGS[self.scaling],
+                             _lib.CVP_FLAG_RAW_VOLUME if self.raw_volume else 0)
+
+
+class Geometry:
+    """Circular cone-beam geometry, built on the current HIP device.
+
+    ``params`` is a plain dict (see ``synth.geometry``): vol_dims, voxel_mm,
+    vol_offset_mm, det_cols, det_rows, pitch_mm, principal_px, sid_mm, sdd_mm,
+    angles_rad."""
+
+    def __init__(self, params):
+        self.params = dict(params)
+        desc, self._angles = _lib.make_desc(params)
+        h = ctypes.c_void_p()
+        _lib.check(_lib.lib().cvp_geometry_from_views(ctypes.byref(desc), ctypes.byref(h)))
+        self.handle = h
+        n1, n2, n3 = (int(v) for v in params["vol_dims"])
+        self.vol_shape = (n3, n2, n1)
+        self.proj_shape = (len(params["angles_rad"]), int(params["det_rows"]), int(params["det_cols"]))
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib._lib is not None:
+            _lib._lib.cvp_geometry_destroy(h)
+            self.handle = None
+
+    @property
+    def n_voxels(self):
+        n3, n2, n1 = self.vol_shape
+        return n1 * n2 * n3
+
+    @property
+    def n_views(self):
+        return self.proj_shape[0]
+
+
+def _check_tensor(t, shape, name):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous float32 tensor on the GPU" % name)
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def project(x, geom: Geometry, opts: Options = Options(), out=None):
+    """b = A x (overwrites ``out`` if given)."""
+    _check_tensor(x, geom.vol_shape, "x")
+    if out is None:
+        out = torch.empty(geom.proj_shape, dtype=torch.float32, device=x.device)
+    _check_tensor(out, geom.proj_shape, "out")
+    o = opts.c()
+    _lib.check(_lib.lib().cvp_project(geom.handle, ctypes.byref(o), ctypes.c_void_p(x.data_ptr()),
+                                      ctypes.c_void_p(out.data_ptr()), _stream()))
+    return out
+
+
+def backproject(b, geom: Geometry, opts: Options = Options(), out=None):
+    """x = A^T b (overwrites ``out`` if given)."""
+    _check_tensor(b, geom.proj_shape, "b")
+    if out is None:
+        out = torch.empty(geom.vol_shape, dtype=torch.float32, device=b.device)
+    _check_tensor(out, geom.vol_shape, "out")
+    o = opts.c()
+    _lib.check(_lib.lib().cvp_backproject(geom.handle, ctypes.byref(o), ctypes.c_void_p(b.data_ptr()),
+                                          ctypes.c_void_p(out.data_ptr()), _stream()))
+    return out

@@ -1,0 +1,90 @@
+"""The C-ABI library without a GPU: it loads, exports every function the
+public header declares, and rejects invalid arguments with a status and a
+message naming the field, before any device work."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+import torch
+
+from paper_2110_09841_amd import _lib, synth
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "cvp.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cvp_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    L = _lib.lib()
+    names = declared_functions()
+    assert "cvp_project" in names and "cvp_backproject" in names
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_status_strings():
+    for s, name in enumerate(["CVP_OK", "CVP_E_INVALID", "CVP_E_NOMEM", "CVP_E_DEVICE",
+                              "CVP_E_UNSUPPORTED", "CVP_E_BREAKDOWN"]):
+        assert _lib.status_string(s) == name
+    assert _lib.lib().cvp_last_error_detail(None, 10) == _lib.CVP_E_INVALID
+
+
+def _create(mutate):
+    g = synth.config_small()
+    d, keep = _lib.make_desc(g)
+    mutate(d)
+    h = ctypes.c_void_p()
+    st = _lib.lib().cvp_geometry_from_views(ctypes.byref(d), ctypes.byref(h))
+    if st == _lib.CVP_OK:
+        _lib.lib().cvp_geometry_destroy(h)
+    return st, _lib.last_error()
+
+
+@pytest.mark.parametrize("field,mutate,expect", [
+    ("vol_dims[1]", lambda d: d.vol_dims.__setitem__(1, 0), _lib.CVP_E_INVALID),
+    ("voxel_mm[2]", lambda d: d.voxel_mm.__setitem__(2, -1.0), _lib.CVP_E_INVALID),
+    ("voxel_mm[0]", lambda d: d.voxel_mm.__setitem__(0, math.nan), _lib.CVP_E_INVALID),
+    ("det_cols", lambda d: setattr(d, "det_cols", 0), _lib.CVP_E_INVALID),
+    ("pitch_mm", lambda d: d.pitch_mm.__setitem__(1, 0.0), _lib.CVP_E_INVALID),
+    ("source_det_mm", lambda d: setattr(d, "source_det_mm", 700.0), _lib.CVP_E_INVALID),
+    ("source_iso_mm", lambda d: setattr(d, "source_iso_mm", 30.0), _lib.CVP_E_INVALID),
+    ("n_views", lambda d: setattr(d, "n_views", 0), _lib.CVP_E_INVALID),
+    ("angles_rad", lambda d: setattr(d, "angles_rad", None), _lib.CVP_E_INVALID),
+    ("principal_px", lambda d: d.principal_px.__setitem__(0, math.inf), _lib.CVP_E_INVALID),
+    ("columns", lambda d: d.pitch_mm.__setitem__(0, 0.05), _lib.CVP_E_UNSUPPORTED),
+])
+def test_invalid_geometry_rejected(field, mutate, expect):
+    st, msg = _create(mutate)
+    assert st == expect, (st, msg)
+    assert field.split("[")[0] in msg or expect == _lib.CVP_E_UNSUPPORTED, msg
+
+
+def test_null_arguments():
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    assert L.cvp_geometry_from_views(None, ctypes.byref(h)) == _lib.CVP_E_INVALID
+    assert "desc" in _lib.last_error()
+    o = _lib.OptionsC(0, 1, 0, 0)
+    assert L.cvp_project(None, ctypes.byref(o), None, None, None) == _lib.CVP_E_INVALID
+    assert L.cvp_backproject(None, ctypes.byref(o), None, None, None) == _lib.CVP_E_INVALID
+    L.cvp_geometry_destroy(None)
+
+
+@pytest.mark.skipif(torch.cuda.is_available(), reason="checks the no-device path")
+def test_valid_geometry_without_device_reports_device_error():
+    st, msg = _create(lambda d: None)
+    assert st == _lib.CVP_E_DEVICE, (st, msg)
+
+
+def test_operators_fail_loudly_without_library(monkeypatch):
+    """No silent fallback: a missing library raises."""
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", "/nonexistent/libcvp.so")
+    with pytest.raises(RuntimeError, match="not built"):
+        _lib.lib()
