@@ -1,0 +1,152 @@
+"""Benchmark: cutting voxel projector A x + A^T b on one MI355X.
+
+Workload: 512^3 voxels of 0.25 mm, 616x480 detector of 0.616 mm, SID 749 /
+SDD 1198 mm, 248 views over 200 degrees (C-arm short scan); relaxed CVP with
+elevation correction; phantom of 80 seeded ellipsoids plus 1% uniform noise;
+projection data U[0,1).  One step = one projection A x and one
+backprojection A^T b, inputs resident in HBM.
+
+value = 2 * n_voxels * n_views / (t_A + t_AT)   [voxel-view updates/s]
+
+Prints one JSON line.  The CPU baseline times the FP64 oracle on a bounded
+sample of the same workload (one view of A x and a voxel sample of A^T b).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--variant", default="relaxed", choices=["relaxed", "exact"])
+    ap.add_argument("--no-ec", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cgls", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run only a 1 GiB device copy (counter calibration)")
+    return ap.parse_args()
+
+
+def calib_copy():
+    import torch
+    n = 1 << 28    # 2^28 floats = 1 GiB
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calib_copy_bytes": 4 * n}))
+
+
+def cpu_baseline(g, x, b):
+    """FP64 oracle on a bounded sample: A x for one view of the full volume
+    and A^T b for 32768 voxels over all views."""
+    import numpy as np
+    import oracle
+    o = oracle.Options(exact=False, ec=True)
+    n1, n2, n3 = g["vol_dims"]
+    V = len(g["angles_rad"])
+    t0 = time.perf_counter()
+    oracle.project(g, o, x, views=(0, 1))
+    t1 = time.perf_counter()
+    rng = np.random.default_rng(7)
+    idx = rng.integers(0, n1 * n2 * n3, size=32768)
+    oracle.backproject_voxels(g, o, b, idx)
+    t2 = time.perf_counter()
+    vv = n1 * n2 * n3 * 1 + len(idx) * V
+    return {"value": vv / (t2 - t0), "unit": "voxel-view updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "A x for 1 of 248 views (%d voxel-views, %.1f s) + A^T b for 32768 voxels x %d views "
+                      "(%.1f s), FP64 C/OpenMP" % (n1 * n2 * n3, t1 - t0, V, t2 - t1)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); got --gpus %d" % args.gpus)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2110_09841_amd import costmodel, cvp, synth
+    if args.calib_copy:
+        calib_copy()
+        return
+    torch.cuda.set_device(0)
+    g = synth.config_carm()
+    n1, n2, n3 = g["vol_dims"]
+    V = len(g["angles_rad"])
+    x_h = synth.ellipsoid_phantom(512, 0.25, 80, seed=31, noise_frac=0.01)
+    b_h = synth.uniform_projections((V, g["det_rows"], g["det_cols"]), seed=32)
+    G = cvp.Geometry(g)
+    ec = not args.no_ec
+    opts = cvp.Options(variant=args.variant, ec=ec)
+    x = torch.from_numpy(x_h).cuda()
+    b = torch.from_numpy(b_h).cuda()
+    p_out = torch.empty(G.proj_shape, dtype=torch.float32, device="cuda")
+    v_out = torch.empty(G.vol_shape, dtype=torch.float32, device="cuda")
+
+    for _ in range(args.warmup):
+        cvp.project(x, G, opts, out=p_out)
+        cvp.backproject(b, G, opts, out=v_out)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        ev[s][0].record()
+        cvp.project(x, G, opts, out=p_out)
+        ev[s][1].record()
+        cvp.backproject(b, G, opts, out=v_out)
+        ev[s][2].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tA = np.array([ev[s][0].elapsed_time(ev[s][1]) for s in range(args.steps)]) * 1e-3
+    tB = np.array([ev[s][1].elapsed_time(ev[s][2]) for s in range(args.steps)]) * 1e-3
+    vv = n1 * n2 * n3 * V
+    value = 2 * vv / (tA.mean() + tB.mean())
+
+    exact = args.variant == "exact"
+    rA = costmodel.roofline(g, exact, ec, tA.mean())
+    rB = costmodel.roofline(g, exact, ec, tB.mean())
+    dom, rdom, name = (tA, rA, "cvp_project") if tA.mean() >= tB.mean() else (tB, rB, "cvp_backproject")
+    out = {
+        "metric": "voxel-view updates/s (CVP Ax+A^T b, 512^3, 248 views)",
+        "value": float(value),
+        "unit": "voxel-view updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded ellipsoid phantom + 1% noise; U[0,1) projections)",
+        "config": {"workload": "carm_512c_248v", "volume": [n1, n2, n3], "voxel_mm": 0.25,
+                   "detector": [g["det_cols"], g["det_rows"]], "pitch_mm": 0.616, "views": V,
+                   "arc_deg": 200, "sid_mm": 749, "sdd_mm": 1198, "variant": args.variant,
+                   "elevation_correction": ec, "scaling": "solid_angle"},
+        "project": {"ms": 1e3 * tA.mean(), "voxel_views_per_s": vv / tA.mean()},
+        "backproject": {"ms": 1e3 * tB.mean(), "voxel_views_per_s": vv / tB.mean()},
+        "roofline": {"bound": "alu", "kernel": name, "achieved": rdom["achieved"] / 1e12,
+                     "peak": rdom["peak"] / 1e12, "unit": "TOP/s (FP32 VALU lane-ops)",
+                     "frac": rdom["frac"], "ops_per_voxel_view": rdom["ops_per_vv"],
+                     "pieces_per_voxel_view": [rdom["n_c"], rdom["n_p"]], "traffic": None},
+    }
+    del x, b, p_out, v_out
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(g, x_h, b_h)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -131,6 +131,64 @@ cvp_status cvp_project(const cvp_geometry *g, const cvp_options *opts,
 cvp_status cvp_backproject(const cvp_geometry *g, const cvp_options *opts,
                            const float *d_proj, float *d_vol, void *hip_stream);
 
+/*
+ * Batches: several independent problems (each with its own geometry) in one
+ * persistent launch per direction.  A fixed grid of workgroups (as many as
+ * fit on the GPU) takes work items from an atomic counter until all problems
+ * are done, largest items first; every problem's result equals its
+ * single-problem result bitwise (each item is summed by one workgroup in a
+ * fixed order).  The per-call pointer setup and the counter reset are one
+ * tiny kernel on the same stream, so a batched call can be graph-captured.
+ * n: 1..32 geometries on the same device; the batch keeps pointers to them
+ * (they must outlive it) and owns small device tables.
+ */
+typedef struct cvp_batch cvp_batch;   /* opaque */
+cvp_status cvp_batch_create(const cvp_geometry *const *geoms, int32_t n, cvp_batch **out);
+void cvp_batch_destroy(cvp_batch *b);
+/* d_vols / d_projs: host arrays of n device pointers (layouts as above).
+ * Calls that overlap in time must not share a batch object (it holds the
+ * work counter). */
+cvp_status cvp_project_batched(const cvp_batch *b, const cvp_options *opts,
+                               const float *const *d_vols, float *const *d_projs,
+                               void *hip_stream);
+cvp_status cvp_backproject_batched(const cvp_batch *b, const cvp_options *opts,
+                                   const float *const *d_projs, float *const *d_vols,
+                                   void *hip_stream);
+
+/*
+ * CGLS on the normal equations A^T A x = A^T b (Hestenes-Stiefel form; the
+ * paper times its operators inside CGLS, Sec. IV-A):
+ *   start:   r = b - A x,  s = A^T r,  p = s,  gamma = |s|^2
+ *   iterate: q = A p,  alpha = gamma/|q|^2,  x += alpha p,  r -= alpha q,
+ *            s = A^T r,  gamma' = |s|^2,  p = s + (gamma'/gamma) p
+ * Vectors are caller-owned device float32 buffers: x, s, p of volume size;
+ * b, r, q of projection size.  The scalars stay on the device, in the
+ * caller-owned workspace d_work (cvp_cgls_workspace_size bytes, 8-byte
+ * aligned), laid out as doubles:
+ *   [0] gamma  [1] |q|^2  [2] alpha  [3] beta  [4] gamma0 = |A^T(b - A x0)|^2
+ *   [5] |r|^2  [6] k (iterations done)  [7] breakdown flag (A p = 0 met)
+ *   [8 .. 8+4095]        |s_k|^2 for k = 0..4095
+ *   [4104 .. 4104+4095]  |r_k|^2 after iteration k+1
+ *   then reduction partials.
+ * The relative residual rho_k = sqrt(|s_k|^2 / gamma0) is read from the
+ * history.  Calls enqueue kernels only (no allocation, no host sync), so a
+ * run of cvp_cgls_iterate can be captured in a HIP graph.  Dot products
+ * accumulate FP64 in a fixed order (bitwise reproducible).
+ */
+#define CVP_CGLS_HISTORY 4096
+cvp_status cvp_cgls_workspace_size(int64_t n_voxels, int64_t n_pixels_total, int64_t *bytes);
+cvp_status cvp_cgls_start(const cvp_geometry *g, const cvp_options *opts, const float *d_b,
+                          float *d_x, float *d_r, float *d_s, float *d_p, float *d_q,
+                          void *d_work, void *hip_stream);
+cvp_status cvp_cgls_iterate(const cvp_geometry *g, const cvp_options *opts, int32_t n_iter,
+                            float *d_x, float *d_r, float *d_s, float *d_p, float *d_q,
+                            void *d_work, void *hip_stream);
+
+/* *d_result = sum_i a[i] b[i] accumulated in FP64 (device scalar), using the
+ * partials area of a CGLS workspace d_work.  n >= 0. */
+cvp_status cvp_dot(const float *d_a, const float *d_b, int64_t n, double *d_result,
+                   void *d_work, void *hip_stream);
+
 /* Geometry queries (host-side, no device work). */
 cvp_status cvp_geometry_sizes(const cvp_geometry *g, int64_t *n_voxels,
                               int64_t *n_pixels_total);

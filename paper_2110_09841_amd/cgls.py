@@ -1,0 +1,112 @@
+"""CGLS on the GPU through the C ABI, with HIP-graph capture.
+
+The whole iteration (two operator launches, FP64 dot products, fused vector
+updates and the scalar recurrences) runs on the device; the host only reads
+the residual history between graph replays.  Relative residual:
+rho_k = |A^T (b - A x_k)| / |A^T (b - A x_0)|.
+"""
+import ctypes
+import time
+
+import numpy as np
+import torch
+
+from . import _lib
+from .cvp import Geometry, Options, _check_tensor, _stream
+
+N_SCALARS = 8
+HISTORY = 4096
+
+
+class CGLS:
+    def __init__(self, geom: Geometry, opts: Options, b, x0=None):
+        _check_tensor(b, geom.proj_shape, "b")
+        self.geom, self.opts, self.b = geom, opts, b
+        dev = b.device
+        self.x = torch.zeros(geom.vol_shape, dtype=torch.float32, device=dev) if x0 is None \
+            else x0.detach().clone().contiguous()
+        _check_tensor(self.x, geom.vol_shape, "x0")
+        self.r = torch.empty(geom.proj_shape, dtype=torch.float32, device=dev)
+        self.q = torch.empty(geom.proj_shape, dtype=torch.float32, device=dev)
+        self.s = torch.empty(geom.vol_shape, dtype=torch.float32, device=dev)
+        self.p = torch.empty(geom.vol_shape, dtype=torch.float32, device=dev)
+        nbytes = ctypes.c_int64()
+        _lib.check(_lib.lib().cvp_cgls_workspace_size(geom.n_voxels, self.r.numel(), ctypes.byref(nbytes)))
+        self.work = torch.zeros(nbytes.value // 8, dtype=torch.float64, device=dev)
+        self._o = opts.c()
+        self.graph = None
+        self.graph_iters = 0
+
+    def _ptrs(self):
+        return [ctypes.c_void_p(t.data_ptr()) for t in (self.x, self.r, self.s, self.p, self.q, self.work)]
+
+    def start(self):
+        """r = b - A x0, s = A^T r, p = s, gamma0 = |s|^2."""
+        x, r, s, p, q, w = self._ptrs()
+        _lib.check(_lib.lib().cvp_cgls_start(self.geom.handle, ctypes.byref(self._o),
+                                             ctypes.c_void_p(self.b.data_ptr()), x, r, s, p, q, w, _stream()))
+
+    def iterate(self, n: int):
+        x, r, s, p, q, w = self._ptrs()
+        _lib.check(_lib.lib().cvp_cgls_iterate(self.geom.handle, ctypes.byref(self._o), int(n),
+                                               x, r, s, p, q, w, _stream()))
+
+    def capture(self, n: int):
+        """Capture n iterations in one HIP graph (replayed by replay())."""
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g, stream=side):
+                self.iterate(n)
+        torch.cuda.current_stream().wait_stream(side)
+        self.graph, self.graph_iters = g, n
+
+    def replay(self):
+        self.graph.replay()
+
+    def scalars(self):
+        return self.work[:N_SCALARS].cpu().numpy()
+
+    def gamma_history(self):
+        """|s_k|^2 for k = 0 .. iterations done."""
+        sc = self.scalars()
+        k = int(sc[6])
+        return self.work[N_SCALARS:N_SCALARS + min(k, HISTORY - 1) + 1].cpu().numpy()
+
+    def residual_history(self):
+        """|r_k|^2 = |b - A x_k|^2 for k = 1 .. iterations done."""
+        k = int(self.scalars()[6])
+        off = N_SCALARS + HISTORY
+        return self.work[off:off + min(k, HISTORY)].cpu().numpy()
+
+    def rho(self):
+        g = self.gamma_history()
+        return np.sqrt(np.maximum(g, 0.0) / g[0])
+
+    def breakdown(self):
+        return bool(self.scalars()[7] != 0.0)
+
+    def run(self, tol=1e-3, max_iter=400, per_graph=20, use_graph=True):
+        """Iterate until rho_k <= tol (checked every per_graph iterations) or
+        max_iter; returns (iterations, seconds, rho history).  Time counts
+        from the start call to the replay boundary where rho <= tol."""
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        self.start()
+        if use_graph and (self.graph is None or self.graph_iters != per_graph):
+            self.capture(per_graph)
+        done = 0
+        while done < max_iter:
+            if use_graph:
+                self.replay()
+            else:
+                self.iterate(per_graph)
+            done += per_graph
+            rho = self.rho()          # synchronises
+            if rho[-1] <= tol or self.breakdown():
+                break
+        t1 = time.perf_counter()
+        rho = self.rho()
+        hit = np.nonzero(rho <= tol)[0]
+        return (int(hit[0]) if len(hit) else done), t1 - t0, rho

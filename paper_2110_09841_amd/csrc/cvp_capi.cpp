@@ -17,7 +17,12 @@
 
 namespace cvp {
 hipError_t configure_kernel_lds(size_t max_lds);
+constexpr size_t kLdsBudget = 78 * 1024;   // two workgroups per CU (160 KB LDS)
+bool plan_projection(int N, int n2, int M, int nviews, int pmax, ProjLaunch &L);
+bool plan_backprojection(const DevGeom &G, int pmax, double zabs, double Dmin, int force_gw,
+                         BackLaunch &L);
 }
+using cvp::kLdsBudget;
 
 struct cvp_geometry {
     std::vector<double> angles;
@@ -28,6 +33,7 @@ struct cvp_geometry {
     cvp::ProjLaunch pl{};
     cvp::BackLaunch bl{};
     int64_t nvox = 0, npix = 0;
+    double zabs = 0.0, Dmin = 0.0;   // for launch planning
 };
 
 namespace {
@@ -59,7 +65,6 @@ cvp_status device_fail(hipError_t e, const char *what)
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
-constexpr size_t kLdsBudget = 78 * 1024;   // two workgroups per CU (160 KB LDS)
 
 // Solid angle of the rectangle [x0,x1] x [y0,y1] on a plane at distance f
 // (pixel edges relative to the principal point): the standard arctan form.
@@ -70,6 +75,71 @@ double rect_solid_angle(double f, double x0, double x1, double y0, double y1)
 }
 
 }  // namespace
+
+namespace cvp {
+
+size_t project_lds_bytes(int U, int N, int n2, int pmax)
+{
+    const size_t npad = (size_t)(N | 1);
+    return (size_t)kWaves * U * npad * 4 + (size_t)(2 * n2 + 1 + kBlock + 4) * 4 + 16 +
+           (size_t)kWaves * (16 * pmax * kRecFloats + 16) * 4;
+}
+
+size_t backproject_lds_bytes(int gw, int pmax, int winCap)
+{
+    const size_t waveFloats = ((size_t)gw * pmax * kRecFloats + gw + winCap + 3) / 4 * 4;
+    return kWaves * waveFloats * 4;
+}
+
+// Projection: bands of U detector columns, U as large as the LDS budget
+// allows (per-wave bins of U x N, row tables, per-wave piece records).
+bool plan_projection(int N, int n2, int M, int nviews, int pmax, ProjLaunch &L)
+{
+    const size_t fixed = project_lds_bytes(0, N, n2, pmax);
+    const size_t perU = project_lds_bytes(1, N, n2, pmax) - fixed;
+    if (fixed + perU > kLdsBudget) return false;
+    int U = (int)((kLdsBudget - fixed) / perU);
+    U = std::max(1, std::min(U, 32));
+    L.U = U;
+    L.nbands = (M + U - 1) / U;
+    L.items = L.nbands * nviews;
+    L.chunk = (L.items + 7) / 8;
+    L.pmax = pmax;
+    L.lds = project_lds_bytes(U, N, n2, pmax);
+    return true;
+}
+
+// Backprojection: stacks of GW columns x 64 voxels; the widest GW whose
+// estimated detector window fits the per-wave LDS window (force_gw > 0 fixes it).
+bool plan_backprojection(const DevGeom &G, int pmax, double zabs, double Dmin, int force_gw,
+                         BackLaunch &L)
+{
+    const double mag = G.f / Dmin;
+    int gw = 4, cap = 0;
+    for (int cand : {16, 8, 4}) {
+        if (force_gw > 0 && cand != force_gw) continue;
+        const size_t rec = (size_t)cand * pmax * kRecFloats + cand;
+        const int c = (int)((kLdsBudget / (kWaves * 4) - rec) / 4 * 4);
+        const double wu = std::hypot(cand * G.a1, G.a2) * mag / G.b1 + pmax + 2;
+        const double zspan = std::hypot(cand * G.a1, G.a2);
+        const double wv = 64 * G.a3 * mag / G.b2 + zabs * (G.f / G.b2) * zspan / (Dmin * Dmin) + 6;
+        gw = cand;
+        cap = c;
+        if (wu * ((int)wv | 1) <= c) break;
+    }
+    if (cap < 1024) return false;
+    L.gw = gw;
+    L.win_cap = cap;
+    L.pmax = pmax;
+    L.ngroups = (G.n1 + gw - 1) / gw;
+    L.nkchunks = (G.n3 + 63) / 64;
+    L.items = G.n2 * L.ngroups * L.nkchunks;
+    L.chunk = (L.items + 7) / 8;
+    L.lds = backproject_lds_bytes(gw, pmax, cap);
+    return true;
+}
+
+}  // namespace cvp
 
 extern "C" {
 
@@ -212,56 +282,15 @@ cvp_status cvp_geometry_from_views(const cvp_geometry_desc *d, cvp_geometry **ou
     G.raw_volume = 0;
 
     const int pmax = pieces <= 4 ? 4 : 8;
-    // projection: bands of U detector columns; LDS = per-wave bins + row
-    // tables + per-wave piece records
-    {
-        cvp::ProjLaunch &L = g->pl;
-        const size_t npad = (size_t)(N | 1);
-        const size_t other = (size_t)(2 * n2 + 1 + cvp::kBlock + 4) * 4 + 16 +
-                             (size_t)cvp::kWaves * (16 * pmax * cvp::kRecFloats + 16) * 4;
-        if (other + cvp::kWaves * npad * 4 > kLdsBudget) {
-            cvp_geometry_destroy(g);
-            return fail(CVP_E_UNSUPPORTED, "detector rows (%d) or volume rows (%d) too large for the projection LDS layout", N, n2);
-        }
-        int U = (int)((kLdsBudget - other) / (cvp::kWaves * npad * 4));
-        U = std::max(1, std::min(U, 32));
-        L.U = U;
-        L.nbands = (M + U - 1) / U;
-        L.items = L.nbands * d->n_views;
-        L.chunk = (L.items + 7) / 8;
-        L.pmax = pmax;
-        L.lds = other + cvp::kWaves * (size_t)U * npad * 4;
+    g->zabs = zabs;
+    g->Dmin = Dmin;
+    if (!cvp::plan_projection(N, n2, M, d->n_views, pmax, g->pl)) {
+        cvp_geometry_destroy(g);
+        return fail(CVP_E_UNSUPPORTED, "detector rows (%d) or volume rows (%d) too large for the projection LDS layout", N, n2);
     }
-    // backprojection: stacks of GW columns x 64 voxels; LDS = per-wave piece
-    // records + per-wave detector window (also reused for the final sum)
-    {
-        cvp::BackLaunch &L = g->bl;
-        const double mag = f / Dmin;
-        int gw = 4;
-        int cap = 0;
-        for (int cand : {16, 8, 4}) {
-            const size_t rec = (size_t)cand * pmax * cvp::kRecFloats + cand;
-            const int c = (int)((kLdsBudget / (cvp::kWaves * 4) - rec) / 4 * 4);
-            const double wu = std::hypot(cand * a1, a2) * mag / b1 + pmax + 2;
-            const double zspan = std::hypot(cand * a1, a2);
-            const double wv = 64 * a3 * mag / b2 + zabs * (f / b2) * zspan / (Dmin * Dmin) + 6;
-            gw = cand;
-            cap = c;
-            if (wu * ((int)wv | 1) <= c) break;
-        }
-        L.gw = gw;
-        L.win_cap = cap;
-        L.pmax = pmax;
-        L.ngroups = (n1 + gw - 1) / gw;
-        L.nkchunks = (n3 + 63) / 64;
-        L.items = n2 * L.ngroups * L.nkchunks;
-        L.chunk = (L.items + 7) / 8;
-        const size_t waveFloats = ((size_t)gw * pmax * cvp::kRecFloats + gw + cap + 3) / 4 * 4;
-        L.lds = cvp::kWaves * waveFloats * 4;
-        if (cap < 1024) {
-            cvp_geometry_destroy(g);
-            return fail(CVP_E_UNSUPPORTED, "backprojection LDS window too small");
-        }
+    if (!cvp::plan_backprojection(G, pmax, zabs, Dmin, 0, g->bl)) {
+        cvp_geometry_destroy(g);
+        return fail(CVP_E_UNSUPPORTED, "backprojection LDS window too small");
     }
     *out = g;
     return ok();
@@ -322,6 +351,228 @@ cvp_status cvp_backproject(const cvp_geometry *g, const cvp_options *o, const fl
     hipError_t e = cvp::launch_backproject(G, g->bl, o->variant == CVP_EXACT, o->elevation_correction != 0,
                                            d_proj, d_vol, (hipStream_t)stream);
     if (e != hipSuccess) return device_fail(e, "backprojection launch");
+    return ok();
+}
+
+}  // extern "C"
+
+struct cvp_batch {
+    int n = 0;
+    int device = 0;
+    std::vector<const cvp_geometry *> geoms;
+    cvp::BatchProblem *d_probs = nullptr;
+    cvp::BatchTable *d_ptab = nullptr, *d_btab = nullptr;
+    int *d_counter = nullptr;
+    int pmax = 4, gw = 16, win_cap = 0;
+    size_t plds = 0, blds = 0;
+    int pgrid = 0, bgrid = 0;
+};
+
+extern "C" {
+
+void cvp_batch_destroy(cvp_batch *b)
+{
+    if (!b) return;
+    if (b->d_probs) (void)hipFree(b->d_probs);
+    if (b->d_ptab) (void)hipFree(b->d_ptab);
+    if (b->d_btab) (void)hipFree(b->d_btab);
+    if (b->d_counter) (void)hipFree(b->d_counter);
+    delete b;
+}
+
+cvp_status cvp_batch_create(const cvp_geometry *const *geoms, int32_t n, cvp_batch **out)
+{
+    if (!out) return fail(CVP_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!geoms) return fail(CVP_E_INVALID, "geoms is NULL");
+    if (n < 1 || n > cvp::kMaxBatch) return fail(CVP_E_INVALID, "n = %d (must be 1..%d)", n, cvp::kMaxBatch);
+    for (int q = 0; q < n; ++q) {
+        if (!geoms[q]) return fail(CVP_E_INVALID, "geoms[%d] is NULL", q);
+        if (geoms[q]->device != geoms[0]->device)
+            return fail(CVP_E_INVALID, "geoms[%d] lives on another device", q);
+    }
+    cvp_batch *b = new (std::nothrow) cvp_batch();
+    if (!b) return fail(CVP_E_NOMEM, "host allocation");
+    b->n = n;
+    b->device = geoms[0]->device;
+    b->geoms.assign(geoms, geoms + n);
+    // common template parameters: the largest piece count, the narrowest
+    // backprojection column group; each problem's launch plan is redone
+    // with them so that one dynamic LDS size fits all
+    for (int q = 0; q < n; ++q) {
+        b->pmax = std::max(b->pmax, geoms[q]->pl.pmax);
+        b->gw = std::min(b->gw, geoms[q]->bl.gw);
+    }
+    std::vector<cvp::BatchProblem> probs(n);
+    std::vector<double> pcost(n), bcost(n);
+    for (int q = 0; q < n; ++q) {
+        const cvp_geometry *g = geoms[q];
+        cvp::ProjLaunch pl;
+        cvp::BackLaunch bl;
+        if (!cvp::plan_projection(g->base.N, g->base.n2, g->base.M, g->base.nviews, b->pmax, pl) ||
+            !cvp::plan_backprojection(g->base, b->pmax, g->zabs, g->Dmin, b->gw, bl)) {
+            cvp_batch_destroy(b);
+            return fail(CVP_E_UNSUPPORTED, "problem %d does not fit the common launch plan", q);
+        }
+        cvp::BatchProblem &P = probs[q];
+        P.G = g->base;
+        P.U = pl.U;
+        P.pitems = pl.items;
+        P.ngroups = bl.ngroups;
+        P.nkchunks = bl.nkchunks;
+        P.bitems = bl.items;
+        P.in = nullptr;
+        P.out = nullptr;
+        b->plds = std::max(b->plds, pl.lds);
+        b->blds = std::max(b->blds, bl.lds);
+        b->win_cap = q == 0 ? bl.win_cap : std::min(b->win_cap, bl.win_cap);
+        pcost[q] = (double)g->nvox / pl.nbands;           // voxels per band (all k)
+        bcost[q] = (double)g->base.nviews;                // views per voxel stack
+    }
+    auto table = [&](const std::vector<double> &cost, bool back) {
+        cvp::BatchTable T{};
+        std::vector<int> ord(n);
+        for (int q = 0; q < n; ++q) ord[q] = q;
+        std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+        T.n = n;
+        T.start[0] = 0;
+        for (int q = 0; q < n; ++q) {
+            T.order[q] = ord[q];
+            T.start[q + 1] = T.start[q] + (back ? probs[ord[q]].bitems : probs[ord[q]].pitems);
+        }
+        return T;
+    };
+    const cvp::BatchTable pt = table(pcost, false), bt = table(bcost, true);
+    int cus = 0;
+    hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_probs, n * sizeof(cvp::BatchProblem));
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_ptab, sizeof(cvp::BatchTable));
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_btab, sizeof(cvp::BatchTable));
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_counter, 2 * sizeof(int));
+    if (e == hipSuccess) e = hipMemcpy(b->d_probs, probs.data(), n * sizeof(cvp::BatchProblem), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->d_ptab, &pt, sizeof(pt), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->d_btab, &bt, sizeof(bt), hipMemcpyHostToDevice);
+    if (e != hipSuccess) { cvp_batch_destroy(b); return device_fail(e, "batch tables"); }
+    b->pgrid = cus * cvp::batched_blocks_per_cu(false, b->plds);
+    b->bgrid = cus * cvp::batched_blocks_per_cu(true, b->blds);
+    *out = b;
+    return ok();
+}
+
+static cvp_status batched(const cvp_batch *b, const cvp_options *o, const float *const *ins,
+                          float *const *outs, void *stream, bool backward)
+{
+    if (!b) return fail(CVP_E_INVALID, "batch is NULL");
+    if (!o) return fail(CVP_E_INVALID, "options is NULL");
+    if (!ins || !outs) return fail(CVP_E_INVALID, "pointer array is NULL");
+    cvp::BatchIO io{};
+    io.n = b->n;
+    io.raw = (o->flags & CVP_FLAG_RAW_VOLUME) ? 1 : 0;
+    for (int q = 0; q < b->n; ++q) {
+        cvp::DevGeom G;
+        cvp_status st = prepare(b->geoms[q], o, ins[q], outs[q], G);
+        if (st != CVP_OK) return fail(st, "problem %d: %s", q, g_err.c_str());
+        io.in[q] = ins[q];
+        io.out[q] = outs[q];
+        io.sigma[q] = G.sigma;
+    }
+    hipError_t e = cvp::launch_batched(backward, b->d_probs, backward ? b->d_btab : b->d_ptab,
+                                       b->d_counter, io, b->pmax, b->gw, b->win_cap,
+                                       o->variant == CVP_EXACT, o->elevation_correction != 0,
+                                       backward ? b->bgrid : b->pgrid, backward ? b->blds : b->plds,
+                                       (hipStream_t)stream);
+    if (e != hipSuccess) return device_fail(e, "batched launch");
+    return ok();
+}
+
+cvp_status cvp_project_batched(const cvp_batch *b, const cvp_options *o, const float *const *d_vols,
+                               float *const *d_projs, void *stream)
+{
+    return batched(b, o, d_vols, d_projs, stream, false);
+}
+
+cvp_status cvp_backproject_batched(const cvp_batch *b, const cvp_options *o, const float *const *d_projs,
+                                   float *const *d_vols, void *stream)
+{
+    return batched(b, o, d_projs, d_vols, stream, true);
+}
+
+cvp_status cvp_cgls_workspace_size(int64_t n_voxels, int64_t n_pixels_total, int64_t *bytes)
+{
+    if (!bytes) return fail(CVP_E_INVALID, "bytes is NULL");
+    if (n_voxels < 0 || n_pixels_total < 0) return fail(CVP_E_INVALID, "negative size");
+    *bytes = cvp::kCglsWorkDoubles * (int64_t)sizeof(double);
+    return ok();
+}
+
+static cvp_status cgls_args(const cvp_geometry *g, const cvp_options *o, const void *x,
+                            const void *r, const void *s, const void *p, const void *q,
+                            const void *work, cvp::DevGeom &G)
+{
+    const void *ptrs[6] = {x, r, s, p, q, work};
+    const char *names[6] = {"x", "r", "s", "p", "q", "work"};
+    for (int a = 0; a < 6; ++a)
+        if (!ptrs[a]) return fail(CVP_E_INVALID, "%s is NULL", names[a]);
+    for (int a = 0; a < 5; ++a)
+        for (int b = a + 1; b < 5; ++b)
+            if (ptrs[a] == ptrs[b]) return fail(CVP_E_INVALID, "%s and %s alias", names[a], names[b]);
+    if (reinterpret_cast<uintptr_t>(work) & 7) return fail(CVP_E_INVALID, "work must be 8-byte aligned");
+    return prepare(g, o, x, const_cast<void *>(r), G);
+}
+
+cvp_status cvp_cgls_start(const cvp_geometry *g, const cvp_options *o, const float *d_b, float *d_x,
+                          float *d_r, float *d_s, float *d_p, float *d_q, void *d_work, void *stream)
+{
+    cvp::DevGeom G;
+    if (!d_b) return fail(CVP_E_INVALID, "b is NULL");
+    cvp_status st = cgls_args(g, o, d_x, d_r, d_s, d_p, d_q, d_work, G);
+    if (st != CVP_OK) return st;
+    hipStream_t sm = (hipStream_t)stream;
+    double *sc = (double *)d_work;
+    double *part = sc + cvp::kCglsScalars + 2 * cvp::kCglsHistory;
+    const bool ex = o->variant == CVP_EXACT, ec = o->elevation_correction != 0;
+    hipError_t e = cvp::launch_project(G, g->pl, ex, ec, d_x, d_q, sm);
+    if (e == hipSuccess) e = cvp::blas_residual(d_r, d_b, d_q, g->npix, sm);
+    if (e == hipSuccess) e = cvp::launch_backproject(G, g->bl, ex, ec, d_r, d_s, sm);
+    if (e == hipSuccess) e = cvp::blas_update_p(d_p, d_s, g->nvox, sc, 1, sm);
+    if (e == hipSuccess) e = cvp::blas_dot(d_s, d_s, g->nvox, part, sc, 0, nullptr, sm);
+    if (e != hipSuccess) return device_fail(e, "cgls start");
+    return ok();
+}
+
+cvp_status cvp_cgls_iterate(const cvp_geometry *g, const cvp_options *o, int32_t n_iter, float *d_x,
+                            float *d_r, float *d_s, float *d_p, float *d_q, void *d_work, void *stream)
+{
+    cvp::DevGeom G;
+    if (n_iter < 0) return fail(CVP_E_INVALID, "n_iter = %d", n_iter);
+    cvp_status st = cgls_args(g, o, d_x, d_r, d_s, d_p, d_q, d_work, G);
+    if (st != CVP_OK) return st;
+    hipStream_t sm = (hipStream_t)stream;
+    double *sc = (double *)d_work;
+    double *part = sc + cvp::kCglsScalars + 2 * cvp::kCglsHistory;
+    const bool ex = o->variant == CVP_EXACT, ec = o->elevation_correction != 0;
+    hipError_t e = hipSuccess;
+    for (int it = 0; it < n_iter && e == hipSuccess; ++it) {
+        e = cvp::launch_project(G, g->pl, ex, ec, d_p, d_q, sm);                        // q = A p
+        if (e == hipSuccess) e = cvp::blas_dot(d_q, d_q, g->npix, part, sc, 1, nullptr, sm);   // alpha
+        if (e == hipSuccess) e = cvp::blas_update_xr(d_x, d_p, g->nvox, d_r, d_q, g->npix, sc, part, sm);
+        if (e == hipSuccess) e = cvp::launch_backproject(G, g->bl, ex, ec, d_r, d_s, sm);   // s = A^T r
+        if (e == hipSuccess) e = cvp::blas_dot(d_s, d_s, g->nvox, part, sc, 2, nullptr, sm);   // beta
+        if (e == hipSuccess) e = cvp::blas_update_p(d_p, d_s, g->nvox, sc, 0, sm);           // p
+    }
+    if (e != hipSuccess) return device_fail(e, "cgls iterate");
+    return ok();
+}
+
+cvp_status cvp_dot(const float *d_a, const float *d_b, int64_t n, double *d_result, void *d_work,
+                   void *stream)
+{
+    if (!d_a || !d_b || !d_result || !d_work) return fail(CVP_E_INVALID, "NULL pointer");
+    if (n < 0) return fail(CVP_E_INVALID, "n < 0");
+    double *sc = (double *)d_work;
+    double *part = sc + cvp::kCglsScalars + 2 * cvp::kCglsHistory;
+    hipError_t e = cvp::blas_dot(d_a, d_b, n, part, sc, 4, d_result, (hipStream_t)stream);
+    if (e != hipSuccess) return device_fail(e, "dot");
     return ok();
 }
 

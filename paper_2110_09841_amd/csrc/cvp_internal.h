@@ -56,6 +56,56 @@ struct BackLaunch {
     size_t lds;
 };
 
+// Batched, persistent launches over up to kMaxBatch problems.
+constexpr int kMaxBatch = 32;
+
+struct BatchProblem {        // device table entry (one per problem)
+    DevGeom G;
+    int U;                   // projection band width
+    int pitems;              // projection work items
+    int ngroups;             // backprojection column groups per row (common GW)
+    int nkchunks;
+    int bitems;              // backprojection work items
+    const float *in;         // set per call by batch_setup
+    float *out;
+};
+
+struct BatchTable {          // device: work segments, largest items first
+    int n;
+    int start[kMaxBatch + 1];
+    int order[kMaxBatch];
+};
+
+struct BatchIO {             // per call, by value
+    int n;
+    int raw;
+    const float *in[kMaxBatch];
+    float *out[kMaxBatch];
+    const float *sigma[kMaxBatch];
+};
+
+hipError_t launch_batched(bool backward, BatchProblem *probs, const BatchTable *tab, int *counter,
+                          const BatchIO &io, int pmax, int gw, int winCap, bool exact, bool ec,
+                          int grid, size_t lds, hipStream_t s);
+int batched_blocks_per_cu(bool backward, size_t lds);
+size_t project_lds_bytes(int U, int N, int n2, int pmax);
+size_t backproject_lds_bytes(int gw, int pmax, int winCap);
+
+// CGLS workspace (FP64): scalars, then the |s|^2 and |r|^2 histories, then the
+// reduction partials.
+constexpr int kCglsScalars = 8;      // gamma, |q|^2, alpha, beta, gamma0, |r|^2, k, breakdown
+constexpr int kCglsHistory = 4096;
+constexpr int kCglsPartials = 1024;
+constexpr int64_t kCglsWorkDoubles = kCglsScalars + 2 * kCglsHistory + kCglsPartials;
+
+hipError_t blas_dot(const float *a, const float *b, int64_t n, double *partials, double *sc,
+                    int mode, double *out, hipStream_t s);
+hipError_t blas_update_xr(float *x, const float *p, int64_t nv, float *r, const float *q, int64_t np,
+                          double *sc, double *partials, hipStream_t s);
+hipError_t blas_update_p(float *p, const float *sv, int64_t n, const double *sc, int init,
+                         hipStream_t s);
+hipError_t blas_residual(float *r, const float *b, const float *q, int64_t n, hipStream_t s);
+
 hipError_t launch_project(const DevGeom &g, const ProjLaunch &L, bool exact, bool ec,
                           const float *vol, float *proj, hipStream_t stream);
 hipError_t launch_backproject(const DevGeom &g, const BackLaunch &L, bool exact, bool ec,

@@ -261,15 +261,14 @@ __device__ __forceinline__ void build_records(const DevGeom &G, const ViewGeom &
 
 // ------------------------------------------------------------ projection
 
+// One work item of the projection: detector-column band item / nviews of view
+// item % nviews.  smem holds the LDS layout described below.
 template <bool EXACT, bool EC, int PMAX>
-__global__ void __launch_bounds__(kBlock)
-project_kernel(const DevGeom G, const int U, const int items, const int chunk,
-               const float *__restrict__ vol, float *__restrict__ proj)
+__device__ __forceinline__ void project_item(const DevGeom &G, const int U, const int item,
+                                             float *smem, const float *__restrict__ vol,
+                                             float *__restrict__ proj)
 {
     constexpr int GW = 16;
-    extern __shared__ __align__(16) float smem[];
-    const int item = (blockIdx.x & 7) * chunk + (blockIdx.x >> 3);   // XCD-contiguous items
-    if (item >= items) return;
     const int view = item % G.nviews;
     const int u0 = (item / G.nviews) * U;
     const int ub = min(u0 + U, G.M) - 1;
@@ -285,9 +284,10 @@ project_kernel(const DevGeom G, const int U, const int items, const int chunk,
     int *rowStart = reinterpret_cast<int *>(bins + kWaves * U * Npad);
     int *rowQ = rowStart + (G.n2 + 1);
     int *part = rowQ + G.n2;
-    float *recAll = reinterpret_cast<float *>(part + kBlock + 4);
-    recAll = reinterpret_cast<float *>((reinterpret_cast<uintptr_t>(recAll) + 15) & ~uintptr_t(15));
-    float *rec = recAll + wave * (GW * PMAX * kRecFloats + GW);
+    // records start at a 16-byte boundary; offsets are computed on indices so
+    // the pointers keep the LDS address space (ds_* rather than flat_* access)
+    const int recOff = (kWaves * U * Npad + 2 * G.n2 + 1 + kBlock + 4 + 3) & ~3;
+    float *rec = smem + recOff + wave * (GW * PMAX * kRecFloats + GW);
     int *npc = reinterpret_cast<int *>(rec + GW * PMAX * kRecFloats);
 
     for (int idx = tid; idx < kWaves * U * Npad; idx += kBlock) bins[idx] = 0.0f;
@@ -458,17 +458,27 @@ project_kernel(const DevGeom G, const int U, const int items, const int chunk,
     }
 }
 
-// ------------------------------------------------------------ backprojection
-
-template <bool EXACT, bool EC, int PMAX, int GW>
+template <bool EXACT, bool EC, int PMAX>
 __global__ void __launch_bounds__(kBlock)
-backproject_kernel(const DevGeom G, const int ngroups, const int nkchunks, const int items,
-                   const int chunk, const int winCap, const float *__restrict__ proj,
-                   float *__restrict__ vol)
+project_kernel(const DevGeom G, const int U, const int items, const int chunk,
+               const float *__restrict__ vol, float *__restrict__ proj)
 {
     extern __shared__ __align__(16) float smem[];
-    const int item = (blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
+    const int item = (blockIdx.x & 7) * chunk + (blockIdx.x >> 3);   // XCD-contiguous items
     if (item >= items) return;
+    project_item<EXACT, EC, PMAX>(G, U, item, smem, vol, proj);
+}
+
+// ------------------------------------------------------------ backprojection
+
+// One work item of the backprojection: a stack of GW columns x 64 voxels.
+template <bool EXACT, bool EC, int PMAX, int GW>
+__device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngroups,
+                                                 const int nkchunks, const int winCap,
+                                                 const int item, float *smem,
+                                                 const float *__restrict__ proj,
+                                                 float *__restrict__ vol)
+{
     const int kch = item % nkchunks;
     const int t = item / nkchunks;
     const int q = t % ngroups;
@@ -622,6 +632,80 @@ backproject_kernel(const DevGeom G, const int ngroups, const int nkchunks, const
     }
 }
 
+template <bool EXACT, bool EC, int PMAX, int GW>
+__global__ void __launch_bounds__(kBlock)
+backproject_kernel(const DevGeom G, const int ngroups, const int nkchunks, const int items,
+                   const int chunk, const int winCap, const float *__restrict__ proj,
+                   float *__restrict__ vol)
+{
+    extern __shared__ __align__(16) float smem[];
+    const int item = (blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
+    if (item >= items) return;
+    backproject_item<EXACT, EC, PMAX, GW>(G, ngroups, nkchunks, winCap, item, smem, proj, vol);
+}
+
+// ------------------------------------------------------------ batched, persistent
+
+// Next work item of a persistent workgroup (one atomic per item) and the
+// problem it belongs to; segments are ordered largest items first.
+__device__ __forceinline__ bool next_item(const BatchTable &T, int *counter, int &p, int &local)
+{
+    __shared__ int s_item;
+    __syncthreads();   // the previous item's LDS use is over
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int item = __builtin_amdgcn_readfirstlane(s_item);   // uniform: scalar loads below
+    if (item >= T.start[T.n]) return false;
+    int seg = 0;
+    while (T.start[seg + 1] <= item) ++seg;
+    p = __builtin_amdgcn_readfirstlane(T.order[seg]);
+    local = item - T.start[seg];
+    return true;
+}
+
+template <bool EXACT, bool EC, int PMAX>
+__global__ void __launch_bounds__(kBlock)
+project_batched_kernel(const BatchProblem *__restrict__ probs, const BatchTable *__restrict__ T,
+                       int *counter)
+{
+    extern __shared__ __align__(16) float smem[];
+    int p, local;
+    while (next_item(*T, counter, p, local)) {
+        const BatchProblem &P = probs[p];
+        project_item<EXACT, EC, PMAX>(P.G, P.U, local, smem, P.in, P.out);
+    }
+}
+
+template <bool EXACT, bool EC, int PMAX, int GW>
+__global__ void __launch_bounds__(kBlock)
+backproject_batched_kernel(const BatchProblem *__restrict__ probs, const BatchTable *__restrict__ T,
+                           int *counter, int winCap)
+{
+    extern __shared__ __align__(16) float smem[];
+    int p, local;
+    while (next_item(*T, counter, p, local)) {
+        const BatchProblem &P = probs[p];
+        backproject_item<EXACT, EC, PMAX, GW>(P.G, P.ngroups, P.nkchunks, winCap, local, smem, P.in, P.out);
+    }
+}
+
+// Per-call setup of a batched launch (a kernel, so it can sit in a graph):
+// the I/O pointers of every problem and a zeroed work counter.
+__global__ void batch_setup(BatchProblem *probs, const BatchIO io, int *counter)
+{
+    if (threadIdx.x != 0) return;
+#pragma unroll
+    for (int q = 0; q < kMaxBatch; ++q) {
+        if (q < io.n) {
+            probs[q].in = io.in[q];
+            probs[q].out = io.out[q];
+            probs[q].G.sigma = io.sigma[q];
+            probs[q].G.raw_volume = io.raw;
+        }
+    }
+    *counter = 0;
+}
+
 template <bool EXACT, bool EC>
 hipError_t launch_p(const DevGeom &g, const ProjLaunch &L, const float *vol, float *proj,
                     hipStream_t s)
@@ -683,7 +767,100 @@ hipError_t set_lds_one(size_t n)
     return e;
 }
 
+template <bool EXACT, bool EC, int PMAX>
+hipError_t launch_pb(BatchProblem *probs, const BatchTable *tab, int *counter, int grid, size_t lds,
+                     hipStream_t s)
+{
+    hipLaunchKernelGGL((project_batched_kernel<EXACT, EC, PMAX>), dim3(grid), dim3(kBlock), lds, s,
+                       probs, tab, counter);
+    return hipGetLastError();
+}
+
+template <bool EXACT, bool EC, int PMAX>
+hipError_t launch_bb(BatchProblem *probs, const BatchTable *tab, int *counter, int gw, int winCap,
+                     int grid, size_t lds, hipStream_t s)
+{
+    switch (gw) {
+    case 16:
+        hipLaunchKernelGGL((backproject_batched_kernel<EXACT, EC, PMAX, 16>), dim3(grid), dim3(kBlock),
+                           lds, s, probs, tab, counter, winCap);
+        break;
+    case 8:
+        hipLaunchKernelGGL((backproject_batched_kernel<EXACT, EC, PMAX, 8>), dim3(grid), dim3(kBlock),
+                           lds, s, probs, tab, counter, winCap);
+        break;
+    default:
+        hipLaunchKernelGGL((backproject_batched_kernel<EXACT, EC, PMAX, 4>), dim3(grid), dim3(kBlock),
+                           lds, s, probs, tab, counter, winCap);
+        break;
+    }
+    return hipGetLastError();
+}
+
+template <bool EXACT, bool EC, int PMAX>
+hipError_t set_lds_batched(size_t n)
+{
+    hipError_t e = hipFuncSetAttribute((const void *)project_batched_kernel<EXACT, EC, PMAX>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)backproject_batched_kernel<EXACT, EC, PMAX, 16>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)backproject_batched_kernel<EXACT, EC, PMAX, 8>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)backproject_batched_kernel<EXACT, EC, PMAX, 4>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
+    return e;
+}
+
 }  // namespace
+
+hipError_t launch_batched(bool backward, BatchProblem *probs, const BatchTable *tab, int *counter,
+                          const BatchIO &io, int pmax, int gw, int winCap, bool exact, bool ec,
+                          int grid, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_setup, dim3(1), dim3(64), 0, s, probs, io, counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (!backward) {
+        if (pmax <= 4) {
+            if (exact) return ec ? launch_pb<true, true, 4>(probs, tab, counter, grid, lds, s)
+                                 : launch_pb<true, false, 4>(probs, tab, counter, grid, lds, s);
+            return ec ? launch_pb<false, true, 4>(probs, tab, counter, grid, lds, s)
+                      : launch_pb<false, false, 4>(probs, tab, counter, grid, lds, s);
+        }
+        if (exact) return ec ? launch_pb<true, true, 8>(probs, tab, counter, grid, lds, s)
+                             : launch_pb<true, false, 8>(probs, tab, counter, grid, lds, s);
+        return ec ? launch_pb<false, true, 8>(probs, tab, counter, grid, lds, s)
+                  : launch_pb<false, false, 8>(probs, tab, counter, grid, lds, s);
+    }
+    if (pmax <= 4) {
+        if (exact) return ec ? launch_bb<true, true, 4>(probs, tab, counter, gw, winCap, grid, lds, s)
+                             : launch_bb<true, false, 4>(probs, tab, counter, gw, winCap, grid, lds, s);
+        return ec ? launch_bb<false, true, 4>(probs, tab, counter, gw, winCap, grid, lds, s)
+                  : launch_bb<false, false, 4>(probs, tab, counter, gw, winCap, grid, lds, s);
+    }
+    if (exact) return ec ? launch_bb<true, true, 8>(probs, tab, counter, gw, winCap, grid, lds, s)
+                         : launch_bb<true, false, 8>(probs, tab, counter, gw, winCap, grid, lds, s);
+    return ec ? launch_bb<false, true, 8>(probs, tab, counter, gw, winCap, grid, lds, s)
+              : launch_bb<false, false, 8>(probs, tab, counter, gw, winCap, grid, lds, s);
+}
+
+// Workgroups of a persistent batched kernel that fit on one CU at this LDS size.
+int batched_blocks_per_cu(bool backward, size_t lds)
+{
+    int nb = 0;
+    hipError_t e;
+    if (!backward)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)project_batched_kernel<false, true, 8>,
+                                                         kBlock, lds);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)backproject_batched_kernel<false, true, 8, 16>,
+                                                         kBlock, lds);
+    if (e != hipSuccess || nb < 1) nb = 1;
+    return nb;
+}
 
 // Allow the dynamic LDS sizes chosen by the host (above the 64 KB default).
 hipError_t configure_kernel_lds(size_t max_lds)
@@ -697,6 +874,14 @@ hipError_t configure_kernel_lds(size_t max_lds)
     if (e == hipSuccess) e = set_lds_one<true, false, 8>(max_lds);
     if (e == hipSuccess) e = set_lds_one<false, true, 8>(max_lds);
     if (e == hipSuccess) e = set_lds_one<false, false, 8>(max_lds);
+    if (e == hipSuccess) e = set_lds_batched<true, true, 4>(max_lds);
+    if (e == hipSuccess) e = set_lds_batched<true, false, 4>(max_lds);
+    if (e == hipSuccess) e = set_lds_batched<false, true, 4>(max_lds);
+    if (e == hipSuccess) e = set_lds_batched<false, false, 4>(max_lds);
+    if (e == hipSuccess) e = set_lds_batched<true, true, 8>(max_lds);
+    if (e == hipSuccess) e = set_lds_batched<true, false, 8>(max_lds);
+    if (e == hipSuccess) e = set_lds_batched<false, true, 8>(max_lds);
+    if (e == hipSuccess) e = set_lds_batched<false, false, 8>(max_lds);
     return e;
 }
 

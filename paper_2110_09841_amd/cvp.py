@@ -99,3 +99,59 @@ def backproject(b, geom: Geometry, opts: Options = Options(), out=None):
     _lib.check(_lib.lib().cvp_backproject(geom.handle, ctypes.byref(o), ctypes.c_void_p(b.data_ptr()),
                                           ctypes.c_void_p(out.data_ptr()), _stream()))
     return out
+
+
+class Batch:
+    """Several geometries served by one persistent launch per direction."""
+
+    def __init__(self, geoms):
+        self.geoms = list(geoms)
+        arr = (ctypes.c_void_p * len(self.geoms))(*[g.handle.value for g in self.geoms])
+        h = ctypes.c_void_p()
+        _lib.check(_lib.lib().cvp_batch_create(arr, len(self.geoms), ctypes.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib._lib is not None:
+            _lib._lib.cvp_batch_destroy(h)
+            self.handle = None
+
+    def __len__(self):
+        return len(self.geoms)
+
+
+def _ptr_array(ts):
+    return (ctypes.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+
+
+def project_batched(xs, batch: Batch, opts: Options = Options(), outs=None):
+    """[A_q x_q for each problem q] in one persistent launch."""
+    if len(xs) != len(batch):
+        raise ValueError("expected %d volumes" % len(batch))
+    for x, g in zip(xs, batch.geoms):
+        _check_tensor(x, g.vol_shape, "x")
+    if outs is None:
+        outs = [torch.empty(g.proj_shape, dtype=torch.float32, device=x.device) for x, g in zip(xs, batch.geoms)]
+    for o, g in zip(outs, batch.geoms):
+        _check_tensor(o, g.proj_shape, "out")
+    oc = opts.c()
+    _lib.check(_lib.lib().cvp_project_batched(batch.handle, ctypes.byref(oc), _ptr_array(xs),
+                                              _ptr_array(outs), _stream()))
+    return outs
+
+
+def backproject_batched(bs, batch: Batch, opts: Options = Options(), outs=None):
+    """[A_q^T b_q for each problem q] in one persistent launch."""
+    if len(bs) != len(batch):
+        raise ValueError("expected %d projection stacks" % len(batch))
+    for b, g in zip(bs, batch.geoms):
+        _check_tensor(b, g.proj_shape, "b")
+    if outs is None:
+        outs = [torch.empty(g.vol_shape, dtype=torch.float32, device=b.device) for b, g in zip(bs, batch.geoms)]
+    for o, g in zip(outs, batch.geoms):
+        _check_tensor(o, g.vol_shape, "out")
+    oc = opts.c()
+    _lib.check(_lib.lib().cvp_backproject_batched(batch.handle, ctypes.byref(oc), _ptr_array(bs),
+                                                  _ptr_array(outs), _stream()))
+    return outs

@@ -88,3 +88,21 @@ def test_operators_fail_loudly_without_library(monkeypatch):
     monkeypatch.setattr(_lib, "LIB_PATH", "/nonexistent/libcvp.so")
     with pytest.raises(RuntimeError, match="not built"):
         _lib.lib()
+
+
+def test_batch_and_cgls_argument_errors():
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    assert L.cvp_batch_create(None, 3, ctypes.byref(h)) == _lib.CVP_E_INVALID
+    arr = (ctypes.c_void_p * 2)(None, None)
+    assert L.cvp_batch_create(arr, 0, ctypes.byref(h)) == _lib.CVP_E_INVALID
+    assert L.cvp_batch_create(arr, 33, ctypes.byref(h)) == _lib.CVP_E_INVALID
+    assert L.cvp_batch_create(arr, 2, ctypes.byref(h)) == _lib.CVP_E_INVALID
+    assert "geoms[0]" in _lib.last_error()
+    L.cvp_batch_destroy(None)
+    nbytes = ctypes.c_int64()
+    assert L.cvp_cgls_workspace_size(10, 20, ctypes.byref(nbytes)) == _lib.CVP_OK
+    assert nbytes.value >= 8 * (8 + 2 * 4096)
+    assert L.cvp_cgls_workspace_size(-1, 20, ctypes.byref(nbytes)) == _lib.CVP_E_INVALID
+    o = _lib.OptionsC(0, 1, 0, 0)
+    assert L.cvp_cgls_iterate(None, ctypes.byref(o), 1, None, None, None, None, None, None, None) == _lib.CVP_E_INVALID
