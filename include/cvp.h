@@ -189,6 +189,62 @@ cvp_status cvp_cgls_iterate(const cvp_geometry *g, const cvp_options *opts, int3
 cvp_status cvp_dot(const float *d_a, const float *d_b, int64_t n, double *d_result,
                    void *d_work, void *hip_stream);
 
+/*
+ * Learned warm start: kernels of a small 3D U-Net (3x3x3 convolutions, BF16
+ * activations and weights, FP32 accumulation on the MFMA unit).  Tensors are
+ * channels-last BF16 [d][h][w][stride] (channel slices allowed: data points
+ * at the first channel, stride = channels of the full tensor); channels and
+ * stride are multiples of 8, data 16-byte aligned.  All calls are
+ * asynchronous on the stream, allocate nothing, and return CVP_E_INVALID for
+ * bad descriptors, CVP_E_UNSUPPORTED for channel counts without a kernel.
+ */
+typedef struct {
+    void *data;
+    int32_t d, h, w;
+    int32_t channels;
+    int32_t stride;
+} cvp_nn_tensor;
+
+/* out = [relu](conv3d(in, W) + bias), 3x3x3, zero padding 1.  weight: BF16
+ * [27][Cout][Cin] (tap = 9 dz + 3 dy + dx); Cout in {16, 32, 64}.  flip = 1
+ * mirrors the taps: with weights from cvp_nn_transpose_weights this is the
+ * backward-data convolution. */
+cvp_status cvp_nn_conv3d(const cvp_nn_tensor *in, const void *weight, const float *bias,
+                         const cvp_nn_tensor *out, int32_t relu, int32_t flip, void *stream);
+/* dW[tap][co][ci] = sum_v dY[v][co] X[v + off(tap)][ci] (FP32), via per-chunk
+ * partials in work (cvp_nn_wgrad_workspace floats) and a fixed-order sum. */
+cvp_status cvp_nn_wgrad_workspace(const cvp_nn_tensor *x, const cvp_nn_tensor *dy, int64_t *floats);
+cvp_status cvp_nn_conv3d_wgrad(const cvp_nn_tensor *x, const cvp_nn_tensor *dy, float *dw, float *work,
+                               int64_t work_floats, void *stream);
+/* out[c] = sum_v a[v][c] (bias gradient); work >= ceil(d*h/16) * channels floats */
+cvp_status cvp_nn_channel_sum(const cvp_nn_tensor *a, float *out, float *work, int64_t work_floats,
+                              void *stream);
+/* dy[v][c] = 0 where y[v][c] <= 0 (ReLU backward from the post-ReLU output) */
+cvp_status cvp_nn_relu_mask(const cvp_nn_tensor *dy, const cvp_nn_tensor *y, void *stream);
+cvp_status cvp_nn_avgpool2(const cvp_nn_tensor *in, const cvp_nn_tensor *out, void *stream);
+cvp_status cvp_nn_avgpool2_bwd(const cvp_nn_tensor *dout, const cvp_nn_tensor *din, void *stream);
+cvp_status cvp_nn_upsample2(const cvp_nn_tensor *in, const cvp_nn_tensor *out, void *stream);
+cvp_status cvp_nn_upsample2_bwd(const cvp_nn_tensor *dout, const cvp_nn_tensor *din, void *stream);
+/* wt[tap][ci][co] = w[tap][co][ci] (BF16) */
+cvp_status cvp_nn_transpose_weights(const void *w, void *wt, int32_t cout, int32_t cin, void *stream);
+/* out channels 0, 1 = scale * x1, scale * x2 (FP32 volumes); channels 2..15 = 0 */
+cvp_status cvp_nn_pack_input(const float *x1, const float *x2, float scale, const cvp_nn_tensor *out,
+                             void *stream);
+/* x0 = x2 + (sum_c w[c] h[v][c] + b[0]) / scale  (1x1x1 head, residual on x2) */
+cvp_status cvp_nn_head(const cvp_nn_tensor *h, const float *w, const float *b, const float *x2,
+                       float scale, float *x0, void *stream);
+/* head backward: dh = w g / scale (BF16); dwb[0..15] = dL/dw, dwb[16] = dL/db */
+cvp_status cvp_nn_head_bwd(const cvp_nn_tensor *h, const float *w, const float *g, float scale,
+                           const cvp_nn_tensor *dh, float *dwb, float *work, int64_t work_floats,
+                           void *stream);
+/* grad = 2 (a - b) / n, *loss = mean (a - b)^2 (device FP64); work >= 1024 doubles */
+cvp_status cvp_nn_mse(const float *a, const float *b, int64_t n, float *grad, double *loss,
+                      double *work, int64_t work_doubles, void *stream);
+/* Adam step on FP32 parameters (bias-corrected, step >= 1), optional BF16 copy */
+cvp_status cvp_nn_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr,
+                       float beta1, float beta2, float eps, int32_t step, void *p_bf16,
+                       void *stream);
+
 /* Geometry queries (host-side, no device work). */
 cvp_status cvp_geometry_sizes(const cvp_geometry *g, int64_t *n_voxels,
                               int64_t *n_pixels_total);

@@ -16,8 +16,9 @@
 #include "cvp_internal.h"
 
 namespace cvp {
-hipError_t configure_kernel_lds(size_t max_lds);
+hipError_t configure_kernel_lds(size_t max_lds, size_t max_lds_batched);
 constexpr size_t kLdsBudget = 78 * 1024;   // two workgroups per CU (160 KB LDS)
+constexpr size_t kLdsBatchMax = 156 * 1024; // batched kernels: one workgroup per CU at worst
 bool plan_projection(int N, int n2, int M, int nviews, int pmax, ProjLaunch &L);
 bool plan_backprojection(const DevGeom &G, int pmax, double zabs, double Dmin, int force_gw,
                          BackLaunch &L);
@@ -81,8 +82,8 @@ namespace cvp {
 size_t project_lds_bytes(int U, int N, int n2, int pmax)
 {
     const size_t npad = (size_t)(N | 1);
-    return (size_t)kWaves * U * npad * 4 + (size_t)(2 * n2 + 1 + kBlock + 4) * 4 + 16 +
-           (size_t)kWaves * (16 * pmax * kRecFloats + 16) * 4;
+    (void)pmax;   // piece records live in registers
+    return (size_t)kWaves * U * npad * 4 + (size_t)(2 * n2 + 1 + kBlock + 4) * 4 + 16;
 }
 
 size_t backproject_lds_bytes(int gw, int pmax, int winCap)
@@ -269,7 +270,7 @@ cvp_status cvp_geometry_from_views(const cvp_geometry_desc *d, cvp_geometry **ou
     if (e != hipSuccess) { cvp_geometry_destroy(g); return device_fail(e, "device tables"); }
     static std::once_flag lds_once;
     static hipError_t lds_err = hipSuccess;
-    std::call_once(lds_once, [] { lds_err = cvp::configure_kernel_lds(kLdsBudget); });
+    std::call_once(lds_once, [] { lds_err = cvp::configure_kernel_lds(kLdsBudget, cvp::kLdsBatchMax); });
     if (lds_err != hipSuccess) { cvp_geometry_destroy(g); return device_fail(lds_err, "kernel LDS attribute"); }
 
     cvp::DevGeom &G = g->base;
@@ -407,9 +408,13 @@ cvp_status cvp_batch_create(const cvp_geometry *const *geoms, int32_t n, cvp_bat
     std::vector<double> pcost(n), bcost(n);
     for (int q = 0; q < n; ++q) {
         const cvp_geometry *g = geoms[q];
-        cvp::ProjLaunch pl;
+        // each problem keeps its own band width U (the per-pixel order of
+        // additions, hence the bits of the result, depend on it); only the
+        // record stride (pmax) is common
+        cvp::ProjLaunch pl = g->pl;
+        pl.lds = cvp::project_lds_bytes(pl.U, g->base.N, g->base.n2, b->pmax);
         cvp::BackLaunch bl;
-        if (!cvp::plan_projection(g->base.N, g->base.n2, g->base.M, g->base.nviews, b->pmax, pl) ||
+        if (pl.lds > cvp::kLdsBatchMax ||
             !cvp::plan_backprojection(g->base, b->pmax, g->zabs, g->Dmin, b->gw, bl)) {
             cvp_batch_destroy(b);
             return fail(CVP_E_UNSUPPORTED, "problem %d does not fit the common launch plan", q);

@@ -33,6 +33,9 @@ namespace cvp {
 namespace {
 
 // ------------------------------------------------------------ FP64 column stage
+// FP contraction is off in this stage, so the records do not depend on the
+// kernel the stage is inlined into (single-problem and batched launches give
+// the same bits).
 
 // Shoelace sums of a polygon: a2 = 2A, sx = 6A cx, sy = 6A cy,
 // sxx = 12 int x^2, syy = 12 int y^2, sxy = 24 int xy.
@@ -42,6 +45,7 @@ struct Mom {
 
 __device__ __forceinline__ void mom_edge(Mom &m, double x0, double y0, double x1, double y1)
 {
+#pragma clang fp contract(off)
     const double cr = x0 * y1 - x1 * y0;
     m.a2 += cr;
     m.sx += (x0 + x1) * cr;
@@ -57,6 +61,7 @@ __device__ __forceinline__ void mom_edge(Mom &m, double x0, double y0, double x1
 __device__ __forceinline__ Mom halfplane_moments(double h1, double h2, double gx, double gy,
                                                  double c)
 {
+#pragma clang fp contract(off)
     const double px[4] = {-h1, h1, h1, -h1};
     const double py[4] = {-h2, -h2, h2, h2};
     double val[4];
@@ -100,6 +105,7 @@ struct Column {
 
 __device__ __forceinline__ Column make_column(const DevGeom &G, const ViewGeom &V, int i, int j)
 {
+#pragma clang fp contract(off)
     Column C;
     C.xc1 = G.x1lo + (i + 0.5) * G.a1;
     C.xc2 = G.x2lo + (j + 0.5) * G.a2;
@@ -125,6 +131,7 @@ __device__ __forceinline__ Column make_column(const DevGeom &G, const ViewGeom &
 __device__ __forceinline__ Mom column_prefix(const DevGeom &G, const ViewGeom &V, const Column &C,
                                              double t)
 {
+#pragma clang fp contract(off)
     const double fb = G.f / G.b1;
     const double inv = 1.0 / C.Dc;
     const double gx = (fb * V.e1x - (t - G.c1) * V.dx) * inv;
@@ -142,6 +149,7 @@ template <bool EXACT, bool EC>
 __device__ __forceinline__ void piece_record(const DevGeom &G, const ViewGeom &V, const Column &C,
                                              int u, float *rec)
 {
+#pragma clang fp contract(off)
     const Mom hi = column_prefix(G, V, C, u + 0.5);
     const Mom lo = column_prefix(G, V, C, u - 0.5);
     const double a2 = hi.a2 - lo.a2;
@@ -187,26 +195,23 @@ __device__ __forceinline__ void piece_record(const DevGeom &G, const ViewGeom &V
 
 // ------------------------------------------------------------ FP32 voxel stage
 
-// Box average over the depth box of max(s, 0), where s moves uniformly over
-// [s - e, s + e] (Sec. III-B reading); e = 0 gives max(s, 0).
-__device__ __forceinline__ float tbox(float s, float e, float inv4e)
-{
-    const float a = s + e;
-    const float quad = a * a * inv4e;
-    const float low = (s <= -e) ? 0.0f : quad;
-    return (s >= e) ? s : low;
-}
-
 // C(t): the part of the voxel's chi2 extent [Ytop, Ytop + beta] that lies
-// beyond row boundary t (averaged over the depth box with EC).  s1 = Ytop - t.
+// beyond row boundary t, s1 = Ytop - t.  With the elevation correction the
+// boundary position is averaged over the depth box, i.e. s moves uniformly
+// over [s - e, s + e] with e = |t - c2| h / D (Sec. III-B reading); the box
+// average of max(s, 0) is max(s, 0) + max(e - |s|, 0)^2 / (4e), so
+// C = [max(s0,0) - max(s1,0)] + (phi0^2 - phi1^2) / (4e).
 template <bool EC>
 __device__ __forceinline__ float cum(float s1, float beta, float tc, float rho)
 {
     const float s0 = s1 + beta;
-    if (!EC) return fmaxf(s0, 0.0f) - fmaxf(s1, 0.0f);
+    const float plain = fmaxf(s0, 0.0f) - fmaxf(s1, 0.0f);
+    if (!EC) return plain;
     const float e = fabsf(tc) * rho;
-    const float inv = 0.25f * __builtin_amdgcn_rcpf(e);
-    return tbox(s0, e, inv) - tbox(s1, e, inv);
+    const float p0 = fmaxf(e - fabsf(s0), 0.0f);
+    const float p1 = fmaxf(e - fabsf(s1), 0.0f);
+    const float inv4e = 0.25f * __builtin_amdgcn_rcpf(fmaxf(e, 1e-30f));
+    return fmaf((p0 - p1) * (p0 + p1), inv4e, plain);
 }
 
 __device__ __forceinline__ void lds_add(float *p, float v)
@@ -277,18 +282,12 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
     const int ngroups = (G.n1 + GW - 1) / GW;
 
     // per-wavefront bins (each wave sums into its own band image, so the
-    // order of additions into any pixel is fixed), then row tables, then the
-    // per-wave piece records
+    // order of additions into any pixel is fixed), then the row tables
     float *bins = smem;
     float *wbins = bins + wave * U * Npad;
     int *rowStart = reinterpret_cast<int *>(bins + kWaves * U * Npad);
     int *rowQ = rowStart + (G.n2 + 1);
     int *part = rowQ + G.n2;
-    // records start at a 16-byte boundary; offsets are computed on indices so
-    // the pointers keep the LDS address space (ds_* rather than flat_* access)
-    const int recOff = (kWaves * U * Npad + 2 * G.n2 + 1 + kBlock + 4 + 3) & ~3;
-    float *rec = smem + recOff + wave * (GW * PMAX * kRecFloats + GW);
-    int *npc = reinterpret_cast<int *>(rec + GW * PMAX * kRecFloats);
 
     for (int idx = tid; idx < kWaves * U * Npad; idx += kBlock) bins[idx] = 0.0f;
 
@@ -369,15 +368,28 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
         const int j = lo;
         const int i0 = (rowQ[j] + (gi - rowStart[j])) * GW;
 
-        build_records<EXACT, EC, PMAX, GW>(G, V, i0, j, u0, ub, rec, npc, lane);
-        wave_sync();
-        int any = 0;
+        // Piece records stay in the registers of the lanes that computed them
+        // (lane c + 16 s holds slot s of column c, pass q in rq[q]); the voxel
+        // loop fetches them with readlane, so no LDS read (and no wait on the
+        // outstanding LDS atomics) sits between consecutive pieces.
+        constexpr int PASSES = PMAX / 4;
+        float rq[PASSES][kRecFloats];
+        int ncol = 0;
+        {
+            const int c = lane & 15, slot = lane >> 4;
+            const int i = i0 + c;
+            if (i < G.n1) {
+                const Column C = make_column(G, V, i, j);
+                const int ufirst = max((int)floor(C.chimin + 0.5), u0);
+                const int ulast = min((int)floor(C.chimax + 0.5), ub);
+                ncol = min(max(ulast - ufirst + 1, 0), PMAX);
 #pragma unroll
-        for (int c = 0; c < GW; ++c) any |= npc[c];
-        if (any == 0) {
-            wave_sync();
-            continue;
+                for (int q = 0; q < PASSES; ++q) {
+                    if (slot + 4 * q < ncol) piece_record<EXACT, EC>(G, V, C, ufirst + slot + 4 * q, rq[q]);
+                }
+            }
         }
+        if (__ballot(ncol > 0) == 0) continue;
         const bool full = vec_rows && (i0 + GW <= G.n1);
 
         for (int kc = 0; kc < G.n3; kc += kWave) {
@@ -400,22 +412,30 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
             const float zc = zt - 0.5f * a3f;           // centre of voxel k
 #pragma unroll
             for (int c = 0; c < GW; ++c) {
-                const int np = npc[c];
+                const int np = __builtin_amdgcn_readlane(ncol, c);
                 if (np == 0) continue;
                 const float m = kv ? mu[c] : 0.0f;
                 if (__ballot(m != 0.0f) == 0) continue;
-                const float *rc = rec + c * PMAX * kRecFloats;
                 float base = m;
-                if (!EXACT && !raw) base = m * __builtin_amdgcn_rcpf(fmaf(zc, zc, rc[8]));
+                if (!EXACT && !raw)
+                    base = m * __builtin_amdgcn_rcpf(fmaf(zc, zc, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rq[0][8]), c))));
                 for (int p = 0; p < np; ++p) {
-                    const float4 r0 = *reinterpret_cast<const float4 *>(rc + p * kRecFloats);
-                    const float4 r1 = *reinterpret_cast<const float4 *>(rc + p * kRecFloats + 4);
-                    const float4 r2 = *reinterpret_cast<const float4 *>(rc + p * kRecFloats + 8);
-                    const int u = __float_as_int(r0.x);
-                    const float coef = base * r0.y;
-                    const float Yh = fmaf(-kf, r1.x, r0.z);
-                    const float Yl = fmaf(-kf, r1.y, r0.w);
-                    const float beta = r1.z, rho = r1.w;
+                    const int src = c + 16 * (p & 3);
+                    float r[kRecFloats];
+                    if (PASSES == 1 || p < 4) {
+#pragma unroll
+                        for (int e = 0; e < kRecFloats; ++e)
+                            r[e] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rq[0][e]), src));
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < kRecFloats; ++e)
+                            r[e] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rq[PASSES - 1][e]), src));
+                    }
+                    const int u = __float_as_int(r[0]);
+                    const float coef = base * r[1];
+                    const float Yh = fmaf(-kf, r[4], r[2]);
+                    const float Yl = fmaf(-kf, r[5], r[3]);
+                    const float beta = r[6], rho = r[7];
                     int vlo, vhi;
                     row_range<EC>(Yh + Yl, beta, rho, c2f, G.N, vlo, vhi);
                     float *bcol = wbins + (u - u0) * Npad;
@@ -430,8 +450,8 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
                         if (EXACT && !raw) {
                             float mm = 0.5f * (fmaxf(0.0f, -s1p) + fminf(beta, -s1n));
                             mm = fminf(fmaxf(mm, 0.0f), beta);
-                            const float zb = fmaf(-mm, r2.y, zt);
-                            w *= __builtin_amdgcn_rcpf(fmaf(zb, zb, r2.x));
+                            const float zb = fmaf(-mm, r[9], zt);
+                            w *= __builtin_amdgcn_rcpf(fmaf(zb, zb, r[8]));
                         }
                         lds_add(bcol + v, w);
                         Cp = Cn;
@@ -440,7 +460,6 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
                 }
             }
         }
-        wave_sync();
     }
     __syncthreads();
 
@@ -863,7 +882,7 @@ int batched_blocks_per_cu(bool backward, size_t lds)
 }
 
 // Allow the dynamic LDS sizes chosen by the host (above the 64 KB default).
-hipError_t configure_kernel_lds(size_t max_lds)
+hipError_t configure_kernel_lds(size_t max_lds, size_t max_lds_batched)
 {
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = set_lds_one<true, true, 4>(max_lds);
@@ -874,14 +893,14 @@ hipError_t configure_kernel_lds(size_t max_lds)
     if (e == hipSuccess) e = set_lds_one<true, false, 8>(max_lds);
     if (e == hipSuccess) e = set_lds_one<false, true, 8>(max_lds);
     if (e == hipSuccess) e = set_lds_one<false, false, 8>(max_lds);
-    if (e == hipSuccess) e = set_lds_batched<true, true, 4>(max_lds);
-    if (e == hipSuccess) e = set_lds_batched<true, false, 4>(max_lds);
-    if (e == hipSuccess) e = set_lds_batched<false, true, 4>(max_lds);
-    if (e == hipSuccess) e = set_lds_batched<false, false, 4>(max_lds);
-    if (e == hipSuccess) e = set_lds_batched<true, true, 8>(max_lds);
-    if (e == hipSuccess) e = set_lds_batched<true, false, 8>(max_lds);
-    if (e == hipSuccess) e = set_lds_batched<false, true, 8>(max_lds);
-    if (e == hipSuccess) e = set_lds_batched<false, false, 8>(max_lds);
+    if (e == hipSuccess) e = set_lds_batched<true, true, 4>(max_lds_batched);
+    if (e == hipSuccess) e = set_lds_batched<true, false, 4>(max_lds_batched);
+    if (e == hipSuccess) e = set_lds_batched<false, true, 4>(max_lds_batched);
+    if (e == hipSuccess) e = set_lds_batched<false, false, 4>(max_lds_batched);
+    if (e == hipSuccess) e = set_lds_batched<true, true, 8>(max_lds_batched);
+    if (e == hipSuccess) e = set_lds_batched<true, false, 8>(max_lds_batched);
+    if (e == hipSuccess) e = set_lds_batched<false, true, 8>(max_lds_batched);
+    if (e == hipSuccess) e = set_lds_batched<false, false, 8>(max_lds_batched);
     return e;
 }
 

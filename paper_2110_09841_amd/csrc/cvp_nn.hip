@@ -1,0 +1,623 @@
+// Kernels of the learned CGLS warm start: a small 3D U-Net with 3x3x3
+// convolutions, BF16 activations and weights, FP32 accumulation.
+//
+// Layout: channels last, [D][H][W][C] BF16, with an explicit channel stride
+// (so a tensor can be a channel slice of a wider one: concatenation costs
+// nothing) and channel counts that are multiples of 8.
+//
+// conv3d (forward and backward-data) is an implicit GEMM on the MFMA unit:
+//   out[v][co] = sum_k A[v][k] B[k][co],  k = tap * Cin + ci,  27 taps,
+// with v_mfma_f32_16x16x32_bf16.  Lane l of a wave holds, for the 16x32 A
+// tile, row l%16 and the 8 consecutive k of group l/16 -- 8 consecutive input
+// channels of one tap, i.e. one 16-byte load in channels-last layout; the B
+// tile likewise holds 8 consecutive input channels of one output channel
+// (weights stored [tap][co][ci]).  The 16x16 FP32 result has row 4*(l/16)+e,
+// column l%16 in element e of lane l.
+// conv3d backward-weight reduces over voxels: D[co][ci] = sum_v dY[v][co] X[v+off][ci],
+// with dY and the shifted X rows staged transposed in LDS so that the 8
+// consecutive voxels of a lane are one 16-byte LDS read.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cvpnn {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+struct Act {             // a channels-last BF16 tensor (or channel slice)
+    __bf16 *p;
+    int D, H, W;
+    int C;               // channels used
+    int stride;          // channels between consecutive voxels (>= C)
+};
+
+__device__ __forceinline__ bf16x8 zero8()
+{
+    bf16x8 z;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) z[e] = (__bf16)0.0f;
+    return z;
+}
+
+// ------------------------------------------------------------------ conv3d
+
+// One wave computes 64 consecutive voxels of one (d, h) row (4 row tiles of
+// 16) for all output channels (CO/16 column tiles).  Weights wt: [27][Co][Ci].
+// flip = 1 mirrors the taps (used by backward-data with the transposed
+// weights).  relu = 1 applies max(., 0) before the BF16 store.
+template <int CO>
+__global__ void __launch_bounds__(256)
+conv3d_kernel(const Act in, const __bf16 *__restrict__ wt, const float *__restrict__ bias,
+              Act out, int relu, int flip)
+{
+    constexpr int NT = CO / 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int segs = (in.W + 63) / 64;
+    const int row = blockIdx.x * 4 + wave;           // (d, h, segment)
+    if (row >= in.D * in.H * segs) return;
+    const int seg = row % segs;
+    const int dh = row / segs;
+    const int d = dh / in.H, h = dh % in.H;
+    const int w0 = seg * 64;
+    const int Ci = in.C;
+    const int K = 27 * Ci;
+    const int ksteps = (K + 31) / 32;
+
+    f32x4 acc[4][NT];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int n = 0; n < NT; ++n) acc[r][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    const int i16 = lane & 15;
+    const int kg = lane >> 4;        // which group of 8 k within the 32
+    for (int ks = 0; ks < ksteps; ++ks) {
+        const int k = ks * 32 + kg * 8;
+        const int tap = k / Ci;
+        const int ci = k - tap * Ci;
+        const bool tv = tap < 27;
+        const int tp = flip ? 26 - tap : tap;
+        const int dz = tp / 9 - 1, dy = (tp / 3) % 3 - 1, dx = tp % 3 - 1;
+        const int z = d + dz, y = h + dy;
+        const bool zy = tv && z >= 0 && z < in.D && y >= 0 && y < in.H;
+        bf16x8 a[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int x = w0 + r * 16 + i16 + dx;
+            if (zy && x >= 0 && x < in.W)
+                a[r] = *reinterpret_cast<const bf16x8 *>(in.p + (((size_t)z * in.H + y) * in.W + x) * in.stride + ci);
+            else
+                a[r] = zero8();
+        }
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            const int co = n * 16 + i16;
+            bf16x8 b = tv ? *reinterpret_cast<const bf16x8 *>(wt + ((size_t)tap * CO + co) * Ci + ci) : zero8();
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[r][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], b, acc[r][n], 0, 0, 0);
+        }
+    }
+    // epilogue: lane holds rows 4*(l/16)+e, column l%16 of each tile
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+        const int co = n * 16 + i16;
+        const float bv = bias ? bias[co] : 0.0f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int x = w0 + r * 16 + (lane >> 4) * 4 + e;
+                if (x < out.W) {
+                    float v = acc[r][n][e] + bv;
+                    if (relu) v = fmaxf(v, 0.0f);
+                    out.p[(((size_t)d * out.H + h) * out.W + x) * out.stride + co] = (__bf16)v;
+                }
+            }
+        }
+    }
+}
+
+// Backward-weight partials: for the taps (dz, dy) = tap9 and all three dx,
+// and a chunk of `rows` (d, h) rows, part[chunk][tap][co][ci] =
+// sum over the chunk's voxels of dY[v][co] * X[v + off][ci].  dY and the
+// three dx-shifted X rows of one 64-voxel segment are staged transposed in
+// LDS ([channel][voxel]); lanes read 8 consecutive voxels per 16-byte read.
+// Wave w owns output-channel tiles co in [16 w', ...) round-robin.
+template <int CO, int CI>
+__global__ void __launch_bounds__(256)
+conv3d_wgrad_kernel(const Act x, const Act dy, int rows_per_chunk, float *__restrict__ part)
+{
+    constexpr int MT = CO / 16, NT = CI / 16;
+    constexpr int TILES = MT * NT;                 // 16x16 tiles per tap
+    constexpr int PER_WAVE = (TILES + 3) / 4;
+    __shared__ __align__(16) __bf16 sdy[CO][64];
+    __shared__ __align__(16) __bf16 sx[3][CI][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tap9 = blockIdx.y;                   // (dz, dy) in 0..8
+    const int dz = tap9 / 3 - 1, dyo = tap9 % 3 - 1;
+    const int chunk = blockIdx.x;
+    const int nrows = x.D * x.H;
+    const int r0 = chunk * rows_per_chunk;
+    const int r1 = min(r0 + rows_per_chunk, nrows);
+    const int segs = (x.W + 63) / 64;
+
+    f32x4 acc[3][PER_WAVE];
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+        for (int q = 0; q < PER_WAVE; ++q) acc[t][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int rr = r0; rr < r1; ++rr) {
+        const int d = rr / x.H, h = rr % x.H;
+        const int z = d + dz, y = h + dyo;
+        const bool zy = z >= 0 && z < x.D && y >= 0 && y < x.H;
+        for (int seg = 0; seg < segs; ++seg) {
+            const int w0 = seg * 64;
+            __syncthreads();
+            // stage dY[v][co] -> sdy[co][v] and X[z][y][w0 + v + dx][ci] -> sx[dx][ci][v]
+            for (int idx = threadIdx.x; idx < 64 * CO; idx += 256) {
+                const int v = idx / CO, c = idx % CO;
+                const int w = w0 + v;
+                sdy[c][v] = (w < dy.W) ? dy.p[(((size_t)d * dy.H + h) * dy.W + w) * dy.stride + c] : (__bf16)0.0f;
+            }
+            for (int idx = threadIdx.x; idx < 3 * 64 * CI; idx += 256) {
+                const int t = idx / (64 * CI);
+                const int rem = idx % (64 * CI);
+                const int v = rem / CI, c = rem % CI;
+                const int w = w0 + v + t - 1;
+                const bool ok = zy && w >= 0 && w < x.W && (w0 + v) < x.W;
+                sx[t][c][v] = ok ? x.p[(((size_t)z * x.H + y) * x.W + w) * x.stride + c] : (__bf16)0.0f;
+            }
+            __syncthreads();
+            // K = 64 voxels = 2 MFMA steps of 32
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                const int v0 = ks * 32 + (lane >> 4) * 8;
+#pragma unroll
+                for (int q = 0; q < PER_WAVE; ++q) {
+                    const int tile = wave + 4 * q;
+                    if (tile < TILES) {
+                        const int mt = tile / NT, nt = tile % NT;
+                        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&sdy[mt * 16 + (lane & 15)][v0]);
+#pragma unroll
+                        for (int t = 0; t < 3; ++t) {
+                            const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&sx[t][nt * 16 + (lane & 15)][v0]);
+                            acc[t][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t][q], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    // part layout: [chunk][27][CO][CI]; tap = tap9 * 3 + (dx + 1)
+#pragma unroll
+    for (int q = 0; q < PER_WAVE; ++q) {
+        const int tile = wave + 4 * q;
+        if (tile >= TILES) continue;
+        const int mt = tile / NT, nt = tile % NT;
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            float *dst = part + (((size_t)chunk * 27 + tap9 * 3 + t) * CO) * CI;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int co = mt * 16 + (lane >> 4) * 4 + e;
+                const int ci = nt * 16 + (lane & 15);
+                dst[co * CI + ci] = acc[t][q][e];
+            }
+        }
+    }
+}
+
+// out[i] = sum over chunks of part[chunk][i] (fixed order), i < n
+__global__ void reduce_chunks(const float *__restrict__ part, int chunks, int64_t n, float *__restrict__ out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        float s = 0.0f;
+        for (int c = 0; c < chunks; ++c) s += part[(size_t)c * n + i];
+        out[i] = s;
+    }
+}
+
+// Per-channel sums over voxels (bias gradient), partials per block row chunk.
+__global__ void channel_sum_partials(const Act a, int rows_per_chunk, float *__restrict__ part)
+{
+    const int chunk = blockIdx.x;
+    const int nvox = a.D * a.H * a.W;
+    const int v0 = chunk * rows_per_chunk * a.W;
+    const int v1 = min(v0 + rows_per_chunk * a.W, nvox);
+    for (int c = threadIdx.x; c < a.C; c += blockDim.x) {
+        float s = 0.0f;
+        for (int v = v0; v < v1; ++v) s += (float)a.p[(size_t)v * a.stride + c];
+        part[(size_t)chunk * a.C + c] = s;
+    }
+}
+
+// dY *= (Y > 0) in place (ReLU backward; Y is the post-ReLU output)
+__global__ void relu_mask(Act dy, const Act y)
+{
+    const int64_t n = (int64_t)dy.D * dy.H * dy.W * dy.C;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = i / dy.C;
+        const int c = (int)(i % dy.C);
+        if (!((float)y.p[v * y.stride + c] > 0.0f)) dy.p[v * dy.stride + c] = (__bf16)0.0f;
+    }
+}
+
+// 2x2x2 average pooling: out (D/2,H/2,W/2) from in
+__global__ void avgpool2(const Act in, Act out)
+{
+    const int64_t n = (int64_t)out.D * out.H * out.W * out.C;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % out.C);
+        int64_t v = i / out.C;
+        const int x = (int)(v % out.W); v /= out.W;
+        const int y = (int)(v % out.H);
+        const int z = (int)(v / out.H);
+        float s = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int zz = 2 * z + (q >> 2), yy = 2 * y + ((q >> 1) & 1), xx = 2 * x + (q & 1);
+            s += (float)in.p[(((size_t)zz * in.H + yy) * in.W + xx) * in.stride + c];
+        }
+        out.p[(((size_t)z * out.H + y) * out.W + x) * out.stride + c] = (__bf16)(0.125f * s);
+    }
+}
+
+// backward of avgpool2: din = dout(parent) / 8
+__global__ void avgpool2_bwd(const Act dout, Act din)
+{
+    const int64_t n = (int64_t)din.D * din.H * din.W * din.C;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % din.C);
+        int64_t v = i / din.C;
+        const int x = (int)(v % din.W); v /= din.W;
+        const int y = (int)(v % din.H);
+        const int z = (int)(v / din.H);
+        const float g = (float)dout.p[(((size_t)(z / 2) * dout.H + y / 2) * dout.W + x / 2) * dout.stride + c];
+        din.p[(((size_t)z * din.H + y) * din.W + x) * din.stride + c] = (__bf16)(0.125f * g);
+    }
+}
+
+// nearest 2x upsampling: out (2D,2H,2W) from in
+__global__ void upsample2(const Act in, Act out)
+{
+    const int64_t n = (int64_t)out.D * out.H * out.W * out.C;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % out.C);
+        int64_t v = i / out.C;
+        const int x = (int)(v % out.W); v /= out.W;
+        const int y = (int)(v % out.H);
+        const int z = (int)(v / out.H);
+        out.p[(((size_t)z * out.H + y) * out.W + x) * out.stride + c] =
+            in.p[(((size_t)(z / 2) * in.H + y / 2) * in.W + x / 2) * in.stride + c];
+    }
+}
+
+// backward of upsample2: din = sum of the 8 children of dout
+__global__ void upsample2_bwd(const Act dout, Act din)
+{
+    const int64_t n = (int64_t)din.D * din.H * din.W * din.C;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % din.C);
+        int64_t v = i / din.C;
+        const int x = (int)(v % din.W); v /= din.W;
+        const int y = (int)(v % din.H);
+        const int z = (int)(v / din.H);
+        float s = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int zz = 2 * z + (q >> 2), yy = 2 * y + ((q >> 1) & 1), xx = 2 * x + (q & 1);
+            s += (float)dout.p[(((size_t)zz * dout.H + yy) * dout.W + xx) * dout.stride + c];
+        }
+        din.p[(((size_t)z * din.H + y) * din.W + x) * din.stride + c] = (__bf16)s;
+    }
+}
+
+// Pack two FP32 volumes into channels 0 and 1 of a 16-channel BF16 tensor
+// (channels 2..15 zero), scaled by `scale`.
+__global__ void pack_input(const float *__restrict__ x1, const float *__restrict__ x2, int64_t nvox,
+                           float scale, Act out)
+{
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nvox; v += (int64_t)gridDim.x * blockDim.x) {
+        __bf16 *o = out.p + v * out.stride;
+        bf16x8 a = zero8(), b = zero8();
+        a[0] = (__bf16)(scale * x1[v]);
+        a[1] = (__bf16)(scale * x2[v]);
+        *reinterpret_cast<bf16x8 *>(o) = a;
+        *reinterpret_cast<bf16x8 *>(o + 8) = b;
+    }
+}
+
+// Output head (1x1x1 convolution 16 -> 1, in FP32) with the residual on x2:
+//   x0 = x2 + (sum_c w[c] h[v][c] + b) / scale
+__global__ void head_fwd(const Act h, const float *__restrict__ w, const float *__restrict__ b,
+                         const float *__restrict__ x2, float inv_scale, float *__restrict__ x0)
+{
+    const int64_t n = (int64_t)h.D * h.H * h.W;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        float s = b[0];
+        for (int c = 0; c < h.C; ++c) s = fmaf(w[c], (float)h.p[v * h.stride + c], s);
+        x0[v] = x2[v] + s * inv_scale;
+    }
+}
+
+// Head backward: dh[v][c] = w[c] g[v] / scale (BF16), partial sums for dw, db
+__global__ void head_bwd(const Act h, const float *__restrict__ w, const float *__restrict__ g,
+                         float inv_scale, Act dh, int64_t per_block, float *__restrict__ part)
+{
+    __shared__ float sh[17][256];
+    const int64_t n = (int64_t)h.D * h.H * h.W;
+    const int64_t v0 = (int64_t)blockIdx.x * per_block;
+    const int64_t v1 = v0 + per_block < n ? v0 + per_block : n;
+    float acc[17];
+    for (int c = 0; c < 17; ++c) acc[c] = 0.0f;
+    for (int64_t v = v0 + threadIdx.x; v < v1; v += blockDim.x) {
+        const float gv = g[v] * inv_scale;
+        for (int c = 0; c < h.C; ++c) {
+            acc[c] = fmaf((float)h.p[v * h.stride + c], gv, acc[c]);
+            dh.p[v * dh.stride + c] = (__bf16)(w[c] * gv);
+        }
+        acc[16] += gv;
+    }
+    for (int c = 0; c < 17; ++c) sh[c][threadIdx.x] = acc[c];
+    __syncthreads();
+    if (threadIdx.x < 17) {
+        float s = 0.0f;
+        for (int t = 0; t < (int)blockDim.x; ++t) s += sh[threadIdx.x][t];
+        part[(size_t)blockIdx.x * 17 + threadIdx.x] = s;
+    }
+}
+
+// Weights [27][Co][Ci] -> [27][Ci][Co] (backward-data uses the mirrored taps)
+__global__ void transpose_weights(const __bf16 *__restrict__ w, __bf16 *__restrict__ wt, int co, int ci)
+{
+    const int n = 27 * co * ci;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int t = i / (co * ci), r = i % (co * ci);
+        const int o = r / ci, c = r % ci;
+        wt[((size_t)t * ci + c) * co + o] = w[i];
+    }
+}
+
+// MSE: grad = 2 (a - b) / n, partial sums of (a - b)^2 (FP64)
+__global__ void mse_kernel(const float *__restrict__ a, const float *__restrict__ b, int64_t n,
+                           float *__restrict__ grad, double *__restrict__ part)
+{
+    __shared__ double sh[256];
+    double acc = 0.0;
+    const float sc = 2.0f / (float)n;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float dlt = a[i] - b[i];
+        grad[i] = sc * dlt;
+        acc += (double)dlt * dlt;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int t = 0; t < (int)blockDim.x; ++t) s += sh[t];
+        part[blockIdx.x] = s;
+    }
+}
+
+__global__ void sum_partials_f64(const double *__restrict__ part, int n, double scale, double *__restrict__ out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += part[i];
+        *out = s * scale;
+    }
+}
+
+// Adam on FP32 master weights, with a BF16 copy for the kernels (optional)
+__global__ void adam_kernel(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                            float *__restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
+                            float c1, float c2, __bf16 *__restrict__ pb)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        const float upd = lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+        const float np = p[i] - upd;
+        p[i] = np;
+        if (pb) pb[i] = (__bf16)np;
+    }
+}
+
+}  // namespace cvpnn
+
+// ------------------------------------------------------------------ C ABI
+#include "cvp.h"
+
+namespace {
+
+cvpnn::Act act(const cvp_nn_tensor *t)
+{
+    cvpnn::Act a;
+    a.p = reinterpret_cast<__bf16 *>(t->data);
+    a.D = t->d; a.H = t->h; a.W = t->w; a.C = t->channels; a.stride = t->stride;
+    return a;
+}
+
+bool valid(const cvp_nn_tensor *t)
+{
+    return t && t->data && t->d > 0 && t->h > 0 && t->w > 0 && t->channels > 0 &&
+           t->stride >= t->channels && (t->channels % 8) == 0 && (t->stride % 8) == 0 &&
+           (reinterpret_cast<uintptr_t>(t->data) & 15) == 0;
+}
+
+cvp_status st(hipError_t e) { return e == hipSuccess ? CVP_OK : CVP_E_DEVICE; }
+
+int grid_for(int64_t n) { return (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096); }
+
+}  // namespace
+
+extern "C" {
+
+cvp_status cvp_nn_conv3d(const cvp_nn_tensor *in, const void *weight, const float *bias,
+                         const cvp_nn_tensor *out, int32_t relu, int32_t flip, void *stream)
+{
+    if (!valid(in) || !valid(out) || !weight) return CVP_E_INVALID;
+    if (in->d != out->d || in->h != out->h || in->w != out->w) return CVP_E_INVALID;
+    const cvpnn::Act a = act(in), o = act(out);
+    const int rows = in->d * in->h * ((in->w + 63) / 64);
+    const dim3 grid((rows + 3) / 4), block(256);
+    hipStream_t s = (hipStream_t)stream;
+    const __bf16 *w = reinterpret_cast<const __bf16 *>(weight);
+    switch (out->channels) {
+    case 16: hipLaunchKernelGGL(cvpnn::conv3d_kernel<16>, grid, block, 0, s, a, w, bias, o, relu, flip); break;
+    case 32: hipLaunchKernelGGL(cvpnn::conv3d_kernel<32>, grid, block, 0, s, a, w, bias, o, relu, flip); break;
+    case 64: hipLaunchKernelGGL(cvpnn::conv3d_kernel<64>, grid, block, 0, s, a, w, bias, o, relu, flip); break;
+    default: return CVP_E_UNSUPPORTED;
+    }
+    return st(hipGetLastError());
+}
+
+cvp_status cvp_nn_wgrad_workspace(const cvp_nn_tensor *x, const cvp_nn_tensor *dy, int64_t *floats)
+{
+    if (!x || !dy || !floats) return CVP_E_INVALID;
+    const int rows = x->d * x->h;
+    const int chunks = (rows + 63) / 64;
+    *floats = (int64_t)chunks * 27 * dy->channels * x->channels;
+    return CVP_OK;
+}
+
+cvp_status cvp_nn_conv3d_wgrad(const cvp_nn_tensor *x, const cvp_nn_tensor *dy, float *dw, float *work,
+                               int64_t work_floats, void *stream)
+{
+    if (!valid(x) || !valid(dy) || !dw || !work) return CVP_E_INVALID;
+    int64_t need = 0;
+    cvp_nn_wgrad_workspace(x, dy, &need);
+    if (work_floats < need) return CVP_E_INVALID;
+    const cvpnn::Act a = act(x), g = act(dy);
+    const int rows = x->d * x->h, rpc = 64, chunks = (rows + rpc - 1) / rpc;
+    const dim3 grid(chunks, 9), block(256);
+    hipStream_t s = (hipStream_t)stream;
+    const int co = dy->channels, ci = x->channels;
+#define WG(CO_, CI_) hipLaunchKernelGGL((cvpnn::conv3d_wgrad_kernel<CO_, CI_>), grid, block, 0, s, a, g, rpc, work)
+    if (co == 16 && ci == 16) WG(16, 16);
+    else if (co == 16 && ci == 32) WG(16, 32);
+    else if (co == 32 && ci == 16) WG(32, 16);
+    else if (co == 32 && ci == 32) WG(32, 32);
+    else if (co == 32 && ci == 64) WG(32, 64);
+    else if (co == 64 && ci == 32) WG(64, 32);
+    else if (co == 64 && ci == 64) WG(64, 64);
+    else if (co == 16 && ci == 64) WG(16, 64);
+    else return CVP_E_UNSUPPORTED;
+#undef WG
+    const int64_t n = (int64_t)27 * co * ci;
+    hipLaunchKernelGGL(cvpnn::reduce_chunks, dim3(grid_for(n)), dim3(256), 0, s, work, chunks, n, dw);
+    return st(hipGetLastError());
+}
+
+cvp_status cvp_nn_channel_sum(const cvp_nn_tensor *a, float *out, float *work, int64_t work_floats,
+                              void *stream)
+{
+    if (!valid(a) || !out || !work) return CVP_E_INVALID;
+    const int rows = a->d * a->h, rpc = 16, chunks = (rows + rpc - 1) / rpc;
+    if (work_floats < (int64_t)chunks * a->channels) return CVP_E_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(cvpnn::channel_sum_partials, dim3(chunks), dim3(64), 0, s, act(a), rpc, work);
+    hipLaunchKernelGGL(cvpnn::reduce_chunks, dim3(1), dim3(64), 0, s, work, chunks, (int64_t)a->channels, out);
+    return st(hipGetLastError());
+}
+
+cvp_status cvp_nn_relu_mask(const cvp_nn_tensor *dy, const cvp_nn_tensor *y, void *stream)
+{
+    if (!valid(dy) || !valid(y)) return CVP_E_INVALID;
+    const int64_t n = (int64_t)dy->d * dy->h * dy->w * dy->channels;
+    hipLaunchKernelGGL(cvpnn::relu_mask, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, act(dy), act(y));
+    return st(hipGetLastError());
+}
+
+static cvp_status resample(int kind, const cvp_nn_tensor *a, const cvp_nn_tensor *b, void *stream)
+{
+    if (!valid(a) || !valid(b) || a->channels != b->channels) return CVP_E_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    const cvp_nn_tensor *big = (kind == 0 || kind == 3) ? a : b;    // fine-resolution operand
+    const cvp_nn_tensor *small = big == a ? b : a;
+    if (big->d != 2 * small->d || big->h != 2 * small->h || big->w != 2 * small->w) return CVP_E_INVALID;
+    const int64_t nb = (int64_t)big->d * big->h * big->w * big->channels;
+    const int64_t ns = nb / 8;
+    switch (kind) {
+    case 0: hipLaunchKernelGGL(cvpnn::avgpool2, dim3(grid_for(ns)), dim3(256), 0, s, act(a), act(b)); break;
+    case 1: hipLaunchKernelGGL(cvpnn::avgpool2_bwd, dim3(grid_for(nb)), dim3(256), 0, s, act(a), act(b)); break;
+    case 2: hipLaunchKernelGGL(cvpnn::upsample2, dim3(grid_for(nb)), dim3(256), 0, s, act(a), act(b)); break;
+    default: hipLaunchKernelGGL(cvpnn::upsample2_bwd, dim3(grid_for(ns)), dim3(256), 0, s, act(a), act(b)); break;
+    }
+    return st(hipGetLastError());
+}
+
+cvp_status cvp_nn_avgpool2(const cvp_nn_tensor *in, const cvp_nn_tensor *out, void *stream) { return resample(0, in, out, stream); }
+cvp_status cvp_nn_avgpool2_bwd(const cvp_nn_tensor *dout, const cvp_nn_tensor *din, void *stream) { return resample(1, dout, din, stream); }
+cvp_status cvp_nn_upsample2(const cvp_nn_tensor *in, const cvp_nn_tensor *out, void *stream) { return resample(2, in, out, stream); }
+cvp_status cvp_nn_upsample2_bwd(const cvp_nn_tensor *dout, const cvp_nn_tensor *din, void *stream) { return resample(3, dout, din, stream); }
+
+cvp_status cvp_nn_transpose_weights(const void *w, void *wt, int32_t co, int32_t ci, void *stream)
+{
+    if (!w || !wt || co <= 0 || ci <= 0) return CVP_E_INVALID;
+    const int64_t n = (int64_t)27 * co * ci;
+    hipLaunchKernelGGL(cvpnn::transpose_weights, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream,
+                       reinterpret_cast<const __bf16 *>(w), reinterpret_cast<__bf16 *>(wt), co, ci);
+    return st(hipGetLastError());
+}
+
+cvp_status cvp_nn_pack_input(const float *x1, const float *x2, float scale, const cvp_nn_tensor *out, void *stream)
+{
+    if (!x1 || !x2 || !valid(out) || out->channels != 16) return CVP_E_INVALID;
+    const int64_t n = (int64_t)out->d * out->h * out->w;
+    hipLaunchKernelGGL(cvpnn::pack_input, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, x1, x2, n, scale, act(out));
+    return st(hipGetLastError());
+}
+
+cvp_status cvp_nn_head(const cvp_nn_tensor *h, const float *w, const float *b, const float *x2, float scale,
+                       float *x0, void *stream)
+{
+    if (!valid(h) || h->channels > 16 || !w || !b || !x2 || !x0 || !(scale > 0)) return CVP_E_INVALID;
+    const int64_t n = (int64_t)h->d * h->h * h->w;
+    hipLaunchKernelGGL(cvpnn::head_fwd, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, act(h), w, b, x2,
+                       1.0f / scale, x0);
+    return st(hipGetLastError());
+}
+
+cvp_status cvp_nn_head_bwd(const cvp_nn_tensor *h, const float *w, const float *g, float scale,
+                           const cvp_nn_tensor *dh, float *dwb /*17*/, float *work, int64_t work_floats,
+                           void *stream)
+{
+    if (!valid(h) || !valid(dh) || h->channels > 16 || !w || !g || !dwb || !work || !(scale > 0)) return CVP_E_INVALID;
+    const int64_t n = (int64_t)h->d * h->h * h->w;
+    const int64_t per = 4096;
+    const int blocks = (int)((n + per - 1) / per);
+    if (work_floats < (int64_t)blocks * 17) return CVP_E_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(cvpnn::head_bwd, dim3(blocks), dim3(256), 0, s, act(h), w, g, 1.0f / scale, act(dh), per, work);
+    hipLaunchKernelGGL(cvpnn::reduce_chunks, dim3(1), dim3(64), 0, s, work, blocks, (int64_t)17, dwb);
+    return st(hipGetLastError());
+}
+
+cvp_status cvp_nn_mse(const float *a, const float *b, int64_t n, float *grad, double *loss, double *work,
+                      int64_t work_doubles, void *stream)
+{
+    if (!a || !b || !grad || !loss || !work || n <= 0 || work_doubles < 1024) return CVP_E_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(cvpnn::mse_kernel, dim3(1024), dim3(256), 0, s, a, b, n, grad, work);
+    hipLaunchKernelGGL(cvpnn::sum_partials_f64, dim3(1), dim3(64), 0, s, work, 1024, 1.0 / (double)n, loss);
+    return st(hipGetLastError());
+}
+
+cvp_status cvp_nn_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float beta1,
+                       float beta2, float eps, int32_t step, void *p_bf16, void *stream)
+{
+    if (!p || !g || !m || !v || n <= 0 || step < 1) return CVP_E_INVALID;
+    const float c1 = 1.0f / (1.0f - powf(beta1, (float)step));
+    const float c2 = 1.0f / (1.0f - powf(beta2, (float)step));
+    hipLaunchKernelGGL(cvpnn::adam_kernel, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, p, g, m, v, n, lr,
+                       beta1, beta2, eps, c1, c2, reinterpret_cast<__bf16 *>(p_bf16));
+    return st(hipGetLastError());
+}
+
+}  // extern "C"
