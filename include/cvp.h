@@ -225,6 +225,9 @@ cvp_status cvp_nn_avgpool2(const cvp_nn_tensor *in, const cvp_nn_tensor *out, vo
 cvp_status cvp_nn_avgpool2_bwd(const cvp_nn_tensor *dout, const cvp_nn_tensor *din, void *stream);
 cvp_status cvp_nn_upsample2(const cvp_nn_tensor *in, const cvp_nn_tensor *out, void *stream);
 cvp_status cvp_nn_upsample2_bwd(const cvp_nn_tensor *dout, const cvp_nn_tensor *din, void *stream);
+/* out = a + b (BF16, same shape) */
+cvp_status cvp_nn_add(const cvp_nn_tensor *a, const cvp_nn_tensor *b, const cvp_nn_tensor *out,
+                      void *stream);
 /* wt[tap][ci][co] = w[tap][co][ci] (BF16) */
 cvp_status cvp_nn_transpose_weights(const void *w, void *wt, int32_t cout, int32_t cin, void *stream);
 /* out channels 0, 1 = scale * x1, scale * x2 (FP32 volumes); channels 2..15 = 0 */
@@ -244,6 +247,20 @@ cvp_status cvp_nn_mse(const float *a, const float *b, int64_t n, float *grad, do
 cvp_status cvp_nn_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr,
                        float beta1, float beta2, float eps, int32_t step, void *p_bf16,
                        void *stream);
+
+/*
+ * Synthetic inputs on the device (training data of the warm start; not part
+ * of the operator).  cvp_synth_ellipsoids: vol[k][j][i] = sum of mu over the
+ * ellipsoids containing the voxel centre ((i - (n1-1)/2) a1, ...); d_params is
+ * a device array of n x 16 doubles (centre, semi-axes, row-major rotation
+ * body -> world, mu), evaluated in FP64 without contraction.
+ * cvp_synth_add_gaussian: out[i] += sigma * N(0,1), Philox4x32-10 with
+ * counter i/4 and key seed, Box-Muller.
+ */
+cvp_status cvp_synth_ellipsoids(const double *d_params, int32_t n, const int32_t dims[3],
+                                const double voxel_mm[3], float *d_vol, void *hip_stream);
+cvp_status cvp_synth_add_gaussian(float *d_out, int64_t n, float sigma, uint64_t seed,
+                                  void *hip_stream);
 
 /* Geometry queries (host-side, no device work). */
 cvp_status cvp_geometry_sizes(const cvp_geometry *g, int64_t *n_voxels,

@@ -314,6 +314,17 @@ __global__ void upsample2_bwd(const Act dout, Act din)
     }
 }
 
+// out = a + b (BF16 tensors of the same shape; slices allowed)
+__global__ void add_kernel(const Act a, const Act b, Act out)
+{
+    const int64_t n = (int64_t)out.D * out.H * out.W * out.C;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = i / out.C;
+        const int c = (int)(i % out.C);
+        out.p[v * out.stride + c] = (__bf16)((float)a.p[v * a.stride + c] + (float)b.p[v * b.stride + c]);
+    }
+}
+
 // Pack two FP32 volumes into channels 0 and 1 of a 16-channel BF16 tensor
 // (channels 2..15 zero), scaled by `scale`.
 __global__ void pack_input(const float *__restrict__ x1, const float *__restrict__ x2, int64_t nvox,
@@ -556,6 +567,16 @@ cvp_status cvp_nn_avgpool2(const cvp_nn_tensor *in, const cvp_nn_tensor *out, vo
 cvp_status cvp_nn_avgpool2_bwd(const cvp_nn_tensor *dout, const cvp_nn_tensor *din, void *stream) { return resample(1, dout, din, stream); }
 cvp_status cvp_nn_upsample2(const cvp_nn_tensor *in, const cvp_nn_tensor *out, void *stream) { return resample(2, in, out, stream); }
 cvp_status cvp_nn_upsample2_bwd(const cvp_nn_tensor *dout, const cvp_nn_tensor *din, void *stream) { return resample(3, dout, din, stream); }
+
+cvp_status cvp_nn_add(const cvp_nn_tensor *a, const cvp_nn_tensor *b, const cvp_nn_tensor *out, void *stream)
+{
+    if (!valid(a) || !valid(b) || !valid(out) || a->channels != out->channels || b->channels != out->channels ||
+        a->d != out->d || a->h != out->h || a->w != out->w || b->d != out->d || b->h != out->h || b->w != out->w)
+        return CVP_E_INVALID;
+    const int64_t n = (int64_t)out->d * out->h * out->w * out->channels;
+    hipLaunchKernelGGL(cvpnn::add_kernel, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, act(a), act(b), act(out));
+    return st(hipGetLastError());
+}
 
 cvp_status cvp_nn_transpose_weights(const void *w, void *wt, int32_t co, int32_t ci, void *stream)
 {

@@ -77,23 +77,20 @@ def config_batch(seed: int = 41, n_problems: int = 16):
     return out
 
 
-def ellipsoid_phantom(vol_dims, voxel_mm, n_ellipsoids, seed, semi_axes_mm=(3.0, 25.0),
-                      mu_range=(0.001, 0.02), noise_frac=0.0, dtype=np.float32):
-    """Sum of random ellipsoids, sampled at voxel centres.
+def draw_ellipsoids(vol_dims, voxel_mm, n_ellipsoids, seed, semi_axes_mm=(3.0, 25.0),
+                    mu_range=(0.001, 0.02)):
+    """Random ellipsoids as an (n, 16) float64 array: centre (3), semi-axes (3),
+    rotation matrix R row-major (9, body frame -> world), attenuation (1).
 
     Centres are uniform in a ball of radius 0.45 * (smallest volume edge),
     semi-axes uniform in semi_axes_mm, orientation uniform (random rotation
-    from a normalised Gaussian quaternion), attenuation uniform in mu_range;
-    a voxel gets the sum of mu over the ellipsoids containing its centre.
-    noise_frac > 0 adds U[0, noise_frac * max mu) per voxel.
-    Returned layout: [n3][n2][n1] (x1 fastest)."""
+    from a normalised Gaussian quaternion), attenuation uniform in mu_range."""
     n1, n2, n3 = (vol_dims,) * 3 if np.isscalar(vol_dims) else vol_dims
     a = (voxel_mm,) * 3 if np.isscalar(voxel_mm) else voxel_mm
     rng = np.random.Generator(np.random.PCG64(seed))
-    ax = [(np.arange(n, dtype=np.float64) - (n - 1) / 2.0) * av for n, av in zip((n1, n2, n3), a)]
-    vol = np.zeros((n3, n2, n1), dtype=np.float64)
     radius = 0.45 * min(n1 * a[0], n2 * a[1], n3 * a[2])
-    for _ in range(n_ellipsoids):
+    out = np.zeros((n_ellipsoids, 16))
+    for e in range(n_ellipsoids):
         while True:
             c = rng.uniform(-radius, radius, size=3)
             if np.dot(c, c) <= radius * radius:
@@ -106,6 +103,23 @@ def ellipsoid_phantom(vol_dims, voxel_mm, n_ellipsoids, seed, semi_axes_mm=(3.0,
                       [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
                       [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]])
         mu = rng.uniform(mu_range[0], mu_range[1])
+        out[e, 0:3], out[e, 3:6], out[e, 6:15], out[e, 15] = c, sa, R.ravel(), mu
+    return out, rng
+
+
+def ellipsoid_phantom(vol_dims, voxel_mm, n_ellipsoids, seed, semi_axes_mm=(3.0, 25.0),
+                      mu_range=(0.001, 0.02), noise_frac=0.0, dtype=np.float32):
+    """Sum of random ellipsoids (draw_ellipsoids), sampled at voxel centres: a
+    voxel gets the sum of mu over the ellipsoids containing its centre.
+    noise_frac > 0 adds U[0, noise_frac * max mu) per voxel.
+    Returned layout: [n3][n2][n1] (x1 fastest)."""
+    n1, n2, n3 = (vol_dims,) * 3 if np.isscalar(vol_dims) else vol_dims
+    a = (voxel_mm,) * 3 if np.isscalar(voxel_mm) else voxel_mm
+    ells, rng = draw_ellipsoids(vol_dims, voxel_mm, n_ellipsoids, seed, semi_axes_mm, mu_range)
+    ax = [(np.arange(n, dtype=np.float64) - (n - 1) / 2.0) * av for n, av in zip((n1, n2, n3), a)]
+    vol = np.zeros((n3, n2, n1), dtype=np.float64)
+    for e in ells:
+        c, sa, R, mu = e[0:3], e[3:6], e[6:15].reshape(3, 3), e[15]
         rmax = sa.max()
         lo = [np.searchsorted(ax[d], c[d] - rmax) for d in range(3)]
         hi = [np.searchsorted(ax[d], c[d] + rmax, side="right") for d in range(3)]
