@@ -71,8 +71,8 @@ def lib():
 
 
 def _register_extra(L):
-    """Signatures of the solver / batch entry points (present in the same
-    library)."""
+    """Signatures of the solver, batch and input-generation entry points
+    (present in the same library)."""
     vp = ctypes.c_void_p
     st = ctypes.c_int
     specs = {
@@ -84,6 +84,9 @@ def _register_extra(L):
         "cvp_cgls_start": ([vp, ctypes.POINTER(OptionsC), vp, vp, vp, vp, vp, vp, vp, vp], st),
         "cvp_cgls_iterate": ([vp, ctypes.POINTER(OptionsC), ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp], st),
         "cvp_dot": ([vp, vp, ctypes.c_int64, vp, vp, vp], st),
+        "cvp_synth_ellipsoids": ([vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
+                                  vp, vp], st),
+        "cvp_synth_add_gaussian": ([vp, ctypes.c_int64, ctypes.c_float, ctypes.c_uint64, vp], st),
     }
     for name, (args, res) in specs.items():
         if hasattr(L, name):

@@ -21,7 +21,8 @@ HISTORY = 4096
 class CGLS:
     def __init__(self, geom: Geometry, opts: Options, b, x0=None):
         _check_tensor(b, geom.proj_shape, "b")
-        self.geom, self.opts, self.b = geom, opts, b
+        self.geom, self.opts = geom, opts
+        self.b = b
         dev = b.device
         self.x = torch.zeros(geom.vol_shape, dtype=torch.float32, device=dev) if x0 is None \
             else x0.detach().clone().contiguous()
@@ -87,26 +88,39 @@ class CGLS:
     def breakdown(self):
         return bool(self.scalars()[7] != 0.0)
 
-    def run(self, tol=1e-3, max_iter=400, per_graph=20, use_graph=True):
+    def reset(self, b=None, x0=None):
+        """New right-hand side and/or starting point in the same buffers (a
+        captured graph stays valid)."""
+        if b is not None:
+            self.b.copy_(b)
+        if x0 is None:
+            self.x.zero_()
+        else:
+            self.x.copy_(x0)
+
+    def run(self, tol=1e-3, max_iter=400, per_graph=20, use_graph=True, gamma_ref=None, start=True):
         """Iterate until rho_k <= tol (checked every per_graph iterations) or
-        max_iter; returns (iterations, seconds, rho history).  Time counts
-        from the start call to the replay boundary where rho <= tol."""
+        max_iter.  rho_k = |s_k| / sqrt(gamma_ref), by default gamma_ref =
+        |s_0|^2 of this run.  Returns (iterations, seconds, rho history); time
+        counts from the start call to the replay boundary where rho <= tol."""
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        self.start()
+        if start:
+            self.start()
         if use_graph and (self.graph is None or self.graph_iters != per_graph):
             self.capture(per_graph)
         done = 0
-        while done < max_iter:
+        while True:
+            g = self.gamma_history()      # synchronises
+            ref = g[0] if gamma_ref is None else gamma_ref
+            rho = np.sqrt(np.maximum(g, 0.0) / ref)
+            if rho[-1] <= tol or self.breakdown() or done >= max_iter:
+                break
             if use_graph:
                 self.replay()
             else:
                 self.iterate(per_graph)
             done += per_graph
-            rho = self.rho()          # synchronises
-            if rho[-1] <= tol or self.breakdown():
-                break
         t1 = time.perf_counter()
-        rho = self.rho()
         hit = np.nonzero(rho <= tol)[0]
-        return (int(hit[0]) if len(hit) else done), t1 - t0, rho
+        return (int(hit[0]) if len(hit) else len(rho) - 1), t1 - t0, rho

@@ -154,3 +154,51 @@ def uniform_volume(shape, seed, dtype=np.float32):
 def gaussian_noise(shape, sigma, seed, dtype=np.float32):
     rng = np.random.Generator(np.random.PCG64(seed))
     return (sigma * rng.standard_normal(size=shape)).astype(dtype)
+
+
+# ---------------------------------------------------------------- Philox noise
+# Host definition of the counter-based Gaussian noise that the GPU generator
+# adds (same counters and key), used to check it.  Philox4x32-10 as published
+# by Salmon, Moraes, Dror and Shaw (SC 2011): ten rounds of two 32x32->64-bit
+# multiplications with the key bumped by the Weyl constants between rounds.
+_PH_M = (0xD2511F53, 0xCD9E8D57)
+_PH_W = (0x9E3779B9, 0xBB67AE85)
+
+
+def philox4x32_10(counters, key):
+    """counters: (n, 4) integer array (uint32 values); key: (k0, k1).
+    Returns the (n, 4) uint32 outputs."""
+    c = [np.asarray(counters, dtype=np.uint64)[:, e].copy() for e in range(4)]
+    k0, k1 = int(key[0]) & 0xFFFFFFFF, int(key[1]) & 0xFFFFFFFF
+    mask = np.uint64(0xFFFFFFFF)
+    for _ in range(10):
+        p0 = np.uint64(_PH_M[0]) * c[0]
+        p1 = np.uint64(_PH_M[1]) * c[2]
+        c = [(p1 >> np.uint64(32)) ^ c[1] ^ np.uint64(k0), p1 & mask,
+             (p0 >> np.uint64(32)) ^ c[3] ^ np.uint64(k1), p0 & mask]
+        k0 = (k0 + _PH_W[0]) & 0xFFFFFFFF
+        k1 = (k1 + _PH_W[1]) & 0xFFFFFFFF
+    return np.stack(c, axis=1).astype(np.uint32)
+
+
+def philox_gaussian(n: int, seed: int) -> np.ndarray:
+    """Standard normal draws z[i], i < n: counter (i // 4, hi, 0, 0), key =
+    (seed low, seed high); Box-Muller on output pairs (0,1) and (2,3) with
+    u = (float32(x) + 0.5) * 2^-32 formed in float32, as the GPU forms them;
+    the transcendental functions in float64."""
+    nq = (n + 3) // 4
+    q = np.arange(nq, dtype=np.uint64)
+    ctr = np.zeros((nq, 4), dtype=np.uint64)
+    ctr[:, 0] = q & np.uint64(0xFFFFFFFF)
+    ctr[:, 1] = q >> np.uint64(32)
+    out = philox4x32_10(ctr, (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF))
+    scale = np.float32(2.3283064365386963e-10)
+    u = (out.astype(np.float32) + np.float32(0.5)) * scale          # float32 arithmetic
+    z = np.empty((nq, 4))
+    for h in range(2):
+        u1 = u[:, 2 * h].astype(np.float64)
+        ang = (np.float32(6.283185307179586) * u[:, 2 * h + 1]).astype(np.float64)
+        r = np.sqrt(-2.0 * np.log(u1))
+        z[:, 2 * h] = r * np.cos(ang)
+        z[:, 2 * h + 1] = r * np.sin(ang)
+    return z.reshape(-1)[:n]

@@ -1,0 +1,188 @@
+"""Learned CGLS warm start on the GPU.
+
+Training data: seeded random-ellipsoid phantoms voxelised on the GPU,
+projected by relaxed CVP (with elevation correction), Gaussian noise of
+sigma = noise_frac * rms of the clean projections, then the first two CGLS
+iterates from zero.  The U-Net maps the two iterates to a warm start x0 (a
+residual on the second iterate); the training target is the phantom.
+Evaluation runs CGLS to rho <= tol from zero and from the warm start, with
+rho = |A^T (b - A x)| / |A^T b| (the same denominator for both); the warm
+start's cost includes its two initial iterations and the network inference.
+Plain CGLS from zero is the fallback and the judge of the residual.
+
+Run as a module for the held-out experiment:
+  python -m paper_2110_09841_amd.warmstart --train 2000 --eval 200
+"""
+import argparse
+import ctypes
+import json
+import time
+
+import numpy as np
+import torch
+
+from . import _lib, synth
+from .cgls import CGLS
+from .cvp import Geometry, Options, project
+from .unet import UNet
+
+HELD_OUT_SEED0 = 100000
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Pipeline:
+    def __init__(self, params=None, n_ellipsoids=16, noise_frac=0.01,
+                 opts=Options(variant="relaxed", ec=True), per_graph=5):
+        self.params = params or synth.config_warmstart()
+        self.geom = Geometry(self.params)
+        self.opts = opts
+        self.n_ellipsoids = n_ellipsoids
+        self.noise_frac = noise_frac
+        self.shape = self.geom.vol_shape
+        self.b = torch.empty(self.geom.proj_shape, dtype=torch.float32, device="cuda")
+        self.solver = CGLS(self.geom, opts, self.b)
+        self.per_graph = per_graph
+        self.solver.capture(per_graph)          # captured once, outside any timing
+        self._dims = (ctypes.c_int32 * 3)(*self.params["vol_dims"])
+        self._vox = (ctypes.c_double * 3)(*self.params["voxel_mm"])
+
+    def phantom(self, seed):
+        """Ellipsoid phantom of draw_ellipsoids(seed), voxelised on the GPU."""
+        ells, _ = synth.draw_ellipsoids(self.params["vol_dims"], self.params["voxel_mm"], self.n_ellipsoids, seed)
+        d = torch.from_numpy(ells).cuda()
+        x = torch.empty(self.shape, dtype=torch.float32, device="cuda")
+        _lib.check(_lib.lib().cvp_synth_ellipsoids(ctypes.c_void_p(d.data_ptr()), len(ells), self._dims, self._vox,
+                                                   ctypes.c_void_p(x.data_ptr()), _stream()))
+        return x
+
+    def measure(self, x_true, seed, out=None):
+        """b = A x_true + N(0, (noise_frac * rms(A x_true))^2)."""
+        b = project(x_true, self.geom, self.opts, out=out)
+        rms = float(torch.sqrt((b.double() ** 2).mean()))
+        _lib.check(_lib.lib().cvp_synth_add_gaussian(ctypes.c_void_p(b.data_ptr()), b.numel(),
+                                                     ctypes.c_float(self.noise_frac * rms),
+                                                     ctypes.c_uint64(1000003 * seed + 17), _stream()))
+        return b
+
+    def iterates(self, b):
+        """The first two CGLS iterates from zero (copies)."""
+        self.solver.reset(b)
+        self.solver.start()
+        self.solver.iterate(1)
+        x1 = self.solver.x.clone()
+        self.solver.iterate(1)
+        return x1, self.solver.x.clone()
+
+    def sample(self, seed):
+        x_true = self.phantom(seed)
+        b = self.measure(x_true, seed, out=self.b)
+        x1, x2 = self.iterates(b)
+        return x1, x2, x_true
+
+    def dataset(self, seeds, log=None):
+        out = []
+        for n, s in enumerate(seeds):
+            out.append(self.sample(s))
+            if log and (n + 1) % 200 == 0:
+                torch.cuda.synchronize()
+                log("generated %d / %d" % (n + 1, len(seeds)))
+        return out
+
+    def train(self, net: UNet, data, epochs=2, lr=1e-3, seed=0, log=None):
+        """Adam on the MSE to the phantom, one sample per step, shuffled each
+        epoch.  Returns the mean sampled loss per epoch."""
+        rng = np.random.default_rng(seed)
+        losses = []
+        for ep in range(epochs):
+            sampled = []
+            for n, i in enumerate(rng.permutation(len(data))):
+                loss = net.train_step(*data[i], lr=lr)
+                if n % 50 == 0:
+                    sampled.append(float(loss))      # synchronises
+            losses.append(float(np.mean(sampled)))
+            if log:
+                log("epoch %d: mean sampled loss %.4e" % (ep, losses[-1]))
+        return losses
+
+    def evaluate(self, net: UNet, seed, tol=1e-3, max_iter=400):
+        """Iterations and seconds to rho <= tol from zero and from the warm
+        start on the held-out phantom of this seed."""
+        x_true = self.phantom(seed)
+        b = self.measure(x_true, seed).clone()
+        self.solver.reset(b)
+        it0, t0, rho0 = self.solver.run(tol=tol, max_iter=max_iter, per_graph=self.per_graph)
+        gamma_ref = float(self.solver.gamma_history()[0])        # |A^T b|^2
+        err0 = float(torch.linalg.vector_norm(self.solver.x - x_true) / torch.linalg.vector_norm(x_true))
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        x1, x2 = self.iterates(b)
+        x0 = net.forward(x1, x2)
+        self.solver.reset(None, x0)
+        itw, _, rhow = self.solver.run(tol=tol, max_iter=max_iter, per_graph=self.per_graph, gamma_ref=gamma_ref)
+        t_warm = time.perf_counter() - ts
+        errw = float(torch.linalg.vector_norm(self.solver.x - x_true) / torch.linalg.vector_norm(x_true))
+        return dict(seed=seed, zero_iters=it0, zero_s=t0, warm_iters=itw + 2, warm_s=t_warm,
+                    rho0_warm=float(rhow[0]), reached_zero=bool(rho0[it0] <= tol),
+                    reached_warm=bool(rhow[itw] <= tol), err_zero=err0, err_warm=errw)
+
+
+def main():
+    ap = argparse.ArgumentParser(description="learned CGLS warm start: train, then evaluate on held-out phantoms")
+    ap.add_argument("--train", type=int, default=2000, help="training phantoms (seeds 0 .. n-1)")
+    ap.add_argument("--eval", type=int, default=200, help="held-out phantoms (seeds 100000 ..)")
+    ap.add_argument("--epochs", type=int, default=2)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--tol", type=float, default=1e-3)
+    ap.add_argument("--max-iter", type=int, default=400)
+    ap.add_argument("--out", default=None, help="write the JSON record here as well")
+    args = ap.parse_args()
+
+    def log(msg):
+        print(msg, flush=True)
+
+    torch.cuda.set_device(0)
+    pipe = Pipeline()
+    net = UNet(pipe.shape, seed=1)
+    t0 = time.perf_counter()
+    data = pipe.dataset(range(args.train), log=log)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    losses = pipe.train(net, data, epochs=args.epochs, lr=args.lr, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del data
+    torch.cuda.empty_cache()
+    rows = []
+    for n in range(args.eval):
+        rows.append(pipe.evaluate(net, HELD_OUT_SEED0 + n, tol=args.tol, max_iter=args.max_iter))
+        if (n + 1) % 10 == 0:
+            r = rows[-1]
+            log("eval %d / %d: zero %d it %.3f s, warm %d it %.3f s" % (n + 1, args.eval, r["zero_iters"], r["zero_s"],
+                                                                      r["warm_iters"], r["warm_s"]))
+
+    def stat(key):
+        v = np.array([r[key] for r in rows], dtype=np.float64)
+        return {"mean": float(v.mean()), "median": float(np.median(v)), "min": float(v.min()), "max": float(v.max())}
+
+    rec = {"workload": "warmstart_128c_180v", "train_phantoms": args.train, "eval_phantoms": args.eval,
+           "epochs": args.epochs, "lr": args.lr, "tol": args.tol, "per_graph": pipe.per_graph,
+           "data_s": t_data, "train_s": t_train, "epoch_loss": losses,
+           "zero_iters": stat("zero_iters"), "warm_iters": stat("warm_iters"),
+           "zero_s": stat("zero_s"), "warm_s": stat("warm_s"),
+           "err_zero": stat("err_zero"), "err_warm": stat("err_warm"), "rho0_warm": stat("rho0_warm"),
+           "reached_zero": int(sum(r["reached_zero"] for r in rows)),
+           "reached_warm": int(sum(r["reached_warm"] for r in rows)),
+           "warm_faster": int(sum(r["warm_s"] < r["zero_s"] for r in rows))}
+    line = json.dumps(rec)
+    print(line, flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(line + "\n")
+
+
+if __name__ == "__main__":
+    main()
