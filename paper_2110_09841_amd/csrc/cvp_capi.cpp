@@ -83,7 +83,8 @@ size_t project_lds_bytes(int U, int N, int n2, int pmax)
 {
     const size_t npad = (size_t)(N | 1);
     (void)pmax;   // piece records live in registers
-    return (size_t)kWaves * U * npad * 4 + (size_t)(2 * n2 + 1 + kBlock + 4) * 4 + 16;
+    // 64-bit band image, row tables, prefix-sum scratch, per-wave maxima
+    return (size_t)U * npad * 8 + (size_t)(2 * n2 + 1 + kBlock + kWaves) * 4 + 16;
 }
 
 size_t backproject_lds_bytes(int gw, int pmax, int winCap)
@@ -93,7 +94,7 @@ size_t backproject_lds_bytes(int gw, int pmax, int winCap)
 }
 
 // Projection: bands of U detector columns, U as large as the LDS budget
-// allows (per-wave bins of U x N, row tables, per-wave piece records).
+// allows (a 64-bit band image of U x N, row tables).
 bool plan_projection(int N, int n2, int M, int nviews, int pmax, ProjLaunch &L)
 {
     const size_t fixed = project_lds_bytes(0, N, n2, pmax);
@@ -281,6 +282,16 @@ cvp_status cvp_geometry_from_views(const cvp_geometry_desc *d, cvp_geometry **ou
     G.views = g->d_views;
     G.sigma = nullptr;
     G.raw_volume = 0;
+    {
+        // Any pixel's summed weight per unit |mu| is at most its solid angle
+        // (<= b1 b2 / f^2) times the integral of r^-2 r^2 dr (or of r^2 dr for
+        // raw volumes) over the source distances the volume spans; 64 covers
+        // the approximations of the cut volumes with a wide margin.
+        const double om = b1 * b2 / (f * f);
+        const double r0 = Dmin, r1 = std::hypot(D + rmax, zabs);
+        G.wsum_bound = 64.0 * om * (r1 - r0);
+        G.wsum_bound_raw = 64.0 * om * (r1 * r1 * r1 - r0 * r0 * r0) / 3.0;
+    }
 
     const int pmax = pieces <= 4 ? 4 : 8;
     g->zabs = zabs;

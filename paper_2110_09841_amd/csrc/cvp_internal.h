@@ -34,6 +34,9 @@ struct DevGeom {
     const ViewGeom *views;     // device, [nviews]
     const float *sigma;        // device, [N][M] pixel factors (nullptr: 1)
     int raw_volume;            // weight = cut volume (no 1/r^2)
+    // Bounds on any pixel's weight sum per unit |mu| (with and without the
+    // 1/r^2 factor), used to scale the projection's fixed-point sums.
+    double wsum_bound, wsum_bound_raw;
 };
 
 struct ProjLaunch {
