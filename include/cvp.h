@@ -116,8 +116,11 @@ void cvp_geometry_destroy(cvp_geometry *g);
 /*
  * b = A x.  d_vol: [n3][n2][n1] float32 input; d_proj: [n_views][rows][cols]
  * float32 output, overwritten.  Projection is voxel driven; each workgroup
- * owns a band of detector columns of one view and sums into LDS, so there are
- * no global atomics and results are bitwise reproducible.
+ * owns a band of detector columns of one view and sums into LDS in 64-bit
+ * fixed point, with a scale chosen from the largest |mu| it reads, so there
+ * are no global atomics and the sums do not depend on the order of the
+ * additions: results are bitwise reproducible for a given launch plan.  A
+ * non-finite input value makes every band that reads it NaN.
  * Errors: CVP_E_INVALID (null pointer or option), CVP_E_DEVICE (launch).
  */
 cvp_status cvp_project(const cvp_geometry *g, const cvp_options *opts,
@@ -136,8 +139,9 @@ cvp_status cvp_backproject(const cvp_geometry *g, const cvp_options *opts,
  * persistent launch per direction.  A fixed grid of workgroups (as many as
  * fit on the GPU) takes work items from an atomic counter until all problems
  * are done, largest items first; every problem's result equals its
- * single-problem result bitwise (each item is summed by one workgroup in a
- * fixed order).  The per-call pointer setup and the counter reset are one
+ * single-problem result bitwise (each item is summed by one workgroup, in
+ * fixed point for the projection and in a fixed order for the
+ * backprojection).  The per-call pointer setup and the counter reset are one
  * tiny kernel on the same stream, so a batched call can be graph-captured.
  * n: 1..32 geometries on the same device; the batch keeps pointers to them
  * (they must outlive it) and owns small device tables.
@@ -261,6 +265,30 @@ cvp_status cvp_synth_ellipsoids(const double *d_params, int32_t n, const int32_t
                                 const double voxel_mm[3], float *d_vol, void *hip_stream);
 cvp_status cvp_synth_add_gaussian(float *d_out, int64_t n, float sigma, uint64_t seed,
                                   void *hip_stream);
+
+/* Launch plan of a geometry: how the work is split, never what is computed.
+ *   proj_band_cols  detector columns per projection work item (1..32); the
+ *                   work item's fixed-point band image takes 8 bytes per
+ *                   detector row and column of LDS (at most 156 KB in all), so
+ *                   small values let more workgroups share a compute unit.
+ *   bp_stack_cols   voxel columns per backprojection workgroup (16, 8 or 4).
+ * cvp_geometry_get_launch reports the plan in use (the planner's default
+ * after cvp_geometry_from_views).  cvp_geometry_set_launch replaces it; a zero
+ * field restores the default for that field.  Errors: CVP_E_INVALID (NULL or a
+ * value outside the sets above), CVP_E_UNSUPPORTED (the plan does not fit
+ * LDS); the plan is unchanged on error.  Set the plan while no other call
+ * uses the geometry; launches already enqueued keep the plan they were
+ * given, and batches keep the plans of their members at cvp_batch_create.
+ * Results of a given plan are bitwise reproducible; two plans may differ in
+ * the last bit of a few projection values (the fixed-point scale of a work
+ * item depends on the part of the volume it reads). */
+typedef struct {
+    int32_t proj_band_cols;
+    int32_t bp_stack_cols;
+} cvp_launch;
+
+cvp_status cvp_geometry_get_launch(const cvp_geometry *g, cvp_launch *out);
+cvp_status cvp_geometry_set_launch(cvp_geometry *g, const cvp_launch *in);
 
 /* Geometry queries (host-side, no device work). */
 cvp_status cvp_geometry_sizes(const cvp_geometry *g, int64_t *n_voxels,

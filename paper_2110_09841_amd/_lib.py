@@ -70,6 +70,10 @@ def lib():
     return L
 
 
+class LaunchC(ctypes.Structure):
+    _fields_ = [("proj_band_cols", ctypes.c_int32), ("bp_stack_cols", ctypes.c_int32)]
+
+
 def _register_extra(L):
     """Signatures of the solver, batch and input-generation entry points
     (present in the same library)."""
@@ -87,6 +91,8 @@ def _register_extra(L):
         "cvp_synth_ellipsoids": ([vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
                                   vp, vp], st),
         "cvp_synth_add_gaussian": ([vp, ctypes.c_int64, ctypes.c_float, ctypes.c_uint64, vp], st),
+        "cvp_geometry_get_launch": ([vp, ctypes.POINTER(LaunchC)], st),
+        "cvp_geometry_set_launch": ([vp, ctypes.POINTER(LaunchC)], st),
     }
     for name, (args, res) in specs.items():
         if hasattr(L, name):

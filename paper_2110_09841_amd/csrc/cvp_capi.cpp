@@ -17,9 +17,10 @@
 
 namespace cvp {
 hipError_t configure_kernel_lds(size_t max_lds, size_t max_lds_batched);
-constexpr size_t kLdsBudget = 78 * 1024;   // two workgroups per CU (160 KB LDS)
-constexpr size_t kLdsBatchMax = 156 * 1024; // batched kernels: one workgroup per CU at worst
-bool plan_projection(int N, int n2, int M, int nviews, int pmax, ProjLaunch &L);
+constexpr size_t kLdsBudget = 78 * 1024;   // default plans: two workgroups per CU (160 KB LDS)
+constexpr size_t kLdsMax = 156 * 1024;      // any plan: one workgroup per CU at worst
+constexpr size_t kLdsBatchMax = kLdsMax;
+bool plan_projection(int N, int n2, int M, int nviews, int pmax, int force_u, ProjLaunch &L);
 bool plan_backprojection(const DevGeom &G, int pmax, double zabs, double Dmin, int force_gw,
                          BackLaunch &L);
 }
@@ -93,19 +94,25 @@ size_t backproject_lds_bytes(int gw, int pmax, int winCap)
     return kWaves * waveFloats * 4;
 }
 
-// Projection: bands of U detector columns, U as large as the LDS budget
-// allows (a 64-bit band image of U x N, row tables).
-bool plan_projection(int N, int n2, int M, int nviews, int pmax, ProjLaunch &L)
+// Projection: bands of U detector columns (a 64-bit band image of U x N and
+// the row tables in LDS).  force_u = 0: U as large as the default LDS budget
+// allows; otherwise U = force_u if its LDS fits one workgroup.
+bool plan_projection(int N, int n2, int M, int nviews, int pmax, int force_u, ProjLaunch &L)
 {
     const size_t fixed = project_lds_bytes(0, N, n2, pmax);
     const size_t perU = project_lds_bytes(1, N, n2, pmax) - fixed;
-    if (fixed + perU > kLdsBudget) return false;
-    int U = (int)((kLdsBudget - fixed) / perU);
-    U = std::max(1, std::min(U, 32));
+    int U = force_u;
+    if (U <= 0) {
+        if (fixed + perU > kLdsBudget) return false;
+        U = (int)((kLdsBudget - fixed) / perU);
+        U = std::max(1, std::min(U, 32));
+    } else if (U > 32 || project_lds_bytes(U, N, n2, pmax) > kLdsMax) {
+        return false;
+    }
     L.U = U;
     L.nbands = (M + U - 1) / U;
     L.items = L.nbands * nviews;
-    L.chunk = (L.items + 7) / 8;
+    L.chunk = nviews * ((L.nbands + 7) / 8);   // work items per XCD (bands interleaved over XCDs)
     L.pmax = pmax;
     L.lds = project_lds_bytes(U, N, n2, pmax);
     return true;
@@ -271,7 +278,7 @@ cvp_status cvp_geometry_from_views(const cvp_geometry_desc *d, cvp_geometry **ou
     if (e != hipSuccess) { cvp_geometry_destroy(g); return device_fail(e, "device tables"); }
     static std::once_flag lds_once;
     static hipError_t lds_err = hipSuccess;
-    std::call_once(lds_once, [] { lds_err = cvp::configure_kernel_lds(kLdsBudget, cvp::kLdsBatchMax); });
+    std::call_once(lds_once, [] { lds_err = cvp::configure_kernel_lds(cvp::kLdsMax, cvp::kLdsBatchMax); });
     if (lds_err != hipSuccess) { cvp_geometry_destroy(g); return device_fail(lds_err, "kernel LDS attribute"); }
 
     cvp::DevGeom &G = g->base;
@@ -296,7 +303,7 @@ cvp_status cvp_geometry_from_views(const cvp_geometry_desc *d, cvp_geometry **ou
     const int pmax = pieces <= 4 ? 4 : 8;
     g->zabs = zabs;
     g->Dmin = Dmin;
-    if (!cvp::plan_projection(N, n2, M, d->n_views, pmax, g->pl)) {
+    if (!cvp::plan_projection(N, n2, M, d->n_views, pmax, 0, g->pl)) {
         cvp_geometry_destroy(g);
         return fail(CVP_E_UNSUPPORTED, "detector rows (%d) or volume rows (%d) too large for the projection LDS layout", N, n2);
     }
@@ -305,6 +312,36 @@ cvp_status cvp_geometry_from_views(const cvp_geometry_desc *d, cvp_geometry **ou
         return fail(CVP_E_UNSUPPORTED, "backprojection LDS window too small");
     }
     *out = g;
+    return ok();
+}
+
+cvp_status cvp_geometry_get_launch(const cvp_geometry *g, cvp_launch *out)
+{
+    if (!g) return fail(CVP_E_INVALID, "geometry is NULL");
+    if (!out) return fail(CVP_E_INVALID, "out is NULL");
+    out->proj_band_cols = g->pl.U;
+    out->bp_stack_cols = g->bl.gw;
+    return ok();
+}
+
+cvp_status cvp_geometry_set_launch(cvp_geometry *g, const cvp_launch *in)
+{
+    if (!g) return fail(CVP_E_INVALID, "geometry is NULL");
+    if (!in) return fail(CVP_E_INVALID, "launch is NULL");
+    const int u = in->proj_band_cols, gw = in->bp_stack_cols;
+    if (u < 0 || u > 32) return fail(CVP_E_INVALID, "launch.proj_band_cols = %d (0 or 1..32)", u);
+    if (gw != 0 && gw != 4 && gw != 8 && gw != 16)
+        return fail(CVP_E_INVALID, "launch.bp_stack_cols = %d (0, 4, 8 or 16)", gw);
+    const cvp::DevGeom &G = g->base;
+    cvp::ProjLaunch pl{};
+    cvp::BackLaunch bl{};
+    if (!cvp::plan_projection(G.N, G.n2, G.M, G.nviews, g->pl.pmax, u, pl))
+        return fail(CVP_E_UNSUPPORTED, "launch.proj_band_cols = %d: band image of %zu bytes exceeds the LDS limit", u,
+                    cvp::project_lds_bytes(u, G.N, G.n2, g->pl.pmax));
+    if (!cvp::plan_backprojection(G, g->bl.pmax, g->zabs, g->Dmin, gw, bl))
+        return fail(CVP_E_UNSUPPORTED, "launch.bp_stack_cols = %d: detector window does not fit LDS", gw);
+    g->pl = pl;
+    g->bl = bl;
     return ok();
 }
 

@@ -43,7 +43,7 @@ struct ProjLaunch {
     int U;           // detector columns per band
     int nbands;
     int items;       // nbands * nviews
-    int chunk;       // items per XCD slot
+    int chunk;       // work-item slots per XCD (grid = 8 * chunk)
     int pmax;        // 4 or 8
     size_t lds;      // dynamic LDS bytes
 };

@@ -536,13 +536,18 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
 
 template <bool EXACT, bool EC, int PMAX>
 __global__ void __launch_bounds__(kBlock)
-project_kernel(const DevGeom G, const int U, const int items, const int chunk,
-               const float *__restrict__ vol, float *__restrict__ proj)
+project_kernel(const DevGeom G, const int U, const int nbands, const float *__restrict__ vol,
+               float *__restrict__ proj)
 {
     extern __shared__ __align__(16) float smem[];
-    const int item = (blockIdx.x & 7) * chunk + (blockIdx.x >> 3);   // XCD-contiguous items
-    if (item >= items) return;
-    project_item<EXACT, EC, PMAX>(G, U, item, smem, vol, proj);
+    // Workgroups go to the 8 XCDs round robin.  XCD x takes bands x, x + 8,
+    // x + 16, ..., each for all views in order: the costly central bands are
+    // spread over all XCDs, and the workgroups an XCD runs at a time share a
+    // band and neighbouring views, so their wedges overlap in its L2.
+    const int slot = blockIdx.x >> 3;
+    const int band = (blockIdx.x & 7) + 8 * (slot / G.nviews);
+    if (band >= nbands) return;
+    project_item<EXACT, EC, PMAX>(G, U, band * G.nviews + slot % G.nviews, smem, vol, proj);
 }
 
 // ------------------------------------------------------------ backprojection
@@ -788,11 +793,9 @@ hipError_t launch_p(const DevGeom &g, const ProjLaunch &L, const float *vol, flo
 {
     const dim3 grid(8 * L.chunk), block(kBlock);
     if (L.pmax <= 4)
-        hipLaunchKernelGGL((project_kernel<EXACT, EC, 4>), grid, block, L.lds, s, g, L.U, L.items,
-                           L.chunk, vol, proj);
+        hipLaunchKernelGGL((project_kernel<EXACT, EC, 4>), grid, block, L.lds, s, g, L.U, L.nbands, vol, proj);
     else
-        hipLaunchKernelGGL((project_kernel<EXACT, EC, 8>), grid, block, L.lds, s, g, L.U, L.items,
-                           L.chunk, vol, proj);
+        hipLaunchKernelGGL((project_kernel<EXACT, EC, 8>), grid, block, L.lds, s, g, L.U, L.nbands, vol, proj);
     return hipGetLastError();
 }
 

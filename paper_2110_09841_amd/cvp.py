@@ -63,6 +63,20 @@ class Geometry:
     def n_views(self):
         return self.proj_shape[0]
 
+    @property
+    def launch(self):
+        """Launch plan in use: (projection band columns, backprojection
+        stack columns)."""
+        lp = _lib.LaunchC()
+        _lib.check(_lib.lib().cvp_geometry_get_launch(self.handle, ctypes.byref(lp)))
+        return int(lp.proj_band_cols), int(lp.bp_stack_cols)
+
+    def set_launch(self, proj_band_cols=0, bp_stack_cols=0):
+        """Replace the launch plan (0 keeps the planner's default for that
+        field).  Raises CVPError if the plan does not fit."""
+        lp = _lib.LaunchC(int(proj_band_cols), int(bp_stack_cols))
+        _lib.check(_lib.lib().cvp_geometry_set_launch(self.handle, ctypes.byref(lp)))
+
 
 def _check_tensor(t, shape, name):
     if not isinstance(t, torch.Tensor):
