@@ -8,6 +8,11 @@ backprojection A^T b, inputs resident in HBM.
 
 value = 2 * n_voxels * n_views / (t_A + t_AT)   [voxel-view updates/s]
 
+Before the timed region the autotuner picks the launch plan (projection band
+width, backprojection stack width) on random data of the same shape.  After
+it, CGLS from zero on consistent data b = A x_true is run to
+|A^T (b - A x)| <= 1e-3 |A^T b| and its wall time reported ("cgls").
+
 Prints one JSON line.  The CPU baseline times the FP64 oracle on a bounded
 sample of the same workload (one view of A x and a voxel sample of A^T b).
 """
@@ -30,6 +35,9 @@ def parse():
     ap.add_argument("--no-ec", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cgls", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the planner's default launch plan")
+    ap.add_argument("--launch", default=None, metavar="U,GW",
+                    help="fixed launch plan (projection band columns, backprojection stack columns); no autotuning")
     ap.add_argument("--cgls-max-iter", type=int, default=200)
     ap.add_argument("--calib-copy", action="store_true",
                     help="run only a 1 GiB device copy (counter calibration)")
@@ -99,6 +107,7 @@ def main():
     import numpy as np
     import torch
     from paper_2110_09841_amd import costmodel, cvp, synth
+    from paper_2110_09841_amd.autotune import autotune
     if args.calib_copy:
         calib_copy()
         return
@@ -111,6 +120,14 @@ def main():
     G = cvp.Geometry(g)
     ec = not args.no_ec
     opts = cvp.Options(variant=args.variant, ec=ec)
+    plan = {"default": list(G.launch)}
+    if args.launch:
+        u, gw = (int(t) for t in args.launch.split(","))
+        G.set_launch(u, gw)
+        plan["fixed"] = list(G.launch)
+    elif not args.no_autotune:
+        rec = autotune(G, opts, reps=2)
+        plan.update(tuned=list(G.launch), project_ms=rec["project_ms"], backproject_ms=rec["backproject_ms"])
     x = torch.from_numpy(x_h).cuda()
     b = torch.from_numpy(b_h).cuda()
     p_out = torch.empty(G.proj_shape, dtype=torch.float32, device="cuda")
@@ -155,7 +172,9 @@ def main():
         "config": {"workload": "carm_512c_248v", "volume": [n1, n2, n3], "voxel_mm": 0.25,
                    "detector": [g["det_cols"], g["det_rows"]], "pitch_mm": 0.616, "views": V,
                    "arc_deg": 200, "sid_mm": 749, "sdd_mm": 1198, "variant": args.variant,
-                   "elevation_correction": ec, "scaling": "solid_angle"},
+                   "elevation_correction": ec, "scaling": "solid_angle",
+                   "launch": {"proj_band_cols": G.launch[0], "bp_stack_cols": G.launch[1]}},
+        "autotune": plan,
         "project": {"ms": 1e3 * tA.mean(), "voxel_views_per_s": vv / tA.mean()},
         "backproject": {"ms": 1e3 * tB.mean(), "voxel_views_per_s": vv / tB.mean()},
         "roofline": {"bound": "alu", "kernel": name, "achieved": rdom["achieved"] / 1e12,

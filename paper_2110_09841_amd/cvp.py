@@ -50,8 +50,9 @@ class Geometry:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value and _lib._lib is not None:
-            _lib._lib.cvp_geometry_destroy(h)
+        L = getattr(_lib, "_lib", None) if _lib is not None else None   # None at interpreter exit
+        if h is not None and h.value and L is not None:
+            L.cvp_geometry_destroy(h)
             self.handle = None
 
     @property
@@ -127,8 +128,9 @@ class Batch:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value and _lib._lib is not None:
-            _lib._lib.cvp_batch_destroy(h)
+        L = getattr(_lib, "_lib", None) if _lib is not None else None   # None at interpreter exit
+        if h is not None and h.value and L is not None:
+            L.cvp_batch_destroy(h)
             self.handle = None
 
     def __len__(self):
