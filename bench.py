@@ -77,6 +77,27 @@ def cpu_baseline(g, x, b):
                       "(%.1f s), FP64 C/OpenMP" % (n1 * n2 * n3, t1 - t0, V, t2 - t1)}
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary of this workload (FETCH_SIZE + WRITE_SIZE, calibrated against a
+    1 GiB copy), or None when the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_carm_512c_248v.json")
+    src = os.path.join(ROOT, "paper_2110_09841_amd", "csrc", "cvp_kernels.hip")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        with open(src, "rb") as f:
+            sha = hashlib.sha1(f.read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("kernel_source_sha1") != sha or kernel not in rec:
+        return None
+    return {"bytes": rec[kernel]["fetch_bytes"] + rec[kernel]["write_bytes"],
+            "fetch_bytes": rec[kernel]["fetch_bytes"], "write_bytes": rec[kernel]["write_bytes"],
+            "algorithmic_bytes": rec["algorithmic_bytes_per_launch"], "plan": rec.get("plan")}
+
+
 def cgls_to_tolerance(G, opts, x_true, max_iter):
     """CGLS from zero on b = A x_true until rho = |A^T(b - A x)| / |A^T b|
     <= 1e-3; 5 iterations per replay of a captured HIP graph (captured
@@ -156,6 +177,7 @@ def main():
     rA = costmodel.roofline(g, exact, ec, tA.mean())
     rB = costmodel.roofline(g, exact, ec, tB.mean())
     dom, rdom, name = (tA, rA, "cvp_project") if tA.mean() >= tB.mean() else (tB, rB, "cvp_backproject")
+    traffic = measured_traffic(name)
     out = {
         "metric": "voxel-view updates/s (CVP Ax+A^T b, 512^3, 248 views); CGLS time to 1e-3 residual",
         "value": float(value),
@@ -180,7 +202,9 @@ def main():
         "roofline": {"bound": "alu", "kernel": name, "achieved": rdom["achieved"] / 1e12,
                      "peak": rdom["peak"] / 1e12, "unit": "TOP/s (FP32 VALU lane-ops)",
                      "frac": rdom["frac"], "ops_per_voxel_view": rdom["ops_per_vv"],
-                     "pieces_per_voxel_view": [rdom["n_c"], rdom["n_p"]], "traffic": None},
+                     "pieces_per_voxel_view": [rdom["n_c"], rdom["n_p"]],
+                     "traffic": traffic["bytes"] if traffic else None, "traffic_unit": "bytes per launch",
+                     "traffic_detail": traffic},
     }
     if not args.no_cgls:
         out["cgls"] = cgls_to_tolerance(G, opts, x, args.cgls_max_iter)
