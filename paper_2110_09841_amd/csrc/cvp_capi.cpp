@@ -412,7 +412,7 @@ struct cvp_batch {
     cvp::BatchProblem *d_probs = nullptr;
     cvp::BatchTable *d_ptab = nullptr, *d_btab = nullptr;
     int *d_counter = nullptr;
-    int pmax = 4, gw = 16, win_cap = 0;
+    int pmax = 4, win_cap = 0;
     size_t plds = 0, blds = 0;
     int pgrid = 0, bgrid = 0;
 };
@@ -445,13 +445,9 @@ cvp_status cvp_batch_create(const cvp_geometry *const *geoms, int32_t n, cvp_bat
     b->n = n;
     b->device = geoms[0]->device;
     b->geoms.assign(geoms, geoms + n);
-    // common template parameters: the largest piece count, the narrowest
-    // backprojection column group; each problem's launch plan is redone
-    // with them so that one dynamic LDS size fits all
-    for (int q = 0; q < n; ++q) {
-        b->pmax = std::max(b->pmax, geoms[q]->pl.pmax);
-        b->gw = std::min(b->gw, geoms[q]->bl.gw);
-    }
+    // common template parameter: the largest piece count; each problem keeps
+    // its own band width and stack width, and one dynamic LDS size fits all
+    for (int q = 0; q < n; ++q) b->pmax = std::max(b->pmax, geoms[q]->pl.pmax);
     std::vector<cvp::BatchProblem> probs(n);
     std::vector<double> pcost(n), bcost(n);
     for (int q = 0; q < n; ++q) {
@@ -463,13 +459,14 @@ cvp_status cvp_batch_create(const cvp_geometry *const *geoms, int32_t n, cvp_bat
         pl.lds = cvp::project_lds_bytes(pl.U, g->base.N, g->base.n2, b->pmax);
         cvp::BackLaunch bl;
         if (pl.lds > cvp::kLdsBatchMax ||
-            !cvp::plan_backprojection(g->base, b->pmax, g->zabs, g->Dmin, b->gw, bl)) {
+            !cvp::plan_backprojection(g->base, b->pmax, g->zabs, g->Dmin, g->bl.gw, bl)) {
             cvp_batch_destroy(b);
             return fail(CVP_E_UNSUPPORTED, "problem %d does not fit the common launch plan", q);
         }
         cvp::BatchProblem &P = probs[q];
         P.G = g->base;
         P.U = pl.U;
+        P.gw = bl.gw;
         P.pitems = pl.items;
         P.ngroups = bl.ngroups;
         P.nkchunks = bl.nkchunks;
@@ -477,7 +474,6 @@ cvp_status cvp_batch_create(const cvp_geometry *const *geoms, int32_t n, cvp_bat
         P.in = nullptr;
         P.out = nullptr;
         b->plds = std::max(b->plds, pl.lds);
-        b->blds = std::max(b->blds, bl.lds);
         b->win_cap = q == 0 ? bl.win_cap : std::min(b->win_cap, bl.win_cap);
         pcost[q] = (double)g->nvox / pl.nbands;           // voxels per band (all k)
         bcost[q] = (double)g->base.nviews;                // views per voxel stack
@@ -495,6 +491,13 @@ cvp_status cvp_batch_create(const cvp_geometry *const *geoms, int32_t n, cvp_bat
         }
         return T;
     };
+    b->blds = 0;
+    for (int q = 0; q < n; ++q)
+        b->blds = std::max(b->blds, cvp::backproject_lds_bytes(probs[q].gw, b->pmax, b->win_cap));
+    if (b->blds > cvp::kLdsBatchMax) {
+        cvp_batch_destroy(b);
+        return fail(CVP_E_UNSUPPORTED, "backprojection windows of the problems exceed the LDS limit together");
+    }
     const cvp::BatchTable pt = table(pcost, false), bt = table(bcost, true);
     int cus = 0;
     hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
@@ -530,7 +533,7 @@ static cvp_status batched(const cvp_batch *b, const cvp_options *o, const float 
         io.sigma[q] = G.sigma;
     }
     hipError_t e = cvp::launch_batched(backward, b->d_probs, backward ? b->d_btab : b->d_ptab,
-                                       b->d_counter, io, b->pmax, b->gw, b->win_cap,
+                                       b->d_counter, io, b->pmax, b->win_cap,
                                        o->variant == CVP_EXACT, o->elevation_correction != 0,
                                        backward ? b->bgrid : b->pgrid, backward ? b->blds : b->plds,
                                        (hipStream_t)stream);

@@ -66,7 +66,8 @@ struct BatchProblem {        // device table entry (one per problem)
     DevGeom G;
     int U;                   // projection band width
     int pitems;              // projection work items
-    int ngroups;             // backprojection column groups per row (common GW)
+    int gw;                  // backprojection stack width of the problem's own plan
+    int ngroups;             // backprojection column groups per row
     int nkchunks;
     int bitems;              // backprojection work items
     const float *in;         // set per call by batch_setup
@@ -88,7 +89,7 @@ struct BatchIO {             // per call, by value
 };
 
 hipError_t launch_batched(bool backward, BatchProblem *probs, const BatchTable *tab, int *counter,
-                          const BatchIO &io, int pmax, int gw, int winCap, bool exact, bool ec,
+                          const BatchIO &io, int pmax, int winCap, bool exact, bool ec,
                           int grid, size_t lds, hipStream_t s);
 int batched_blocks_per_cu(bool backward, size_t lds);
 size_t project_lds_bytes(int U, int N, int n2, int pmax);

@@ -35,6 +35,12 @@
 namespace cvp {
 namespace {
 
+// No implicit FP contraction anywhere in this file: a multiply-add is fused
+// only where the source says fmaf/fma.  Otherwise the compiler may fuse
+// differently in each kernel a device function is inlined into, and the
+// single-problem and batched launches would not give the same bits.
+#pragma clang fp contract(off)
+
 // ------------------------------------------------------------ FP64 column stage
 // FP contraction is off in this stage, so the records do not depend on the
 // kernel the stage is inlined into (single-problem and batched launches give
@@ -208,11 +214,11 @@ template <bool EC>
 __device__ __forceinline__ float cum(float s1, float beta, float tc, float rho)
 {
     const float s0 = s1 + beta;
-    const float plain = fmaxf(s0, 0.0f) - fmaxf(s1, 0.0f);
+    const float plain = __builtin_amdgcn_fmed3f(s0, 0.0f, beta);   // = max(s0,0) - max(s1,0)
     if (!EC) return plain;
     const float e = fabsf(tc) * rho;
-    const float p0 = fmaxf(e - fabsf(s0), 0.0f);
-    const float p1 = fmaxf(e - fabsf(s1), 0.0f);
+    const float p0 = fmaxf(fmaf(fabsf(tc), rho, -fabsf(s0)), 0.0f);
+    const float p1 = fmaxf(fmaf(fabsf(tc), rho, -fabsf(s1)), 0.0f);
     const float inv4e = 0.25f * __builtin_amdgcn_rcpf(fmaxf(e, 1e-30f));
     return fmaf((p0 - p1) * (p0 + p1), inv4e, plain);
 }
@@ -495,9 +501,9 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
                     const float Yh = fmaf(-kf, r[4], r[2]);
                     const float Yl = fmaf(-kf, r[5], r[3]);
                     const float beta = r[6], rho = r[7];
+                    unsigned long long *bcol = bins + (u - u0) * Npad;
                     int vlo, vhi;
                     row_range<EC>(Yh + Yl, beta, rho, c2f, G.N, vlo, vhi);
-                    unsigned long long *bcol = bins + (u - u0) * Npad;
                     float tb = (float)vlo - 0.5f;
                     float s1p = (Yh - tb) + Yl;
                     float Cp = cum<EC>(s1p, beta, tb - c2f, rho);
@@ -628,8 +634,11 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
         const int Wd = wu1 - wu0 + 1;
         const int H = wv1 - wv0 + 1;
         const int Hp = H | 1;
-        const bool useWin = Wd * Hp <= winCap;
         const float *pv = proj + (size_t)view * G.N * G.M;
+        const float zt = fmaf(kf, a3f, (float)(G.x3lo + G.a3 - V.s3));
+        const float zc = zt - 0.5f * a3f;
+
+        const bool useWin = Wd * Hp <= winCap;
         if (useWin) {
             for (int idx = lane; idx < Wd * H; idx += kWave) {
                 const int uu = idx % Wd, vv = idx / Wd;
@@ -641,8 +650,6 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
         }
         wave_sync();
 
-        const float zt = fmaf(kf, a3f, (float)(G.x3lo + G.a3 - V.s3));
-        const float zc = zt - 0.5f * a3f;
 #pragma unroll
         for (int c = 0; c < GW; ++c) {
             const int np = npc[c];
@@ -757,7 +764,9 @@ project_batched_kernel(const BatchProblem *__restrict__ probs, const BatchTable 
     }
 }
 
-template <bool EXACT, bool EC, int PMAX, int GW>
+// Each problem runs with its own stack width, so its items are exactly those
+// of its single-problem launch.
+template <bool EXACT, bool EC, int PMAX>
 __global__ void __launch_bounds__(kBlock)
 backproject_batched_kernel(const BatchProblem *__restrict__ probs, const BatchTable *__restrict__ T,
                            int *counter, int winCap)
@@ -766,7 +775,12 @@ backproject_batched_kernel(const BatchProblem *__restrict__ probs, const BatchTa
     int p, local;
     while (next_item(*T, counter, p, local)) {
         const BatchProblem &P = probs[p];
-        backproject_item<EXACT, EC, PMAX, GW>(P.G, P.ngroups, P.nkchunks, winCap, local, smem, P.in, P.out);
+        if (P.gw == 16)
+            backproject_item<EXACT, EC, PMAX, 16>(P.G, P.ngroups, P.nkchunks, winCap, local, smem, P.in, P.out);
+        else if (P.gw == 8)
+            backproject_item<EXACT, EC, PMAX, 8>(P.G, P.ngroups, P.nkchunks, winCap, local, smem, P.in, P.out);
+        else
+            backproject_item<EXACT, EC, PMAX, 4>(P.G, P.ngroups, P.nkchunks, winCap, local, smem, P.in, P.out);
     }
 }
 
@@ -856,23 +870,11 @@ hipError_t launch_pb(BatchProblem *probs, const BatchTable *tab, int *counter, i
 }
 
 template <bool EXACT, bool EC, int PMAX>
-hipError_t launch_bb(BatchProblem *probs, const BatchTable *tab, int *counter, int gw, int winCap,
-                     int grid, size_t lds, hipStream_t s)
+hipError_t launch_bb(BatchProblem *probs, const BatchTable *tab, int *counter, int winCap, int grid,
+                     size_t lds, hipStream_t s)
 {
-    switch (gw) {
-    case 16:
-        hipLaunchKernelGGL((backproject_batched_kernel<EXACT, EC, PMAX, 16>), dim3(grid), dim3(kBlock),
-                           lds, s, probs, tab, counter, winCap);
-        break;
-    case 8:
-        hipLaunchKernelGGL((backproject_batched_kernel<EXACT, EC, PMAX, 8>), dim3(grid), dim3(kBlock),
-                           lds, s, probs, tab, counter, winCap);
-        break;
-    default:
-        hipLaunchKernelGGL((backproject_batched_kernel<EXACT, EC, PMAX, 4>), dim3(grid), dim3(kBlock),
-                           lds, s, probs, tab, counter, winCap);
-        break;
-    }
+    hipLaunchKernelGGL((backproject_batched_kernel<EXACT, EC, PMAX>), dim3(grid), dim3(kBlock), lds, s, probs, tab,
+                       counter, winCap);
     return hipGetLastError();
 }
 
@@ -882,13 +884,7 @@ hipError_t set_lds_batched(size_t n)
     hipError_t e = hipFuncSetAttribute((const void *)project_batched_kernel<EXACT, EC, PMAX>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
     if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)backproject_batched_kernel<EXACT, EC, PMAX, 16>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)backproject_batched_kernel<EXACT, EC, PMAX, 8>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)backproject_batched_kernel<EXACT, EC, PMAX, 4>,
+        e = hipFuncSetAttribute((const void *)backproject_batched_kernel<EXACT, EC, PMAX>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
     return e;
 }
@@ -896,7 +892,7 @@ hipError_t set_lds_batched(size_t n)
 }  // namespace
 
 hipError_t launch_batched(bool backward, BatchProblem *probs, const BatchTable *tab, int *counter,
-                          const BatchIO &io, int pmax, int gw, int winCap, bool exact, bool ec,
+                          const BatchIO &io, int pmax, int winCap, bool exact, bool ec,
                           int grid, size_t lds, hipStream_t s)
 {
     hipLaunchKernelGGL(batch_setup, dim3(1), dim3(64), 0, s, probs, io, counter);
@@ -915,15 +911,15 @@ hipError_t launch_batched(bool backward, BatchProblem *probs, const BatchTable *
                   : launch_pb<false, false, 8>(probs, tab, counter, grid, lds, s);
     }
     if (pmax <= 4) {
-        if (exact) return ec ? launch_bb<true, true, 4>(probs, tab, counter, gw, winCap, grid, lds, s)
-                             : launch_bb<true, false, 4>(probs, tab, counter, gw, winCap, grid, lds, s);
-        return ec ? launch_bb<false, true, 4>(probs, tab, counter, gw, winCap, grid, lds, s)
-                  : launch_bb<false, false, 4>(probs, tab, counter, gw, winCap, grid, lds, s);
+        if (exact) return ec ? launch_bb<true, true, 4>(probs, tab, counter, winCap, grid, lds, s)
+                             : launch_bb<true, false, 4>(probs, tab, counter, winCap, grid, lds, s);
+        return ec ? launch_bb<false, true, 4>(probs, tab, counter, winCap, grid, lds, s)
+                  : launch_bb<false, false, 4>(probs, tab, counter, winCap, grid, lds, s);
     }
-    if (exact) return ec ? launch_bb<true, true, 8>(probs, tab, counter, gw, winCap, grid, lds, s)
-                         : launch_bb<true, false, 8>(probs, tab, counter, gw, winCap, grid, lds, s);
-    return ec ? launch_bb<false, true, 8>(probs, tab, counter, gw, winCap, grid, lds, s)
-              : launch_bb<false, false, 8>(probs, tab, counter, gw, winCap, grid, lds, s);
+    if (exact) return ec ? launch_bb<true, true, 8>(probs, tab, counter, winCap, grid, lds, s)
+                         : launch_bb<true, false, 8>(probs, tab, counter, winCap, grid, lds, s);
+    return ec ? launch_bb<false, true, 8>(probs, tab, counter, winCap, grid, lds, s)
+              : launch_bb<false, false, 8>(probs, tab, counter, winCap, grid, lds, s);
 }
 
 // Workgroups of a persistent batched kernel that fit on one CU at this LDS size.
@@ -935,7 +931,7 @@ int batched_blocks_per_cu(bool backward, size_t lds)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)project_batched_kernel<false, true, 8>,
                                                          kBlock, lds);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)backproject_batched_kernel<false, true, 8, 16>,
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)backproject_batched_kernel<false, true, 8>,
                                                          kBlock, lds);
     if (e != hipSuccess || nb < 1) nb = 1;
     return nb;

@@ -83,6 +83,34 @@ def test_large_voxels_many_pieces():
             run_pair(g, x, b, variant, ec, "solid_angle", "large-voxels")
 
 
+def test_wide_elevation_boxes():
+    """Large voxels close to the source on a tall detector, the volume
+    shifted along x3: the EC depth boxes are wider than half a row, so the
+    box average moves several row boundaries of a voxel edge."""
+    g = synth.geometry((6, 7, 5), 2.0, 64, 160, 0.8, 150.0, 240.0, 9, 360.0, vol_offset_mm=(0.0, 0.0, 30.0))
+    x = synth.uniform_volume((5, 7, 6), seed=17)
+    b = synth.uniform_projections((9, 160, 64), seed=18)
+    for variant in ("exact", "relaxed"):
+        run_pair(g, x, b, variant, True, "solid_angle", "wide-EC")
+
+
+def test_raw_volume_backprojection():
+    """Raw cut volumes (no 1/r^2, no pixel factor) in both directions."""
+    g = ragged()
+    x = synth.uniform_volume((70, 29, 37), seed=19)
+    b = synth.uniform_projections((5, 41, 53), seed=20)
+    for variant in ("exact", "relaxed"):
+        for ec in (True, False):
+            say("raw", variant, ec)
+            G = cvp.Geometry(g)
+            opts = gopts(variant, ec, "none", raw=True)
+            o = oopts(variant, ec, "none", raw=True)
+            assert_parity(cvp.project(torch.from_numpy(x).cuda(), G, opts).cpu().numpy(), O.project(g, o, x),
+                          "raw A x")
+            assert_parity(cvp.backproject(torch.from_numpy(b).cuda(), G, opts).cpu().numpy(),
+                          O.backproject(g, o, b), "raw A^T b")
+
+
 def test_single_voxel_and_single_view():
     g = synth.geometry((1, 1, 1), 1.0, 5, 4, 0.9, 100.0, 170.0, 1, 360.0)
     x = np.ones((1, 1, 1), np.float32)
