@@ -17,7 +17,8 @@
 
 namespace cvp {
 hipError_t configure_kernel_lds(size_t max_lds, size_t max_lds_batched);
-constexpr size_t kLdsBudget = 78 * 1024;   // default plans: two workgroups per CU (160 KB LDS)
+constexpr size_t kLdsBudget = 39 * 1024;   // default projection plans: four workgroups per CU (160 KB LDS)
+constexpr size_t kBackLdsBudget = 52 * 1024;   // backprojection windows: three workgroups per CU
 constexpr size_t kLdsMax = 156 * 1024;      // any plan: one workgroup per CU at worst
 constexpr size_t kLdsBatchMax = kLdsMax;
 bool plan_projection(int N, int n2, int M, int nviews, int pmax, int force_u, ProjLaunch &L);
@@ -96,15 +97,17 @@ size_t backproject_lds_bytes(int gw, int pmax, int winCap)
 
 // Projection: bands of U detector columns (a 64-bit band image of U x N and
 // the row tables in LDS).  force_u = 0: U as large as the default LDS budget
-// allows; otherwise U = force_u if its LDS fits one workgroup.
+// (four workgroups per compute unit) allows; otherwise U = force_u if its LDS
+// fits one workgroup.
 bool plan_projection(int N, int n2, int M, int nviews, int pmax, int force_u, ProjLaunch &L)
 {
     const size_t fixed = project_lds_bytes(0, N, n2, pmax);
     const size_t perU = project_lds_bytes(1, N, n2, pmax) - fixed;
     int U = force_u;
     if (U <= 0) {
-        if (fixed + perU > kLdsBudget) return false;
-        U = (int)((kLdsBudget - fixed) / perU);
+        // as wide as the default budget allows; a single column may use more
+        if (fixed + perU > kLdsMax) return false;
+        U = fixed + perU <= kLdsBudget ? (int)((kLdsBudget - fixed) / perU) : 1;
         U = std::max(1, std::min(U, 32));
     } else if (U > 32 || project_lds_bytes(U, N, n2, pmax) > kLdsMax) {
         return false;
@@ -128,7 +131,7 @@ bool plan_backprojection(const DevGeom &G, int pmax, double zabs, double Dmin, i
     for (int cand : {16, 8, 4}) {
         if (force_gw > 0 && cand != force_gw) continue;
         const size_t rec = (size_t)cand * pmax * kRecFloats + cand;
-        const int c = (int)((kLdsBudget / (kWaves * 4) - rec) / 4 * 4);
+        const int c = (int)((kBackLdsBudget / (kWaves * 4) - rec) / 4 * 4);
         const double wu = std::hypot(cand * G.a1, G.a2) * mag / G.b1 + pmax + 2;
         const double zspan = std::hypot(cand * G.a1, G.a2);
         const double wv = 64 * G.a3 * mag / G.b2 + zabs * (G.f / G.b2) * zspan / (Dmin * Dmin) + 6;

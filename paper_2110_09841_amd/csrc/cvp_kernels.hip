@@ -540,8 +540,12 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
     }
 }
 
+// Register budgets: the projection is held to 128 VGPRs (4 waves per SIMD,
+// a few spills) and the backprojection to 168 (3 waves per SIMD); both ran
+// about 20% faster at 512^3 x 248 views than at their natural 190-220 VGPRs
+// with 2 waves per SIMD.
 template <bool EXACT, bool EC, int PMAX>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
 project_kernel(const DevGeom G, const int U, const int nbands, const float *__restrict__ vol,
                float *__restrict__ proj)
 {
@@ -721,7 +725,7 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
 }
 
 template <bool EXACT, bool EC, int PMAX, int GW>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
 backproject_kernel(const DevGeom G, const int ngroups, const int nkchunks, const int items,
                    const int chunk, const int winCap, const float *__restrict__ proj,
                    float *__restrict__ vol)
@@ -752,7 +756,7 @@ __device__ __forceinline__ bool next_item(const BatchTable &T, int *counter, int
 }
 
 template <bool EXACT, bool EC, int PMAX>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
 project_batched_kernel(const BatchProblem *__restrict__ probs, const BatchTable *__restrict__ T,
                        int *counter)
 {
@@ -767,7 +771,7 @@ project_batched_kernel(const BatchProblem *__restrict__ probs, const BatchTable 
 // Each problem runs with its own stack width, so its items are exactly those
 // of its single-problem launch.
 template <bool EXACT, bool EC, int PMAX>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
 backproject_batched_kernel(const BatchProblem *__restrict__ probs, const BatchTable *__restrict__ T,
                            int *counter, int winCap)
 {
