@@ -1,13 +1,13 @@
-"""U-Net kernels (BF16 MFMA convolutions, FP32 accumulation) against plain
-PyTorch CPU FP64 ops on the same BF16-rounded inputs, and a short training
-run that must lower the loss."""
+"""U-Net kernels (BF16 MFMA convolutions, FP32 accumulation) against the
+FP64 layer reference (oracle/unet.py) on the same BF16-rounded inputs, and a
+short training run that must lower the loss."""
 import ctypes
 
 import numpy as np
 import pytest
 import torch
-import torch.nn.functional as F
 
+from oracle import unet as OU
 from paper_2110_09841_amd import unet
 from paper_2110_09841_amd.unet import _check, _p, _s, desc, lib
 
@@ -23,13 +23,13 @@ def rnd(shape, seed, scale=1.0):
     return (scale * torch.randn(shape, generator=g)).to(torch.bfloat16)
 
 
+def f64(t):
+    return t.detach().cpu().double().numpy()
+
+
 def ref_conv(x_bf, w_bf, b=None):
     """x (D,H,W,Ci) bf16, w (27,Co,Ci) bf16 -> (D,H,W,Co) float64"""
-    x = x_bf.double().permute(3, 0, 1, 2).unsqueeze(0)
-    co, ci = w_bf.shape[1], w_bf.shape[2]
-    w = w_bf.double().reshape(3, 3, 3, co, ci).permute(3, 4, 0, 1, 2)
-    y = F.conv3d(x, w, bias=None if b is None else b.double(), padding=1)
-    return y[0].permute(1, 2, 3, 0)
+    return torch.from_numpy(OU.conv3d(f64(x_bf), f64(w_bf), None if b is None else f64(b)))
 
 
 def close_bf16(got, ref, what, k=2.0):
@@ -63,10 +63,7 @@ def test_conv3d_forward_backward_data_and_weight(ci, co, shape):
     _check(L.cvp_nn_transpose_weights(_p(wd), _p(wt), co, ci, _s()))
     gx = torch.empty((D, H, W, ci), dtype=torch.bfloat16, device="cuda")
     _check(L.cvp_nn_conv3d(ctypes.byref(desc(gy.cuda())), _p(wt), None, ctypes.byref(desc(gx)), 0, 1, _s()))
-    xr = x.double().permute(3, 0, 1, 2).unsqueeze(0)
-    wr = w.double().reshape(3, 3, 3, co, ci).permute(3, 4, 0, 1, 2)
-    gyr = gy.double().permute(3, 0, 1, 2).unsqueeze(0)
-    gx_ref = torch.nn.grad.conv3d_input(xr.shape, wr, gyr, padding=1)[0].permute(1, 2, 3, 0)
+    gx_ref = torch.from_numpy(OU.conv3d_grad_input(f64(gy), f64(w)))
     close_bf16(gx.cpu(), gx_ref, "conv backward-data")
     # backward-weight (FP32 out)
     n = ctypes.c_int64()
@@ -75,15 +72,14 @@ def test_conv3d_forward_backward_data_and_weight(ci, co, shape):
     gw = torch.empty((27, co, ci), dtype=torch.float32, device="cuda")
     gyd = gy.cuda()
     _check(L.cvp_nn_conv3d_wgrad(ctypes.byref(desc(xd)), ctypes.byref(desc(gyd)), _p(gw), _p(work), n.value, _s()))
-    gw_ref = torch.nn.grad.conv3d_weight(xr, wr.shape, gyr, padding=1)        # (co, ci, 3, 3, 3)
-    gw_ref = gw_ref.permute(2, 3, 4, 0, 1).reshape(27, co, ci)
+    gw_ref = torch.from_numpy(OU.conv3d_grad_weight(f64(x), f64(gy)))
     err = (gw.cpu().double() - gw_ref).abs().max() / gw_ref.abs().max()
     say("conv backward-weight rel err %.3e" % float(err))
     assert err < 1e-5
     # bias gradient
     gb = torch.empty(co, dtype=torch.float32, device="cuda")
     _check(L.cvp_nn_channel_sum(ctypes.byref(desc(gyd)), _p(gb), _p(work), n.value, _s()))
-    assert torch.allclose(gb.cpu().double(), gy.double().sum(dim=(0, 1, 2)), rtol=1e-5, atol=1e-4)
+    assert np.allclose(f64(gb), OU.bias_grad(f64(gy)), rtol=1e-5, atol=1e-4)
 
 
 def test_channel_slices_pool_upsample_add_head():
@@ -93,18 +89,18 @@ def test_channel_slices_pool_upsample_add_head():
     sl = desc(big, 16, 16)                         # channels 16..31
     pooled = torch.empty((D // 2, H // 2, W // 2, 16), dtype=torch.bfloat16, device="cuda")
     _check(L.cvp_nn_avgpool2(ctypes.byref(sl), ctypes.byref(desc(pooled)), _s()))
-    ref = F.avg_pool3d(big[..., 16:].cpu().double().permute(3, 0, 1, 2).unsqueeze(0), 2)[0].permute(1, 2, 3, 0)
+    ref = torch.from_numpy(OU.avgpool2(f64(big[..., 16:])))
     close_bf16(pooled.cpu(), ref, "avgpool")
     up = torch.empty((D, H, W, 16), dtype=torch.bfloat16, device="cuda")
     _check(L.cvp_nn_upsample2(ctypes.byref(desc(pooled)), ctypes.byref(desc(up)), _s()))
-    refu = pooled.cpu().double().repeat_interleave(2, 0).repeat_interleave(2, 1).repeat_interleave(2, 2)
+    refu = torch.from_numpy(OU.upsample2(f64(pooled)))
     assert torch.equal(up.cpu().double(), refu)
     gin = torch.empty((D, H, W, 16), dtype=torch.bfloat16, device="cuda")
     _check(L.cvp_nn_avgpool2_bwd(ctypes.byref(desc(pooled)), ctypes.byref(desc(gin)), _s()))
-    close_bf16(gin.cpu(), refu / 8, "avgpool backward")
+    close_bf16(gin.cpu(), torch.from_numpy(OU.avgpool2_grad(f64(pooled))), "avgpool backward")
     gsm = torch.empty_like(pooled)
     _check(L.cvp_nn_upsample2_bwd(ctypes.byref(desc(up)), ctypes.byref(desc(gsm)), _s()))
-    close_bf16(gsm.cpu(), 8 * pooled.cpu().double(), "upsample backward")
+    close_bf16(gsm.cpu(), torch.from_numpy(OU.upsample2_grad(f64(up))), "upsample backward")
     s = torch.empty_like(up)
     _check(L.cvp_nn_add(ctypes.byref(desc(up)), ctypes.byref(desc(gin)), ctypes.byref(desc(s)), _s()))
     close_bf16(s.cpu(), up.cpu().double() + gin.cpu().double(), "add")
@@ -116,18 +112,18 @@ def test_channel_slices_pool_upsample_add_head():
     x0 = torch.empty_like(x2)
     sc = unet.INPUT_SCALE
     _check(L.cvp_nn_head(ctypes.byref(desc(h)), _p(w), _p(b), _p(x2), ctypes.c_float(sc), _p(x0), _s()))
-    ref0 = x2.double().cpu() + ((h.cpu().double() * w.cpu().double()).sum(-1) + 0.3) / sc
-    assert torch.allclose(x0.cpu().double(), ref0, rtol=1e-5, atol=1e-6)
+    ref0 = OU.head(f64(h), f64(w), 0.3, f64(x2), sc)
+    assert np.allclose(f64(x0), ref0, rtol=1e-5, atol=1e-6)
     g = torch.rand((D, H, W), device="cuda")
     dh = torch.empty_like(h)
     dwb = torch.empty(17, device="cuda")
     work = torch.empty(4096, device="cuda")
     _check(L.cvp_nn_head_bwd(ctypes.byref(desc(h)), _p(w), _p(g), ctypes.c_float(sc), ctypes.byref(desc(dh)), _p(dwb),
                              _p(work), 4096, _s()))
-    gd = g.cpu().double() / sc
-    close_bf16(dh.cpu(), gd.unsqueeze(-1) * w.cpu().double(), "head backward dh")
-    assert torch.allclose(dwb[:16].cpu().double(), (h.cpu().double() * gd.unsqueeze(-1)).sum(dim=(0, 1, 2)), rtol=1e-4)
-    assert abs(float(dwb[16]) - float(gd.sum())) < 1e-4 * abs(float(gd.sum()))
+    rdh, rdw, rdb = OU.head_grad(f64(h), f64(w), f64(g), sc)
+    close_bf16(dh.cpu(), torch.from_numpy(rdh), "head backward dh")
+    assert np.allclose(f64(dwb[:16]), rdw, rtol=1e-4)
+    assert abs(float(dwb[16]) - rdb) < 1e-4 * abs(rdb)
 
 
 def test_mse_and_adam():
@@ -138,10 +134,9 @@ def test_mse_and_adam():
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
     work = torch.empty(1024, dtype=torch.float64, device="cuda")
     _check(L.cvp_nn_mse(_p(a), _p(b), 1000, _p(g), _p(loss), _p(work), 1024, _s()))
-    ad, bd = a.cpu().double(), b.cpu().double()
-    ref = float(((ad - bd) ** 2).mean())
+    ref, rgrad = OU.mse(f64(a), f64(b))
     assert abs(float(loss) - ref) < 1e-7 * ref   # FP32 differences, FP64 sum
-    assert torch.allclose(g.cpu().double(), 2 * (ad - bd) / 1000, rtol=1e-6, atol=1e-9)
+    assert np.allclose(f64(g), rgrad, rtol=1e-6, atol=1e-9)
     p = torch.rand(50, device="cuda")
     p0 = p.cpu().double().clone()
     gr = torch.randn(50, device="cuda")
@@ -150,10 +145,7 @@ def test_mse_and_adam():
     pm, pv, pp = np.zeros(50), np.zeros(50), p0.numpy().copy()
     for step in range(1, 4):
         _check(L.cvp_nn_adam(_p(p), _p(gr), _p(m), _p(v), 50, 1e-2, 0.9, 0.999, 1e-8, step, None, _s()))
-        gg = gr.cpu().double().numpy()
-        pm = 0.9 * pm + 0.1 * gg
-        pv = 0.999 * pv + 0.001 * gg * gg
-        pp = pp - 1e-2 * (pm / (1 - 0.9 ** step)) / (np.sqrt(pv / (1 - 0.999 ** step)) + 1e-8)
+        pp, pm, pv = OU.adam_step(pp, f64(gr), pm, pv, step, 1e-2)
     assert np.allclose(p.cpu().double().numpy(), pp, rtol=1e-5, atol=1e-6)
 
 
