@@ -120,10 +120,14 @@ conv3d_kernel(const Act in, const __bf16 *__restrict__ wt, const float *__restri
 
 // Backward-weight partials: for the taps (dz, dy) = tap9 and all three dx,
 // and a chunk of `rows` (d, h) rows, part[chunk][tap][co][ci] =
-// sum over the chunk's voxels of dY[v][co] * X[v + off][ci].  dY and the
-// three dx-shifted X rows of one 64-voxel segment are staged transposed in
-// LDS ([channel][voxel]); lanes read 8 consecutive voxels per 16-byte read.
-// Wave w owns output-channel tiles co in [16 w', ...) round-robin.
+// sum over the chunk's voxels of dY[v][co] * X[v + off][ci].  Per 64-voxel
+// segment, dY and the three dx-shifted X rows are staged transposed in LDS
+// as [channel][voxel pair]: a thread loads 8 channels of two neighbouring
+// voxels (two 16-byte loads) and writes 8 words each holding the channel's
+// two BF16 values, so the writes of a wave are consecutive words.  A lane's
+// MFMA fragment (8 consecutive voxels of one channel) is then one 16-byte
+// LDS read; the row pitch of 36 words keeps those reads conflict free.
+// Wave w owns the 16x16 (co, ci) tiles w, w + 4, ...
 template <int CO, int CI>
 __global__ void __launch_bounds__(256)
 conv3d_wgrad_kernel(const Act x, const Act dy, int rows_per_chunk, float *__restrict__ part)
@@ -131,8 +135,9 @@ conv3d_wgrad_kernel(const Act x, const Act dy, int rows_per_chunk, float *__rest
     constexpr int MT = CO / 16, NT = CI / 16;
     constexpr int TILES = MT * NT;                 // 16x16 tiles per tap
     constexpr int PER_WAVE = (TILES + 3) / 4;
-    __shared__ __align__(16) __bf16 sdy[CO][64];
-    __shared__ __align__(16) __bf16 sx[3][CI][64];
+    constexpr int PITCH = 36;                      // words per channel row (32 voxel pairs + pad)
+    __shared__ __align__(16) unsigned sdy[CO * PITCH];
+    __shared__ __align__(16) unsigned sx[3 * CI * PITCH];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int tap9 = blockIdx.y;                   // (dz, dy) in 0..8
     const int dz = tap9 / 3 - 1, dyo = tap9 % 3 - 1;
@@ -148,41 +153,58 @@ conv3d_wgrad_kernel(const Act x, const Act dy, int rows_per_chunk, float *__rest
 #pragma unroll
         for (int q = 0; q < PER_WAVE; ++q) acc[t][q] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    // 8 channels of voxel w of a row (zero outside [0, W) or when !ok)
+    auto load8 = [](const Act &a, size_t rowbase, int w, int c0, bool ok) {
+        if (ok && w >= 0 && w < a.W)
+            return *reinterpret_cast<const bf16x8 *>(a.p + (rowbase + w) * a.stride + c0);
+        return zero8();
+    };
+    auto pack = [](__bf16 lo, __bf16 hi) {
+        return (unsigned)__builtin_bit_cast(unsigned short, lo) | ((unsigned)__builtin_bit_cast(unsigned short, hi) << 16);
+    };
+
     for (int rr = r0; rr < r1; ++rr) {
         const int d = rr / x.H, h = rr % x.H;
         const int z = d + dz, y = h + dyo;
         const bool zy = z >= 0 && z < x.D && y >= 0 && y < x.H;
+        const size_t dyrow = ((size_t)d * dy.H + h) * dy.W;
+        const size_t xrow = ((size_t)z * x.H + y) * x.W;
         for (int seg = 0; seg < segs; ++seg) {
             const int w0 = seg * 64;
             __syncthreads();
-            // stage dY[v][co] -> sdy[co][v] and X[z][y][w0 + v + dx][ci] -> sx[dx][ci][v]
-            for (int idx = threadIdx.x; idx < 64 * CO; idx += 256) {
-                const int v = idx / CO, c = idx % CO;
-                const int w = w0 + v;
-                sdy[c][v] = (w < dy.W) ? dy.p[(((size_t)d * dy.H + h) * dy.W + w) * dy.stride + c] : (__bf16)0.0f;
+            // dY: tasks (pair m, channel group g)
+            for (int task = threadIdx.x; task < 32 * (CO / 8); task += 256) {
+                const int m = task & 31, g = task >> 5;
+                const int wa = w0 + 2 * m;
+                const bf16x8 a = load8(dy, dyrow, wa, 8 * g, true);
+                const bf16x8 b = load8(dy, dyrow, wa + 1, 8 * g, true);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) sdy[(8 * g + e) * PITCH + m] = pack(a[e], b[e]);
             }
-            for (int idx = threadIdx.x; idx < 3 * 64 * CI; idx += 256) {
-                const int t = idx / (64 * CI);
-                const int rem = idx % (64 * CI);
-                const int v = rem / CI, c = rem % CI;
-                const int w = w0 + v + t - 1;
-                const bool ok = zy && w >= 0 && w < x.W && (w0 + v) < x.W;
-                sx[t][c][v] = ok ? x.p[(((size_t)z * x.H + y) * x.W + w) * x.stride + c] : (__bf16)0.0f;
+            // X, three dx shifts: tasks (pair m, channel group g, shift t)
+            for (int task = threadIdx.x; task < 3 * 32 * (CI / 8); task += 256) {
+                const int m = task & 31, g = (task >> 5) % (CI / 8), t = task / (32 * (CI / 8));
+                const int va = 2 * m, wa = w0 + va + t - 1;
+                const bf16x8 a = load8(x, xrow, wa, 8 * g, zy && w0 + va < x.W);
+                const bf16x8 b = load8(x, xrow, wa + 1, 8 * g, zy && w0 + va + 1 < x.W);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) sx[(t * CI + 8 * g + e) * PITCH + m] = pack(a[e], b[e]);
             }
             __syncthreads();
-            // K = 64 voxels = 2 MFMA steps of 32
+            // K = 64 voxels = 2 MFMA steps of 32; lane reads voxels v0 .. v0+7
 #pragma unroll
             for (int ks = 0; ks < 2; ++ks) {
-                const int v0 = ks * 32 + (lane >> 4) * 8;
+                const int p0 = ks * 16 + (lane >> 4) * 4;          // first voxel pair
 #pragma unroll
                 for (int q = 0; q < PER_WAVE; ++q) {
                     const int tile = wave + 4 * q;
                     if (tile < TILES) {
                         const int mt = tile / NT, nt = tile % NT;
-                        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&sdy[mt * 16 + (lane & 15)][v0]);
+                        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&sdy[(mt * 16 + (lane & 15)) * PITCH + p0]);
 #pragma unroll
                         for (int t = 0; t < 3; ++t) {
-                            const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&sx[t][nt * 16 + (lane & 15)][v0]);
+                            const bf16x8 b =
+                                *reinterpret_cast<const bf16x8 *>(&sx[(t * CI + nt * 16 + (lane & 15)) * PITCH + p0]);
                             acc[t][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t][q], 0, 0, 0);
                         }
                     }
@@ -220,16 +242,37 @@ __global__ void reduce_chunks(const float *__restrict__ part, int chunks, int64_
 }
 
 // Per-channel sums over voxels (bias gradient), partials per block row chunk.
+// Thread t takes channel group t % (C/8) of every (256/(C/8))-th voxel with
+// 16-byte loads; the block then adds the per-thread sums of each channel in
+// a fixed order.
 __global__ void channel_sum_partials(const Act a, int rows_per_chunk, float *__restrict__ part)
 {
+    __shared__ float red[256 * 8];
     const int chunk = blockIdx.x;
     const int nvox = a.D * a.H * a.W;
     const int v0 = chunk * rows_per_chunk * a.W;
     const int v1 = min(v0 + rows_per_chunk * a.W, nvox);
-    for (int c = threadIdx.x; c < a.C; c += blockDim.x) {
-        float s = 0.0f;
-        for (int v = v0; v < v1; ++v) s += (float)a.p[(size_t)v * a.stride + c];
-        part[(size_t)chunk * a.C + c] = s;
+    const int groups = a.C / 8;
+    const int g = threadIdx.x % groups, lanes = 256 / groups;
+    const int vt = threadIdx.x / groups;
+    float s[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) s[e] = 0.0f;
+    if (vt < lanes) {
+        for (int v = v0 + vt; v < v1; v += lanes) {
+            const bf16x8 q = *reinterpret_cast<const bf16x8 *>(a.p + (size_t)v * a.stride + 8 * g);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) s[e] += (float)q[e];
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) red[threadIdx.x * 8 + e] = s[e];
+    __syncthreads();
+    for (int c = threadIdx.x; c < a.C; c += 256) {
+        const int gg = c / 8, e = c % 8;
+        float t = 0.0f;
+        for (int k = 0; k < lanes; ++k) t += red[(k * groups + gg) * 8 + e];
+        part[(size_t)chunk * a.C + c] = t;
     }
 }
 
@@ -529,10 +572,11 @@ cvp_status cvp_nn_channel_sum(const cvp_nn_tensor *a, float *out, float *work, i
                               void *stream)
 {
     if (!valid(a) || !out || !work) return CVP_E_INVALID;
+    if (a->channels > 2048) return CVP_E_UNSUPPORTED;
     const int rows = a->d * a->h, rpc = 16, chunks = (rows + rpc - 1) / rpc;
     if (work_floats < (int64_t)chunks * a->channels) return CVP_E_INVALID;
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(cvpnn::channel_sum_partials, dim3(chunks), dim3(64), 0, s, act(a), rpc, work);
+    hipLaunchKernelGGL(cvpnn::channel_sum_partials, dim3(chunks), dim3(256), 0, s, act(a), rpc, work);
     hipLaunchKernelGGL(cvpnn::reduce_chunks, dim3(1), dim3(64), 0, s, work, chunks, (int64_t)a->channels, out);
     return st(hipGetLastError());
 }
