@@ -231,13 +231,22 @@ conv3d_wgrad_kernel(const Act x, const Act dy, int rows_per_chunk, float *__rest
     }
 }
 
-// out[i] = sum over chunks of part[chunk][i] (fixed order), i < n
+// out[i] = sum over chunks of part[chunk][i], i < n.  A block takes 64
+// consecutive i; wave w sums the chunks c = w, w + 4, ... in order and the
+// four wave sums are added in a fixed order (deterministic).
 __global__ void reduce_chunks(const float *__restrict__ part, int chunks, int64_t n, float *__restrict__ out)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    __shared__ float red[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int64_t base = (int64_t)blockIdx.x * 64; base < n; base += (int64_t)gridDim.x * 64) {
+        const int64_t i = base + lane;
         float s = 0.0f;
-        for (int c = 0; c < chunks; ++c) s += part[(size_t)c * n + i];
-        out[i] = s;
+        if (i < n)
+            for (int c = wave; c < chunks; c += 4) s += part[(size_t)c * n + i];
+        red[wave][lane] = s;
+        __syncthreads();
+        if (wave == 0 && i < n) out[i] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+        __syncthreads();
     }
 }
 
@@ -564,7 +573,7 @@ cvp_status cvp_nn_conv3d_wgrad(const cvp_nn_tensor *x, const cvp_nn_tensor *dy, 
     else return CVP_E_UNSUPPORTED;
 #undef WG
     const int64_t n = (int64_t)27 * co * ci;
-    hipLaunchKernelGGL(cvpnn::reduce_chunks, dim3(grid_for(n)), dim3(256), 0, s, work, chunks, n, dw);
+    hipLaunchKernelGGL(cvpnn::reduce_chunks, dim3(grid_for(4 * n)), dim3(256), 0, s, work, chunks, n, dw);
     return st(hipGetLastError());
 }
 
@@ -577,7 +586,7 @@ cvp_status cvp_nn_channel_sum(const cvp_nn_tensor *a, float *out, float *work, i
     if (work_floats < (int64_t)chunks * a->channels) return CVP_E_INVALID;
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(cvpnn::channel_sum_partials, dim3(chunks), dim3(256), 0, s, act(a), rpc, work);
-    hipLaunchKernelGGL(cvpnn::reduce_chunks, dim3(1), dim3(64), 0, s, work, chunks, (int64_t)a->channels, out);
+    hipLaunchKernelGGL(cvpnn::reduce_chunks, dim3(1), dim3(256), 0, s, work, chunks, (int64_t)a->channels, out);
     return st(hipGetLastError());
 }
 
@@ -660,7 +669,7 @@ cvp_status cvp_nn_head_bwd(const cvp_nn_tensor *h, const float *w, const float *
     if (work_floats < (int64_t)blocks * 17) return CVP_E_INVALID;
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(cvpnn::head_bwd, dim3(blocks), dim3(256), 0, s, act(h), w, g, 1.0f / scale, act(dh), per, work);
-    hipLaunchKernelGGL(cvpnn::reduce_chunks, dim3(1), dim3(64), 0, s, work, blocks, (int64_t)17, dwb);
+    hipLaunchKernelGGL(cvpnn::reduce_chunks, dim3(1), dim3(256), 0, s, work, blocks, (int64_t)17, dwb);
     return st(hipGetLastError());
 }
 
