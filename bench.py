@@ -39,6 +39,7 @@ def parse():
     ap.add_argument("--launch", default=None, metavar="U,GW",
                     help="fixed launch plan (projection band columns, backprojection stack columns); no autotuning")
     ap.add_argument("--cgls-max-iter", type=int, default=200)
+    ap.add_argument("--no-network", action="store_true", help="skip the warm-start network timing")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run only a 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -96,6 +97,38 @@ def measured_traffic(kernel):
     return {"bytes": rec[kernel]["fetch_bytes"] + rec[kernel]["write_bytes"],
             "fetch_bytes": rec[kernel]["fetch_bytes"], "write_bytes": rec[kernel]["write_bytes"],
             "algorithmic_bytes": rec["algorithmic_bytes_per_launch"], "plan": rec.get("plan")}
+
+
+def network_timing(reps=5):
+    """Warm-start U-Net at 128^3 (the warm-start workload's volume): forward
+    pass and full training step (forward, backward, Adam), HIP events."""
+    import torch
+    from paper_2110_09841_amd.unet import UNet, forward_flops
+    shape = (128, 128, 128)
+    net = UNet(shape, seed=1)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x1, x2, t = (0.01 * torch.rand(shape, generator=g, device="cuda") for _ in range(3))
+    for _ in range(2):
+        net.train_step(x1, x2, t)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record()
+    for _ in range(reps):
+        net.forward(x1, x2)
+    ev[1].record()
+    for _ in range(reps):
+        net.train_step(x1, x2, t)
+    ev[2].record()
+    torch.cuda.synchronize()
+    fwd = ev[0].elapsed_time(ev[1]) / reps
+    step = ev[1].elapsed_time(ev[2]) / reps
+    fl = forward_flops(shape)
+    res = {"shape": list(shape), "forward_ms": fwd, "train_step_ms": step, "forward_gflop": fl / 1e9,
+           "forward_tflops": fl / (fwd * 1e-3) / 1e12, "peak_bf16_tflops": 2500.0,
+           "train_step_tflops": 3 * fl / (step * 1e-3) / 1e12}
+    del net
+    torch.cuda.empty_cache()
+    return res
 
 
 def cgls_to_tolerance(G, opts, x_true, max_iter):
@@ -208,6 +241,8 @@ def main():
     }
     if not args.no_cgls:
         out["cgls"] = cgls_to_tolerance(G, opts, x, args.cgls_max_iter)
+    if not args.no_network:
+        out["warm_start_network"] = network_timing()
     del x, b, p_out, v_out
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:

@@ -289,6 +289,7 @@ cvp_status cvp_geometry_from_views(const cvp_geometry_desc *d, cvp_geometry **ou
     G.a1 = a1; G.a2 = a2; G.a3 = a3;
     G.x1lo = x1lo; G.x2lo = x2lo; G.x3lo = x3lo;
     G.b1 = b1; G.b2 = b2; G.c1 = c1; G.c2 = c2; G.f = f;
+    G.fb1 = f / b1; G.fb2 = f / b2; G.b2f = b2 / f;
     G.views = g->d_views;
     G.sigma = nullptr;
     G.raw_volume = 0;

@@ -31,6 +31,7 @@ struct DevGeom {
     double a1, a2, a3;
     double x1lo, x2lo, x3lo;   // lower corner of the volume box
     double b1, b2, c1, c2, f;
+    double fb1, fb2, b2f;      // f / b1, f / b2, b2 / f
     const ViewGeom *views;     // device, [nviews]
     const float *sigma;        // device, [N][M] pixel factors (nullptr: 1)
     int raw_volume;            // weight = cut volume (no 1/r^2)

@@ -108,6 +108,7 @@ __device__ __forceinline__ Mom halfplane_moments(double h1, double h2, double gx
 struct Column {
     double xc1, xc2;   // centre
     double Dc;         // depth of the centre, d.(xc - s)
+    double iDc;        // 1 / Dc
     double chic;       // chi1 of the centre
     double chimin, chimax;
 };
@@ -121,8 +122,9 @@ __device__ __forceinline__ Column make_column(const DevGeom &G, const ViewGeom &
     const double r1 = C.xc1 - V.s1, r2 = C.xc2 - V.s2;
     const double P1 = V.e1x * r1 + V.e1y * r2;
     C.Dc = V.dx * r1 + V.dy * r2;
-    const double fb = G.f / G.b1;
-    C.chic = G.c1 + fb * P1 / C.Dc;
+    C.iDc = 1.0 / C.Dc;
+    const double fb = G.fb1;
+    C.chic = G.c1 + fb * P1 * C.iDc;
     double mn = 1e300, mx = -1e300;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -141,8 +143,8 @@ __device__ __forceinline__ Mom column_prefix(const DevGeom &G, const ViewGeom &V
                                              double t)
 {
 #pragma clang fp contract(off)
-    const double fb = G.f / G.b1;
-    const double inv = 1.0 / C.Dc;
+    const double fb = G.fb1;
+    const double inv = C.iDc;
     const double gx = (fb * V.e1x - (t - G.c1) * V.dx) * inv;
     const double gy = (fb * V.e1y - (t - G.c1) * V.dy) * inv;
     return halfplane_moments(0.5 * G.a1, 0.5 * G.a2, gx, gy, C.chic - t);
@@ -165,17 +167,20 @@ __device__ __forceinline__ void piece_record(const DevGeom &G, const ViewGeom &V
     const double A = 0.5 * a2;
     double cx = 0.0, cy = 0.0, var = 0.0;
     if (A > 1e-12 * G.a1 * G.a2) {
-        cx = (hi.sx - lo.sx) / (3.0 * a2);
-        cy = (hi.sy - lo.sy) / (3.0 * a2);
-        const double cxx = (hi.sxx - lo.sxx) / (12.0 * A) - cx * cx;
-        const double cyy = (hi.syy - lo.syy) / (12.0 * A) - cy * cy;
-        const double cxy = (hi.sxy - lo.sxy) / (24.0 * A) - cx * cy;
+        // one division: 1/(3 a2), 1/(12 A) = 2/(3 a2), 1/(24 A) = 1/(3 a2)
+        const double i3 = 1.0 / (3.0 * a2);
+        cx = (hi.sx - lo.sx) * i3;
+        cy = (hi.sy - lo.sy) * i3;
+        const double cxx = (hi.sxx - lo.sxx) * (0.5 * i3) - cx * cx;
+        const double cyy = (hi.syy - lo.syy) * (0.5 * i3) - cy * cy;
+        const double cxy = (hi.sxy - lo.sxy) * (0.25 * i3) - cx * cy;
         var = V.dx * V.dx * cxx + 2.0 * V.dx * V.dy * cxy + V.dy * V.dy * cyy;
         if (!(var > 0.0)) var = 0.0;
     }
     const double Du = C.Dc + V.dx * cx + V.dy * cy;
-    const double gmm = G.b2 * Du / G.f;          // x3 mm per detector row at depth Du
-    const double ig = G.f / (G.b2 * Du);
+    const double iDu = 1.0 / Du;
+    const double gmm = G.b2f * Du;               // x3 mm per detector row at depth Du
+    const double ig = G.fb2 * iDu;
     const double Y0 = G.c2 - (G.x3lo + G.a3 - V.s3) * ig;
     const double beta = G.a3 * ig;
     const double Y0h = rint(Y0 * 1024.0) * (1.0 / 1024.0);
@@ -195,7 +200,7 @@ __device__ __forceinline__ void piece_record(const DevGeom &G, const ViewGeom &V
     rec[4] = (float)bh;
     rec[5] = (float)(beta - bh);
     rec[6] = (float)beta;
-    rec[7] = EC ? (float)(sqrt(3.0 * var) / Du) : 0.0f;
+    rec[7] = EC ? (float)(sqrt(3.0 * var) * iDu) : 0.0f;
     rec[8] = (float)R2;
     rec[9] = (float)gmm;
     rec[10] = 0.0f;

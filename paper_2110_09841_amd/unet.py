@@ -114,6 +114,17 @@ class Conv:
         _check(lib().cvp_nn_transpose_weights(_p(self.wb), _p(self.wt), self.co, self.ci, _s()))
 
 
+LAYERS = [("c1a", IN_CH, 16, 1), ("c1b", 16, 16, 1), ("c2a", 16, 32, 2), ("c2b", 32, 32, 2), ("c3a", 32, 64, 4),
+          ("c3b", 64, 64, 4), ("u2", 64, 32, 2), ("d2a", 64, 32, 2), ("d2b", 32, 32, 2), ("u1", 32, 16, 1),
+          ("d1a", 32, 16, 1), ("d1b", 16, 16, 1)]   # name, Cin, Cout, resolution divisor
+
+
+def forward_flops(shape):
+    """Multiply-add count x 2 of one forward pass (the 3x3x3 convolutions)."""
+    n = shape[0] * shape[1] * shape[2]
+    return sum(2 * 27 * ci * co * n // (s ** 3) for _, ci, co, s in LAYERS)
+
+
 class UNet:
     def __init__(self, shape, seed=0, device="cuda"):
         D, H, W = shape
@@ -121,10 +132,7 @@ class UNet:
         self.shape = tuple(shape)
         self.device = device
         rng = np.random.default_rng(seed)
-        spec = [("c1a", IN_CH, 16), ("c1b", 16, 16), ("c2a", 16, 32), ("c2b", 32, 32), ("c3a", 32, 64),
-                ("c3b", 64, 64), ("u2", 64, 32), ("d2a", 64, 32), ("d2b", 32, 32), ("u1", 32, 16),
-                ("d1a", 32, 16), ("d1b", 16, 16)]
-        self.convs = {n: Conv(ci, co, rng, device) for n, ci, co in spec}
+        self.convs = {n: Conv(ci, co, rng, device) for n, ci, co, _ in LAYERS}
         self.hw = torch.from_numpy(rng.uniform(-0.25, 0.25, size=16).astype(np.float32)).to(device)
         self.hb = torch.zeros(1, dtype=torch.float32, device=device)
         self.ghead = torch.zeros(17, dtype=torch.float32, device=device)
