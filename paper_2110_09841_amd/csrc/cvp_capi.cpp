@@ -121,7 +121,7 @@ bool plan_projection(int N, int n2, int M, int nviews, int pmax, int force_u, Pr
     return true;
 }
 
-// Backprojection: stacks of GW columns x 64 voxels; the widest GW whose
+// Backprojection: stacks of GW columns x 128 voxels; the widest GW whose
 // estimated detector window fits the per-wave LDS window (force_gw > 0 fixes it).
 bool plan_backprojection(const DevGeom &G, int pmax, double zabs, double Dmin, int force_gw,
                          BackLaunch &L)
@@ -134,7 +134,7 @@ bool plan_backprojection(const DevGeom &G, int pmax, double zabs, double Dmin, i
         const int c = (int)((kBackLdsBudget / (kWaves * 4) - rec) / 4 * 4);
         const double wu = std::hypot(cand * G.a1, G.a2) * mag / G.b1 + pmax + 2;
         const double zspan = std::hypot(cand * G.a1, G.a2);
-        const double wv = 64 * G.a3 * mag / G.b2 + zabs * (G.f / G.b2) * zspan / (Dmin * Dmin) + 6;
+        const double wv = 64 * kBackPasses * G.a3 * mag / G.b2 + zabs * (G.f / G.b2) * zspan / (Dmin * Dmin) + 6;
         gw = cand;
         cap = c;
         if (wu * ((int)wv | 1) <= c) break;
@@ -144,7 +144,7 @@ bool plan_backprojection(const DevGeom &G, int pmax, double zabs, double Dmin, i
     L.win_cap = cap;
     L.pmax = pmax;
     L.ngroups = (G.n1 + gw - 1) / gw;
-    L.nkchunks = (G.n3 + 63) / 64;
+    L.nkchunks = (G.n3 + 64 * kBackPasses - 1) / (64 * kBackPasses);
     L.items = G.n2 * L.ngroups * L.nkchunks;
     L.chunk = (L.items + 7) / 8;
     L.lds = backproject_lds_bytes(gw, pmax, cap);

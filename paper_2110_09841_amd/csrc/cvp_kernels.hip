@@ -16,7 +16,7 @@
 //    largest |mu| it reads).  The band is written once at the end, scaled by
 //    sigma.  Integer sums make the result independent of the order of the
 //    additions, hence of the launch plan.
-//  * backprojection: a workgroup owns a 64-voxel-tall stack of GW columns;
+//  * backprojection: a workgroup owns a 128-voxel-tall stack of GW columns;
 //    each wave takes every 4th view, stages the pre-scaled detector window of
 //    the stack in LDS and gathers into registers.  Each voxel is written once.
 //
@@ -567,7 +567,9 @@ project_kernel(const DevGeom G, const int U, const int nbands, const float *__re
 
 // ------------------------------------------------------------ backprojection
 
-// One work item of the backprojection: a stack of GW columns x 64 voxels.
+// One work item of the backprojection: a stack of GW columns x 128 voxels,
+// gathered in two 64-voxel passes that share each view's piece records and
+// detector window (halving their cost per voxel).
 template <bool EXACT, bool EC, int PMAX, int GW>
 __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngroups,
                                                  const int nkchunks, const int winCap,
@@ -579,12 +581,11 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
     const int t = item / nkchunks;
     const int q = t % ngroups;
     const int j = t / ngroups;
+    constexpr int KP = kBackPasses;
     const int i0 = q * GW;
-    const int k0 = kch * kWave;
+    const int k0 = kch * kWave * KP;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    const int k = k0 + lane;
-    const bool kv = k < G.n3;
-    const int kmax = min(k0 + kWave, G.n3) - 1;
+    const int kmax = min(k0 + kWave * KP, G.n3) - 1;
 
     const int recFloats = GW * PMAX * kRecFloats + GW;
     const int waveFloats = ((recFloats + winCap + 3) / 4) * 4;
@@ -595,11 +596,12 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
     const float c2f = (float)G.c2;
     const float a3f = (float)G.a3;
     const bool raw = G.raw_volume != 0;
-    const float kf = (float)k;
 
-    float acc[GW];
+    float acc[KP][GW];
 #pragma unroll
-    for (int c = 0; c < GW; ++c) acc[c] = 0.0f;
+    for (int ps = 0; ps < KP; ++ps)
+#pragma unroll
+        for (int c = 0; c < GW; ++c) acc[ps][c] = 0.0f;
 
     for (int view = wave; view < G.nviews; view += kWaves) {
         const ViewGeom V = G.views[view];
@@ -644,8 +646,6 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
         const int H = wv1 - wv0 + 1;
         const int Hp = H | 1;
         const float *pv = proj + (size_t)view * G.N * G.M;
-        const float zt = fmaf(kf, a3f, (float)(G.x3lo + G.a3 - V.s3));
-        const float zc = zt - 0.5f * a3f;
 
         const bool useWin = Wd * Hp <= winCap;
         if (useWin) {
@@ -659,6 +659,14 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
         }
         wave_sync();
 
+#pragma unroll
+        for (int ps = 0; ps < KP; ++ps) {
+        if (k0 + ps * kWave >= G.n3) break;           // pass past the last slice
+        const int k = k0 + ps * kWave + lane;
+        const bool kv = k < G.n3;
+        const float kf = (float)k;
+        const float zt = fmaf(kf, a3f, (float)(G.x3lo + G.a3 - V.s3));
+        const float zc = zt - 0.5f * a3f;
 #pragma unroll
         for (int c = 0; c < GW; ++c) {
             const int np = npc[c];
@@ -709,23 +717,28 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
                     s1p = s1n;
                 }
             }
-            acc[c] += a;
+            acc[ps][c] += a;
+        }
         }
         wave_sync();
     }
 
     // Sum the four waves' partial sums in a fixed order; one store per voxel.
-    __syncthreads();
     float *red = smem;   // [kWaves][GW][kWave], aliases the per-wave areas
 #pragma unroll
-    for (int c = 0; c < GW; ++c) red[(wave * GW + c) * kWave + lane] = acc[c];
-    __syncthreads();
-    for (int c = wave; c < GW; c += kWaves) {
-        const int i = i0 + c;
-        float s = red[(0 * GW + c) * kWave + lane];
+    for (int ps = 0; ps < KP; ++ps) {
+        __syncthreads();
 #pragma unroll
-        for (int w = 1; w < kWaves; ++w) s += red[(w * GW + c) * kWave + lane];
-        if (kv && i < G.n1) vol[((size_t)k * G.n2 + j) * G.n1 + i] = s;
+        for (int c = 0; c < GW; ++c) red[(wave * GW + c) * kWave + lane] = acc[ps][c];
+        __syncthreads();
+        const int k = k0 + ps * kWave + lane;
+        for (int c = wave; c < GW; c += kWaves) {
+            const int i = i0 + c;
+            float s = red[(0 * GW + c) * kWave + lane];
+#pragma unroll
+            for (int w = 1; w < kWaves; ++w) s += red[(w * GW + c) * kWave + lane];
+            if (k < G.n3 && i < G.n1) vol[((size_t)k * G.n2 + j) * G.n1 + i] = s;
+        }
     }
 }
 
