@@ -135,6 +135,7 @@ bool plan_backprojection(const DevGeom &G, int pmax, double zabs, double Dmin, i
         const double wu = std::hypot(cand * G.a1, G.a2) * mag / G.b1 + pmax + 2;
         const double zspan = std::hypot(cand * G.a1, G.a2);
         const double wv = 64 * kBackPasses * G.a3 * mag / G.b2 + zabs * (G.f / G.b2) * zspan / (Dmin * Dmin) + 6;
+        if (c < kBackPasses * cand * 64) continue;     // the window area also parks the accumulators
         gw = cand;
         cap = c;
         if (wu * ((int)wv | 1) <= c) break;

@@ -605,6 +605,13 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
 
     for (int view = wave; view < G.nviews; view += kWaves) {
         const ViewGeom V = G.views[view];
+        // The accumulators wait in the (idle) window area while the FP64
+        // record stage, the kernel's register peak, runs.
+#pragma unroll
+        for (int ps = 0; ps < KP; ++ps)
+#pragma unroll
+            for (int c = 0; c < GW; ++c) win[(ps * GW + c) * kWave + lane] = acc[ps][c];
+        wave_sync();
         build_records<EXACT, EC, PMAX, GW>(G, V, i0, j, 0, G.M - 1, rec, npc, lane);
         wave_sync();
 
@@ -635,10 +642,12 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
                 wv1 = max(wv1, __shfl_xor(wv1, off));
             }
         }
-        if (wu1 < wu0 || wv1 < wv0) {
-            wave_sync();
-            continue;
-        }
+#pragma unroll
+        for (int ps = 0; ps < KP; ++ps)
+#pragma unroll
+            for (int c = 0; c < GW; ++c) acc[ps][c] = win[(ps * GW + c) * kWave + lane];
+        wave_sync();
+        if (wu1 < wu0 || wv1 < wv0) continue;
         // one spare row each side absorbs FP32 rounding of intermediate k
         wv0 = max(wv0 - 1, 0);
         wv1 = min(wv1 + 1, G.N - 1);
