@@ -40,6 +40,7 @@ def parse():
                     help="fixed launch plan (projection band columns, backprojection stack columns); no autotuning")
     ap.add_argument("--cgls-max-iter", type=int, default=200)
     ap.add_argument("--no-network", action="store_true", help="skip the warm-start network timing")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 16-problem batched timing")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run only a 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -97,6 +98,50 @@ def measured_traffic(kernel):
     return {"bytes": rec[kernel]["fetch_bytes"] + rec[kernel]["write_bytes"],
             "fetch_bytes": rec[kernel]["fetch_bytes"], "write_bytes": rec[kernel]["write_bytes"],
             "algorithmic_bytes": rec["algorithmic_bytes_per_launch"], "plan": rec.get("plan")}
+
+
+def batched_timing(reps=2):
+    """The 16-problem batch (volumes 96^3..320^3, 60..400 views): one
+    persistent launch per direction against 16 single-problem launches."""
+    import torch
+    from paper_2110_09841_amd import cvp, synth
+    params = synth.config_batch()
+    geoms = [cvp.Geometry(p) for p in params]
+    batch = cvp.Batch(geoms)
+    opts = cvp.Options(variant="relaxed", ec=True)
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    xs = [torch.rand(g.vol_shape, generator=gen, device="cuda") for g in geoms]
+    bs = [torch.rand(g.proj_shape, generator=gen, device="cuda") for g in geoms]
+    po = [torch.empty(g.proj_shape, device="cuda") for g in geoms]
+    vo = [torch.empty(g.vol_shape, device="cuda") for g in geoms]
+
+    def batched():
+        cvp.project_batched(xs, batch, opts, outs=po)
+        cvp.backproject_batched(bs, batch, opts, outs=vo)
+
+    def single():
+        for q, g in enumerate(geoms):
+            cvp.project(xs[q], g, opts, out=po[q])
+            cvp.backproject(bs[q], g, opts, out=vo[q])
+
+    times = {}
+    for name, fn in (("batched", batched), ("single", single)):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        times[name] = e0.elapsed_time(e1) / reps
+    vv = 2 * sum(g.n_voxels * g.n_views for g in geoms)
+    res = {"workload": "batch16_96c_320c", "problems": len(geoms), "voxel_views": vv,
+           "batched_ms": times["batched"], "single_launches_ms": times["single"],
+           "batched_voxel_views_per_s": vv / (times["batched"] * 1e-3)}
+    del xs, bs, po, vo, batch, geoms
+    torch.cuda.empty_cache()
+    return res
 
 
 def network_timing(reps=5):
@@ -243,6 +288,8 @@ def main():
         out["cgls"] = cgls_to_tolerance(G, opts, x, args.cgls_max_iter)
     if not args.no_network:
         out["warm_start_network"] = network_timing()
+    if not args.no_batched:
+        out["batched"] = batched_timing()
     del x, b, p_out, v_out
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
