@@ -36,8 +36,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cgls", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the planner's default launch plan")
-    ap.add_argument("--launch", default=None, metavar="U,GW",
-                    help="fixed launch plan (projection band columns, backprojection stack columns); no autotuning")
+    ap.add_argument("--launch", default=None, metavar="U,GW,KP",
+                    help="fixed launch plan (projection band columns, backprojection stack columns and passes); "
+                         "no autotuning")
     ap.add_argument("--cgls-max-iter", type=int, default=200)
     ap.add_argument("--no-network", action="store_true", help="skip the warm-start network timing")
     ap.add_argument("--no-batched", action="store_true", help="skip the 16-problem batched timing")
@@ -221,8 +222,7 @@ def main():
     opts = cvp.Options(variant=args.variant, ec=ec)
     plan = {"default": list(G.launch)}
     if args.launch:
-        u, gw = (int(t) for t in args.launch.split(","))
-        G.set_launch(u, gw)
+        G.set_launch(*(int(t) for t in args.launch.split(",")))
         plan["fixed"] = list(G.launch)
     elif not args.no_autotune:
         rec = autotune(G, opts, reps=2)
@@ -273,7 +273,7 @@ def main():
                    "detector": [g["det_cols"], g["det_rows"]], "pitch_mm": 0.616, "views": V,
                    "arc_deg": 200, "sid_mm": 749, "sdd_mm": 1198, "variant": args.variant,
                    "elevation_correction": ec, "scaling": "solid_angle",
-                   "launch": {"proj_band_cols": G.launch[0], "bp_stack_cols": G.launch[1]}},
+                   "launch": dict(zip(("proj_band_cols", "bp_stack_cols", "bp_passes"), G.launch))},
         "autotune": plan,
         "project": {"ms": 1e3 * tA.mean(), "voxel_views_per_s": vv / tA.mean()},
         "backproject": {"ms": 1e3 * tB.mean(), "voxel_views_per_s": vv / tB.mean()},

@@ -272,6 +272,9 @@ cvp_status cvp_synth_add_gaussian(float *d_out, int64_t n, float sigma, uint64_t
  *                   detector row and column of LDS (at most 156 KB in all), so
  *                   small values let more workgroups share a compute unit.
  *   bp_stack_cols   voxel columns per backprojection workgroup (16, 8 or 4).
+ *   bp_passes       64-voxel passes per backprojection stack (1 or 2): two
+ *                   passes share each view's piece records and detector
+ *                   window, one keeps the window small enough for LDS.
  * cvp_geometry_get_launch reports the plan in use (the planner's default
  * after cvp_geometry_from_views).  cvp_geometry_set_launch replaces it; a zero
  * field restores the default for that field.  Errors: CVP_E_INVALID (NULL or a
@@ -279,12 +282,14 @@ cvp_status cvp_synth_add_gaussian(float *d_out, int64_t n, float sigma, uint64_t
  * LDS); the plan is unchanged on error.  Set the plan while no other call
  * uses the geometry; launches already enqueued keep the plan they were
  * given, and batches keep the plans of their members at cvp_batch_create.
- * Results of a given plan are bitwise reproducible; two plans may differ in
- * the last bit of a few projection values (the fixed-point scale of a work
- * item depends on the part of the volume it reads). */
+ * Results of a given plan are bitwise reproducible; backprojections do not
+ * depend on the plan at all, while two plans may differ in the last bit of a
+ * few projection values (the fixed-point scale of a work item depends on the
+ * part of the volume it reads). */
 typedef struct {
     int32_t proj_band_cols;
     int32_t bp_stack_cols;
+    int32_t bp_passes;
 } cvp_launch;
 
 cvp_status cvp_geometry_get_launch(const cvp_geometry *g, cvp_launch *out);

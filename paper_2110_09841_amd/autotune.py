@@ -2,7 +2,8 @@
 
 Times the projection for a set of band widths (detector columns per work
 item, which also sets how many workgroups share a compute unit through their
-LDS footprint) and the backprojection for each stack width, on seeded random
+LDS footprint) and the backprojection for each stack width and number of
+64-voxel passes per stack, on seeded random
 data of the geometry's own shape, with HIP events on the current stream, and
 keeps the fastest of each.  Results can be cached in a JSON file keyed by the
 geometry and the options, so a later process reuses them without timing.
@@ -19,6 +20,7 @@ from .cvp import Geometry, Options, backproject, project
 
 DEFAULT_BANDS = (4, 6, 8, 9, 10, 12, 16, 19, 24, 32)
 DEFAULT_STACKS = (16, 8, 4)
+DEFAULT_PASSES = (2, 1)
 
 
 def _key(geom: Geometry, opts: Options):
@@ -48,8 +50,8 @@ def _time(fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def autotune(geom: Geometry, opts: Options, bands=DEFAULT_BANDS, stacks=DEFAULT_STACKS, reps=2,
-             cache=None, seed=0, log=None):
+def autotune(geom: Geometry, opts: Options, bands=DEFAULT_BANDS, stacks=DEFAULT_STACKS, passes=DEFAULT_PASSES,
+             reps=2, cache=None, seed=0, log=None):
     """Pick and set the fastest launch plan for (geom, opts).  Returns a dict
     with the chosen plan and the measured milliseconds per candidate.  With
     cache = path of a JSON file, a stored plan for the same key is applied
@@ -60,7 +62,7 @@ def autotune(geom: Geometry, opts: Options, bands=DEFAULT_BANDS, stacks=DEFAULT_
             table = json.load(f)
         if key in table:
             rec = table[key]
-            geom.set_launch(rec["proj_band_cols"], rec["bp_stack_cols"])
+            geom.set_launch(rec["proj_band_cols"], rec["bp_stack_cols"], rec["bp_passes"])
             return dict(rec, cached=True)
     g = torch.Generator(device=geom.device).manual_seed(seed)
     x = torch.rand(geom.vol_shape, generator=g, device=geom.device)
@@ -71,26 +73,27 @@ def autotune(geom: Geometry, opts: Options, bands=DEFAULT_BANDS, stacks=DEFAULT_
     p_ms, b_ms = {}, {}
     for u in bands:
         try:
-            geom.set_launch(u, default[1])
+            geom.set_launch(u, default[1], default[2])
         except _lib.CVPError:
             continue                            # band image too large for LDS
         p_ms[u] = _time(lambda: project(x, geom, opts, out=p_out), reps)
         if log:
             log("projection band %d: %.2f ms" % (u, p_ms[u]))
     for gw in stacks:
-        try:
-            geom.set_launch(default[0], gw)
-        except _lib.CVPError:
-            continue
-        b_ms[gw] = _time(lambda: backproject(b, geom, opts, out=v_out), reps)
-        if log:
-            log("backprojection stack %d: %.2f ms" % (gw, b_ms[gw]))
+        for kp in passes:
+            try:
+                geom.set_launch(default[0], gw, kp)
+            except _lib.CVPError:
+                continue
+            b_ms[(gw, kp)] = _time(lambda: backproject(b, geom, opts, out=v_out), reps)
+            if log:
+                log("backprojection stack %d, %d passes: %.2f ms" % (gw, kp, b_ms[(gw, kp)]))
     best_u = min(p_ms, key=p_ms.get) if p_ms else default[0]
-    best_gw = min(b_ms, key=b_ms.get) if b_ms else default[1]
-    geom.set_launch(best_u, best_gw)
-    rec = {"proj_band_cols": best_u, "bp_stack_cols": best_gw, "default": list(default),
+    best_gw, best_kp = min(b_ms, key=b_ms.get) if b_ms else (default[1], default[2])
+    geom.set_launch(best_u, best_gw, best_kp)
+    rec = {"proj_band_cols": best_u, "bp_stack_cols": best_gw, "bp_passes": best_kp, "default": list(default),
            "project_ms": {str(k): v for k, v in p_ms.items()},
-           "backproject_ms": {str(k): v for k, v in b_ms.items()}}
+           "backproject_ms": {"%d/%d" % k: v for k, v in b_ms.items()}}
     if cache:
         table = {}
         if os.path.exists(cache):

@@ -23,7 +23,7 @@ constexpr size_t kLdsMax = 156 * 1024;      // any plan: one workgroup per CU at
 constexpr size_t kLdsBatchMax = kLdsMax;
 bool plan_projection(int N, int n2, int M, int nviews, int pmax, int force_u, ProjLaunch &L);
 bool plan_backprojection(const DevGeom &G, int pmax, double zabs, double Dmin, int force_gw,
-                         BackLaunch &L);
+                         int force_kp, BackLaunch &L);
 }
 using cvp::kLdsBudget;
 
@@ -121,31 +121,39 @@ bool plan_projection(int N, int n2, int M, int nviews, int pmax, int force_u, Pr
     return true;
 }
 
-// Backprojection: stacks of GW columns x 128 voxels; the widest GW whose
-// estimated detector window fits the per-wave LDS window (force_gw > 0 fixes it).
+// Backprojection: stacks of GW columns x 64 kp voxels; the largest stack whose
+// estimated detector window fits the per-wave LDS window (force_gw > 0 and
+// force_kp > 0 fix them).
 bool plan_backprojection(const DevGeom &G, int pmax, double zabs, double Dmin, int force_gw,
-                         BackLaunch &L)
+                         int force_kp, BackLaunch &L)
 {
     const double mag = G.f / Dmin;
-    int gw = 4, cap = 0;
-    for (int cand : {16, 8, 4}) {
-        if (force_gw > 0 && cand != force_gw) continue;
+    // (stack width, passes) by stack area; the first whose estimated window
+    // fits the per-wave LDS window, else the last admissible one (its windows
+    // are then read from global memory)
+    static const int cands[6][2] = {{16, 2}, {16, 1}, {8, 2}, {8, 1}, {4, 2}, {4, 1}};
+    int gw = 0, kp = 0, cap = 0;
+    for (const auto &cd : cands) {
+        const int cand = cd[0], ckp = cd[1];
+        if ((force_gw > 0 && cand != force_gw) || (force_kp > 0 && ckp != force_kp)) continue;
         const size_t rec = (size_t)cand * pmax * kRecFloats + cand;
         const int c = (int)((kBackLdsBudget / (kWaves * 4) - rec) / 4 * 4);
+        if (c < kBackPasses * cand * 64 || c < 1024) continue;   // the window area also parks the accumulators
         const double wu = std::hypot(cand * G.a1, G.a2) * mag / G.b1 + pmax + 2;
         const double zspan = std::hypot(cand * G.a1, G.a2);
-        const double wv = 64 * kBackPasses * G.a3 * mag / G.b2 + zabs * (G.f / G.b2) * zspan / (Dmin * Dmin) + 6;
-        if (c < kBackPasses * cand * 64) continue;     // the window area also parks the accumulators
+        const double wv = 64 * ckp * G.a3 * mag / G.b2 + zabs * (G.f / G.b2) * zspan / (Dmin * Dmin) + 6;
         gw = cand;
+        kp = ckp;
         cap = c;
         if (wu * ((int)wv | 1) <= c) break;
     }
-    if (cap < 1024) return false;
+    if (gw == 0) return false;
     L.gw = gw;
+    L.kp = kp;
     L.win_cap = cap;
     L.pmax = pmax;
     L.ngroups = (G.n1 + gw - 1) / gw;
-    L.nkchunks = (G.n3 + 64 * kBackPasses - 1) / (64 * kBackPasses);
+    L.nkchunks = (G.n3 + 64 * kp - 1) / (64 * kp);
     L.items = G.n2 * L.ngroups * L.nkchunks;
     L.chunk = (L.items + 7) / 8;
     L.lds = backproject_lds_bytes(gw, pmax, cap);
@@ -312,7 +320,7 @@ cvp_status cvp_geometry_from_views(const cvp_geometry_desc *d, cvp_geometry **ou
         cvp_geometry_destroy(g);
         return fail(CVP_E_UNSUPPORTED, "detector rows (%d) or volume rows (%d) too large for the projection LDS layout", N, n2);
     }
-    if (!cvp::plan_backprojection(G, pmax, zabs, Dmin, 0, g->bl)) {
+    if (!cvp::plan_backprojection(G, pmax, zabs, Dmin, 0, 0, g->bl)) {
         cvp_geometry_destroy(g);
         return fail(CVP_E_UNSUPPORTED, "backprojection LDS window too small");
     }
@@ -326,6 +334,7 @@ cvp_status cvp_geometry_get_launch(const cvp_geometry *g, cvp_launch *out)
     if (!out) return fail(CVP_E_INVALID, "out is NULL");
     out->proj_band_cols = g->pl.U;
     out->bp_stack_cols = g->bl.gw;
+    out->bp_passes = g->bl.kp;
     return ok();
 }
 
@@ -333,18 +342,19 @@ cvp_status cvp_geometry_set_launch(cvp_geometry *g, const cvp_launch *in)
 {
     if (!g) return fail(CVP_E_INVALID, "geometry is NULL");
     if (!in) return fail(CVP_E_INVALID, "launch is NULL");
-    const int u = in->proj_band_cols, gw = in->bp_stack_cols;
+    const int u = in->proj_band_cols, gw = in->bp_stack_cols, kp = in->bp_passes;
     if (u < 0 || u > 32) return fail(CVP_E_INVALID, "launch.proj_band_cols = %d (0 or 1..32)", u);
     if (gw != 0 && gw != 4 && gw != 8 && gw != 16)
         return fail(CVP_E_INVALID, "launch.bp_stack_cols = %d (0, 4, 8 or 16)", gw);
+    if (kp < 0 || kp > cvp::kBackPasses) return fail(CVP_E_INVALID, "launch.bp_passes = %d (0, 1 or 2)", kp);
     const cvp::DevGeom &G = g->base;
     cvp::ProjLaunch pl{};
     cvp::BackLaunch bl{};
     if (!cvp::plan_projection(G.N, G.n2, G.M, G.nviews, g->pl.pmax, u, pl))
         return fail(CVP_E_UNSUPPORTED, "launch.proj_band_cols = %d: band image of %zu bytes exceeds the LDS limit", u,
                     cvp::project_lds_bytes(u, G.N, G.n2, g->pl.pmax));
-    if (!cvp::plan_backprojection(G, g->bl.pmax, g->zabs, g->Dmin, gw, bl))
-        return fail(CVP_E_UNSUPPORTED, "launch.bp_stack_cols = %d: detector window does not fit LDS", gw);
+    if (!cvp::plan_backprojection(G, g->bl.pmax, g->zabs, g->Dmin, gw, kp, bl))
+        return fail(CVP_E_UNSUPPORTED, "launch.bp_stack_cols = %d, bp_passes = %d: does not fit LDS", gw, kp);
     g->pl = pl;
     g->bl = bl;
     return ok();
@@ -463,8 +473,12 @@ cvp_status cvp_batch_create(const cvp_geometry *const *geoms, int32_t n, cvp_bat
         cvp::ProjLaunch pl = g->pl;
         pl.lds = cvp::project_lds_bytes(pl.U, g->base.N, g->base.n2, b->pmax);
         cvp::BackLaunch bl;
+        // the backprojection's sums do not depend on the stack shape, so a
+        // problem whose own stack width does not fit the common record
+        // stride may take another
         if (pl.lds > cvp::kLdsBatchMax ||
-            !cvp::plan_backprojection(g->base, b->pmax, g->zabs, g->Dmin, g->bl.gw, bl)) {
+            (!cvp::plan_backprojection(g->base, b->pmax, g->zabs, g->Dmin, g->bl.gw, g->bl.kp, bl) &&
+             !cvp::plan_backprojection(g->base, b->pmax, g->zabs, g->Dmin, 0, 0, bl))) {
             cvp_batch_destroy(b);
             return fail(CVP_E_UNSUPPORTED, "problem %d does not fit the common launch plan", q);
         }
@@ -472,6 +486,7 @@ cvp_status cvp_batch_create(const cvp_geometry *const *geoms, int32_t n, cvp_bat
         P.G = g->base;
         P.U = pl.U;
         P.gw = bl.gw;
+        P.kp = bl.kp;
         P.pitems = pl.items;
         P.ngroups = bl.ngroups;
         P.nkchunks = bl.nkchunks;

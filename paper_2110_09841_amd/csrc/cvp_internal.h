@@ -12,7 +12,7 @@ constexpr int kBlock = 256;           // threads per workgroup
 constexpr int kWaves = kBlock / kWave;
 constexpr int kRecFloats = 12;        // floats per cut-piece record
 constexpr float kYQuantumInv = 1024.0f;
-constexpr int kBackPasses = 2;        // 64-voxel passes per backprojection stack
+constexpr int kBackPasses = 2;        // most 64-voxel passes per backprojection stack
 
 // Per-view source-centred frame (Sec. II-C), FP64.  e1 and d have no x3
 // component on a circular orbit (that is what makes chi1 independent of x3,
@@ -53,7 +53,8 @@ struct ProjLaunch {
 struct BackLaunch {
     int gw;          // columns per group (16, 8 or 4)
     int ngroups;     // groups per row (ceil(n1 / gw))
-    int nkchunks;    // ceil(n3 / (64 * kBackPasses))
+    int kp;          // 64-voxel passes per stack (1 or 2)
+    int nkchunks;    // ceil(n3 / (64 * kp))
     int items;
     int chunk;
     int pmax;
@@ -69,6 +70,7 @@ struct BatchProblem {        // device table entry (one per problem)
     int U;                   // projection band width
     int pitems;              // projection work items
     int gw;                  // backprojection stack width of the problem's own plan
+    int kp;                  // and its passes per stack
     int ngroups;             // backprojection column groups per row
     int nkchunks;
     int bitems;              // backprojection work items

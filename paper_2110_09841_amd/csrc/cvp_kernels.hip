@@ -567,12 +567,12 @@ project_kernel(const DevGeom G, const int U, const int nbands, const float *__re
 
 // ------------------------------------------------------------ backprojection
 
-// One work item of the backprojection: a stack of GW columns x 128 voxels,
-// gathered in two 64-voxel passes that share each view's piece records and
-// detector window (halving their cost per voxel).
+// One work item of the backprojection: a stack of GW columns x 64 kp voxels
+// (kp = 1 or 2), gathered in kp 64-voxel passes that share each view's piece
+// records and detector window (with kp = 2, half their cost per voxel).
 template <bool EXACT, bool EC, int PMAX, int GW>
 __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngroups,
-                                                 const int nkchunks, const int winCap,
+                                                 const int nkchunks, const int kp, const int winCap,
                                                  const int item, float *smem,
                                                  const float *__restrict__ proj,
                                                  float *__restrict__ vol)
@@ -583,9 +583,9 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
     const int j = t / ngroups;
     constexpr int KP = kBackPasses;
     const int i0 = q * GW;
-    const int k0 = kch * kWave * KP;
+    const int k0 = kch * kWave * kp;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    const int kmax = min(k0 + kWave * KP, G.n3) - 1;
+    const int kmax = min(k0 + kWave * kp, G.n3) - 1;
 
     const int recFloats = GW * PMAX * kRecFloats + GW;
     const int waveFloats = ((recFloats + winCap + 3) / 4) * 4;
@@ -670,7 +670,7 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
 
 #pragma unroll
         for (int ps = 0; ps < KP; ++ps) {
-        if (k0 + ps * kWave >= G.n3) break;           // pass past the last slice
+        if (ps >= kp || k0 + ps * kWave >= G.n3) break;   // unused pass
         const int k = k0 + ps * kWave + lane;
         const bool kv = k < G.n3;
         const float kf = (float)k;
@@ -736,6 +736,7 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
     float *red = smem;   // [kWaves][GW][kWave], aliases the per-wave areas
 #pragma unroll
     for (int ps = 0; ps < KP; ++ps) {
+        if (ps >= kp) break;
         __syncthreads();
 #pragma unroll
         for (int c = 0; c < GW; ++c) red[(wave * GW + c) * kWave + lane] = acc[ps][c];
@@ -753,14 +754,14 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
 
 template <bool EXACT, bool EC, int PMAX, int GW>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
-backproject_kernel(const DevGeom G, const int ngroups, const int nkchunks, const int items,
+backproject_kernel(const DevGeom G, const int ngroups, const int nkchunks, const int kp, const int items,
                    const int chunk, const int winCap, const float *__restrict__ proj,
                    float *__restrict__ vol)
 {
     extern __shared__ __align__(16) float smem[];
     const int item = (blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
     if (item >= items) return;
-    backproject_item<EXACT, EC, PMAX, GW>(G, ngroups, nkchunks, winCap, item, smem, proj, vol);
+    backproject_item<EXACT, EC, PMAX, GW>(G, ngroups, nkchunks, kp, winCap, item, smem, proj, vol);
 }
 
 // ------------------------------------------------------------ batched, persistent
@@ -807,11 +808,11 @@ backproject_batched_kernel(const BatchProblem *__restrict__ probs, const BatchTa
     while (next_item(*T, counter, p, local)) {
         const BatchProblem &P = probs[p];
         if (P.gw == 16)
-            backproject_item<EXACT, EC, PMAX, 16>(P.G, P.ngroups, P.nkchunks, winCap, local, smem, P.in, P.out);
+            backproject_item<EXACT, EC, PMAX, 16>(P.G, P.ngroups, P.nkchunks, P.kp, winCap, local, smem, P.in, P.out);
         else if (P.gw == 8)
-            backproject_item<EXACT, EC, PMAX, 8>(P.G, P.ngroups, P.nkchunks, winCap, local, smem, P.in, P.out);
+            backproject_item<EXACT, EC, PMAX, 8>(P.G, P.ngroups, P.nkchunks, P.kp, winCap, local, smem, P.in, P.out);
         else
-            backproject_item<EXACT, EC, PMAX, 4>(P.G, P.ngroups, P.nkchunks, winCap, local, smem, P.in, P.out);
+            backproject_item<EXACT, EC, PMAX, 4>(P.G, P.ngroups, P.nkchunks, P.kp, winCap, local, smem, P.in, P.out);
     }
 }
 
@@ -852,15 +853,15 @@ hipError_t launch_bp_gw(const DevGeom &g, const BackLaunch &L, const float *proj
     switch (L.gw) {
     case 16:
         hipLaunchKernelGGL((backproject_kernel<EXACT, EC, PMAX, 16>), grid, block, L.lds, s, g,
-                           L.ngroups, L.nkchunks, L.items, L.chunk, L.win_cap, proj, vol);
+                           L.ngroups, L.nkchunks, L.kp, L.items, L.chunk, L.win_cap, proj, vol);
         break;
     case 8:
         hipLaunchKernelGGL((backproject_kernel<EXACT, EC, PMAX, 8>), grid, block, L.lds, s, g,
-                           L.ngroups, L.nkchunks, L.items, L.chunk, L.win_cap, proj, vol);
+                           L.ngroups, L.nkchunks, L.kp, L.items, L.chunk, L.win_cap, proj, vol);
         break;
     default:
         hipLaunchKernelGGL((backproject_kernel<EXACT, EC, PMAX, 4>), grid, block, L.lds, s, g,
-                           L.ngroups, L.nkchunks, L.items, L.chunk, L.win_cap, proj, vol);
+                           L.ngroups, L.nkchunks, L.kp, L.items, L.chunk, L.win_cap, proj, vol);
         break;
     }
     return hipGetLastError();

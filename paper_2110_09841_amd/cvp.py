@@ -67,15 +67,15 @@ class Geometry:
     @property
     def launch(self):
         """Launch plan in use: (projection band columns, backprojection
-        stack columns)."""
+        stack columns, backprojection passes per stack)."""
         lp = _lib.LaunchC()
         _lib.check(_lib.lib().cvp_geometry_get_launch(self.handle, ctypes.byref(lp)))
-        return int(lp.proj_band_cols), int(lp.bp_stack_cols)
+        return int(lp.proj_band_cols), int(lp.bp_stack_cols), int(lp.bp_passes)
 
-    def set_launch(self, proj_band_cols=0, bp_stack_cols=0):
-        """Replace the launch plan (0 keeps the planner's default for that
+    def set_launch(self, proj_band_cols=0, bp_stack_cols=0, bp_passes=0):
+        """Replace the launch plan (0 selects the planner's default for that
         field).  Raises CVPError if the plan does not fit."""
-        lp = _lib.LaunchC(int(proj_band_cols), int(bp_stack_cols))
+        lp = _lib.LaunchC(int(proj_band_cols), int(bp_stack_cols), int(bp_passes))
         _lib.check(_lib.lib().cvp_geometry_set_launch(self.handle, ctypes.byref(lp)))
 
 

@@ -35,17 +35,23 @@ def test_every_plan_matches_the_oracle():
     for u in (1, 3, 7, 16, 32):
         say("plan band", u)
         G.set_launch(u, 0)
-        assert G.launch == (u, default[1])
+        assert G.launch == (u,) + default[1:]
         p = cvp.project(xd, G, opts).cpu().numpy()
         assert_parity(p, ref_p, "A x, band %d" % u)
         outs.append(p)
     for p in outs[1:]:
         assert rel_l2(p, outs[0]) < 1e-6
+    backs = []
     for gw in (4, 8, 16):
-        say("plan stack", gw)
-        G.set_launch(0, gw)
-        assert G.launch == (default[0], gw)
-        assert_parity(cvp.backproject(bd, G, opts).cpu().numpy(), ref_b, "A^T b, stack %d" % gw)
+        for kp in (1, 2):
+            say("plan stack", gw, "passes", kp)
+            G.set_launch(0, gw, kp)
+            assert G.launch == (default[0], gw, kp)
+            backs.append(cvp.backproject(bd, G, opts).cpu().numpy())
+            assert_parity(backs[-1], ref_b, "A^T b, stack %d, %d passes" % (gw, kp))
+    # the backprojection's sums do not depend on the plan
+    for v in backs[1:]:
+        assert np.array_equal(v, backs[0])
     G.set_launch(0, 0)
     assert G.launch == default
 
@@ -54,11 +60,12 @@ def test_invalid_plans_are_rejected_and_leave_the_plan():
     g = synth.geometry(16, 1.0, 32, 3000, 0.5, 750.0, 1200.0, 2, 360.0)
     G = cvp.Geometry(g)
     before = G.launch
-    for u, gw, status in ((33, 0, _lib.CVP_E_INVALID), (-1, 0, _lib.CVP_E_INVALID), (0, 5, _lib.CVP_E_INVALID),
-                          (32, 0, _lib.CVP_E_UNSUPPORTED)):
+    for u, gw, kp, status in ((33, 0, 0, _lib.CVP_E_INVALID), (-1, 0, 0, _lib.CVP_E_INVALID),
+                              (0, 5, 0, _lib.CVP_E_INVALID), (0, 0, 3, _lib.CVP_E_INVALID),
+                              (32, 0, 0, _lib.CVP_E_UNSUPPORTED)):
         with pytest.raises(_lib.CVPError) as ei:
-            G.set_launch(u, gw)
-        assert ei.value.status == status, (u, gw, ei.value)
+            G.set_launch(u, gw, kp)
+        assert ei.value.status == status, (u, gw, kp, ei.value)
         assert G.launch == before
 
 
@@ -70,8 +77,8 @@ def test_autotune_sets_and_caches_a_plan(tmp_path):
     say("autotune")
     rec = autotune(G, opts, bands=(4, 8, 16), stacks=(16, 8), reps=1, cache=cache)
     assert not rec["cached"]
-    assert G.launch == (rec["proj_band_cols"], rec["bp_stack_cols"])
-    assert rec["proj_band_cols"] in (4, 8, 16) and rec["bp_stack_cols"] in (16, 8)
+    assert G.launch == (rec["proj_band_cols"], rec["bp_stack_cols"], rec["bp_passes"])
+    assert rec["proj_band_cols"] in (4, 8, 16) and rec["bp_stack_cols"] in (16, 8) and rec["bp_passes"] in (1, 2)
     G2 = cvp.Geometry(g)
     rec2 = autotune(G2, opts, cache=cache)
     assert rec2["cached"] and G2.launch == G.launch
