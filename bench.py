@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--cgls-max-iter", type=int, default=200)
     ap.add_argument("--no-network", action="store_true", help="skip the warm-start network timing")
     ap.add_argument("--no-batched", action="store_true", help="skip the 16-problem batched timing")
+    ap.add_argument("--no-cone", action="store_true", help="skip the 256^3 cone-beam timing")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run only a 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -99,6 +100,42 @@ def measured_traffic(kernel):
     return {"bytes": rec[kernel]["fetch_bytes"] + rec[kernel]["write_bytes"],
             "fetch_bytes": rec[kernel]["fetch_bytes"], "write_bytes": rec[kernel]["write_bytes"],
             "algorithmic_bytes": rec["algorithmic_bytes_per_launch"], "plan": rec.get("plan")}
+
+
+def cone_timing(reps=2):
+    """The 12-degree cone workload (256^3 voxels of 0.5 mm, 512x384 pixels
+    of 0.388 mm, SID 600 / SDD 900, 360 views): A and A^T timed separately
+    for the exact and the relaxed form, EC on, autotuned plan per form."""
+    import torch
+    from paper_2110_09841_amd import cvp, synth
+    from paper_2110_09841_amd.autotune import autotune
+    G = cvp.Geometry(synth.config_cone())
+    vv = G.n_voxels * G.n_views
+    gen = torch.Generator(device="cuda").manual_seed(6)
+    x = torch.rand(G.vol_shape, generator=gen, device="cuda")
+    b = torch.rand(G.proj_shape, generator=gen, device="cuda")
+    po, vo = torch.empty_like(b), torch.empty_like(x)
+    res = {"workload": "cone_256c_360v", "voxel_views": vv}
+    for variant in ("exact", "relaxed"):
+        opts = cvp.Options(variant=variant, ec=True)
+        autotune(G, opts, bands=(6, 8, 9, 12), reps=1)
+        ms = {}
+        for name, fn in (("project", lambda: cvp.project(x, G, opts, out=po)),
+                         ("backproject", lambda: cvp.backproject(b, G, opts, out=vo))):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms[name] = e0.elapsed_time(e1) / reps
+        res[variant] = {"launch": list(G.launch), "project_ms": ms["project"], "backproject_ms": ms["backproject"],
+                        "voxel_views_per_s": 2 * vv / ((ms["project"] + ms["backproject"]) * 1e-3)}
+    del x, b, po, vo
+    torch.cuda.empty_cache()
+    return res
 
 
 def batched_timing(reps=2):
@@ -193,6 +230,16 @@ def cgls_to_tolerance(G, opts, x_true, max_iter):
     res = {"tol": 1e-3, "iterations": it, "seconds": sec, "reached": bool(rho[it] <= 1e-3),
            "rho_final": float(rho[-1]), "iterations_run": len(rho) - 1, "per_graph": 5,
            "data": "b = A x_true (consistent), x0 = 0"}
+    # one replay of a graph of 20 iterations, from a fresh start
+    solver.reset(b)
+    solver.start()
+    solver.capture(20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solver.replay()
+    torch.cuda.synchronize()
+    res["graph20_replay_s"] = time.perf_counter() - t0
+    res["graph20_rho"] = float(solver.rho()[-1])
     del solver, b
     torch.cuda.empty_cache()
     return res
@@ -290,6 +337,8 @@ def main():
         out["warm_start_network"] = network_timing()
     if not args.no_batched:
         out["batched"] = batched_timing()
+    if not args.no_cone:
+        out["cone"] = cone_timing()
     del x, b, p_out, v_out
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
