@@ -427,7 +427,6 @@ struct cvp_batch {
     cvp::BatchProblem *d_probs = nullptr;
     cvp::BatchTable *d_ptab = nullptr, *d_btab = nullptr;
     int *d_counter = nullptr;
-    int pmax = 4, win_cap = 0;
     size_t plds = 0, blds = 0;
     int pgrid = 0, bgrid = 0;
 };
@@ -460,33 +459,22 @@ cvp_status cvp_batch_create(const cvp_geometry *const *geoms, int32_t n, cvp_bat
     b->n = n;
     b->device = geoms[0]->device;
     b->geoms.assign(geoms, geoms + n);
-    // common template parameter: the largest piece count; each problem keeps
-    // its own band width and stack width, and one dynamic LDS size fits all
-    for (int q = 0; q < n; ++q) b->pmax = std::max(b->pmax, geoms[q]->pl.pmax);
+    // every problem runs with its own single-problem plans (the batched
+    // kernels dispatch on the piece stride and stack width per item), so its
+    // results are those of its own launches; one dynamic LDS size fits all
     std::vector<cvp::BatchProblem> probs(n);
     std::vector<double> pcost(n), bcost(n);
     for (int q = 0; q < n; ++q) {
         const cvp_geometry *g = geoms[q];
-        // each problem keeps its own band width U (the per-pixel order of
-        // additions, hence the bits of the result, depend on it); only the
-        // record stride (pmax) is common
-        cvp::ProjLaunch pl = g->pl;
-        pl.lds = cvp::project_lds_bytes(pl.U, g->base.N, g->base.n2, b->pmax);
-        cvp::BackLaunch bl;
-        // the backprojection's sums do not depend on the stack shape, so a
-        // problem whose own stack width does not fit the common record
-        // stride may take another
-        if (pl.lds > cvp::kLdsBatchMax ||
-            (!cvp::plan_backprojection(g->base, b->pmax, g->zabs, g->Dmin, g->bl.gw, g->bl.kp, bl) &&
-             !cvp::plan_backprojection(g->base, b->pmax, g->zabs, g->Dmin, 0, 0, bl))) {
-            cvp_batch_destroy(b);
-            return fail(CVP_E_UNSUPPORTED, "problem %d does not fit the common launch plan", q);
-        }
+        const cvp::ProjLaunch &pl = g->pl;
+        const cvp::BackLaunch &bl = g->bl;
         cvp::BatchProblem &P = probs[q];
         P.G = g->base;
         P.U = pl.U;
+        P.pmax = bl.pmax;
         P.gw = bl.gw;
         P.kp = bl.kp;
+        P.win_cap = bl.win_cap;
         P.pitems = pl.items;
         P.ngroups = bl.ngroups;
         P.nkchunks = bl.nkchunks;
@@ -494,7 +482,7 @@ cvp_status cvp_batch_create(const cvp_geometry *const *geoms, int32_t n, cvp_bat
         P.in = nullptr;
         P.out = nullptr;
         b->plds = std::max(b->plds, pl.lds);
-        b->win_cap = q == 0 ? bl.win_cap : std::min(b->win_cap, bl.win_cap);
+        b->blds = std::max(b->blds, bl.lds);
         pcost[q] = (double)g->nvox / pl.nbands;           // voxels per band (all k)
         bcost[q] = (double)g->base.nviews;                // views per voxel stack
     }
@@ -511,13 +499,6 @@ cvp_status cvp_batch_create(const cvp_geometry *const *geoms, int32_t n, cvp_bat
         }
         return T;
     };
-    b->blds = 0;
-    for (int q = 0; q < n; ++q)
-        b->blds = std::max(b->blds, cvp::backproject_lds_bytes(probs[q].gw, b->pmax, b->win_cap));
-    if (b->blds > cvp::kLdsBatchMax) {
-        cvp_batch_destroy(b);
-        return fail(CVP_E_UNSUPPORTED, "backprojection windows of the problems exceed the LDS limit together");
-    }
     const cvp::BatchTable pt = table(pcost, false), bt = table(bcost, true);
     int cus = 0;
     hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
@@ -553,7 +534,7 @@ static cvp_status batched(const cvp_batch *b, const cvp_options *o, const float 
         io.sigma[q] = G.sigma;
     }
     hipError_t e = cvp::launch_batched(backward, b->d_probs, backward ? b->d_btab : b->d_ptab,
-                                       b->d_counter, io, b->pmax, b->win_cap,
+                                       b->d_counter, io,
                                        o->variant == CVP_EXACT, o->elevation_correction != 0,
                                        backward ? b->bgrid : b->pgrid, backward ? b->blds : b->plds,
                                        (hipStream_t)stream);

@@ -69,8 +69,10 @@ struct BatchProblem {        // device table entry (one per problem)
     DevGeom G;
     int U;                   // projection band width
     int pitems;              // projection work items
-    int gw;                  // backprojection stack width of the problem's own plan
-    int kp;                  // and its passes per stack
+    int pmax;                // the problem's own single-problem plan: piece stride,
+    int gw;                  // backprojection stack width,
+    int kp;                  // passes per stack
+    int win_cap;             // and per-wave window (floats)
     int ngroups;             // backprojection column groups per row
     int nkchunks;
     int bitems;              // backprojection work items
@@ -93,8 +95,7 @@ struct BatchIO {             // per call, by value
 };
 
 hipError_t launch_batched(bool backward, BatchProblem *probs, const BatchTable *tab, int *counter,
-                          const BatchIO &io, int pmax, int winCap, bool exact, bool ec,
-                          int grid, size_t lds, hipStream_t s);
+                          const BatchIO &io, bool exact, bool ec, int grid, size_t lds, hipStream_t s);
 int batched_blocks_per_cu(bool backward, size_t lds);
 size_t project_lds_bytes(int U, int N, int n2, int pmax);
 size_t backproject_lds_bytes(int gw, int pmax, int winCap);

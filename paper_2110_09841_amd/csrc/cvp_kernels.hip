@@ -783,7 +783,7 @@ __device__ __forceinline__ bool next_item(const BatchTable &T, int *counter, int
     return true;
 }
 
-template <bool EXACT, bool EC, int PMAX>
+template <bool EXACT, bool EC>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
 project_batched_kernel(const BatchProblem *__restrict__ probs, const BatchTable *__restrict__ T,
                        int *counter)
@@ -792,27 +792,39 @@ project_batched_kernel(const BatchProblem *__restrict__ probs, const BatchTable 
     int p, local;
     while (next_item(*T, counter, p, local)) {
         const BatchProblem &P = probs[p];
-        project_item<EXACT, EC, PMAX>(P.G, P.U, local, smem, P.in, P.out);
+        if (P.pmax <= 4)
+            project_item<EXACT, EC, 4>(P.G, P.U, local, smem, P.in, P.out);
+        else
+            project_item<EXACT, EC, 8>(P.G, P.U, local, smem, P.in, P.out);
     }
 }
 
-// Each problem runs with its own stack width, so its items are exactly those
-// of its single-problem launch.
+// Each problem runs with its own single-problem plan (piece stride, stack
+// width, passes, window), so its items are exactly those of its own launch.
 template <bool EXACT, bool EC, int PMAX>
+__device__ __forceinline__ void backproject_batched_item(const BatchProblem &P, int local, float *smem)
+{
+    if (P.gw == 16)
+        backproject_item<EXACT, EC, PMAX, 16>(P.G, P.ngroups, P.nkchunks, P.kp, P.win_cap, local, smem, P.in, P.out);
+    else if (P.gw == 8)
+        backproject_item<EXACT, EC, PMAX, 8>(P.G, P.ngroups, P.nkchunks, P.kp, P.win_cap, local, smem, P.in, P.out);
+    else
+        backproject_item<EXACT, EC, PMAX, 4>(P.G, P.ngroups, P.nkchunks, P.kp, P.win_cap, local, smem, P.in, P.out);
+}
+
+template <bool EXACT, bool EC>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
 backproject_batched_kernel(const BatchProblem *__restrict__ probs, const BatchTable *__restrict__ T,
-                           int *counter, int winCap)
+                           int *counter)
 {
     extern __shared__ __align__(16) float smem[];
     int p, local;
     while (next_item(*T, counter, p, local)) {
         const BatchProblem &P = probs[p];
-        if (P.gw == 16)
-            backproject_item<EXACT, EC, PMAX, 16>(P.G, P.ngroups, P.nkchunks, P.kp, winCap, local, smem, P.in, P.out);
-        else if (P.gw == 8)
-            backproject_item<EXACT, EC, PMAX, 8>(P.G, P.ngroups, P.nkchunks, P.kp, winCap, local, smem, P.in, P.out);
+        if (P.pmax <= 4)
+            backproject_batched_item<EXACT, EC, 4>(P, local, smem);
         else
-            backproject_item<EXACT, EC, PMAX, 4>(P.G, P.ngroups, P.nkchunks, P.kp, winCap, local, smem, P.in, P.out);
+            backproject_batched_item<EXACT, EC, 8>(P, local, smem);
     }
 }
 
@@ -892,31 +904,28 @@ hipError_t set_lds_one(size_t n)
     return e;
 }
 
-template <bool EXACT, bool EC, int PMAX>
+template <bool EXACT, bool EC>
 hipError_t launch_pb(BatchProblem *probs, const BatchTable *tab, int *counter, int grid, size_t lds,
                      hipStream_t s)
 {
-    hipLaunchKernelGGL((project_batched_kernel<EXACT, EC, PMAX>), dim3(grid), dim3(kBlock), lds, s,
-                       probs, tab, counter);
+    hipLaunchKernelGGL((project_batched_kernel<EXACT, EC>), dim3(grid), dim3(kBlock), lds, s, probs, tab, counter);
     return hipGetLastError();
 }
 
-template <bool EXACT, bool EC, int PMAX>
-hipError_t launch_bb(BatchProblem *probs, const BatchTable *tab, int *counter, int winCap, int grid,
-                     size_t lds, hipStream_t s)
+template <bool EXACT, bool EC>
+hipError_t launch_bb(BatchProblem *probs, const BatchTable *tab, int *counter, int grid, size_t lds, hipStream_t s)
 {
-    hipLaunchKernelGGL((backproject_batched_kernel<EXACT, EC, PMAX>), dim3(grid), dim3(kBlock), lds, s, probs, tab,
-                       counter, winCap);
+    hipLaunchKernelGGL((backproject_batched_kernel<EXACT, EC>), dim3(grid), dim3(kBlock), lds, s, probs, tab, counter);
     return hipGetLastError();
 }
 
-template <bool EXACT, bool EC, int PMAX>
+template <bool EXACT, bool EC>
 hipError_t set_lds_batched(size_t n)
 {
-    hipError_t e = hipFuncSetAttribute((const void *)project_batched_kernel<EXACT, EC, PMAX>,
+    hipError_t e = hipFuncSetAttribute((const void *)project_batched_kernel<EXACT, EC>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
     if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)backproject_batched_kernel<EXACT, EC, PMAX>,
+        e = hipFuncSetAttribute((const void *)backproject_batched_kernel<EXACT, EC>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
     return e;
 }
@@ -924,34 +933,21 @@ hipError_t set_lds_batched(size_t n)
 }  // namespace
 
 hipError_t launch_batched(bool backward, BatchProblem *probs, const BatchTable *tab, int *counter,
-                          const BatchIO &io, int pmax, int winCap, bool exact, bool ec,
-                          int grid, size_t lds, hipStream_t s)
+                          const BatchIO &io, bool exact, bool ec, int grid, size_t lds, hipStream_t s)
 {
     hipLaunchKernelGGL(batch_setup, dim3(1), dim3(64), 0, s, probs, io, counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (!backward) {
-        if (pmax <= 4) {
-            if (exact) return ec ? launch_pb<true, true, 4>(probs, tab, counter, grid, lds, s)
-                                 : launch_pb<true, false, 4>(probs, tab, counter, grid, lds, s);
-            return ec ? launch_pb<false, true, 4>(probs, tab, counter, grid, lds, s)
-                      : launch_pb<false, false, 4>(probs, tab, counter, grid, lds, s);
-        }
-        if (exact) return ec ? launch_pb<true, true, 8>(probs, tab, counter, grid, lds, s)
-                             : launch_pb<true, false, 8>(probs, tab, counter, grid, lds, s);
-        return ec ? launch_pb<false, true, 8>(probs, tab, counter, grid, lds, s)
-                  : launch_pb<false, false, 8>(probs, tab, counter, grid, lds, s);
+        if (exact) return ec ? launch_pb<true, true>(probs, tab, counter, grid, lds, s)
+                             : launch_pb<true, false>(probs, tab, counter, grid, lds, s);
+        return ec ? launch_pb<false, true>(probs, tab, counter, grid, lds, s)
+                  : launch_pb<false, false>(probs, tab, counter, grid, lds, s);
     }
-    if (pmax <= 4) {
-        if (exact) return ec ? launch_bb<true, true, 4>(probs, tab, counter, winCap, grid, lds, s)
-                             : launch_bb<true, false, 4>(probs, tab, counter, winCap, grid, lds, s);
-        return ec ? launch_bb<false, true, 4>(probs, tab, counter, winCap, grid, lds, s)
-                  : launch_bb<false, false, 4>(probs, tab, counter, winCap, grid, lds, s);
-    }
-    if (exact) return ec ? launch_bb<true, true, 8>(probs, tab, counter, winCap, grid, lds, s)
-                         : launch_bb<true, false, 8>(probs, tab, counter, winCap, grid, lds, s);
-    return ec ? launch_bb<false, true, 8>(probs, tab, counter, winCap, grid, lds, s)
-              : launch_bb<false, false, 8>(probs, tab, counter, winCap, grid, lds, s);
+    if (exact) return ec ? launch_bb<true, true>(probs, tab, counter, grid, lds, s)
+                         : launch_bb<true, false>(probs, tab, counter, grid, lds, s);
+    return ec ? launch_bb<false, true>(probs, tab, counter, grid, lds, s)
+              : launch_bb<false, false>(probs, tab, counter, grid, lds, s);
 }
 
 // Workgroups of a persistent batched kernel that fit on one CU at this LDS size.
@@ -960,10 +956,10 @@ int batched_blocks_per_cu(bool backward, size_t lds)
     int nb = 0;
     hipError_t e;
     if (!backward)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)project_batched_kernel<false, true, 8>,
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)project_batched_kernel<false, true>,
                                                          kBlock, lds);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)backproject_batched_kernel<false, true, 8>,
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)backproject_batched_kernel<false, true>,
                                                          kBlock, lds);
     if (e != hipSuccess || nb < 1) nb = 1;
     return nb;
@@ -981,14 +977,10 @@ hipError_t configure_kernel_lds(size_t max_lds, size_t max_lds_batched)
     if (e == hipSuccess) e = set_lds_one<true, false, 8>(max_lds);
     if (e == hipSuccess) e = set_lds_one<false, true, 8>(max_lds);
     if (e == hipSuccess) e = set_lds_one<false, false, 8>(max_lds);
-    if (e == hipSuccess) e = set_lds_batched<true, true, 4>(max_lds_batched);
-    if (e == hipSuccess) e = set_lds_batched<true, false, 4>(max_lds_batched);
-    if (e == hipSuccess) e = set_lds_batched<false, true, 4>(max_lds_batched);
-    if (e == hipSuccess) e = set_lds_batched<false, false, 4>(max_lds_batched);
-    if (e == hipSuccess) e = set_lds_batched<true, true, 8>(max_lds_batched);
-    if (e == hipSuccess) e = set_lds_batched<true, false, 8>(max_lds_batched);
-    if (e == hipSuccess) e = set_lds_batched<false, true, 8>(max_lds_batched);
-    if (e == hipSuccess) e = set_lds_batched<false, false, 8>(max_lds_batched);
+    if (e == hipSuccess) e = set_lds_batched<true, true>(max_lds_batched);
+    if (e == hipSuccess) e = set_lds_batched<true, false>(max_lds_batched);
+    if (e == hipSuccess) e = set_lds_batched<false, true>(max_lds_batched);
+    if (e == hipSuccess) e = set_lds_batched<false, false>(max_lds_batched);
     return e;
 }
 
