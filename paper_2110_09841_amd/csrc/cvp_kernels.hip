@@ -254,15 +254,79 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// EC margin of a piece's row range: at least the box half-width e(t) =
+// |t - c2| rho at every boundary t within a row of the extent, i.e. E with
+// E (1 - rho) >= rho (max |Y - c2| + 1.001), so the range covers every row
+// the box average reaches and C is exactly beta / 0 at its first / last
+// boundary.  Valid for rho < 0.9 (a box narrower than the source distance).
+template <bool EC>
+__device__ __forceinline__ float ec_margin(float Ytop, float beta, float rho, float c2f)
+{
+    if (!EC) return 0.0f;
+    const float M = fmaxf(fabsf(Ytop - c2f), fabsf(Ytop + beta - c2f));
+    return 1.01f * rho * (M + 1.01f) * __builtin_amdgcn_rcpf(fmaxf(1.0f - rho, 0.05f));
+}
+
 // Rows touched by a piece of voxel k: [vlo, vhi] clipped to the detector.
 template <bool EC>
 __device__ __forceinline__ void row_range(float Ytop, float beta, float rho, float c2f, int N,
                                           int &vlo, int &vhi)
 {
-    float E = 0.0f;
-    if (EC) E = 1.01f * rho * (fmaxf(fabsf(Ytop - c2f), fabsf(Ytop + beta - c2f)) + 1.0f);
+    const float E = ec_margin<EC>(Ytop, beta, rho, c2f);
     vlo = max((int)floorf(Ytop - E + 0.5f - 1e-3f), 0);
     vhi = min((int)floorf(Ytop + beta + E + 0.5f + 1e-3f), N - 1);
+}
+
+// The same range before clipping to the detector.
+template <bool EC>
+__device__ __forceinline__ void row_range_unclipped(float Ytop, float beta, float rho, float c2f, int &vlo0,
+                                                    int &vhi0)
+{
+    const float E = ec_margin<EC>(Ytop, beta, rho, c2f);
+    vlo0 = (int)floorf(Ytop - E + 0.5f - 1e-3f);
+    vhi0 = (int)floorf(Ytop + beta + E + 0.5f + 1e-3f);
+}
+
+// Row weights of one voxel piece: rows [vlo, vhi] (already clipped) of the
+// unclipped range [vlo0, vhi0]; row(v, w) is called for each.  The unclipped
+// range includes the EC margin, so at its first boundary C is exactly beta
+// and at its last exactly 0 (the box average is zero there); those two
+// evaluations are skipped unless clipping moved the boundary.
+template <bool EC, bool EXACT, class Row>
+__device__ __forceinline__ void sweep_rows(int vlo0, int vhi0, int vlo, int vhi, float Yh, float Yl, float beta,
+                                           float rho, float c2f, float coef, bool raw, float zt, float r8,
+                                           float r9, Row &&row)
+{
+    const bool ends = !EC || rho < 0.9f;         // the margin guarantees the end values
+    float tb = (float)vlo - 0.5f;
+    float s1p = (Yh - tb) + Yl;
+    float Cp = beta;
+    if (vlo != vlo0 || !ends) Cp = cum<EC>(s1p, beta, tb - c2f, rho);
+    auto weight = [&](float s1n, float Cn) {
+        float w = coef * (Cp - Cn);
+        if (EXACT && !raw) {
+            float mm = 0.5f * (fmaxf(0.0f, -s1p) + fminf(beta, -s1n));
+            mm = fminf(fmaxf(mm, 0.0f), beta);
+            const float zb = fmaf(-mm, r9, zt);
+            w *= __builtin_amdgcn_rcpf(fmaf(zb, zb, r8));
+        }
+        return w;
+    };
+    for (int v = vlo; v < vhi; ++v) {
+        tb += 1.0f;
+        const float s1n = (Yh - tb) + Yl;
+        const float Cn = cum<EC>(s1n, beta, tb - c2f, rho);
+        row(v, weight(s1n, Cn));
+        Cp = Cn;
+        s1p = s1n;
+    }
+    if (vlo <= vhi) {
+        tb += 1.0f;
+        const float s1n = (Yh - tb) + Yl;
+        float Cn = 0.0f;
+        if (vhi != vhi0 || !ends) Cn = cum<EC>(s1n, beta, tb - c2f, rho);
+        row(vhi, weight(s1n, Cn));
+    }
 }
 
 // Record phase shared by both directions: lanes (c, slot) compute the pieces
@@ -507,26 +571,11 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
                     const float Yl = fmaf(-kf, r[5], r[3]);
                     const float beta = r[6], rho = r[7];
                     unsigned long long *bcol = bins + (u - u0) * Npad;
-                    int vlo, vhi;
-                    row_range<EC>(Yh + Yl, beta, rho, c2f, G.N, vlo, vhi);
-                    float tb = (float)vlo - 0.5f;
-                    float s1p = (Yh - tb) + Yl;
-                    float Cp = cum<EC>(s1p, beta, tb - c2f, rho);
-                    for (int v = vlo; v <= vhi; ++v) {
-                        tb += 1.0f;
-                        const float s1n = (Yh - tb) + Yl;
-                        const float Cn = cum<EC>(s1n, beta, tb - c2f, rho);
-                        float w = coef * (Cp - Cn);
-                        if (EXACT && !raw) {
-                            float mm = 0.5f * (fmaxf(0.0f, -s1p) + fminf(beta, -s1n));
-                            mm = fminf(fmaxf(mm, 0.0f), beta);
-                            const float zb = fmaf(-mm, r[9], zt);
-                            w *= __builtin_amdgcn_rcpf(fmaf(zb, zb, r[8]));
-                        }
-                        lds_add_fixed(bcol + v, w);
-                        Cp = Cn;
-                        s1p = s1n;
-                    }
+                    int vlo0, vhi0;
+                    row_range_unclipped<EC>(Yh + Yl, beta, rho, c2f, vlo0, vhi0);
+                    sweep_rows<EC, EXACT>(vlo0, vhi0, max(vlo0, 0), min(vhi0, G.N - 1), Yh, Yl, beta, rho, c2f,
+                                          coef, raw, zt, r[8], r[9],
+                                          [&](int v, float w) { lds_add_fixed(bcol + v, w); });
                 }
             }
         }
@@ -693,6 +742,9 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
                 const float Yh = fmaf(-kf, r1.x, r0.z);
                 const float Yl = fmaf(-kf, r1.y, r0.w);
                 const float beta = r1.z, rho = r1.w;
+                // (the gather keeps every boundary evaluation in its loop:
+                // skipping the two end values as the projection does was
+                // measured slower here)
                 int vlo, vhi;
                 row_range<EC>(Yh + Yl, beta, rho, c2f, G.N, vlo, vhi);
                 vlo = max(vlo, wv0);
