@@ -154,7 +154,7 @@ __device__ __forceinline__ Mom column_prefix(const DevGeom &G, const ViewGeom &V
 //  [0] u (int bits)  [1] W = A_u * b2 D_u / f       [2] Y0 hi   [3] Y0 lo
 //  [4] beta hi       [5] beta lo   [6] beta          [7] rho = h/D (EC)
 //  [8] R^2 (x1x2 part of r^2: cut centroid, or column centre if relaxed)
-//  [9] b2 D_u / f (mm of x3 per row)  [10..11] unused
+//  [9] b2 D_u / f (mm of x3 per row)  [10] EC row margin factor  [11] unused
 // Y(k) = Y0 - k beta is chi2 of the top face of voxel k at the centroid depth.
 template <bool EXACT, bool EC>
 __device__ __forceinline__ void piece_record(const DevGeom &G, const ViewGeom &V, const Column &C,
@@ -203,7 +203,10 @@ __device__ __forceinline__ void piece_record(const DevGeom &G, const ViewGeom &V
     rec[7] = EC ? (float)(sqrt(3.0 * var) * iDu) : 0.0f;
     rec[8] = (float)R2;
     rec[9] = (float)gmm;
-    rec[10] = 0.0f;
+    // EC row margin factor 1.01 rho / (1 - rho) from the FP32 rho the voxel
+    // stage uses (see ec_margin)
+    const double rho32 = (double)rec[7];
+    rec[10] = EC ? (float)(1.01 * rho32 / fmax(1.0 - rho32, 0.05)) : 0.0f;
     rec[11] = 0.0f;
 }
 
@@ -259,30 +262,31 @@ __device__ __forceinline__ void wave_sync()
 // E (1 - rho) >= rho (max |Y - c2| + 1.001), so the range covers every row
 // the box average reaches and C is exactly beta / 0 at its first / last
 // boundary.  Valid for rho < 0.9 (a box narrower than the source distance).
+// mfac = 1.01 rho / max(1 - rho, 0.05) comes with the piece record.
 template <bool EC>
-__device__ __forceinline__ float ec_margin(float Ytop, float beta, float rho, float c2f)
+__device__ __forceinline__ float ec_margin(float Ytop, float beta, float mfac, float c2f)
 {
     if (!EC) return 0.0f;
     const float M = fmaxf(fabsf(Ytop - c2f), fabsf(Ytop + beta - c2f));
-    return 1.01f * rho * (M + 1.01f) * __builtin_amdgcn_rcpf(fmaxf(1.0f - rho, 0.05f));
+    return mfac * (M + 1.01f);
 }
 
 // Rows touched by a piece of voxel k: [vlo, vhi] clipped to the detector.
 template <bool EC>
-__device__ __forceinline__ void row_range(float Ytop, float beta, float rho, float c2f, int N,
+__device__ __forceinline__ void row_range(float Ytop, float beta, float mfac, float c2f, int N,
                                           int &vlo, int &vhi)
 {
-    const float E = ec_margin<EC>(Ytop, beta, rho, c2f);
+    const float E = ec_margin<EC>(Ytop, beta, mfac, c2f);
     vlo = max((int)floorf(Ytop - E + 0.5f - 1e-3f), 0);
     vhi = min((int)floorf(Ytop + beta + E + 0.5f + 1e-3f), N - 1);
 }
 
 // The same range before clipping to the detector.
 template <bool EC>
-__device__ __forceinline__ void row_range_unclipped(float Ytop, float beta, float rho, float c2f, int &vlo0,
+__device__ __forceinline__ void row_range_unclipped(float Ytop, float beta, float mfac, float c2f, int &vlo0,
                                                     int &vhi0)
 {
-    const float E = ec_margin<EC>(Ytop, beta, rho, c2f);
+    const float E = ec_margin<EC>(Ytop, beta, mfac, c2f);
     vlo0 = (int)floorf(Ytop - E + 0.5f - 1e-3f);
     vhi0 = (int)floorf(Ytop + beta + E + 0.5f + 1e-3f);
 }
@@ -572,7 +576,7 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
                     const float beta = r[6], rho = r[7];
                     unsigned long long *bcol = bins + (u - u0) * Npad;
                     int vlo0, vhi0;
-                    row_range_unclipped<EC>(Yh + Yl, beta, rho, c2f, vlo0, vhi0);
+                    row_range_unclipped<EC>(Yh + Yl, beta, r[10], c2f, vlo0, vhi0);
                     sweep_rows<EC, EXACT>(vlo0, vhi0, max(vlo0, 0), min(vhi0, G.N - 1), Yh, Yl, beta, rho, c2f,
                                           coef, raw, zt, r[8], r[9],
                                           [&](int v, float w) { lds_add_fixed(bcol + v, w); });
@@ -673,12 +677,12 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
                 if (s < npc[c]) {
                     const float *r = rec + (c * PMAX + s) * kRecFloats;
                     const int u = __float_as_int(r[0]);
-                    const float beta = r[6], rho = r[7];
+                    const float beta = r[6], mfac = r[10];
                     const float Ytop_hi = fmaf(-(float)kmax, r[4], r[2]) + fmaf(-(float)kmax, r[5], r[3]);
                     const float Ytop_lo = fmaf(-(float)k0, r[4], r[2]) + fmaf(-(float)k0, r[5], r[3]);
                     int a, b, a2, b2;
-                    row_range<EC>(Ytop_hi, beta, rho, c2f, G.N, a, b);
-                    row_range<EC>(Ytop_lo, beta, rho, c2f, G.N, a2, b2);
+                    row_range<EC>(Ytop_hi, beta, mfac, c2f, G.N, a, b);
+                    row_range<EC>(Ytop_lo, beta, mfac, c2f, G.N, a2, b2);
                     wu0 = min(wu0, u); wu1 = max(wu1, u);
                     wv0 = min(wv0, min(a, a2)); wv1 = max(wv1, max(b, b2));
                 }
@@ -746,7 +750,7 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
                 // skipping the two end values as the projection does was
                 // measured slower here)
                 int vlo, vhi;
-                row_range<EC>(Yh + Yl, beta, rho, c2f, G.N, vlo, vhi);
+                row_range<EC>(Yh + Yl, beta, r2.z, c2f, G.N, vlo, vhi);
                 vlo = max(vlo, wv0);
                 vhi = min(vhi, wv1);
                 if (!kv) vhi = vlo - 1;
