@@ -188,6 +188,28 @@ cvp_status cvp_cgls_iterate(const cvp_geometry *g, const cvp_options *opts, int3
                             float *d_x, float *d_r, float *d_s, float *d_p, float *d_q,
                             void *d_work, void *hip_stream);
 
+/*
+ * Batched CGLS: every problem q of the batch runs the recurrences of
+ * cvp_cgls_start / cvp_cgls_iterate on its own vectors and workspace, and
+ * each operator step is one batched launch for all problems (the persistent
+ * kernels above).  Each problem's iterates and scalars equal those of its
+ * single-problem CGLS bitwise.  Arguments are host arrays of b->n device
+ * pointers with the single-problem layouts (d_work[q]: cvp_cgls_workspace_size
+ * bytes, 8-byte aligned); no vector or workspace may serve two problems.
+ * Problems are iterated together: the caller reads each workspace's history
+ * and stops when every problem is done.  Enqueues kernels only, so a run of
+ * cvp_cgls_batched_iterate can be captured in a HIP graph; calls that overlap
+ * in time must not share the batch object.
+ */
+cvp_status cvp_cgls_batched_start(const cvp_batch *b, const cvp_options *opts, const float *const *d_b,
+                                  float *const *d_x, float *const *d_r, float *const *d_s,
+                                  float *const *d_p, float *const *d_q, void *const *d_work,
+                                  void *hip_stream);
+cvp_status cvp_cgls_batched_iterate(const cvp_batch *b, const cvp_options *opts, int32_t n_iter,
+                                    float *const *d_x, float *const *d_r, float *const *d_s,
+                                    float *const *d_p, float *const *d_q, void *const *d_work,
+                                    void *hip_stream);
+
 /* *d_result = sum_i a[i] b[i] accumulated in FP64 (device scalar), using the
  * partials area of a CGLS workspace d_work.  n >= 0. */
 cvp_status cvp_dot(const float *d_a, const float *d_b, int64_t n, double *d_result,

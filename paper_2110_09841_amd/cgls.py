@@ -12,7 +12,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from .cvp import Geometry, Options, _check_tensor, _stream
+from .cvp import Batch, Geometry, Options, _check_tensor, _ptr_array, _stream
 
 N_SCALARS = 8
 HISTORY = 4096
@@ -124,3 +124,116 @@ class CGLS:
         t1 = time.perf_counter()
         hit = np.nonzero(rho <= tol)[0]
         return (int(hit[0]) if len(hit) else len(rho) - 1), t1 - t0, rho
+
+
+def cgls(geom: Geometry, b, opts: Options = Options(), x0=None, tol=1e-3, max_iter=400, per_graph=20,
+         use_graph=True):
+    """Least-squares solution of A x = b by CGLS from x0 (zero by default)
+    until rho_k <= tol or max_iter iterations.  Returns (x, info) with info
+    = {"iterations", "seconds", "rho", "breakdown"}; rho is the residual
+    history (one entry per iteration run)."""
+    solver = CGLS(geom, opts, b, x0)
+    it, sec, rho = solver.run(tol=tol, max_iter=max_iter, per_graph=per_graph, use_graph=use_graph)
+    return solver.x, {"iterations": it, "seconds": sec, "rho": rho, "breakdown": solver.breakdown()}
+
+
+class BatchedCGLS:
+    """CGLS on every problem of a Batch at once: each problem keeps its own
+    vectors, scalars and history (those of CGLS on it alone, bitwise), and
+    the two operator steps of an iteration are one batched launch each."""
+
+    def __init__(self, batch: Batch, opts: Options, bs, x0s=None):
+        n = len(batch)
+        if len(bs) != n or (x0s is not None and len(x0s) != n):
+            raise ValueError("expected %d right-hand sides / starting points" % n)
+        self.batch, self.opts = batch, opts
+        self.b = list(bs)
+        for b, g in zip(self.b, batch.geoms):
+            _check_tensor(b, g.proj_shape, "b")
+        dev = self.b[0].device
+        self.x, self.r, self.q, self.s, self.p, self.work = [], [], [], [], [], []
+        nbytes = ctypes.c_int64()
+        for k, g in enumerate(batch.geoms):
+            x = torch.zeros(g.vol_shape, dtype=torch.float32, device=dev) if x0s is None \
+                else x0s[k].detach().clone().contiguous()
+            _check_tensor(x, g.vol_shape, "x0")
+            self.x.append(x)
+            self.r.append(torch.empty(g.proj_shape, dtype=torch.float32, device=dev))
+            self.q.append(torch.empty(g.proj_shape, dtype=torch.float32, device=dev))
+            self.s.append(torch.empty(g.vol_shape, dtype=torch.float32, device=dev))
+            self.p.append(torch.empty(g.vol_shape, dtype=torch.float32, device=dev))
+            _lib.check(_lib.lib().cvp_cgls_workspace_size(g.n_voxels, self.r[-1].numel(), ctypes.byref(nbytes)))
+            self.work.append(torch.zeros(nbytes.value // 8, dtype=torch.float64, device=dev))
+        self._o = opts.c()
+        self._arrs = [_ptr_array(v) for v in (self.x, self.r, self.s, self.p, self.q, self.work)]
+        self._b = _ptr_array(self.b)
+        self.graph = None
+        self.graph_iters = 0
+
+    def __len__(self):
+        return len(self.x)
+
+    def start(self):
+        _lib.check(_lib.lib().cvp_cgls_batched_start(self.batch.handle, ctypes.byref(self._o), self._b,
+                                                     *self._arrs, _stream()))
+
+    def iterate(self, n: int):
+        _lib.check(_lib.lib().cvp_cgls_batched_iterate(self.batch.handle, ctypes.byref(self._o), int(n),
+                                                       *self._arrs, _stream()))
+
+    def capture(self, n: int):
+        """Capture n batched iterations in one HIP graph."""
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g, stream=side):
+                self.iterate(n)
+        torch.cuda.current_stream().wait_stream(side)
+        self.graph, self.graph_iters = g, n
+
+    def replay(self):
+        self.graph.replay()
+
+    def gamma_histories(self):
+        """Per problem: |s_k|^2 for k = 0 .. iterations done."""
+        out = []
+        for w in self.work:
+            sc = w[:N_SCALARS].cpu().numpy()
+            k = int(sc[6])
+            out.append(w[N_SCALARS:N_SCALARS + min(k, HISTORY - 1) + 1].cpu().numpy())
+        return out
+
+    def rho(self):
+        return [np.sqrt(np.maximum(g, 0.0) / g[0]) for g in self.gamma_histories()]
+
+    def breakdown(self):
+        return [bool(float(w[7]) != 0.0) for w in self.work]
+
+    def run(self, tol=1e-3, max_iter=400, per_graph=20, use_graph=True):
+        """Iterate all problems until each has rho_k <= tol (or broke down),
+        checked every per_graph iterations, or max_iter.  Returns (per-problem
+        iterations to reach tol, or the last iteration if not reached;
+        seconds; per-problem rho histories)."""
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        self.start()
+        if use_graph and (self.graph is None or self.graph_iters != per_graph):
+            self.capture(per_graph)
+        done = 0
+        while True:
+            rhos = self.rho()          # synchronises
+            brk = self.breakdown()
+            if all(r[-1] <= tol or b for r, b in zip(rhos, brk)) or done >= max_iter:
+                break
+            if use_graph:
+                self.replay()
+            else:
+                self.iterate(per_graph)
+            done += per_graph
+        t1 = time.perf_counter()
+        its = []
+        for r in rhos:
+            hit = np.nonzero(r <= tol)[0]
+            its.append(int(hit[0]) if len(hit) else len(r) - 1)
+        return its, t1 - t0, rhos

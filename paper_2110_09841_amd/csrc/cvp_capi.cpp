@@ -621,6 +621,103 @@ cvp_status cvp_cgls_iterate(const cvp_geometry *g, const cvp_options *o, int32_t
     return ok();
 }
 
+// Batched CGLS: the single-problem recurrences per problem, each operator
+// step one batched launch over all problems.
+struct BatchedCgls {
+    const float *const *b;
+    float *const *x, *const *r, *const *s, *const *p, *const *q;
+    void *const *work;
+};
+
+static cvp_status cgls_batched_args(const cvp_batch *bt, const cvp_options *o, const BatchedCgls &V,
+                                    bool need_b)
+{
+    if (!bt) return fail(CVP_E_INVALID, "batch is NULL");
+    if (!V.x || !V.r || !V.s || !V.p || !V.q || !V.work || (need_b && !V.b))
+        return fail(CVP_E_INVALID, "pointer array is NULL");
+    for (int k = 0; k < bt->n; ++k) {
+        if (need_b && !V.b[k]) return fail(CVP_E_INVALID, "problem %d: b is NULL", k);
+        cvp::DevGeom G;
+        cvp_status st = cgls_args(bt->geoms[k], o, V.x[k], V.r[k], V.s[k], V.p[k], V.q[k], V.work[k], G);
+        if (st != CVP_OK) return fail(st, "problem %d: %s", k, g_err.c_str());
+    }
+    // no vector or workspace may serve two problems
+    std::vector<const void *> all;
+    for (int k = 0; k < bt->n; ++k)
+        for (const void *ptr : {(const void *)V.x[k], (const void *)V.r[k], (const void *)V.s[k],
+                                (const void *)V.p[k], (const void *)V.q[k], (const void *)V.work[k]})
+            all.push_back(ptr);
+    std::sort(all.begin(), all.end());
+    if (std::adjacent_find(all.begin(), all.end()) != all.end())
+        return fail(CVP_E_INVALID, "a vector or workspace is shared between problems");
+    return CVP_OK;
+}
+
+static double *cgls_scalars(void *work) { return (double *)work; }
+static double *cgls_partials(void *work) { return (double *)work + cvp::kCglsScalars + 2 * cvp::kCglsHistory; }
+
+cvp_status cvp_cgls_batched_start(const cvp_batch *bt, const cvp_options *o, const float *const *d_b,
+                                  float *const *d_x, float *const *d_r, float *const *d_s,
+                                  float *const *d_p, float *const *d_q, void *const *d_work, void *stream)
+{
+    const BatchedCgls V{d_b, d_x, d_r, d_s, d_p, d_q, d_work};
+    cvp_status st = cgls_batched_args(bt, o, V, true);
+    if (st != CVP_OK) return st;
+    hipStream_t sm = (hipStream_t)stream;
+    const int n = bt->n;
+    st = batched(bt, o, (const float *const *)d_x, d_q, stream, false);             // q = A x
+    if (st != CVP_OK) return st;
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < n && e == hipSuccess; ++k)
+        e = cvp::blas_residual(d_r[k], d_b[k], d_q[k], bt->geoms[k]->npix, sm);     // r = b - q
+    if (e != hipSuccess) return device_fail(e, "batched cgls start");
+    st = batched(bt, o, (const float *const *)d_r, d_s, stream, true);              // s = A^T r
+    if (st != CVP_OK) return st;
+    for (int k = 0; k < n && e == hipSuccess; ++k) {
+        const int64_t nv = bt->geoms[k]->nvox;
+        e = cvp::blas_update_p(d_p[k], d_s[k], nv, cgls_scalars(d_work[k]), 1, sm);
+        if (e == hipSuccess)
+            e = cvp::blas_dot(d_s[k], d_s[k], nv, cgls_partials(d_work[k]), cgls_scalars(d_work[k]), 0, nullptr, sm);
+    }
+    if (e != hipSuccess) return device_fail(e, "batched cgls start");
+    return ok();
+}
+
+cvp_status cvp_cgls_batched_iterate(const cvp_batch *bt, const cvp_options *o, int32_t n_iter,
+                                    float *const *d_x, float *const *d_r, float *const *d_s,
+                                    float *const *d_p, float *const *d_q, void *const *d_work, void *stream)
+{
+    if (n_iter < 0) return fail(CVP_E_INVALID, "n_iter = %d", n_iter);
+    const BatchedCgls V{nullptr, d_x, d_r, d_s, d_p, d_q, d_work};
+    cvp_status st = cgls_batched_args(bt, o, V, false);
+    if (st != CVP_OK) return st;
+    hipStream_t sm = (hipStream_t)stream;
+    const int n = bt->n;
+    hipError_t e = hipSuccess;
+    for (int it = 0; it < n_iter; ++it) {
+        st = batched(bt, o, (const float *const *)d_p, d_q, stream, false);         // q = A p
+        if (st != CVP_OK) return st;
+        for (int k = 0; k < n && e == hipSuccess; ++k) {
+            const cvp_geometry *g = bt->geoms[k];
+            double *sc = cgls_scalars(d_work[k]), *part = cgls_partials(d_work[k]);
+            e = cvp::blas_dot(d_q[k], d_q[k], g->npix, part, sc, 1, nullptr, sm);        // alpha
+            if (e == hipSuccess) e = cvp::blas_update_xr(d_x[k], d_p[k], g->nvox, d_r[k], d_q[k], g->npix, sc, part, sm);
+        }
+        if (e != hipSuccess) break;
+        st = batched(bt, o, (const float *const *)d_r, d_s, stream, true);          // s = A^T r
+        if (st != CVP_OK) return st;
+        for (int k = 0; k < n && e == hipSuccess; ++k) {
+            const int64_t nv = bt->geoms[k]->nvox;
+            double *sc = cgls_scalars(d_work[k]), *part = cgls_partials(d_work[k]);
+            e = cvp::blas_dot(d_s[k], d_s[k], nv, part, sc, 2, nullptr, sm);             // beta
+            if (e == hipSuccess) e = cvp::blas_update_p(d_p[k], d_s[k], nv, sc, 0, sm);  // p
+        }
+        if (e != hipSuccess) break;
+    }
+    if (e != hipSuccess) return device_fail(e, "batched cgls iterate");
+    return ok();
+}
+
 cvp_status cvp_dot(const float *d_a, const float *d_b, int64_t n, double *d_result, void *d_work,
                    void *stream)
 {

@@ -171,3 +171,9 @@ def backproject_batched(bs, batch: Batch, opts: Options = Options(), outs=None):
     _lib.check(_lib.lib().cvp_backproject_batched(batch.handle, ctypes.byref(oc), _ptr_array(bs),
                                                   _ptr_array(outs), _stream()))
     return outs
+
+
+# The solver and the differentiable operators under the same namespace
+# (imported last: both modules build on the definitions above).
+from .cgls import CGLS, BatchedCGLS, cgls  # noqa: E402,F401
+from .autograd import BackProject, Project  # noqa: E402,F401

@@ -106,6 +106,10 @@ def test_batch_and_cgls_argument_errors():
     assert L.cvp_cgls_workspace_size(-1, 20, ctypes.byref(nbytes)) == _lib.CVP_E_INVALID
     o = _lib.OptionsC(0, 1, 0, 0)
     assert L.cvp_cgls_iterate(None, ctypes.byref(o), 1, None, None, None, None, None, None, None) == _lib.CVP_E_INVALID
+    assert L.cvp_cgls_batched_start(None, ctypes.byref(o), *([None] * 7), None) == _lib.CVP_E_INVALID
+    assert "batch" in _lib.last_error()
+    assert L.cvp_cgls_batched_iterate(None, ctypes.byref(o), 1, *([None] * 6), None) == _lib.CVP_E_INVALID
+    assert L.cvp_cgls_batched_iterate(None, ctypes.byref(o), -1, *([None] * 6), None) == _lib.CVP_E_INVALID
 
 
 def test_launch_plan_rejects_null_arguments():

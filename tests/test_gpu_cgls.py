@@ -68,3 +68,53 @@ def test_cgls_graph_replay_equals_eager_and_converges():
     # the residual |b - A x_k| never increases
     rr = graphed.residual_history()
     assert np.all(np.diff(rr) <= 1e-6 * rr[0])
+
+
+def _small_batch(n=3):
+    """The n smallest members (voxels x views) of the 16-problem batch workload."""
+    params = synth.config_batch()
+    order = np.argsort([p["vol_dims"][0] ** 3 * len(p["angles_rad"]) for p in params], kind="stable")
+    return [params[q] for q in order[:n]]
+
+
+def test_batched_cgls_equals_single_problem_bitwise():
+    params = _small_batch(3)
+    geoms = [cvp.Geometry(p) for p in params]
+    batch = cvp.Batch(geoms)
+    opts = cvp.Options(variant="relaxed", ec=True)
+    xs = [torch.from_numpy(synth.ellipsoid_phantom(p["vol_dims"], p["voxel_mm"][0], 12, seed=300 + q)).cuda()
+          for q, p in enumerate(params)]
+    bs = [cvp.project(x, g, opts) for x, g in zip(xs, geoms)]
+    say("batched cgls: %s" % [p["vol_dims"][0] for p in params])
+    bc = cvp.BatchedCGLS(batch, opts, bs)
+    bc.start()
+    bc.iterate(4)
+    bc.capture(3)
+    for rep in range(2):
+        say("batched cgls graph replay", rep)
+        bc.replay()
+        torch.cuda.synchronize()
+        _ = (bs[0] * 2.0).sum().item()     # eager work between replays
+    for q, g in enumerate(geoms):
+        single = CGLS(g, opts, bs[q])
+        single.start()
+        single.iterate(10)
+        assert torch.equal(bc.x[q], single.x), q
+        assert np.array_equal(bc.gamma_histories()[q], single.gamma_history()), q
+    assert not any(bc.breakdown())
+
+
+def test_batched_cgls_run_and_cgls_function():
+    params = _small_batch(2)
+    geoms = [cvp.Geometry(p) for p in params]
+    opts = cvp.Options(variant="relaxed", ec=True)
+    xs = [torch.from_numpy(synth.ellipsoid_phantom(p["vol_dims"], p["voxel_mm"][0], 12, seed=400 + q)).cuda()
+          for q, p in enumerate(params)]
+    bs = [cvp.project(x, g, opts) for x, g in zip(xs, geoms)]
+    its, sec, rhos = cvp.BatchedCGLS(cvp.Batch(geoms), opts, bs).run(tol=1e-2, max_iter=100, per_graph=5)
+    say("batched cgls to 1e-2: %s iterations, %.3f s" % (its, sec))
+    for q in range(2):
+        assert rhos[q][its[q]] <= 1e-2
+        x, info = cvp.cgls(geoms[q], bs[q], opts, tol=1e-2, max_iter=100, per_graph=5)
+        assert info["iterations"] == its[q]
+        assert info["rho"][info["iterations"]] <= 1e-2 and not info["breakdown"]
