@@ -177,7 +177,21 @@ def batched_timing(reps=2):
     res = {"workload": "batch16_96c_320c", "problems": len(geoms), "voxel_views": vv,
            "batched_ms": times["batched"], "single_launches_ms": times["single"],
            "batched_voxel_views_per_s": vv / (times["batched"] * 1e-3)}
-    del xs, bs, po, vo, batch, geoms
+    # CGLS on all 16 problems at once (b = the batched projections above):
+    # one replay of a graph of 5 batched iterations
+    cvp.project_batched(xs, batch, opts, outs=po)
+    solver = cvp.BatchedCGLS(batch, opts, po)
+    solver.start()
+    solver.capture(5)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    solver.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    res["cgls_graph5_ms"] = e0.elapsed_time(e1)
+    res["cgls_ms_per_iteration"] = res["cgls_graph5_ms"] / 5
+    del solver, xs, bs, po, vo, batch, geoms
     torch.cuda.empty_cache()
     return res
 

@@ -29,6 +29,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "cvp_internal.h"
 
@@ -218,30 +219,33 @@ __device__ __forceinline__ void piece_record(const DevGeom &G, const ViewGeom &V
 // over [s - e, s + e] with e = |t - c2| h / D (Sec. III-B reading); the box
 // average of max(s, 0) is max(s, 0) + max(e - |s|, 0)^2 / (4e), so
 // C = [max(s0,0) - max(s1,0)] + (phi0^2 - phi1^2) / (4e).
+// rho4 = 4 rho; 1/(4e) is taken of 4e + 1e-30, which only differs from 4e
+// where e = 0, and there p0 = p1 = 0.
 template <bool EC>
-__device__ __forceinline__ float cum(float s1, float beta, float tc, float rho)
+__device__ __forceinline__ float cum(float s1, float beta, float tc, float rho, float rho4)
 {
     const float s0 = s1 + beta;
     const float plain = __builtin_amdgcn_fmed3f(s0, 0.0f, beta);   // = max(s0,0) - max(s1,0)
     if (!EC) return plain;
-    const float e = fabsf(tc) * rho;
     const float p0 = fmaxf(fmaf(fabsf(tc), rho, -fabsf(s0)), 0.0f);
     const float p1 = fmaxf(fmaf(fabsf(tc), rho, -fabsf(s1)), 0.0f);
-    const float inv4e = 0.25f * __builtin_amdgcn_rcpf(fmaxf(e, 1e-30f));
+    const float inv4e = __builtin_amdgcn_rcpf(fmaf(fabsf(tc), rho4, 1e-30f));
     return fmaf((p0 - p1) * (p0 + p1), inv4e, plain);
 }
 
 // Fixed-point accumulation of the projection.  A contribution w, already
-// scaled by the work item's 2^s, is split into w = hi * 2^32 + lo with
-// hi = floor(w / 2^32) and lo in [0, 2^32) (exact for w >= 0), truncated to a
-// 64-bit integer and added with an integer LDS atomic.  On gfx950 the
+// scaled by the work item's 2^s, arrives as t = w / 2^32 and is split into
+// w = hi * 2^32 + lo with hi = floor(t) and lo = frac(t) 2^32 in [0, 2^32)
+// (frac(t) = t - floor(t) is exact; v_fract keeps it below 1), truncated to
+// a 64-bit integer and added with an integer LDS atomic.  On gfx950 the
 // integer atomic is about thirty times cheaper than ds_add_f32, and integer
 // sums do not depend on the order of the additions.
-__device__ __forceinline__ void lds_add_fixed(unsigned long long *p, float w)
+__device__ __forceinline__ void lds_add_fixed(unsigned long long *p, float t)
 {
-    const float hi = floorf(w * 0x1p-32f);
-    const float lo = __builtin_amdgcn_fmed3f(fmaf(-hi, 0x1p32f, w), 0.0f, 4294967040.0f);
-    const unsigned long long q = ((unsigned long long)(unsigned)(int)hi << 32) | (unsigned long long)(unsigned)lo;
+    int hi;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(hi) : "v"(t));
+    const unsigned lo = (unsigned)(__builtin_amdgcn_fractf(t) * 0x1p32f);
+    const unsigned long long q = ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)lo;
     __hip_atomic_fetch_add(p, q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
@@ -295,17 +299,22 @@ __device__ __forceinline__ void row_range_unclipped(float Ytop, float beta, floa
 // unclipped range [vlo0, vhi0]; row(v, w) is called for each.  The unclipped
 // range includes the EC margin, so at its first boundary C is exactly beta
 // and at its last exactly 0 (the box average is zero there); those two
-// evaluations are skipped unless clipping moved the boundary.
+// evaluations are skipped unless clipping moved the boundary.  Boundaries
+// t = vlo - 1/2, vlo + 1/2, ...: d = Yh - t is exact (Yh on a 2^-10 grid) and
+// steps by 1 exactly; tc = t - c2 feeds only the box width.
 template <bool EC, bool EXACT, class Row>
 __device__ __forceinline__ void sweep_rows(int vlo0, int vhi0, int vlo, int vhi, float Yh, float Yl, float beta,
                                            float rho, float c2f, float coef, bool raw, float zt, float r8,
                                            float r9, Row &&row)
 {
     const bool ends = !EC || rho < 0.9f;         // the margin guarantees the end values
-    float tb = (float)vlo - 0.5f;
-    float s1p = (Yh - tb) + Yl;
+    const float rho4 = 4.0f * rho;
+    const float tb = (float)vlo - 0.5f;
+    float d = Yh - tb;
+    float tc = tb - c2f;
+    float s1p = d + Yl;
     float Cp = beta;
-    if (vlo != vlo0 || !ends) Cp = cum<EC>(s1p, beta, tb - c2f, rho);
+    if (vlo != vlo0 || !ends) Cp = cum<EC>(s1p, beta, tc, rho, rho4);
     auto weight = [&](float s1n, float Cn) {
         float w = coef * (Cp - Cn);
         if (EXACT && !raw) {
@@ -317,18 +326,20 @@ __device__ __forceinline__ void sweep_rows(int vlo0, int vhi0, int vlo, int vhi,
         return w;
     };
     for (int v = vlo; v < vhi; ++v) {
-        tb += 1.0f;
-        const float s1n = (Yh - tb) + Yl;
-        const float Cn = cum<EC>(s1n, beta, tb - c2f, rho);
+        d -= 1.0f;
+        tc += 1.0f;
+        const float s1n = d + Yl;
+        const float Cn = cum<EC>(s1n, beta, tc, rho, rho4);
         row(v, weight(s1n, Cn));
         Cp = Cn;
         s1p = s1n;
     }
     if (vlo <= vhi) {
-        tb += 1.0f;
-        const float s1n = (Yh - tb) + Yl;
+        d -= 1.0f;
+        tc += 1.0f;
+        const float s1n = d + Yl;
         float Cn = 0.0f;
-        if (vhi != vhi0 || !ends) Cn = cum<EC>(s1n, beta, tb - c2f, rho);
+        if (vhi != vhi0 || !ends) Cn = cum<EC>(s1n, beta, tc, rho, rho4);
         row(vhi, weight(s1n, Cn));
     }
 }
@@ -556,7 +567,7 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
                 float base = m;
                 if (!EXACT && !raw)
                     base = m * __builtin_amdgcn_rcpf(fmaf(zc, zc, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rq[0][8]), c))));
-                base = ldexpf(base, sc);
+                base = ldexpf(base, sc - 32);   // contributions arrive as w / 2^32
                 for (int p = 0; p < np; ++p) {
                     const int src = c + 16 * (p & 3);
                     float r[kRecFloats];
@@ -721,6 +732,9 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
         }
         wave_sync();
 
+        // the gather, with the window read from LDS (WIN) or global memory
+        auto gather = [&](auto winTag) {
+        constexpr bool WIN = decltype(winTag)::value;
 #pragma unroll
         for (int ps = 0; ps < KP; ++ps) {
         if (ps >= kp || k0 + ps * kWave >= G.n3) break;   // unused pass
@@ -742,10 +756,9 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
                 const float4 r1 = *reinterpret_cast<const float4 *>(rc + p * kRecFloats + 4);
                 const float4 r2 = *reinterpret_cast<const float4 *>(rc + p * kRecFloats + 8);
                 const int u = __float_as_int(r0.x);
-                const float coef = base * r0.y;
                 const float Yh = fmaf(-kf, r1.x, r0.z);
                 const float Yl = fmaf(-kf, r1.y, r0.w);
-                const float beta = r1.z, rho = r1.w;
+                const float beta = r1.z, rho = r1.w, rho4 = 4.0f * r1.w;
                 // (the gather keeps every boundary evaluation in its loop:
                 // skipping the two end values as the projection does was
                 // measured slower here)
@@ -755,14 +768,19 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
                 vhi = min(vhi, wv1);
                 if (!kv) vhi = vlo - 1;
                 const float *wcol = win + (u - wu0) * Hp - wv0;
-                float tb = (float)vlo - 0.5f;
-                float s1p = (Yh - tb) + Yl;
-                float Cp = cum<EC>(s1p, beta, tb - c2f, rho);
+                // boundaries as in sweep_rows: d = Yh - t exact, tc = t - c2
+                const float tb = (float)vlo - 0.5f;
+                float d = Yh - tb;
+                float tc = tb - c2f;
+                float s1p = d + Yl;
+                float Cp = cum<EC>(s1p, beta, tc, rho, rho4);
+                float ap = 0.0f;          // sum of (C_v - C_v+1) [1/r^2] val_v; times coef below
                 for (int v = vlo; v <= vhi; ++v) {
-                    tb += 1.0f;
-                    const float s1n = (Yh - tb) + Yl;
-                    const float Cn = cum<EC>(s1n, beta, tb - c2f, rho);
-                    float w = coef * (Cp - Cn);
+                    d -= 1.0f;
+                    tc += 1.0f;
+                    const float s1n = d + Yl;
+                    const float Cn = cum<EC>(s1n, beta, tc, rho, rho4);
+                    float w = Cp - Cn;
                     if (EXACT && !raw) {
                         float mm = 0.5f * (fmaxf(0.0f, -s1p) + fminf(beta, -s1n));
                         mm = fminf(fmaxf(mm, 0.0f), beta);
@@ -770,21 +788,25 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
                         w *= __builtin_amdgcn_rcpf(fmaf(zb, zb, r2.x));
                     }
                     float val;
-                    if (useWin) {
+                    if (WIN) {
                         val = wcol[v];
                     } else {
                         const size_t off = (size_t)v * G.M + u;
                         val = pv[off];
                         if (G.sigma) val *= G.sigma[off];
                     }
-                    a = fmaf(w, val, a);
+                    ap = fmaf(w, val, ap);
                     Cp = Cn;
                     s1p = s1n;
                 }
+                a = fmaf(base * r0.y, ap, a);
             }
             acc[ps][c] += a;
         }
         }
+        };
+        if (useWin) gather(std::true_type{});
+        else gather(std::false_type{});
         wave_sync();
     }
 
