@@ -311,6 +311,10 @@ cvp_status cvp_geometry_from_views(const cvp_geometry_desc *d, cvp_geometry **ou
         const double r0 = Dmin, r1 = std::hypot(D + rmax, zabs);
         G.wsum_bound = 64.0 * om * (r1 - r0);
         G.wsum_bound_raw = 64.0 * om * (r1 * r1 * r1 - r0 * r0 * r0) / 3.0;
+        // One (voxel, pixel) weight is at most the voxel's cut volume (<= a1
+        // a2 a3) over r^2 >= Dmin^2; a factor 2 covers FP32 rounding.
+        G.wone_bound = 2.0 * a1 * a2 * a3 / (Dmin * Dmin);
+        G.wone_bound_raw = 2.0 * a1 * a2 * a3;
     }
 
     const int pmax = pieces <= 4 ? 4 : 8;

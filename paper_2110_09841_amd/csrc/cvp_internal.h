@@ -38,7 +38,8 @@ struct DevGeom {
     int raw_volume;            // weight = cut volume (no 1/r^2)
     // Bounds on any pixel's weight sum per unit |mu| (with and without the
     // 1/r^2 factor), used to scale the projection's fixed-point sums.
-    double wsum_bound, wsum_bound_raw;
+    double wsum_bound, wsum_bound_raw;   // a pixel's summed weight per unit |mu|
+    double wone_bound, wone_bound_raw;   // one (voxel, pixel) weight per unit |mu|
 };
 
 struct ProjLaunch {

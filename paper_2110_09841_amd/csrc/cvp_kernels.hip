@@ -230,22 +230,20 @@ __device__ __forceinline__ float cum(float s1, float beta, float tc, float rho, 
     const float p0 = fmaxf(fmaf(fabsf(tc), rho, -fabsf(s0)), 0.0f);
     const float p1 = fmaxf(fmaf(fabsf(tc), rho, -fabsf(s1)), 0.0f);
     const float inv4e = __builtin_amdgcn_rcpf(fmaf(fabsf(tc), rho4, 1e-30f));
-    return fmaf((p0 - p1) * (p0 + p1), inv4e, plain);
+    return fmaf(fmaf(p0, p0, -(p1 * p1)), inv4e, plain);
 }
 
 // Fixed-point accumulation of the projection.  A contribution w, already
-// scaled by the work item's 2^s, arrives as t = w / 2^32 and is split into
-// w = hi * 2^32 + lo with hi = floor(t) and lo = frac(t) 2^32 in [0, 2^32)
-// (frac(t) = t - floor(t) is exact; v_fract keeps it below 1), truncated to
-// a 64-bit integer and added with an integer LDS atomic.  On gfx950 the
-// integer atomic is about thirty times cheaper than ds_add_f32, and integer
-// sums do not depend on the order of the additions.
-__device__ __forceinline__ void lds_add_fixed(unsigned long long *p, float t)
+// scaled by the work item's 2^s so that |w| < 2^30, is rounded to the nearest
+// integer (v_cvt_rpi: floor(w + 1/2)), sign-extended to 64 bits and added
+// with an integer LDS atomic; the 64-bit sums hold a pixel's total.  On
+// gfx950 the integer atomic is about thirty times cheaper than ds_add_f32,
+// and integer sums do not depend on the order of the additions.
+__device__ __forceinline__ void lds_add_fixed(unsigned long long *p, float w)
 {
-    int hi;
-    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(hi) : "v"(t));
-    const unsigned lo = (unsigned)(__builtin_amdgcn_fractf(t) * 0x1p32f);
-    const unsigned long long q = ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)lo;
+    int lo;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(lo) : "v"(w));
+    const unsigned long long q = (unsigned long long)(long long)lo;
     __hip_atomic_fetch_add(p, q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
@@ -296,16 +294,16 @@ __device__ __forceinline__ void row_range_unclipped(float Ytop, float beta, floa
 }
 
 // Row weights of one voxel piece: rows [vlo, vhi] (already clipped) of the
-// unclipped range [vlo0, vhi0]; row(v, w) is called for each.  The unclipped
+// unclipped range [vlo0, vhi0], added to the band column bcol.  The unclipped
 // range includes the EC margin, so at its first boundary C is exactly beta
 // and at its last exactly 0 (the box average is zero there); those two
 // evaluations are skipped unless clipping moved the boundary.  Boundaries
 // t = vlo - 1/2, vlo + 1/2, ...: d = Yh - t is exact (Yh on a 2^-10 grid) and
 // steps by 1 exactly; tc = t - c2 feeds only the box width.
-template <bool EC, bool EXACT, class Row>
+template <bool EC, bool EXACT>
 __device__ __forceinline__ void sweep_rows(int vlo0, int vhi0, int vlo, int vhi, float Yh, float Yl, float beta,
                                            float rho, float c2f, float coef, bool raw, float zt, float r8,
-                                           float r9, Row &&row)
+                                           float r9, unsigned long long *bcol)
 {
     const bool ends = !EC || rho < 0.9f;         // the margin guarantees the end values
     const float rho4 = 4.0f * rho;
@@ -325,12 +323,13 @@ __device__ __forceinline__ void sweep_rows(int vlo0, int vhi0, int vlo, int vhi,
         }
         return w;
     };
-    for (int v = vlo; v < vhi; ++v) {
+    unsigned long long *const last = bcol + vhi;
+    for (unsigned long long *q = bcol + vlo; q < last; ++q) {
         d -= 1.0f;
         tc += 1.0f;
         const float s1n = d + Yl;
         const float Cn = cum<EC>(s1n, beta, tc, rho, rho4);
-        row(v, weight(s1n, Cn));
+        lds_add_fixed(q, weight(s1n, Cn));
         Cp = Cn;
         s1p = s1n;
     }
@@ -340,7 +339,7 @@ __device__ __forceinline__ void sweep_rows(int vlo0, int vhi0, int vlo, int vhi,
         const float s1n = d + Yl;
         float Cn = 0.0f;
         if (vhi != vhi0 || !ends) Cn = cum<EC>(s1n, beta, tc, rho, rho4);
-        row(vhi, weight(s1n, Cn));
+        lds_add_fixed(last, weight(s1n, Cn));
     }
 }
 
@@ -491,9 +490,11 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
         }
     };
 
-    // Scale of the fixed-point image: the largest |mu| in the wedge (as the
-    // bit pattern of |mu|, so Inf and NaN compare above every finite value)
-    // times a geometric bound on any pixel's weight sum must stay below 2^61.
+    // Scale of the fixed-point image from the largest |mu| in the wedge (as
+    // the bit pattern of |mu|, so Inf and NaN compare above every finite
+    // value): times a geometric bound on one weight it must stay below 2^30
+    // (each contribution fits a 32-bit integer), times a bound on a pixel's
+    // weight sum below 2^61 (the 64-bit sums cannot overflow).
     unsigned mxl = 0u;
     for (int gi = wave; gi < total; gi += kWaves) {
         int j, i0;
@@ -516,9 +517,10 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
     const bool finite = mxb < 0x7f800000u;
     int sc = 0;
     if (finite && mxb != 0u) {
-        int e;
-        frexp((double)__uint_as_float(mxb) * (raw ? G.wsum_bound_raw : G.wsum_bound), &e);
-        sc = 61 - e;
+        int e1, e2;
+        frexp((double)__uint_as_float(mxb) * (raw ? G.wone_bound_raw : G.wone_bound), &e1);
+        frexp((double)__uint_as_float(mxb) * (raw ? G.wsum_bound_raw : G.wsum_bound), &e2);
+        sc = min(30 - e1, 61 - e2);
     }
     const int ngi = (finite && mxb != 0u) ? total : 0;   // all-zero wedge: nothing to add
 
@@ -567,7 +569,7 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
                 float base = m;
                 if (!EXACT && !raw)
                     base = m * __builtin_amdgcn_rcpf(fmaf(zc, zc, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rq[0][8]), c))));
-                base = ldexpf(base, sc - 32);   // contributions arrive as w / 2^32
+                base = ldexpf(base, sc);
                 for (int p = 0; p < np; ++p) {
                     const int src = c + 16 * (p & 3);
                     float r[kRecFloats];
@@ -589,8 +591,7 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
                     int vlo0, vhi0;
                     row_range_unclipped<EC>(Yh + Yl, beta, r[10], c2f, vlo0, vhi0);
                     sweep_rows<EC, EXACT>(vlo0, vhi0, max(vlo0, 0), min(vhi0, G.N - 1), Yh, Yl, beta, rho, c2f,
-                                          coef, raw, zt, r[8], r[9],
-                                          [&](int v, float w) { lds_add_fixed(bcol + v, w); });
+                                          coef, raw, zt, r[8], r[9], bcol);
                 }
             }
         }
@@ -775,7 +776,7 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
                 float s1p = d + Yl;
                 float Cp = cum<EC>(s1p, beta, tc, rho, rho4);
                 float ap = 0.0f;          // sum of (C_v - C_v+1) [1/r^2] val_v; times coef below
-                for (int v = vlo; v <= vhi; ++v) {
+                auto row = [&](float val) {
                     d -= 1.0f;
                     tc += 1.0f;
                     const float s1n = d + Yl;
@@ -787,17 +788,20 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
                         const float zb = fmaf(-mm, r2.y, zt);
                         w *= __builtin_amdgcn_rcpf(fmaf(zb, zb, r2.x));
                     }
-                    float val;
-                    if (WIN) {
-                        val = wcol[v];
-                    } else {
-                        const size_t off = (size_t)v * G.M + u;
-                        val = pv[off];
-                        if (G.sigma) val *= G.sigma[off];
-                    }
                     ap = fmaf(w, val, ap);
                     Cp = Cn;
                     s1p = s1n;
+                };
+                if (WIN) {
+                    const float *const last = wcol + vhi;
+                    for (const float *q = wcol + vlo; q <= last; ++q) row(*q);
+                } else {
+                    for (int v = vlo; v <= vhi; ++v) {
+                        const size_t off = (size_t)v * G.M + u;
+                        float val = pv[off];
+                        if (G.sigma) val *= G.sigma[off];
+                        row(val);
+                    }
                 }
                 a = fmaf(base * r0.y, ap, a);
             }
