@@ -205,7 +205,7 @@ __device__ __forceinline__ void piece_record(const DevGeom &G, const ViewGeom &V
     rec[8] = (float)R2;
     rec[9] = (float)gmm;
     // EC row margin factor 1.01 rho / (1 - rho) from the FP32 rho the voxel
-    // stage uses (see ec_margin)
+    // stage uses (see row_range_unclipped)
     const double rho32 = (double)rec[7];
     rec[10] = EC ? (float)(1.01 * rho32 / fmax(1.0 - rho32, 0.05)) : 0.0f;
     rec[11] = 0.0f;
@@ -259,38 +259,45 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// EC margin of a piece's row range: at least the box half-width e(t) =
-// |t - c2| rho at every boundary t within a row of the extent, i.e. E with
-// E (1 - rho) >= rho (max |Y - c2| + 1.001), so the range covers every row
-// the box average reaches and C is exactly beta / 0 at its first / last
-// boundary.  Valid for rho < 0.9 (a box narrower than the source distance).
-// mfac = 1.01 rho / max(1 - rho, 0.05) comes with the piece record.
-template <bool EC>
-__device__ __forceinline__ float ec_margin(float Ytop, float beta, float mfac, float c2f)
+// Row range of a piece, before clipping to the detector: the rows its chi2
+// extent [Ytop, Ytop + beta] touches, widened by 1e-3 for FP32 rounding and,
+// with EC, by a margin E at least the box half-width e(t) = |t - c2| rho at
+// every boundary t within a row of the extent, i.e. E (1 - rho) >= rho
+// (max |Y - c2| + 1.001).  Then the range covers every row the box average
+// reaches, and C is exactly beta / 0 at its first / last boundary.  Valid
+// for rho < 0.9 (a box narrower than the source distance).  mfac = 1.01 rho
+// / max(1 - rho, 0.05) comes with the piece record; E = mfac (M + 1.01) with
+// M = max(|Ytop - c2|, |Ytop + beta - c2|) = max(Ytop + beta - c2, c2 - Ytop).
+__device__ __forceinline__ int floor_to_int(float x)
 {
-    if (!EC) return 0.0f;
-    const float M = fmaxf(fabsf(Ytop - c2f), fabsf(Ytop + beta - c2f));
-    return mfac * (M + 1.01f);
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
 }
 
-// Rows touched by a piece of voxel k: [vlo, vhi] clipped to the detector.
-template <bool EC>
-__device__ __forceinline__ void row_range(float Ytop, float beta, float mfac, float c2f, int N,
-                                          int &vlo, int &vhi)
-{
-    const float E = ec_margin<EC>(Ytop, beta, mfac, c2f);
-    vlo = max((int)floorf(Ytop - E + 0.5f - 1e-3f), 0);
-    vhi = min((int)floorf(Ytop + beta + E + 0.5f + 1e-3f), N - 1);
-}
-
-// The same range before clipping to the detector.
 template <bool EC>
 __device__ __forceinline__ void row_range_unclipped(float Ytop, float beta, float mfac, float c2f, int &vlo0,
                                                     int &vhi0)
 {
-    const float E = ec_margin<EC>(Ytop, beta, mfac, c2f);
-    vlo0 = (int)floorf(Ytop - E + 0.5f - 1e-3f);
-    vhi0 = (int)floorf(Ytop + beta + E + 0.5f + 1e-3f);
+    const float yb = Ytop + beta;
+    float lo = Ytop + 0.499f, hi = yb + 0.501f;
+    if (EC) {
+        const float M1 = fmaxf(yb - c2f, c2f - Ytop) + 1.01f;
+        lo = fmaf(-mfac, M1, lo);
+        hi = fmaf(mfac, M1, hi);
+    }
+    vlo0 = floor_to_int(lo);
+    vhi0 = floor_to_int(hi);
+}
+
+// The same range clipped to the detector rows [0, N - 1].
+template <bool EC>
+__device__ __forceinline__ void row_range(float Ytop, float beta, float mfac, float c2f, int N, int &vlo,
+                                          int &vhi)
+{
+    row_range_unclipped<EC>(Ytop, beta, mfac, c2f, vlo, vhi);
+    vlo = max(vlo, 0);
+    vhi = min(vhi, N - 1);
 }
 
 // Row weights of one voxel piece: rows [vlo, vhi] (already clipped) of the
