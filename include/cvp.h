@@ -117,7 +117,7 @@ void cvp_geometry_destroy(cvp_geometry *g);
  * b = A x.  d_vol: [n3][n2][n1] float32 input; d_proj: [n_views][rows][cols]
  * float32 output, overwritten.  Projection is voxel driven; each workgroup
  * owns a band of detector columns of one view and sums into LDS in 64-bit
- * fixed point, with a scale chosen from the largest |mu| it reads, so there
+ * fixed point, with a scale chosen from the largest |mu| in its wedge, so there
  * are no global atomics and the sums do not depend on the order of the
  * additions: results are bitwise reproducible for a given launch plan.  A
  * non-finite input value makes every band that reads it NaN.
@@ -125,6 +125,18 @@ void cvp_geometry_destroy(cvp_geometry *g);
  */
 cvp_status cvp_project(const cvp_geometry *g, const cvp_options *opts,
                        const float *d_vol, float *d_proj, void *hip_stream);
+
+/*
+ * cvp_project with caller-provided device scratch: a first kernel stores the
+ * largest |mu| of every 16-column group of voxel columns in d_work, and the
+ * projection's workgroups take their scales from it instead of reading their
+ * volume wedges a second time.  Results equal cvp_project's bitwise.  d_work:
+ * at least cvp_project_workspace_size bytes, 4-byte aligned, owned by the
+ * caller; calls that overlap in time need distinct work buffers.
+ */
+cvp_status cvp_project_workspace_size(const cvp_geometry *g, int64_t *bytes);
+cvp_status cvp_project_ws(const cvp_geometry *g, const cvp_options *opts,
+                          const float *d_vol, float *d_proj, void *d_work, void *hip_stream);
 
 /*
  * x = A^T b with the same weights (the exact adjoint of cvp_project).

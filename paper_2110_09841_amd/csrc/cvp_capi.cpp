@@ -405,7 +405,31 @@ cvp_status cvp_project(const cvp_geometry *g, const cvp_options *o, const float 
     cvp_status st = prepare(g, o, d_vol, d_proj, G);
     if (st != CVP_OK) return st;
     hipError_t e = cvp::launch_project(G, g->pl, o->variant == CVP_EXACT, o->elevation_correction != 0,
-                                       d_vol, d_proj, (hipStream_t)stream);
+                                       d_vol, d_proj, nullptr, (hipStream_t)stream);
+    if (e != hipSuccess) return device_fail(e, "projection launch");
+    return ok();
+}
+
+cvp_status cvp_project_workspace_size(const cvp_geometry *g, int64_t *bytes)
+{
+    if (!g) return fail(CVP_E_INVALID, "geometry is NULL");
+    if (!bytes) return fail(CVP_E_INVALID, "bytes is NULL");
+    *bytes = cvp::group_max_cells(g->base) * (int64_t)sizeof(unsigned);
+    return ok();
+}
+
+cvp_status cvp_project_ws(const cvp_geometry *g, const cvp_options *o, const float *d_vol, float *d_proj,
+                          void *d_work, void *stream)
+{
+    cvp::DevGeom G;
+    cvp_status st = prepare(g, o, d_vol, d_proj, G);
+    if (st != CVP_OK) return st;
+    if (!d_work) return fail(CVP_E_INVALID, "work is NULL");
+    if (reinterpret_cast<uintptr_t>(d_work) & 3) return fail(CVP_E_INVALID, "work must be 4-byte aligned");
+    if (d_work == (const void *)d_vol || d_work == (void *)d_proj)
+        return fail(CVP_E_INVALID, "work aliases the volume or the projections");
+    hipError_t e = cvp::launch_project(G, g->pl, o->variant == CVP_EXACT, o->elevation_correction != 0,
+                                       d_vol, d_proj, (unsigned *)d_work, (hipStream_t)stream);
     if (e != hipSuccess) return device_fail(e, "projection launch");
     return ok();
 }
@@ -431,6 +455,7 @@ struct cvp_batch {
     cvp::BatchProblem *d_probs = nullptr;
     cvp::BatchTable *d_ptab = nullptr, *d_btab = nullptr;
     int *d_counter = nullptr;
+    std::vector<unsigned *> d_gmax;   // per problem: per-group maxima of the volume
     size_t plds = 0, blds = 0;
     int pgrid = 0, bgrid = 0;
 };
@@ -444,6 +469,8 @@ void cvp_batch_destroy(cvp_batch *b)
     if (b->d_ptab) (void)hipFree(b->d_ptab);
     if (b->d_btab) (void)hipFree(b->d_btab);
     if (b->d_counter) (void)hipFree(b->d_counter);
+    for (unsigned *t : b->d_gmax)
+        if (t) (void)hipFree(t);
     delete b;
 }
 
@@ -485,6 +512,7 @@ cvp_status cvp_batch_create(const cvp_geometry *const *geoms, int32_t n, cvp_bat
         P.bitems = bl.items;
         P.in = nullptr;
         P.out = nullptr;
+        P.gmax = nullptr;   // set below
         b->plds = std::max(b->plds, pl.lds);
         b->blds = std::max(b->blds, bl.lds);
         pcost[q] = (double)g->nvox / pl.nbands;           // voxels per band (all k)
@@ -510,6 +538,11 @@ cvp_status cvp_batch_create(const cvp_geometry *const *geoms, int32_t n, cvp_bat
     if (e == hipSuccess) e = hipMalloc((void **)&b->d_ptab, sizeof(cvp::BatchTable));
     if (e == hipSuccess) e = hipMalloc((void **)&b->d_btab, sizeof(cvp::BatchTable));
     if (e == hipSuccess) e = hipMalloc((void **)&b->d_counter, 2 * sizeof(int));
+    b->d_gmax.assign(n, nullptr);
+    for (int q = 0; q < n && e == hipSuccess; ++q) {
+        e = hipMalloc((void **)&b->d_gmax[q], cvp::group_max_cells(probs[q].G) * sizeof(unsigned));
+        probs[q].gmax = b->d_gmax[q];
+    }
     if (e == hipSuccess) e = hipMemcpy(b->d_probs, probs.data(), n * sizeof(cvp::BatchProblem), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b->d_ptab, &pt, sizeof(pt), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b->d_btab, &bt, sizeof(bt), hipMemcpyHostToDevice);
@@ -536,6 +569,13 @@ static cvp_status batched(const cvp_batch *b, const cvp_options *o, const float 
         io.in[q] = ins[q];
         io.out[q] = outs[q];
         io.sigma[q] = G.sigma;
+    }
+    if (!backward) {
+        // per-group maxima of every volume, for the projection items' scales
+        for (int q = 0; q < b->n; ++q) {
+            hipError_t e = cvp::launch_group_max(b->geoms[q]->base, ins[q], b->d_gmax[q], (hipStream_t)stream);
+            if (e != hipSuccess) return device_fail(e, "batched group maxima");
+        }
     }
     hipError_t e = cvp::launch_batched(backward, b->d_probs, backward ? b->d_btab : b->d_ptab,
                                        b->d_counter, io,
@@ -592,7 +632,9 @@ cvp_status cvp_cgls_start(const cvp_geometry *g, const cvp_options *o, const flo
     double *sc = (double *)d_work;
     double *part = sc + cvp::kCglsScalars + 2 * cvp::kCglsHistory;
     const bool ex = o->variant == CVP_EXACT, ec = o->elevation_correction != 0;
-    hipError_t e = cvp::launch_project(G, g->pl, ex, ec, d_x, d_q, sm);
+    // s (volume sized) is free until A^T r: it holds the projection's
+    // per-group maxima
+    hipError_t e = cvp::launch_project(G, g->pl, ex, ec, d_x, d_q, (unsigned *)d_s, sm);
     if (e == hipSuccess) e = cvp::blas_residual(d_r, d_b, d_q, g->npix, sm);
     if (e == hipSuccess) e = cvp::launch_backproject(G, g->bl, ex, ec, d_r, d_s, sm);
     if (e == hipSuccess) e = cvp::blas_update_p(d_p, d_s, g->nvox, sc, 1, sm);
@@ -614,7 +656,7 @@ cvp_status cvp_cgls_iterate(const cvp_geometry *g, const cvp_options *o, int32_t
     const bool ex = o->variant == CVP_EXACT, ec = o->elevation_correction != 0;
     hipError_t e = hipSuccess;
     for (int it = 0; it < n_iter && e == hipSuccess; ++it) {
-        e = cvp::launch_project(G, g->pl, ex, ec, d_p, d_q, sm);                        // q = A p
+        e = cvp::launch_project(G, g->pl, ex, ec, d_p, d_q, (unsigned *)d_s, sm);       // q = A p (s free)
         if (e == hipSuccess) e = cvp::blas_dot(d_q, d_q, g->npix, part, sc, 1, nullptr, sm);   // alpha
         if (e == hipSuccess) e = cvp::blas_update_xr(d_x, d_p, g->nvox, d_r, d_q, g->npix, sc, part, sm);
         if (e == hipSuccess) e = cvp::launch_backproject(G, g->bl, ex, ec, d_r, d_s, sm);   // s = A^T r

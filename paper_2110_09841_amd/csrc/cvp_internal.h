@@ -79,6 +79,7 @@ struct BatchProblem {        // device table entry (one per problem)
     int bitems;              // backprojection work items
     const float *in;         // set per call by batch_setup
     float *out;
+    unsigned *gmax;          // the problem's per-group maxima (owned by the batch)
 };
 
 struct BatchTable {          // device: work segments, largest items first
@@ -116,8 +117,12 @@ hipError_t blas_update_p(float *p, const float *sv, int64_t n, const double *sc,
                          hipStream_t s);
 hipError_t blas_residual(float *r, const float *b, const float *q, int64_t n, hipStream_t s);
 
+// gmax: device scratch of group_max_cells(g) words for the per-group maxima
+// of |vol| (computed by the call), or nullptr (the kernel scans the wedges).
 hipError_t launch_project(const DevGeom &g, const ProjLaunch &L, bool exact, bool ec,
-                          const float *vol, float *proj, hipStream_t stream);
+                          const float *vol, float *proj, unsigned *gmax, hipStream_t stream);
+int64_t group_max_cells(const DevGeom &g);
+hipError_t launch_group_max(const DevGeom &g, const float *vol, unsigned *gmax, hipStream_t stream);
 hipError_t launch_backproject(const DevGeom &g, const BackLaunch &L, bool exact, bool ec,
                               const float *proj, float *vol, hipStream_t stream);
 

@@ -384,7 +384,7 @@ __device__ __forceinline__ void build_records(const DevGeom &G, const ViewGeom &
 template <bool EXACT, bool EC, int PMAX>
 __device__ __forceinline__ void project_item(const DevGeom &G, const int U, const int item,
                                              float *smem, const float *__restrict__ vol,
-                                             float *__restrict__ proj)
+                                             float *__restrict__ proj, const unsigned *__restrict__ gmax)
 {
     constexpr int GW = 16;
     const int view = item % G.nviews;
@@ -501,18 +501,28 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
     // the bit pattern of |mu|, so Inf and NaN compare above every finite
     // value): times a geometric bound on one weight it must stay below 2^30
     // (each contribution fits a 32-bit integer), times a bound on a pixel's
-    // weight sum below 2^61 (the 64-bit sums cannot overflow).
+    // weight sum below 2^61 (the 64-bit sums cannot overflow).  With gmax
+    // (the per-group maxima of group_max_kernel) the wedge maximum is a
+    // lookup per group; without it the wedge is read once more here.
     unsigned mxl = 0u;
-    for (int gi = wave; gi < total; gi += kWaves) {
-        int j, i0;
-        group(gi, j, i0);
-        const bool full = vec_rows && (i0 + GW <= G.n1);
-        for (int kc = 0; kc < G.n3; kc += kWave) {
-            float mu[GW];
-            load_mu(j, i0, kc + lane, full, mu);
-            if (kc + lane < G.n3) {
+    if (gmax) {
+        for (int gi = tid; gi < total; gi += kBlock) {
+            int j, i0;
+            group(gi, j, i0);
+            mxl = max(mxl, gmax[j * ngroups + i0 / GW]);
+        }
+    } else {
+        for (int gi = wave; gi < total; gi += kWaves) {
+            int j, i0;
+            group(gi, j, i0);
+            const bool full = vec_rows && (i0 + GW <= G.n1);
+            for (int kc = 0; kc < G.n3; kc += kWave) {
+                float mu[GW];
+                load_mu(j, i0, kc + lane, full, mu);
+                if (kc + lane < G.n3) {
 #pragma unroll
-                for (int c = 0; c < GW; ++c) mxl = max(mxl, __float_as_uint(mu[c]) & 0x7fffffffu);
+                    for (int c = 0; c < GW; ++c) mxl = max(mxl, __float_as_uint(mu[c]) & 0x7fffffffu);
+                }
             }
         }
     }
@@ -624,7 +634,7 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
 template <bool EXACT, bool EC, int PMAX>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
 project_kernel(const DevGeom G, const int U, const int nbands, const float *__restrict__ vol,
-               float *__restrict__ proj)
+               float *__restrict__ proj, const unsigned *__restrict__ gmax)
 {
     extern __shared__ __align__(16) float smem[];
     // Workgroups go to the 8 XCDs round robin.  XCD x takes bands x, x + 8,
@@ -634,7 +644,39 @@ project_kernel(const DevGeom G, const int U, const int nbands, const float *__re
     const int slot = blockIdx.x >> 3;
     const int band = (blockIdx.x & 7) + 8 * (slot / G.nviews);
     if (band >= nbands) return;
-    project_item<EXACT, EC, PMAX>(G, U, band * G.nviews + slot % G.nviews, smem, vol, proj);
+    project_item<EXACT, EC, PMAX>(G, U, band * G.nviews + slot % G.nviews, smem, vol, proj, gmax);
+}
+
+// gmax[j * ngroups + q] = the largest |mu| bit pattern over the columns
+// 16 q .. 16 q + 15 (< n1) of row j and all slices: one wave per (j, q),
+// lanes over k.  The projection's wedge maxima are then lookups.
+__global__ void __launch_bounds__(kBlock)
+group_max_kernel(const DevGeom G, const float *__restrict__ vol, unsigned *__restrict__ gmax)
+{
+    constexpr int GW = 16;
+    const int ngroups = (G.n1 + GW - 1) / GW;
+    const int cell = blockIdx.x * kWaves + threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (cell >= G.n2 * ngroups) return;
+    const int j = cell / ngroups, i0 = (cell % ngroups) * GW;
+    const bool full = (G.n1 & 3) == 0 && (reinterpret_cast<uintptr_t>(vol) & 15) == 0 && i0 + GW <= G.n1;
+    unsigned mxl = 0u;
+    for (int k = lane; k < G.n3; k += kWave) {
+        const float *rowp = vol + ((size_t)k * G.n2 + j) * G.n1 + i0;
+        if (full) {
+#pragma unroll
+            for (int q = 0; q < GW / 4; ++q) {
+                const float4 t4 = reinterpret_cast<const float4 *>(rowp)[q];
+                mxl = max(mxl, max(max(__float_as_uint(t4.x) & 0x7fffffffu, __float_as_uint(t4.y) & 0x7fffffffu),
+                                   max(__float_as_uint(t4.z) & 0x7fffffffu, __float_as_uint(t4.w) & 0x7fffffffu)));
+            }
+        } else {
+            for (int c = 0; c < GW && i0 + c < G.n1; ++c) mxl = max(mxl, __float_as_uint(rowp[c]) & 0x7fffffffu);
+        }
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) mxl = max(mxl, (unsigned)__shfl_xor((int)mxl, off));
+    if (lane == 0) gmax[cell] = mxl;
 }
 
 // ------------------------------------------------------------ backprojection
@@ -882,9 +924,9 @@ project_batched_kernel(const BatchProblem *__restrict__ probs, const BatchTable 
     while (next_item(*T, counter, p, local)) {
         const BatchProblem &P = probs[p];
         if (P.pmax <= 4)
-            project_item<EXACT, EC, 4>(P.G, P.U, local, smem, P.in, P.out);
+            project_item<EXACT, EC, 4>(P.G, P.U, local, smem, P.in, P.out, P.gmax);
         else
-            project_item<EXACT, EC, 8>(P.G, P.U, local, smem, P.in, P.out);
+            project_item<EXACT, EC, 8>(P.G, P.U, local, smem, P.in, P.out, P.gmax);
     }
 }
 
@@ -936,13 +978,19 @@ __global__ void batch_setup(BatchProblem *probs, const BatchIO io, int *counter)
 
 template <bool EXACT, bool EC>
 hipError_t launch_p(const DevGeom &g, const ProjLaunch &L, const float *vol, float *proj,
-                    hipStream_t s)
+                    unsigned *gmax, hipStream_t s)
 {
+    if (gmax) {
+        hipError_t e = launch_group_max(g, vol, gmax, s);
+        if (e != hipSuccess) return e;
+    }
     const dim3 grid(8 * L.chunk), block(kBlock);
     if (L.pmax <= 4)
-        hipLaunchKernelGGL((project_kernel<EXACT, EC, 4>), grid, block, L.lds, s, g, L.U, L.nbands, vol, proj);
+        hipLaunchKernelGGL((project_kernel<EXACT, EC, 4>), grid, block, L.lds, s, g, L.U, L.nbands, vol, proj,
+                           gmax);
     else
-        hipLaunchKernelGGL((project_kernel<EXACT, EC, 8>), grid, block, L.lds, s, g, L.U, L.nbands, vol, proj);
+        hipLaunchKernelGGL((project_kernel<EXACT, EC, 8>), grid, block, L.lds, s, g, L.U, L.nbands, vol, proj,
+                           gmax);
     return hipGetLastError();
 }
 
@@ -1074,12 +1122,25 @@ hipError_t configure_kernel_lds(size_t max_lds, size_t max_lds_batched)
 }
 
 hipError_t launch_project(const DevGeom &g, const ProjLaunch &L, bool exact, bool ec,
-                          const float *vol, float *proj, hipStream_t stream)
+                          const float *vol, float *proj, unsigned *gmax, hipStream_t stream)
 {
-    if (exact) return ec ? launch_p<true, true>(g, L, vol, proj, stream)
-                         : launch_p<true, false>(g, L, vol, proj, stream);
-    return ec ? launch_p<false, true>(g, L, vol, proj, stream)
-              : launch_p<false, false>(g, L, vol, proj, stream);
+    if (exact) return ec ? launch_p<true, true>(g, L, vol, proj, gmax, stream)
+                         : launch_p<true, false>(g, L, vol, proj, gmax, stream);
+    return ec ? launch_p<false, true>(g, L, vol, proj, gmax, stream)
+              : launch_p<false, false>(g, L, vol, proj, gmax, stream);
+}
+
+int64_t group_max_cells(const DevGeom &g)
+{
+    return (int64_t)g.n2 * ((g.n1 + 15) / 16);
+}
+
+hipError_t launch_group_max(const DevGeom &g, const float *vol, unsigned *gmax, hipStream_t stream)
+{
+    const int64_t cells = group_max_cells(g);
+    hipLaunchKernelGGL(group_max_kernel, dim3((unsigned)((cells + kWaves - 1) / kWaves)), dim3(kBlock), 0, stream,
+                       g, vol, gmax);
+    return hipGetLastError();
 }
 
 hipError_t launch_backproject(const DevGeom &g, const BackLaunch &L, bool exact, bool ec,

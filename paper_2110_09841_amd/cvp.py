@@ -47,6 +47,9 @@ class Geometry:
         self.vol_shape = (n3, n2, n1)
         self.proj_shape = (len(params["angles_rad"]), int(params["det_rows"]), int(params["det_cols"]))
         self.device = torch.device("cuda", torch.cuda.current_device())
+        nbytes = ctypes.c_int64()
+        _lib.check(_lib.lib().cvp_project_workspace_size(h, ctypes.byref(nbytes)))
+        self.project_work_words = max(1, (nbytes.value + 3) // 4)
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -93,14 +96,18 @@ def _stream():
 
 
 def project(x, geom: Geometry, opts: Options = Options(), out=None):
-    """b = A x (overwrites ``out`` if given)."""
+    """b = A x (overwrites ``out`` if given).  Runs cvp_project_ws with its
+    small scratch (the per-group maxima of |x|) from torch's caching
+    allocator on the current stream."""
     _check_tensor(x, geom.vol_shape, "x")
     if out is None:
         out = torch.empty(geom.proj_shape, dtype=torch.float32, device=x.device)
     _check_tensor(out, geom.proj_shape, "out")
+    work = torch.empty(geom.project_work_words, dtype=torch.int32, device=x.device)
     o = opts.c()
-    _lib.check(_lib.lib().cvp_project(geom.handle, ctypes.byref(o), ctypes.c_void_p(x.data_ptr()),
-                                      ctypes.c_void_p(out.data_ptr()), _stream()))
+    _lib.check(_lib.lib().cvp_project_ws(geom.handle, ctypes.byref(o), ctypes.c_void_p(x.data_ptr()),
+                                         ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(work.data_ptr()),
+                                         _stream()))
     return out
 
 
