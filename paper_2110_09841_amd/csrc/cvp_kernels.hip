@@ -809,21 +809,22 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
                 const float Yh = fmaf(-kf, r1.x, r0.z);
                 const float Yl = fmaf(-kf, r1.y, r0.w);
                 const float beta = r1.z, rho = r1.w, rho4 = 4.0f * r1.w;
-                // (the gather keeps every boundary evaluation in its loop:
-                // skipping the two end values as the projection does was
-                // measured slower here)
-                int vlo, vhi;
-                row_range<EC>(Yh + Yl, beta, r2.z, c2f, G.N, vlo, vhi);
-                vlo = max(vlo, wv0);
-                vhi = min(vhi, wv1);
-                if (!kv) vhi = vlo - 1;
+                // rows clipped to the detector and the window; as in the
+                // projection, C at the first boundary of the unclipped range
+                // is exactly beta
+                int vlo0, vhi0;
+                row_range_unclipped<EC>(Yh + Yl, beta, r2.z, c2f, vlo0, vhi0);
+                const bool ends = !EC || rho < 0.9f;
+                const int vlo = max(max(vlo0, 0), wv0);
+                const int vhi = kv ? min(min(vhi0, G.N - 1), wv1) : vlo - 1;
                 const float *wcol = win + (u - wu0) * Hp - wv0;
                 // boundaries as in sweep_rows: d = Yh - t exact, tc = t - c2
                 const float tb = (float)vlo - 0.5f;
                 float d = Yh - tb;
                 float tc = tb - c2f;
                 float s1p = d + Yl;
-                float Cp = cum<EC>(s1p, beta, tc, rho, rho4);
+                float Cp = beta;
+                if (vlo != vlo0 || !ends) Cp = cum<EC>(s1p, beta, tc, rho, rho4);
                 float ap = 0.0f;          // sum of (C_v - C_v+1) [1/r^2] val_v; times coef below
                 auto row = [&](float val) {
                     d -= 1.0f;
@@ -843,7 +844,24 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
                 };
                 if (WIN) {
                     const float *const last = wcol + vhi;
-                    for (const float *q = wcol + vlo; q <= last; ++q) row(*q);
+                    for (const float *q = wcol + vlo; q < last; ++q) row(*q);
+                    if (vlo <= vhi) {
+                        // last row: C at the last boundary of the unclipped
+                        // range is exactly 0
+                        d -= 1.0f;
+                        tc += 1.0f;
+                        const float s1n = d + Yl;
+                        float Cn = 0.0f;
+                        if (vhi != vhi0 || !ends) Cn = cum<EC>(s1n, beta, tc, rho, rho4);
+                        float w = Cp - Cn;
+                        if (EXACT && !raw) {
+                            float mm = 0.5f * (fmaxf(0.0f, -s1p) + fminf(beta, -s1n));
+                            mm = fminf(fmaxf(mm, 0.0f), beta);
+                            const float zb = fmaf(-mm, r2.y, zt);
+                            w *= __builtin_amdgcn_rcpf(fmaf(zb, zb, r2.x));
+                        }
+                        ap = fmaf(w, *last, ap);
+                    }
                 } else {
                     for (int v = vlo; v <= vhi; ++v) {
                         const size_t off = (size_t)v * G.M + u;
