@@ -91,7 +91,8 @@ size_t project_lds_bytes(int U, int N, int n2, int pmax)
 
 size_t backproject_lds_bytes(int gw, int pmax, int winCap)
 {
-    const size_t waveFloats = ((size_t)gw * pmax * kRecFloats + gw + winCap + 3) / 4 * 4;
+    const size_t rec = (size_t)back_views_per_pass(gw, pmax) * back_rec_floats(gw, pmax);
+    const size_t waveFloats = (rec + winCap + 3) / 4 * 4;
     return kWaves * waveFloats * 4;
 }
 
@@ -136,7 +137,7 @@ bool plan_backprojection(const DevGeom &G, int pmax, double zabs, double Dmin, i
     for (const auto &cd : cands) {
         const int cand = cd[0], ckp = cd[1];
         if ((force_gw > 0 && cand != force_gw) || (force_kp > 0 && ckp != force_kp)) continue;
-        const size_t rec = (size_t)cand * pmax * kRecFloats + cand;
+        const size_t rec = (size_t)back_views_per_pass(cand, pmax) * back_rec_floats(cand, pmax);
         const int c = (int)((kBackLdsBudget / (kWaves * 4) - rec) / 4 * 4);
         if (c < kBackPasses * cand * 64 || c < 1024) continue;   // the window area also parks the accumulators
         const double wu = std::hypot(cand * G.a1, G.a2) * mag / G.b1 + pmax + 2;

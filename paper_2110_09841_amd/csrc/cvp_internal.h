@@ -11,6 +11,13 @@ constexpr int kWave = 64;             // CDNA wavefront
 constexpr int kBlock = 256;           // threads per workgroup
 constexpr int kWaves = kBlock / kWave;
 constexpr int kRecFloats = 12;        // floats per cut-piece record
+
+// Backprojection LDS per view of a record pass: GW x PMAX piece records, the
+// GW piece counts and the 4 window bounds; a record pass covers
+// back_views_per_pass views (64 lanes over GW columns x min(PMAX, 64 / GW)
+// slots each).
+constexpr int back_rec_floats(int gw, int pmax) { return gw * pmax * kRecFloats + gw + 4; }
+constexpr int back_views_per_pass(int gw, int pmax) { return 64 / (gw * (pmax < 64 / gw ? pmax : 64 / gw)); }
 constexpr float kYQuantumInv = 1024.0f;
 constexpr int kBackPasses = 2;        // most 64-voxel passes per backprojection stack
 

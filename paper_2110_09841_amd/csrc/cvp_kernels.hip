@@ -350,15 +350,16 @@ __device__ __forceinline__ void sweep_rows(int vlo0, int vhi0, int vlo, int vhi,
     }
 }
 
-// Record phase shared by both directions: lanes (c, slot) compute the pieces
-// of columns i0 + c of row j whose detector column u lies in [ulo, uhi].
-template <bool EXACT, bool EC, int PMAX, int GW>
+// Record phase of the backprojection: LPV lanes l = (c, slot) compute the
+// pieces of columns i0 + c of row j whose detector column u lies in
+// [ulo, uhi], LPV / GW slots at a time.
+template <bool EXACT, bool EC, int PMAX, int GW, int LPV>
 __device__ __forceinline__ void build_records(const DevGeom &G, const ViewGeom &V, int i0, int j,
-                                              int ulo, int uhi, float *rec, int *npc, int lane)
+                                              int ulo, int uhi, float *rec, int *npc, int l)
 {
-    constexpr int SLOTS = kWave / GW;
-    const int c = lane % GW;
-    const int slot = lane / GW;
+    constexpr int SLOTS = LPV / GW;
+    const int c = l % GW;
+    const int slot = l / GW;
     const int i = i0 + c;
     const bool colok = i < G.n1;
     Column C;
@@ -701,10 +702,15 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const int kmax = min(k0 + kWave * kp, G.n3) - 1;
 
-    const int recFloats = GW * PMAX * kRecFloats + GW;
+    // One record pass covers RV of the wave's views (w, w + 4, ...): LPV
+    // lanes per view, so narrow stacks do not leave most lanes idle in the
+    // FP64 stage.  Per view: records, piece counts, window bounds.
+    constexpr int LPV = GW * (PMAX < kWave / GW ? PMAX : kWave / GW);
+    constexpr int RV = kWave / LPV;
+    constexpr int recView = back_rec_floats(GW, PMAX);
+    const int recFloats = RV * recView;
     const int waveFloats = ((recFloats + winCap + 3) / 4) * 4;
     float *rec = smem + wave * waveFloats;
-    int *npc = reinterpret_cast<int *>(rec + GW * PMAX * kRecFloats);
     float *win = rec + recFloats;
 
     const float c2f = (float)G.c2;
@@ -717,8 +723,7 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
 #pragma unroll
         for (int c = 0; c < GW; ++c) acc[ps][c] = 0.0f;
 
-    for (int view = wave; view < G.nviews; view += kWaves) {
-        const ViewGeom V = G.views[view];
+    for (int vb = wave; vb < G.nviews; vb += kWaves * RV) {
         // The accumulators wait in the (idle) window area while the FP64
         // record stage, the kernel's register peak, runs.
 #pragma unroll
@@ -726,17 +731,31 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
 #pragma unroll
             for (int c = 0; c < GW; ++c) win[(ps * GW + c) * kWave + lane] = acc[ps][c];
         wave_sync();
-        build_records<EXACT, EC, PMAX, GW>(G, V, i0, j, 0, G.M - 1, rec, npc, lane);
+        {
+            const int r = lane / LPV;
+            const int view = vb + r * kWaves;
+            float *rv = rec + r * recView;
+            if (view < G.nviews)
+                build_records<EXACT, EC, PMAX, GW, LPV>(G, G.views[view], i0, j, 0, G.M - 1, rv,
+                                                        reinterpret_cast<int *>(rv + GW * PMAX * kRecFloats),
+                                                        lane % LPV);
+        }
         wave_sync();
 
-        // detector window of the stack: columns of all pieces, rows of the
-        // chunk's top voxel (smallest chi2) to its bottom voxel
-        int wu0 = 1 << 30, wu1 = -1, wv0 = 1 << 30, wv1 = -1;
-        {
+        // detector window of the stack per view: columns of all pieces, rows
+        // of the chunk's top voxel (smallest chi2) to its bottom voxel (the
+        // first view's in registers, the others' after their piece counts)
+        int wb0[4];
+#pragma unroll
+        for (int r = 0; r < RV; ++r) {
+            if (vb + r * kWaves >= G.nviews) break;
+            const float *rv = rec + r * recView;
+            int *npv = reinterpret_cast<int *>(const_cast<float *>(rv) + GW * PMAX * kRecFloats);
+            int wu0 = 1 << 30, wu1 = -1, wv0 = 1 << 30, wv1 = -1;
             const int c = lane % GW, s0 = lane / GW;
             for (int s = s0; s < PMAX; s += kWave / GW) {
-                if (s < npc[c]) {
-                    const float *r = rec + (c * PMAX + s) * kRecFloats;
+                if (s < npv[c]) {
+                    const float *r = rv + (c * PMAX + s) * kRecFloats;
                     const int u = __float_as_int(r[0]);
                     const float beta = r[6], mfac = r[10];
                     const float Ytop_hi = fmaf(-(float)kmax, r[4], r[2]) + fmaf(-(float)kmax, r[5], r[3]);
@@ -755,12 +774,29 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
                 wv0 = min(wv0, __shfl_xor(wv0, off));
                 wv1 = max(wv1, __shfl_xor(wv1, off));
             }
+            if (r == 0) {
+                wb0[0] = wu0; wb0[1] = wu1; wb0[2] = wv0; wb0[3] = wv1;
+            } else if (lane == 0) {
+                npv[GW] = wu0; npv[GW + 1] = wu1; npv[GW + 2] = wv0; npv[GW + 3] = wv1;
+            }
         }
 #pragma unroll
         for (int ps = 0; ps < KP; ++ps)
 #pragma unroll
             for (int c = 0; c < GW; ++c) acc[ps][c] = win[(ps * GW + c) * kWave + lane];
         wave_sync();
+
+#pragma unroll 1
+        for (int r = 0; r < RV; ++r) {
+        const int view = vb + r * kWaves;
+        if (view >= G.nviews) break;
+        const ViewGeom V = G.views[view];
+        const float *recv = rec + r * recView;
+        const int *npc = reinterpret_cast<const int *>(recv + GW * PMAX * kRecFloats);
+        int wu0 = wb0[0], wu1 = wb0[1], wv0 = wb0[2], wv1 = wb0[3];
+        if (r > 0) {
+            wu0 = npc[GW]; wu1 = npc[GW + 1]; wv0 = npc[GW + 2]; wv1 = npc[GW + 3];
+        }
         if (wu1 < wu0 || wv1 < wv0) continue;
         // one spare row each side absorbs FP32 rounding of intermediate k
         wv0 = max(wv0 - 1, 0);
@@ -797,7 +833,7 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
         for (int c = 0; c < GW; ++c) {
             const int np = npc[c];
             if (np == 0) continue;
-            const float *rc = rec + c * PMAX * kRecFloats;
+            const float *rc = recv + c * PMAX * kRecFloats;
             float base = 1.0f;
             if (!EXACT && !raw) base = __builtin_amdgcn_rcpf(fmaf(zc, zc, rc[8]));
             float a = 0.0f;
@@ -879,6 +915,7 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
         if (useWin) gather(std::true_type{});
         else gather(std::false_type{});
         wave_sync();
+        }
     }
 
     // Sum the four waves' partial sums in a fixed order; one store per voxel.
