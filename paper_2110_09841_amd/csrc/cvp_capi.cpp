@@ -17,7 +17,7 @@
 
 namespace cvp {
 hipError_t configure_kernel_lds(size_t max_lds, size_t max_lds_batched);
-constexpr size_t kLdsBudget = 39 * 1024;   // default projection plans: four workgroups per CU (160 KB LDS)
+constexpr size_t kLdsBudget = 30 * 1024;   // default projection plans: five workgroups per CU (160 KB LDS; 5 x 32 KB did not fit)
 constexpr size_t kBackLdsBudget = 52 * 1024;   // backprojection windows: three workgroups per CU
 constexpr size_t kLdsMax = 156 * 1024;      // any plan: one workgroup per CU at worst
 constexpr size_t kLdsBatchMax = kLdsMax;
@@ -98,7 +98,7 @@ size_t backproject_lds_bytes(int gw, int pmax, int winCap)
 
 // Projection: bands of U detector columns (a 64-bit band image of U x N and
 // the row tables in LDS).  force_u = 0: U as large as the default LDS budget
-// (four workgroups per compute unit) allows; otherwise U = force_u if its LDS
+// (five workgroups per compute unit) allows; otherwise U = force_u if its LDS
 // fits one workgroup.
 bool plan_projection(int N, int n2, int M, int nviews, int pmax, int force_u, ProjLaunch &L)
 {
