@@ -131,12 +131,14 @@ cvp_status cvp_project(const cvp_geometry *g, const cvp_options *opts,
  * largest |mu| of every 16-column group of voxel columns in d_work, and the
  * projection's workgroups take their scales from it instead of reading their
  * volume wedges a second time.  Results equal cvp_project's bitwise.  d_work:
- * at least cvp_project_workspace_size bytes, 4-byte aligned, owned by the
- * caller; calls that overlap in time need distinct work buffers.
+ * work_bytes >= cvp_project_workspace_size bytes (else CVP_E_INVALID),
+ * 4-byte aligned, owned by the caller; calls that overlap in time need
+ * distinct work buffers.
  */
 cvp_status cvp_project_workspace_size(const cvp_geometry *g, int64_t *bytes);
 cvp_status cvp_project_ws(const cvp_geometry *g, const cvp_options *opts,
-                          const float *d_vol, float *d_proj, void *d_work, void *hip_stream);
+                          const float *d_vol, float *d_proj, void *d_work, int64_t work_bytes,
+                          void *hip_stream);
 
 /*
  * x = A^T b with the same weights (the exact adjoint of cvp_project).

@@ -91,7 +91,7 @@ def _register_extra(L):
         "cvp_cgls_batched_iterate": ([vp, ctypes.POINTER(OptionsC), ctypes.c_int32] + [ctypes.POINTER(vp)] * 6
                                      + [vp], st),
         "cvp_project_workspace_size": ([vp, ctypes.POINTER(ctypes.c_int64)], st),
-        "cvp_project_ws": ([vp, ctypes.POINTER(OptionsC), vp, vp, vp, vp], st),
+        "cvp_project_ws": ([vp, ctypes.POINTER(OptionsC), vp, vp, vp, ctypes.c_int64, vp], st),
         "cvp_dot": ([vp, vp, ctypes.c_int64, vp, vp, vp], st),
         "cvp_synth_ellipsoids": ([vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
                                   vp, vp], st),

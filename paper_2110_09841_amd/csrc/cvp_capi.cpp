@@ -420,12 +420,16 @@ cvp_status cvp_project_workspace_size(const cvp_geometry *g, int64_t *bytes)
 }
 
 cvp_status cvp_project_ws(const cvp_geometry *g, const cvp_options *o, const float *d_vol, float *d_proj,
-                          void *d_work, void *stream)
+                          void *d_work, int64_t work_bytes, void *stream)
 {
     cvp::DevGeom G;
     cvp_status st = prepare(g, o, d_vol, d_proj, G);
     if (st != CVP_OK) return st;
     if (!d_work) return fail(CVP_E_INVALID, "work is NULL");
+    const int64_t need = cvp::group_max_cells(g->base) * (int64_t)sizeof(unsigned);
+    if (work_bytes < need)
+        return fail(CVP_E_INVALID, "work_bytes = %lld, need %lld (cvp_project_workspace_size)", (long long)work_bytes,
+                    (long long)need);
     if (reinterpret_cast<uintptr_t>(d_work) & 3) return fail(CVP_E_INVALID, "work must be 4-byte aligned");
     if (d_work == (const void *)d_vol || d_work == (void *)d_proj)
         return fail(CVP_E_INVALID, "work aliases the volume or the projections");

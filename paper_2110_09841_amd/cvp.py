@@ -107,7 +107,7 @@ def project(x, geom: Geometry, opts: Options = Options(), out=None):
     o = opts.c()
     _lib.check(_lib.lib().cvp_project_ws(geom.handle, ctypes.byref(o), ctypes.c_void_p(x.data_ptr()),
                                          ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(work.data_ptr()),
-                                         _stream()))
+                                         4 * work.numel(), _stream()))
     return out
 
 

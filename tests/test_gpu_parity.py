@@ -227,3 +227,19 @@ def test_workspace_projection_equals_scanning_projection():
         a, b = cvp.project(xn, G, opts), _project_scanning(xn, G, opts)
         assert torch.equal(torch.isnan(a), torch.isnan(b)) and bool(torch.isnan(a).any())
         assert torch.equal(torch.nan_to_num(a), torch.nan_to_num(b))
+
+
+def test_workspace_too_small_is_rejected():
+    import ctypes
+    from paper_2110_09841_amd import _lib
+    G = cvp.Geometry(synth.config_small())
+    x = torch.zeros(G.vol_shape, dtype=torch.float32, device="cuda")
+    out = torch.empty(G.proj_shape, dtype=torch.float32, device="cuda")
+    need = ctypes.c_int64()
+    _lib.check(_lib.lib().cvp_project_workspace_size(G.handle, ctypes.byref(need)))
+    work = torch.empty(need.value // 4, dtype=torch.int32, device="cuda")
+    o = gopts("relaxed", True, "solid_angle").c()
+    st = _lib.lib().cvp_project_ws(G.handle, ctypes.byref(o), ctypes.c_void_p(x.data_ptr()),
+                                   ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(work.data_ptr()),
+                                   need.value - 4, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert st == _lib.CVP_E_INVALID and "work_bytes" in _lib.last_error()
