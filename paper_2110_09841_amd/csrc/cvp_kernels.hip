@@ -11,17 +11,20 @@
 //    It walks every voxel column whose base meets the band's wedge (by the
 //    column identity of Sec. III-A the wedge is the same for all k), computes
 //    the column cut pieces once per column in FP64, and then, with lanes over
-//    k, scatters each voxel's row pieces into a 64-bit fixed-point band
-//    image in LDS with integer atomics (scale chosen per work item from the
-//    largest |mu| it reads).  The band is written once at the end, scaled by
-//    sigma.  Integer sums make the result independent of the order of the
-//    additions, hence of the launch plan.
-//  * backprojection: a workgroup owns a 128-voxel-tall stack of GW columns;
-//    each wave takes every 4th view, stages the pre-scaled detector window of
-//    the stack in LDS and gathers into registers.  Each voxel is written once.
+//    k, scatters each voxel's row pieces, rounded to integers, into a 64-bit
+//    fixed-point band image in LDS with integer atomics (scale chosen per
+//    work item from the largest |mu| in its wedge, read from per-group maxima
+//    when the caller gives scratch).  The band is written once at the end,
+//    scaled by sigma.  Integer sums make the result independent of the order
+//    of the additions (scheduling, the wave split, batching).
+//  * backprojection: a workgroup owns a stack of GW columns x 64 kp voxels;
+//    each wave takes every 4th view, builds the stack's piece records (for
+//    several views per pass when the stack is narrow), stages the
+//    pre-scaled detector window in LDS and gathers into registers.  Each
+//    voxel is written once, and its sum does not depend on the plan.
 //
 // Numerics: the column stage (polygon moments, centroid depth) runs in FP64
-// (full rate on CDNA4 VALU); the per-voxel stage runs in FP32 on quantities
+// (the rate of unpacked FP32 on CDNA4); the per-voxel stage runs in FP32 on quantities
 // that are small by construction: detector row positions are split into a
 // 2^-10-quantised high part, whose differences with half-integer row
 // boundaries are exact, plus a small low part.
