@@ -160,13 +160,12 @@ __device__ __forceinline__ Mom column_prefix(const DevGeom &G, const ViewGeom &V
 //  [8] R^2 (x1x2 part of r^2: cut centroid, or column centre if relaxed)
 //  [9] b2 D_u / f (mm of x3 per row)  [10] EC row margin factor  [11] unused
 // Y(k) = Y0 - k beta is chi2 of the top face of voxel k at the centroid depth.
+// lo / hi: column_prefix at u - 1/2 and u + 1/2.
 template <bool EXACT, bool EC>
 __device__ __forceinline__ void piece_record(const DevGeom &G, const ViewGeom &V, const Column &C,
-                                             int u, float *rec)
+                                             int u, const Mom &lo, const Mom &hi, float *rec)
 {
 #pragma clang fp contract(off)
-    const Mom hi = column_prefix(G, V, C, u + 0.5);
-    const Mom lo = column_prefix(G, V, C, u - 0.5);
     const double a2 = hi.a2 - lo.a2;
     const double A = 0.5 * a2;
     double cx = 0.0, cy = 0.0, var = 0.0;
@@ -353,12 +352,44 @@ __device__ __forceinline__ void sweep_rows(int vlo0, int vhi0, int vlo, int vhi,
     }
 }
 
+// The lanes of a record pass hold consecutive pieces of a column GW lanes
+// apart, and the upper boundary u + 1/2 of piece s is the lower boundary of
+// piece s + 1: each lane computes its lower prefix (also for s = n, the
+// column's last boundary) and takes the upper one from lane + GW; the last
+// slot of a pass computes its own.  column_prefix gets the same argument
+// either way ((u + 1) - 1/2 = u + 1/2 exactly), so the records are unchanged.
+__device__ __forceinline__ Mom shfl_mom(const Mom &m, int src)
+{
+    Mom r;
+    r.a2 = __shfl(m.a2, src);
+    r.sx = __shfl(m.sx, src);
+    r.sy = __shfl(m.sy, src);
+    r.sxx = __shfl(m.sxx, src);
+    r.sxy = __shfl(m.sxy, src);
+    r.syy = __shfl(m.syy, src);
+    return r;
+}
+
+template <bool EXACT, bool EC>
+__device__ __forceinline__ void piece_pair_record(const DevGeom &G, const ViewGeom &V, const Column &C,
+                                                  bool colok, int ufirst, int n, int s, bool last_slot,
+                                                  int lane, int gw, float *rec)
+{
+    Mom lo = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (colok && s <= n) lo = column_prefix(G, V, C, (ufirst + s) - 0.5);
+    Mom hi = shfl_mom(lo, lane + gw);
+    if (colok && s < n) {
+        if (last_slot) hi = column_prefix(G, V, C, (ufirst + s) + 0.5);
+        piece_record<EXACT, EC>(G, V, C, ufirst + s, lo, hi, rec);
+    }
+}
+
 // Record phase of the backprojection: LPV lanes l = (c, slot) compute the
 // pieces of columns i0 + c of row j whose detector column u lies in
 // [ulo, uhi], LPV / GW slots at a time.
 template <bool EXACT, bool EC, int PMAX, int GW, int LPV>
 __device__ __forceinline__ void build_records(const DevGeom &G, const ViewGeom &V, int i0, int j,
-                                              int ulo, int uhi, float *rec, int *npc, int l)
+                                              int ulo, int uhi, float *rec, int *npc, int l, int lane)
 {
     constexpr int SLOTS = LPV / GW;
     const int c = l % GW;
@@ -377,7 +408,8 @@ __device__ __forceinline__ void build_records(const DevGeom &G, const ViewGeom &
 #pragma unroll
     for (int pass = 0; pass * SLOTS < PMAX; ++pass) {
         const int s = slot + pass * SLOTS;
-        if (colok && s < n) piece_record<EXACT, EC>(G, V, C, ufirst + s, rec + (c * PMAX + s) * kRecFloats);
+        piece_pair_record<EXACT, EC>(G, V, C, colok, ufirst, n, s, slot == SLOTS - 1, lane, GW,
+                                     rec + (c * PMAX + min(s, PMAX - 1)) * kRecFloats);
     }
 }
 
@@ -559,16 +591,19 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
         {
             const int c = lane & 15, slot = lane >> 4;
             const int i = i0 + c;
-            if (i < G.n1) {
-                const Column C = make_column(G, V, i, j);
-                const int ufirst = max((int)floor(C.chimin + 0.5), u0);
+            const bool colok = i < G.n1;
+            Column C;
+            int ufirst = 0;
+            if (colok) {
+                C = make_column(G, V, i, j);
+                ufirst = max((int)floor(C.chimin + 0.5), u0);
                 const int ulast = min((int)floor(C.chimax + 0.5), ub);
                 ncol = min(max(ulast - ufirst + 1, 0), PMAX);
-#pragma unroll
-                for (int q = 0; q < PASSES; ++q) {
-                    if (slot + 4 * q < ncol) piece_record<EXACT, EC>(G, V, C, ufirst + slot + 4 * q, rq[q]);
-                }
             }
+#pragma unroll
+            for (int q = 0; q < PASSES; ++q)
+                piece_pair_record<EXACT, EC>(G, V, C, colok, ufirst, ncol, slot + 4 * q, slot == 3, lane, 16,
+                                             rq[q]);
         }
         if (__ballot(ncol > 0) == 0) continue;
         const bool full = vec_rows && (i0 + GW <= G.n1);
@@ -742,7 +777,7 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
             if (view < G.nviews)
                 build_records<EXACT, EC, PMAX, GW, LPV>(G, G.views[view], i0, j, 0, G.M - 1, rv,
                                                         reinterpret_cast<int *>(rv + GW * PMAX * kRecFloats),
-                                                        lane % LPV);
+                                                        lane % LPV, lane);
         }
         wave_sync();
 
