@@ -1009,7 +1009,7 @@ __device__ __forceinline__ bool next_item(const BatchTable &T, int *counter, int
 }
 
 template <bool EXACT, bool EC>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5)))
 project_batched_kernel(const BatchProblem *__restrict__ probs, const BatchTable *__restrict__ T,
                        int *counter)
 {
