@@ -99,6 +99,7 @@ def lib():
         L.orc_view_frame.argtypes = [G, ctypes.c_int, dp, dp, dp, dp]
         L.orc_set_mutation.argtypes = [ctypes.c_int]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -239,3 +240,8 @@ def set_mutation(m: int):
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def set_num_threads(n: int):
+    """OpenMP threads of the oracle's loops (timing only)."""
+    lib().orc_set_num_threads(int(n))

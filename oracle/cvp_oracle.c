@@ -216,6 +216,7 @@ int orc_column_pieces(const orc_geom *g, const orc_opts *o, int view, int i,
         if (chi[0] > chimax) chimax = chi[0];
     }
     int ulo = (int)floor(chimin + 0.5), uhi = (int)floor(chimax + 0.5);
+    const int ulo_all = ulo, uhi_all = uhi;
     if (ulo < 0) ulo = 0;
     if (uhi > g->ncols - 1) uhi = g->ncols - 1;
 
@@ -238,9 +239,18 @@ int orc_column_pieces(const orc_geom *g, const orc_opts *o, int view, int i,
         /* chi1 >= u - 1/2 : -(n.(x-s)) <= 0 */
         int n1 = clip_halfplane((const double (*)[2])sq, 4, nl0, nl1,
                                 nl0 * rc[0] + nl1 * rc[1], -1.0, p1);
+        if (g_mutation == 7 && u == ulo && ulo_all < ulo) {
+            /* the part left of the detector merged into its first column */
+            memcpy(p1, sq, sizeof(sq));
+            n1 = 4;
+        }
         /* chi1 <= u + 1/2 */
         int n2 = clip_halfplane((const double (*)[2])p1, n1, nh0, nh1,
                                 nh0 * rc[0] + nh1 * rc[1], 1.0, p2);
+        if (g_mutation == 7 && u == uhi && uhi_all > uhi) {
+            memcpy(p2, p1, sizeof(p1));
+            n2 = n1;
+        }
         if (n2 < 3) continue;
         double A, cx, cy, sxx, sxy, syy;
         polygon_moments((const double (*)[2])p2, n2, &A, &cx, &cy, &sxx, &sxy, &syy);
@@ -348,6 +358,7 @@ int orc_voxel_weights(const orc_geom *g, const orc_opts *o, int view, int i,
     voxel_centre(g, i, j, k, xc);
     double z0 = xc[2] - 0.5 * g->a3, z1 = xc[2] + 0.5 * g->a3;
     int n = 0;
+    double volsum = 0.0;
     for (int p = 0; p < np; ++p) {
         const orc_piece *pc = &pcs[p];
         double h = pc->h;
@@ -361,10 +372,19 @@ int orc_voxel_weights(const orc_geom *g, const orc_opts *o, int view, int i,
             if (chi2 > cmax) cmax = chi2;
         }
         int vlo = (int)floor(cmin + 0.5), vhi = (int)floor(cmax + 0.5);
+        const int vlo_all = vlo, vhi_all = vhi;
         if (vlo < 0) vlo = 0;
         if (vhi > g->nrows - 1) vhi = g->nrows - 1;
         for (int v = vlo; v <= vhi; ++v) {
             double len = orc_row_length(g, s[2], v, pc->depth, h, z0, z1);
+            if (g_mutation == 9) {
+                /* rows off the detector merged into its edge rows */
+                if (v == vlo)
+                    for (int vv = vlo_all; vv < vlo; ++vv) len += orc_row_length(g, s[2], vv, pc->depth, h, z0, z1);
+                if (v == vhi)
+                    for (int vv = vhi + 1; vv <= vhi_all; ++vv) len += orc_row_length(g, s[2], vv, pc->depth, h, z0, z1);
+            }
+            volsum += pc->area * len;
             if (!(len > 0)) continue;
             double vol = pc->area * len;              /* eq. cutvolume */
             double w;
@@ -393,6 +413,11 @@ int orc_voxel_weights(const orc_geom *g, const orc_opts *o, int view, int i,
             if (n >= max_out) return -1;
             us[n] = pc->u; vs[n] = v; ws[n] = w; ++n;
         }
+    }
+    if (g_mutation == 8 && volsum > 0) {
+        /* renormalised to the whole voxel volume when parts were dropped */
+        double fix = g->a1 * g->a2 * g->a3 / volsum;
+        for (int q = 0; q < n; ++q) ws[q] *= fix;
     }
     return n;
 }
@@ -565,3 +590,14 @@ int orc_backproject(const orc_geom *g, const orc_opts *o, const double *b,
 }
 
 int orc_num_threads(void) { return nthreads(); }
+
+/* Thread count of the OpenMP loops (timing only; the results do not depend
+ * on it: every output element is summed by one thread in a fixed order). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -1,7 +1,11 @@
 """Planted mistakes in the oracle (switched on in the C code by a test-only
 flag, on the CPU) must each be caught by at least one pin: a mirrored
 detector axis, a wrong pixel edge, the depth taken at the wrong point, a wrong
-row plane, 1/r in place of 1/r^2, a shifted index in A^T."""
+row plane, 1/r in place of 1/r^2, a shifted index in A^T, and three mistakes
+at the detector's edges: the part of a voxel left or right of the detector
+merged into its first or last column, the weights of a partly projected
+voxel renormalised to the whole voxel, the rows above or below the detector
+merged into its edge rows."""
 import math
 
 import numpy as np
@@ -91,8 +95,23 @@ def pin_parallel_limit():
     assert abs(tot - 1.0) < 2e-5     # unit voxel volume over unit object pixels
 
 
+def pin_off_detector():
+    """Voxels straddling the detector's edges keep exactly the cut volumes of
+    their on-detector pixels (the identity of pin_exact_polyhedron); the rest
+    is dropped."""
+    from test_oracle_pins import edge_geometry, straddling_cases
+    g = edge_geometry()
+    G = O.Geometry(g)
+    cases, _ = straddling_cases(g, 3, 10, 11, need_no_crossing=True)
+    for ijk, view in cases:
+        us, vs, ws = O.voxel_weights(G, RAW, view, *ijk)
+        assert np.all((us >= 0) & (us < g["det_cols"]) & (vs >= 0) & (vs < g["det_rows"]))
+        for u, v, w in zip(us, vs, ws):
+            assert abs(w - D.cut_integrals(g, view, ijk, int(u), int(v))[0]) < 1e-9
+
+
 PINS = [pin_volume_partition, pin_exact_polyhedron, pin_adjoint,
-        pin_single_voxel_closed_form, pin_pixel_ray, pin_parallel_limit]
+        pin_single_voxel_closed_form, pin_pixel_ray, pin_parallel_limit, pin_off_detector]
 
 
 def _failing(pins):
@@ -110,7 +129,7 @@ def test_pins_hold_without_mutation():
     assert _failing(PINS) == []
 
 
-@pytest.mark.parametrize("mutation", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("mutation", [1, 2, 3, 4, 5, 6, 7, 8, 9])
 def test_planted_mistake_is_caught(mutation):
     O.set_mutation(mutation)
     try:

@@ -214,6 +214,119 @@ def test_cut_volume_equals_exact_polyhedron_when_no_row_plane_crosses():
         checked += 1
 
 
+# ------------------------------------------------------ off-detector parts
+
+def edge_geometry():
+    """A detector smaller than the shadow of the volume (1 mm voxels seen at
+    magnification 1.5 on 12 x 10 pixels of 1 mm): voxels at the sides and at
+    the top and bottom of the volume project partly off the detector."""
+    return synth.geometry((10, 10, 10), 1.0, 12, 10, 1.0, 100.0, 150.0, 8, 360.0, principal_px=(5.5, 4.5))
+
+
+def enlarged(g, m):
+    """The same pixels on a detector with m more columns and rows each side."""
+    g2 = dict(g)
+    g2["det_cols"] = g["det_cols"] + 2 * m
+    g2["det_rows"] = g["det_rows"] + 2 * m
+    g2["principal_px"] = (g["principal_px"][0] + m, g["principal_px"][1] + m)
+    return g2
+
+
+def row_plane_crosses_face(g, view, ijk):
+    """True if a row boundary plane crosses the top or bottom face of the voxel
+    somewhere over its base (then A_u d_uv is not the exact cut volume)."""
+    lo, hi = D.voxel_box(g, *ijk)
+    s, e1, e2, d = D.frame(g, view)
+    c1, c2 = D.principal(g)
+    f, b2 = g["sdd_mm"], g["pitch_mm"][1]
+    dep = [d[0] * (x - s[0]) + d[1] * (y - s[1]) for x in (lo[0], hi[0]) for y in (lo[1], hi[1])]
+    spans = [c2 - ((z - s[2]) * f / b2) / np.array([min(dep), max(dep)]) for z in (lo[2], hi[2])]
+    return any(np.floor(sp[0] + 0.5) != np.floor(sp[1] + 0.5) for sp in spans)
+
+
+def straddling_cases(g, m, n, seed, need_no_crossing):
+    """(ijk, view) whose footprint on the enlarged detector has pixels both
+    on and off the real detector."""
+    G2 = O.Geometry(enlarged(g, m))
+    M, N = g["det_cols"], g["det_rows"]
+    n1, n2, n3 = g["vol_dims"]
+    rng = np.random.default_rng(seed)
+    out, sides = [], set()
+    for _ in range(20000):
+        ijk = (int(rng.integers(0, n1)), int(rng.integers(0, n2)), int(rng.integers(0, n3)))
+        view = int(rng.integers(0, len(g["angles_rad"])))
+        us, vs, ws = O.voxel_weights(G2, RAW, view, *ijk)
+        u, v = us - m, vs - m
+        off = (u < 0) | (u >= M) | (v < 0) | (v >= N)
+        if not (off.any() and (~off).any()):
+            continue
+        if need_no_crossing and row_plane_crosses_face(g, view, ijk):
+            continue
+        side = ("left" if (u < 0).any() else "") + ("right" if (u >= M).any() else "") + \
+               ("top" if (v < 0).any() else "") + ("bottom" if (v >= N).any() else "")
+        out.append((ijk, view))
+        sides.add(side)
+        if len(out) >= n:
+            break
+    return out, sides
+
+
+def test_off_detector_parts_dropped_exact_cut_volumes():
+    """Reading: parts of a voxel that project off the detector are dropped,
+    with no renormalisation.  For voxels straddling each detector edge, every
+    returned pixel lies on the detector and carries the exact volume of the
+    voxel cut by its ray pyramid (where that identity holds), every on-detector
+    pixel the voxel reaches is returned, and the weights add up to the volume
+    of the voxel inside the union of the on-detector pyramids, computed from
+    the exact polyhedra."""
+    g = edge_geometry()
+    M, N = g["det_cols"], g["det_rows"]
+    cases, sides = straddling_cases(g, 3, 24, 11, need_no_crossing=True)
+    assert len(cases) == 24
+    assert any("left" in t for t in sides) and any("right" in t for t in sides)
+    assert any("top" in t for t in sides) and any("bottom" in t for t in sides)
+    G = O.Geometry(g)
+    for ijk, view in cases:
+        us, vs, ws = O.voxel_weights(G, RAW, view, *ijk)
+        assert np.all((us >= 0) & (us < M) & (vs >= 0) & (vs < N))
+        got = {(int(u), int(v)): w for u, v, w in zip(us, vs, ws)}
+        # every on-detector pixel in a margin around the footprint
+        u2, v2, _ = O.voxel_weights(O.Geometry(enlarged(g, 3)), RAW, view, *ijk)
+        total = 0.0
+        for u in range(max(u2.min() - 4, 0), min(u2.max() - 1, M)):
+            for v in range(max(v2.min() - 4, 0), min(v2.max() - 1, N)):
+                vol = D.cut_integrals(g, view, ijk, u, v)[0]
+                total += vol
+                assert abs(got.get((u, v), 0.0) - vol) < 1e-9, (ijk, view, u, v, got.get((u, v)), vol)
+        assert abs(sum(ws) - total) < 1e-9
+        assert sum(ws) < 1.0 - 1e-6       # something was dropped
+
+
+@pytest.mark.parametrize("opts", [RAW, RAW_EC, EX_EC, REL_EC])
+def test_off_detector_weights_are_restrictions(opts):
+    """The same reading, for the elevation-corrected and scaled forms too: on
+    a detector enlarged by 3 pixels each side every straddling voxel is fully
+    projected (raw weights add up to a1 a2 a3), and the real detector's
+    weights are exactly the enlarged detector's weights of the pixels it
+    has."""
+    g = edge_geometry()
+    M, N = g["det_cols"], g["det_rows"]
+    m = 3
+    G, G2 = O.Geometry(g), O.Geometry(enlarged(g, m))
+    cases, _ = straddling_cases(g, m, 40, 12, need_no_crossing=False)
+    for ijk, view in cases:
+        us, vs, ws = O.voxel_weights(G, opts, view, *ijk)
+        u2, v2, w2 = O.voxel_weights(G2, opts, view, *ijk)
+        if opts.raw_volume:
+            assert abs(w2.sum() - 1.0) < 1e-12
+        keep = (u2 - m >= 0) & (u2 - m < M) & (v2 - m >= 0) & (v2 - m < N)
+        ref = {(int(u) - m, int(v) - m): w for u, v, w in zip(u2[keep], v2[keep], w2[keep])}
+        got = {(int(u), int(v)): w for u, v, w in zip(us, vs, ws)}
+        assert set(got) == set(ref)
+        for key in got:
+            assert abs(got[key] - ref[key]) <= 1e-15 * abs(ref[key]), (ijk, view, key)
+
+
 def _eprj(g, opts, ijk, view, weighting):
     G = O.Geometry(g)
     us, vs, ws = O.voxel_weights(G, EX_EC, view, *ijk)
