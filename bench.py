@@ -14,7 +14,15 @@ it, CGLS from zero on consistent data b = A x_true is run to
 |A^T (b - A x)| <= 1e-3 |A^T b| and its wall time reported ("cgls").
 
 Prints one JSON line.  The CPU baseline times the FP64 oracle on a bounded
-sample of the same workload (one view of A x and a voxel sample of A^T b).
+sample of the same workload (A x and A^T b over three views, extrapolated),
+plus a one-thread run of the 64^3 workload; --cpu-baseline-full runs the
+whole CPU-baseline plan instead (minutes, no GPU) and prints its record.
+
+The roofline counts FP32 VALU lane-operations of the method per voxel-view
+(costmodel.py, fixed constants per step); the instruction overhead beside it
+is the kernel's measured VALU lane-instructions per voxel-view (rocprofv3
+SQ_INSTS_VALU of the committed counter summary, while the kernel source
+matches it) over that count.
 """
 import argparse
 import json
@@ -43,6 +51,8 @@ def parse():
     ap.add_argument("--no-network", action="store_true", help="skip the warm-start network timing")
     ap.add_argument("--no-batched", action="store_true", help="skip the 16-problem batched timing")
     ap.add_argument("--no-cone", action="store_true", help="skip the 256^3 cone-beam timing")
+    ap.add_argument("--cpu-baseline-full", action="store_true",
+                    help="run only the full CPU-baseline plan of the oracle (minutes, no GPU)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run only a 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -59,36 +69,137 @@ def calib_copy():
     print(json.dumps({"calib_copy_bytes": 4 * n}))
 
 
-def cpu_baseline(g, x, b):
-    """FP64 oracle on a bounded sample (about 10 s on 16 host threads): A x
-    for six views of the full volume and A^T b for 262144 voxels over all
-    views."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _time(fn):
+    t0 = time.perf_counter()
+    fn()
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(g, x, b, n_views=3):
+    """The FP64 oracle (C, OpenMP over every host thread) on a bounded sample
+    of the benchmark workload: A x and A^T b for the first n_views views of
+    the whole volume, the rate extrapolated to all views (about 20 s on 16
+    threads); beside it a one-thread run of the 64^3 / 32-view workload in
+    full (A x and A^T b)."""
     import numpy as np
     import oracle
+    from paper_2110_09841_amd import synth
     o = oracle.Options(exact=False, ec=True)
     n1, n2, n3 = g["vol_dims"]
     V = len(g["angles_rad"])
-    t0 = time.perf_counter()
-    nv = 6
-    oracle.project(g, o, x, views=(0, nv))
-    t1 = time.perf_counter()
-    rng = np.random.default_rng(7)
-    idx = rng.integers(0, n1 * n2 * n3, size=262144)
-    oracle.backproject_voxels(g, o, b, idx)
-    t2 = time.perf_counter()
-    vv = n1 * n2 * n3 * nv + len(idx) * V
-    return {"value": vv / (t2 - t0), "unit": "voxel-view updates/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": "A x for %d of %d views (%d voxel-views, %.1f s) + A^T b for %d voxels x %d views "
-                      "(%.1f s), FP64 C/OpenMP" % (nv, V, n1 * n2 * n3 * nv, t1 - t0, len(idx), V, t2 - t1)}
+    threads = oracle.num_threads()
+    tA = _time(lambda: oracle.project(g, o, x, views=(0, n_views)))
+    tB = _time(lambda: oracle.backproject(g, o, b[:n_views], views=(0, n_views)))
+    vv = n1 * n2 * n3 * n_views
+    gs = synth.config_small()
+    xs = synth.ellipsoid_phantom(64, 1.0, 10, seed=11)
+    bs = synth.uniform_projections((32, 96, 96), seed=12)
+    oracle.set_num_threads(1)
+    try:
+        t1A = _time(lambda: oracle.project(gs, o, xs))
+        t1B = _time(lambda: oracle.backproject(gs, o, bs))
+    finally:
+        oracle.set_num_threads(threads)
+    vv1 = 64 ** 3 * 32
+    return {"value": 2 * vv / (tA + tB), "unit": "voxel-view updates/s", "cores": threads,
+            "kind": "oracle", "cpu": cpu_model(),
+            "sample": "FP64 C/OpenMP oracle, relaxed CVP with EC: A x (%.1f s) and A^T b (%.1f s) for %d of %d "
+                      "views of the 512^3 volume; extrapolated to all views: A %.0f s, A^T %.0f s per application"
+                      % (tA, tB, n_views, V, tA * V / n_views, tB * V / n_views),
+            "project_voxel_views_per_s": vv / tA, "backproject_voxel_views_per_s": vv / tB,
+            "one_thread": {"workload": "small_64c_32v (full)", "project_s": t1A, "backproject_s": t1B,
+                           "voxel_views_per_s": 2 * vv1 / (t1A + t1B)}}
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary of this workload (FETCH_SIZE + WRITE_SIZE, calibrated against a
-    1 GiB copy), or None when the kernel source changed since it was taken."""
+def cpu_baseline_full():
+    """The CPU-baseline plan in full (a long run, minutes): the oracle on every
+    host thread and on one thread for the 64^3 / 32-view workload (A, A^T and
+    CGLS to rho <= 1e-3), every thread for the 256^3 / 360-view cone workload
+    in full (exact and relaxed, EC on), and the 512^3 / 248-view workload on
+    8 views, extrapolated."""
+    import numpy as np
+    import oracle
+    from oracle.cgls import cgls
+    from paper_2110_09841_amd import synth
+    threads = oracle.num_threads()
+    out = {"cpu": cpu_model(), "threads": threads, "kind": "oracle (FP64 C/OpenMP)"}
+
+    def log(*a):
+        print("[cpu-baseline]", *a, file=sys.stderr, flush=True)
+
+    gs = synth.config_small()
+    xs = synth.ellipsoid_phantom(64, 1.0, 10, seed=11)
+    bs = synth.uniform_projections((32, 96, 96), seed=12)
+    vv = 64 ** 3 * 32
+    rec = {"voxel_views": vv}
+    orl = oracle.Options(exact=False, ec=True)
+    bcl = oracle.project(gs, orl, xs)                  # consistent data b = A x_true
+
+    def run_cgls(n):
+        return cgls(lambda v: oracle.project(gs, orl, v), lambda r: oracle.backproject(gs, orl, r), bcl, n,
+                    np.zeros(xs.shape))[1]
+    gam = run_cgls(100)
+    rho = np.sqrt(gam / gam[0])
+    it = int(np.argmax(rho <= 1e-3)) if (rho <= 1e-3).any() else len(gam) - 1
+    rec["cgls_relaxed_iterations_to_1e-3"] = it
+    for nthr in (threads, 1):
+        oracle.set_num_threads(nthr)
+        o = oracle.Options(exact=True, ec=True)
+        tA = _time(lambda: oracle.project(gs, o, xs))
+        tB = _time(lambda: oracle.backproject(gs, o, bs))
+        tc = _time(lambda: run_cgls(it))
+        rec["threads_%d" % nthr] = {"exact_project_s": tA, "exact_backproject_s": tB,
+                                    "voxel_views_per_s": 2 * vv / (tA + tB), "cgls_relaxed_to_1e-3_s": tc}
+        log("small", nthr, rec["threads_%d" % nthr])
+    oracle.set_num_threads(threads)
+    out["small_64c_32v"] = rec
+
+    gc = synth.config_cone()
+    xc = synth.ellipsoid_phantom(256, 0.5, 40, seed=21)
+    bc = synth.uniform_projections((360, 384, 512), seed=22)
+    vv = 256 ** 3 * 360
+    rec = {"voxel_views": vv}
+    for variant in ("exact", "relaxed"):
+        o = oracle.Options(exact=variant == "exact", ec=True)
+        tA = _time(lambda: oracle.project(gc, o, xc))
+        tB = _time(lambda: oracle.backproject(gc, o, bc))
+        rec[variant] = {"project_s": tA, "backproject_s": tB, "voxel_views_per_s": 2 * vv / (tA + tB)}
+        log("cone", variant, rec[variant])
+    out["cone_256c_360v"] = rec
+
+    g = synth.config_carm()
+    x = synth.ellipsoid_phantom(512, 0.25, 80, seed=31, noise_frac=0.01)
+    b = synth.uniform_projections((248, 480, 616), seed=32)
+    o = oracle.Options(exact=False, ec=True)
+    nv = 8
+    tA = _time(lambda: oracle.project(g, o, x, views=(0, nv)))
+    tB = _time(lambda: oracle.backproject(g, o, b[:nv], views=(0, nv)))
+    vv = 512 ** 3 * nv
+    out["carm_512c_248v"] = {"extrapolated": True, "views_timed": nv, "project_s_8_views": tA,
+                             "backproject_s_8_views": tB, "project_s_extrapolated": tA * 248 / nv,
+                             "backproject_s_extrapolated": tB * 248 / nv, "voxel_views_per_s": 2 * vv / (tA + tB)}
+    log("carm", out["carm_512c_248v"])
+    return out
+
+
+def measured_counters(kernel):
+    """Counters per launch of `kernel` from the committed rocprofv3 summary
+    of this workload: HBM bytes (FETCH_SIZE + WRITE_SIZE, calibrated against
+    a 1 GiB copy) and VALU instructions, or None when the kernel source
+    changed since they were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_carm_512c_248v.json")
+    path = os.path.join(ROOT, "profiles", "counters_carm_512c_248v.json")
     src = os.path.join(ROOT, "paper_2110_09841_amd", "csrc", "cvp_kernels.hip")
     try:
         with open(path) as f:
@@ -99,8 +210,9 @@ def measured_traffic(kernel):
         return None
     if rec.get("kernel_source_sha1") != sha or kernel not in rec:
         return None
-    return {"bytes": rec[kernel]["fetch_bytes"] + rec[kernel]["write_bytes"],
-            "fetch_bytes": rec[kernel]["fetch_bytes"], "write_bytes": rec[kernel]["write_bytes"],
+    k = rec[kernel]
+    return {"bytes": k["fetch_bytes"] + k["write_bytes"], "fetch_bytes": k["fetch_bytes"],
+            "write_bytes": k["write_bytes"], "sq_insts_valu": k.get("sq_insts_valu"),
             "algorithmic_bytes": rec["algorithmic_bytes_per_launch"], "plan": rec.get("plan")}
 
 
@@ -274,6 +386,9 @@ def main():
     if args.calib_copy:
         calib_copy()
         return
+    if args.cpu_baseline_full:
+        print(json.dumps({"cpu_baseline_full": cpu_baseline_full()}), flush=True)
+        return
     torch.cuda.set_device(0)
     g = synth.config_carm()
     n1, n2, n3 = g["vol_dims"]
@@ -315,10 +430,17 @@ def main():
     value = 2 * vv / (tA.mean() + tB.mean())
 
     exact = args.variant == "exact"
-    rA = costmodel.roofline(g, exact, ec, tA.mean())
-    rB = costmodel.roofline(g, exact, ec, tB.mean())
+    counts = costmodel.estimate_counts(g)
+    rA = costmodel.roofline(g, exact, ec, tA.mean(), counts)
+    rB = costmodel.roofline(g, exact, ec, tB.mean(), counts)
     dom, rdom, name = (tA, rA, "cvp_project") if tA.mean() >= tB.mean() else (tB, rB, "cvp_backproject")
-    traffic = measured_traffic(name)
+    traffic = measured_counters(name)
+
+    def overhead(kernel, r):
+        c = measured_counters(kernel)
+        if not c or not c.get("sq_insts_valu"):
+            return None
+        return c["sq_insts_valu"] * 64 / vv / r["ops_per_vv"]
     out = {
         "metric": "voxel-view updates/s (CVP Ax+A^T b, 512^3, 248 views); CGLS time to 1e-3 residual",
         "value": float(value),
@@ -343,7 +465,14 @@ def main():
         "roofline": {"bound": "alu", "kernel": name, "achieved": rdom["achieved"] / 1e12,
                      "peak": rdom["peak"] / 1e12, "unit": "TOP/s (FP32 VALU lane-ops)",
                      "frac": rdom["frac"], "ops_per_voxel_view": rdom["ops_per_vv"],
-                     "pieces_per_voxel_view": [rdom["n_c"], rdom["n_p"]],
+                     "counts_per_voxel_view": {"column_pieces": rdom["n_c"], "pixels": rdom["n_p"],
+                                               "ec_edge_pixels": rdom["n_e"]},
+                     "instruction_overhead": overhead(name, rdom),
+                     "other_kernel": {"kernel": "cvp_project" if name == "cvp_backproject" else "cvp_backproject",
+                                      "frac": (rA if name == "cvp_backproject" else rB)["frac"],
+                                      "instruction_overhead": overhead(
+                                          "cvp_project" if name == "cvp_backproject" else "cvp_backproject",
+                                          rA if name == "cvp_backproject" else rB)},
                      "traffic": traffic["bytes"] if traffic else None, "traffic_unit": "bytes per launch",
                      "traffic_detail": traffic},
     }

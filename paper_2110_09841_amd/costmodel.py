@@ -1,43 +1,66 @@
 """Algorithmic cost of the cutting voxel projector, for roofline figures.
 
-The operator is bound by plain VALU arithmetic, so its roofline is counted in
-FP32 VALU lane-operations per voxel-view (one per lane instruction; a
-reciprocal counts 4 because the transcendental unit runs at quarter rate).
-The count is that of the minimal per-voxel algorithm, independent of any
-particular kernel:
+The operator is bound by plain VALU arithmetic (its compulsory HBM traffic,
+4 (N_vox + V M N) bytes per application, is a few hundred times below what
+the arithmetic takes), so its roofline is counted in FP32 VALU lane-operations
+per voxel-view.  The count is fixed here, independent of any kernel, from the
+steps of the method (Sec. III-A column polygons, row extents and cut volumes;
+Sec. III-B elevation correction; Sec. II-F 1/r^2; eq. cvpsu sums), with a
+reciprocal or square root counted as 4 and an FMA as 1:
 
-  per voxel-view     relaxed: r^2, reciprocal, scale      7   (exact: 1)
-  per column piece   Y position 3, row range 6, coef 1,
-                     first row boundary C_b               10 + C_b
-  per row piece      next boundary C_b, difference,
-                     weight, accumulate                   C_b + 3
-                     exact form: centroid height and
-                     1/r^2 per piece                       +12
-  column stage       FP64 polygon moments, amortised
-                     over the column's n3 voxels           400 / n3 per piece
-  C_b = 6 without, 24 with the elevation correction (box average).
+  ops/vv = (C_COL + n_b C_BND + n_c C_COLFIN) / K      column stage, shared
+         + n_c C_VOX  [+ C_VOX_RELAXED]               per voxel and column piece
+         + n_p C_PIX  [+ n_e C_PIX_EC_EDGE]            per voxel and pixel
 
-n_c (column pieces) and n_p (row pieces) per voxel-view come from the
-geometry: estimate_counts() samples voxel-views and counts the detector
-columns and rows their footprint spans (numpy, independent of the kernels).
+  C_COL = 36          corners of the voxel base, chi1 range of the column
+  C_BND = 50 (70 EC)  one column boundary: the half-plane polygon moments
+                      (area, centroid; with EC the second moments too)
+  C_COLFIN = 14       one column piece: area and centroid from two prefixes,
+                      depth, row scale
+  C_VOX = 8           one voxel in one column piece: row position, row range,
+                      coefficient
+  C_VOX_RELAXED = 7   relaxed form: r^2 at the voxel centre, its reciprocal
+                      and the scale, once per voxel-view
+  C_PIX = 12 / 16     one (voxel, pixel) weight: row boundary, x3 extent,
+                      volume, accumulation (exact form: the piece centroid's
+                      height and its 1/r^2 add 4)
+  C_PIX_EC_EDGE = 15  elevation correction at a top or bottom pixel of a
+                      piece: the box average of the boundary (Sec. III-B)
+
+n_c, n_p: column pieces and (voxel, pixel) weights per voxel-view; n_b = n_c
++ 1 column boundaries; n_e: pixels at the first or last row of a piece's row
+range (every row of a piece of at most two rows); K: voxels sharing one column
+computation, n3 by the column identity of Sec. III-A (chi1 does not depend on
+x3).  estimate_counts() samples the geometry (numpy, independent of the
+kernels); a CPU test checks its counts against the oracle's weights.
 """
-import math
-
 import numpy as np
 
 PEAK_LANE_OPS = 256 * 64 * 2.4e9   # CUs x lanes x clock: 3.93e13 lane-op/s (FP32, non-packed)
 
+C_COL = 36.0
+C_BND, C_BND_EC = 50.0, 70.0
+C_COLFIN = 14.0
+C_VOX = 8.0
+C_VOX_RELAXED = 7.0
+C_PIX_RELAXED, C_PIX_EXACT = 12.0, 16.0
+C_PIX_EC_EDGE = 15.0
 
-def ops_per_voxel_view(n_c, n_p, exact, ec, n3):
-    cb = 24.0 if ec else 6.0
-    per_vox = 1.0 if exact else 7.0
-    per_row = cb + 3.0 + (12.0 if exact else 0.0)
-    return per_vox + n_c * (10.0 + cb) + n_p * per_row + n_c * 400.0 / n3
+
+def ops_per_voxel_view(n_c, n_p, n_e, exact, ec, K):
+    """Algorithmic FP32 VALU lane-operations per voxel-view."""
+    n_b = n_c + 1.0
+    col = (C_COL + n_b * (C_BND_EC if ec else C_BND) + n_c * C_COLFIN) / K
+    vox = n_c * C_VOX + (0.0 if exact else C_VOX_RELAXED)
+    pix = n_p * (C_PIX_EXACT if exact else C_PIX_RELAXED) + (n_e * C_PIX_EC_EDGE if ec else 0.0)
+    return col + vox + pix
 
 
 def estimate_counts(p, nsample=20000, seed=0):
-    """Mean detector-column pieces and row pieces per voxel-view (voxels whose
-    footprint lies on the detector)."""
+    """Mean column pieces n_c, pixels n_p and edge pixels n_e per voxel-view,
+    over voxel-views whose footprint lies on the detector: the detector
+    columns the voxel base's corners span, and per column the rows between
+    the top and bottom faces at the voxel centre's depth."""
     rng = np.random.default_rng(seed)
     n1, n2, n3 = p["vol_dims"]
     a1, a2, a3 = p["voxel_mm"]
@@ -73,15 +96,16 @@ def estimate_counts(p, nsample=20000, seed=0):
     on = (ulo >= 0) & (uhi < M) & (vlo >= 0) & (vhi < N)
     n_c = (uhi - ulo + 1)[on]
     n_r = (vhi - vlo + 1)[on]
-    return float(n_c.mean()), float((n_c * n_r).mean())
+    return float(n_c.mean()), float((n_c * n_r).mean()), float((n_c * np.minimum(n_r, 2)).mean())
 
 
-def roofline(p, exact, ec, seconds_per_launch):
-    """ALU roofline figures of one operator launch."""
-    n_c, n_p = estimate_counts(p)
+def roofline(p, exact, ec, seconds_per_launch, counts=None):
+    """ALU roofline figures of one operator launch (algorithmic ops per
+    voxel-view times voxel-views per launch over the launch time)."""
+    n_c, n_p, n_e = counts if counts is not None else estimate_counts(p)
     n1, n2, n3 = p["vol_dims"]
     vv = n1 * n2 * n3 * len(p["angles_rad"])
-    ops = ops_per_voxel_view(n_c, n_p, exact, ec, n3)
+    ops = ops_per_voxel_view(n_c, n_p, n_e, exact, ec, n3)
     achieved = vv * ops / seconds_per_launch
-    return dict(n_c=n_c, n_p=n_p, ops_per_vv=ops, voxel_views=vv,
+    return dict(n_c=n_c, n_p=n_p, n_e=n_e, ops_per_vv=ops, voxel_views=vv,
                 achieved=achieved, peak=PEAK_LANE_OPS, frac=achieved / PEAK_LANE_OPS)

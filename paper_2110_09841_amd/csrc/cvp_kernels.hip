@@ -236,16 +236,21 @@ __device__ __forceinline__ float cum(float s1, float beta, float tc, float rho, 
 }
 
 // Fixed-point accumulation of the projection.  A contribution w, already
-// scaled by the work item's 2^s so that |w| < 2^30, is rounded to the nearest
-// integer (v_cvt_rpi: floor(w + 1/2)), sign-extended to 64 bits and added
-// with an integer LDS atomic; the 64-bit sums hold a pixel's total.  On
-// gfx950 the integer atomic is about thirty times cheaper than ds_add_f32,
-// and integer sums do not depend on the order of the additions.
+// scaled by the work item's 2^s so that |w| < 2^51, becomes a 64-bit integer
+// by one FP64 addition: w + 1.5 * 2^52 lies in [2^52, 2^53), where the FP64
+// spacing is 1, so the addition rounds w to the nearest integer (ties to
+// even) and the low 52 bits of the result hold that integer plus 2^51; the
+// bit pattern minus that of 1.5 * 2^52 (whose low word is zero, so only the
+// high word changes) is the integer in two's complement.  It is added with
+// an integer LDS atomic; the 64-bit sums hold a pixel's total.  On gfx950
+// the integer atomic is about thirty times cheaper than ds_add_f32, and
+// integer sums do not depend on the order of the additions.
 __device__ __forceinline__ void lds_add_fixed(unsigned long long *p, float w)
 {
-    int lo;
-    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(lo) : "v"(w));
-    const unsigned long long q = (unsigned long long)(long long)lo;
+    const double d = (double)w + 0x1.8p52;
+    const unsigned hi = (unsigned)__double2hiint(d) - 0x43380000u;
+    const unsigned lo = (unsigned)__double2loint(d);
+    const unsigned long long q = ((unsigned long long)hi << 32) | lo;
     __hip_atomic_fetch_add(p, q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
@@ -535,9 +540,11 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
 
     // Scale of the fixed-point image from the largest |mu| in the wedge (as
     // the bit pattern of |mu|, so Inf and NaN compare above every finite
-    // value): times a geometric bound on one weight it must stay below 2^30
-    // (each contribution fits a 32-bit integer), times a bound on a pixel's
-    // weight sum below 2^61 (the 64-bit sums cannot overflow).  With gmax
+    // value): times a geometric bound on one weight it must stay below 2^51
+    // (each contribution converts exactly, see lds_add_fixed), times a bound
+    // on a pixel's weight sum below 2^61 (the 64-bit sums cannot overflow).
+    // The second bound is the binding one, so a contribution is kept to
+    // about 2^-55 of the largest possible pixel sum of the band.  With gmax
     // (the per-group maxima of group_max_kernel) the wedge maximum is a
     // lookup per group; without it the wedge is read once more here.
     unsigned mxl = 0u;
@@ -573,7 +580,7 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
         int e1, e2;
         frexp((double)__uint_as_float(mxb) * (raw ? G.wone_bound_raw : G.wone_bound), &e1);
         frexp((double)__uint_as_float(mxb) * (raw ? G.wsum_bound_raw : G.wsum_bound), &e2);
-        sc = min(30 - e1, 61 - e2);
+        sc = min(51 - e1, 61 - e2);
     }
     const int ngi = (finite && mxb != 0u) ? total : 0;   // all-zero wedge: nothing to add
 

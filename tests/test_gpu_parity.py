@@ -2,6 +2,8 @@
 C ABI.  Sizes span several column groups, bands and k-chunks with ragged
 tails; the 512^3 / 248-view workload that bench.py times is checked on
 sampled views and voxels the oracle computes one by one."""
+import functools
+
 import numpy as np
 import pytest
 import torch
@@ -136,44 +138,65 @@ def test_raw_volume_sums_to_voxel_volume():
             assert np.all(np.abs(sums - 1.0) < 2e-6), sums
 
 
-def test_cone_workload_sampled():
-    """256^3 / 512x384 / 360 views (12-degree cone): the GPU computes the whole
-    operator, the oracle three full views and 400 voxels."""
-    g = synth.config_cone()
+@functools.lru_cache(maxsize=1)
+def cone_inputs():
     x = synth.ellipsoid_phantom(256, 0.5, 40, seed=21)
     b = synth.uniform_projections((360, 384, 512), seed=22)
+    return x, b
+
+
+@pytest.mark.parametrize("variant", ["exact", "relaxed"])
+def test_cone_workload_sampled(variant):
+    """256^3 / 512x384 / 360 views (12-degree cone): the GPU computes the whole
+    operator, the oracle eight full views spread over the orbit and 2000
+    voxels (plus the eight corners of the volume)."""
+    g = synth.config_cone()
+    x, b = cone_inputs()
     G = cvp.Geometry(g)
     rng = np.random.default_rng(1)
-    idx = rng.integers(0, 256 ** 3, size=400)
-    for variant in ("exact", "relaxed"):
-        o = oopts(variant, True, "solid_angle")
-        say("cone", variant)
-        Ax = cvp.project(torch.from_numpy(x).cuda(), G, gopts(variant, True, "solid_angle")).cpu().numpy()
-        for view in (0, 97, 301):
-            assert_parity(Ax[view], O.project(g, o, x, views=(view, view + 1))[0], "cone A x view %d" % view)
-        Atb = cvp.backproject(torch.from_numpy(b).cuda(), G, gopts(variant, True, "solid_angle")).cpu().numpy()
-        assert_parity(Atb.ravel()[idx], O.backproject_voxels(g, o, b, idx), "cone A^T b sampled")
+    idx = np.concatenate([corner_indices(256, 256, 256), rng.integers(0, 256 ** 3, size=2000)])
+    o = oopts(variant, True, "solid_angle")
+    say("cone", variant)
+    Ax = cvp.project(torch.from_numpy(x).cuda(), G, gopts(variant, True, "solid_angle")).cpu().numpy()
+    for view in (0, 45, 97, 150, 203, 256, 301, 359):
+        assert_parity(Ax[view], O.project(g, o, x, views=(view, view + 1))[0], "cone %s A x view %d" % (variant, view))
+    del Ax
+    Atb = cvp.backproject(torch.from_numpy(b).cuda(), G, gopts(variant, True, "solid_angle")).cpu().numpy()
+    assert_parity(Atb.ravel()[idx], O.backproject_voxels(g, o, b, idx), "cone %s A^T b sampled" % variant)
 
 
-def test_carm_benchmark_workload_sampled():
-    """The benchmark workload (512^3 / 616x480 / 248 views over 200 degrees,
-    relaxed CVP with elevation correction, the launch bench.py times): the
-    oracle checks two full views of A x and 300 voxels of A^T b."""
-    g = synth.config_carm()
+def corner_indices(n1, n2, n3):
+    return np.array([i + n1 * (j + n2 * k) for i in (0, n1 - 1) for j in (0, n2 - 1) for k in (0, n3 - 1)])
+
+
+@functools.lru_cache(maxsize=1)
+def carm_inputs():
     x = synth.ellipsoid_phantom(512, 0.25, 80, seed=31, noise_frac=0.01)
     b = synth.uniform_projections((248, 480, 616), seed=32)
+    return x, b
+
+
+@pytest.mark.parametrize("variant", ["relaxed", "exact"])
+def test_carm_benchmark_workload_sampled(variant):
+    """The benchmark workload (512^3 / 616x480 / 248 views over 200 degrees,
+    elevation correction, the launch plan bench.py times): the oracle checks
+    eight full views of A x spread over the arc and 2000 voxels of A^T b plus
+    the volume's corners, for the relaxed and the exact form."""
+    g = synth.config_carm()
+    x, b = carm_inputs()
     G = cvp.Geometry(g)
-    o = oopts("relaxed", True, "solid_angle")
-    say("carm projection")
-    Ax = cvp.project(torch.from_numpy(x).cuda(), G, gopts("relaxed", True, "solid_angle")).cpu().numpy()
-    for view in (0, 171):
-        assert_parity(Ax[view], O.project(g, o, x, views=(view, view + 1))[0], "carm A x view %d" % view)
+    o = oopts(variant, True, "solid_angle")
+    say("carm projection", variant)
+    Ax = cvp.project(torch.from_numpy(x).cuda(), G, gopts(variant, True, "solid_angle")).cpu().numpy()
+    for view in (0, 31, 66, 99, 124, 171, 208, 247):
+        assert_parity(Ax[view], O.project(g, o, x, views=(view, view + 1))[0],
+                      "carm %s A x view %d" % (variant, view))
     del Ax
-    say("carm backprojection")
-    Atb = cvp.backproject(torch.from_numpy(b).cuda(), G, gopts("relaxed", True, "solid_angle")).cpu().numpy()
+    say("carm backprojection", variant)
+    Atb = cvp.backproject(torch.from_numpy(b).cuda(), G, gopts(variant, True, "solid_angle")).cpu().numpy()
     rng = np.random.default_rng(2)
-    idx = rng.integers(0, 512 ** 3, size=300)
-    assert_parity(Atb.ravel()[idx], O.backproject_voxels(g, o, b, idx), "carm A^T b sampled")
+    idx = np.concatenate([corner_indices(512, 512, 512), rng.integers(0, 512 ** 3, size=2000)])
+    assert_parity(Atb.ravel()[idx], O.backproject_voxels(g, o, b, idx), "carm %s A^T b sampled" % variant)
 
 
 def test_adjoint_and_determinism():

@@ -82,6 +82,69 @@ def test_conv3d_forward_backward_data_and_weight(ci, co, shape):
     assert np.allclose(f64(gb), OU.bias_grad(f64(gy)), rtol=1e-5, atol=1e-4)
 
 
+def _crop(a, z, y, x):
+    """3x3x3 neighbourhood of voxel (z, y, x) of a (D, H, W, C) array, zero
+    outside the volume (the convolution's padding)."""
+    D, H, W, C = a.shape
+    out = np.zeros((3, 3, 3, C))
+    for dz in range(3):
+        for dy in range(3):
+            for dx in range(3):
+                zz, yy, xx = z + dz - 1, y + dy - 1, x + dx - 1
+                if 0 <= zz < D and 0 <= yy < H and 0 <= xx < W:
+                    out[dz, dy, dx] = a[zz, yy, xx]
+    return out
+
+
+# (Cin, Cout, volume edge) of the network's convolutions at the warm-start
+# workload's 128^3 volume: c1a/c1b/d1b, u1/d1a, c2a, c2b/d2b, u2/d2a, c3a, c3b
+NET_CONVS = [(16, 16, 128), (32, 16, 128), (16, 32, 64), (32, 32, 64), (64, 32, 64), (32, 64, 32), (64, 64, 32)]
+
+
+@pytest.mark.parametrize("ci,co,edge", NET_CONVS)
+def test_conv3d_at_network_shapes(ci, co, edge):
+    """Each convolution shape the U-Net runs on 128^3 volumes, at its real
+    size: forward and backward-data on 1500 sampled voxels (the oracle's
+    convolution of each voxel's 3x3x3 neighbourhood), backward-weight (a sum
+    over every voxel) in full."""
+    shape = (edge, edge, edge)
+    x = rnd(shape + (ci,), 11, 0.5)
+    w = rnd((27, co, ci), 12, 0.1)
+    b = torch.randn(co, generator=torch.Generator().manual_seed(13)).float()
+    gy = rnd(shape + (co,), 14)
+    L = lib()
+    xd, wd, bd, gyd = x.cuda(), w.cuda(), b.cuda(), gy.cuda()
+    say("network conv", ci, co, shape)
+    y = torch.empty(shape + (co,), dtype=torch.bfloat16, device="cuda")
+    _check(L.cvp_nn_conv3d(ctypes.byref(desc(xd)), _p(wd), _p(bd), ctypes.byref(desc(y)), 1, 0, _s()))
+    wt = torch.empty((27, ci, co), dtype=torch.bfloat16, device="cuda")
+    _check(L.cvp_nn_transpose_weights(_p(wd), _p(wt), co, ci, _s()))
+    gx = torch.empty(shape + (ci,), dtype=torch.bfloat16, device="cuda")
+    _check(L.cvp_nn_conv3d(ctypes.byref(desc(gyd)), _p(wt), None, ctypes.byref(desc(gx)), 0, 1, _s()))
+    n = ctypes.c_int64()
+    _check(L.cvp_nn_wgrad_workspace(ctypes.byref(desc(xd)), ctypes.byref(desc(gyd)), ctypes.byref(n)))
+    work = torch.empty(n.value, dtype=torch.float32, device="cuda")
+    gw = torch.empty((27, co, ci), dtype=torch.float32, device="cuda")
+    _check(L.cvp_nn_conv3d_wgrad(ctypes.byref(desc(xd)), ctypes.byref(desc(gyd)), _p(gw), _p(work), n.value, _s()))
+    torch.cuda.synchronize()
+    xh, wh, bh, gyh = f64(x), f64(w), f64(b), f64(gy)
+    yg, gxg = y.cpu().double(), gx.cpu().double()
+    rng = np.random.default_rng(ci * 1000 + co + edge)
+    pts = rng.integers(0, edge, size=(1500, 3))
+    pts[:8] = [[0, 0, 0], [edge - 1] * 3, [0, edge - 1, 0], [edge - 1, 0, edge - 1],
+               [0, 5, edge - 1], [edge // 2] * 3, [1, 1, 1], [edge - 2, edge - 2, edge - 2]]
+    ref_y = np.stack([OU.conv3d(_crop(xh, *p), wh, bh, relu=True)[1, 1, 1] for p in pts])
+    ref_gx = np.stack([OU.conv3d_grad_input(_crop(gyh, *p), wh)[1, 1, 1] for p in pts])
+    got_y = torch.stack([yg[tuple(p)] for p in pts])
+    got_gx = torch.stack([gxg[tuple(p)] for p in pts])
+    close_bf16(got_y, torch.from_numpy(ref_y), "forward (relu) %dx%d @%d^3 sampled" % (ci, co, edge))
+    close_bf16(got_gx, torch.from_numpy(ref_gx), "backward-data %dx%d @%d^3 sampled" % (ci, co, edge))
+    gw_ref = OU.conv3d_grad_weight(xh, gyh)
+    err = float(np.abs(gw.cpu().double().numpy() - gw_ref).max() / np.abs(gw_ref).max())
+    say("backward-weight %dx%d @%d^3 rel err %.3e" % (ci, co, edge, err))
+    assert err < 1e-5
+
+
 def test_channel_slices_pool_upsample_add_head():
     L = lib()
     D, H, W = 8, 6, 10
