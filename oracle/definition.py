@@ -231,3 +231,52 @@ def voxel_definition(geom, view, ijk, pixels, weighting="solid_angle"):
             x0, x1, y0, y1 = pixel_edges_mm(geom, u, v)
             out.append(i_sa / pixel_solid_angle_arctan(f, x0, x1, y0, y1))
     return np.array(out)
+
+
+# ------------------------------------------------------------ SiddonK on volumes
+
+def siddon_project(geom, x, K, views=None):
+    """SiddonK projection of a whole volume (Sec. II-D): for every pixel the
+    mean over K x K rays (towards the midpoints of a K x K grid of equal
+    cells on the pixel) of the line integral of mu, each line integral the
+    sum over voxels of mu times the exact chord length (slab method, every
+    voxel tested; no traversal).  x: [n3][n2][n1].  Returns [views][N][M]
+    in FP64.  Brute force over voxels x rays: for tiny grids only."""
+    x = np.asarray(x, dtype=np.float64)
+    n3, n2, n1 = x.shape
+    nz = np.argwhere(x != 0.0)                       # (k, j, i) of non-zero voxels
+    mu = x[nz[:, 0], nz[:, 1], nz[:, 2]]
+    a = np.array(geom["voxel_mm"], dtype=np.float64)
+    o = np.array(geom.get("vol_offset_mm", (0, 0, 0)), dtype=np.float64)
+    base = o - 0.5 * np.array([n1, n2, n3]) * a
+    lo = base[None, :] + nz[:, ::-1] * a[None, :]    # (i, j, k) order -> x1, x2, x3
+    hi = lo + a[None, :]
+    M, N = int(geom["det_cols"]), int(geom["det_rows"])
+    V = len(geom["angles_rad"])
+    views = range(V) if views is None else range(*views)
+    g = (np.arange(K) + 0.5) / K - 0.5
+    G1, G2 = np.meshgrid(g, g, indexing="xy")
+    out = np.zeros((len(views), N, M))
+    for vi, view in enumerate(views):
+        s = frame(geom, view)[0]
+        for v in range(N):
+            for u in range(M):
+                P = detector_point(geom, view, u + G1.ravel(), v + G2.ravel())
+                R = P - s[None, :]
+                dirs = R / np.linalg.norm(R, axis=1)[:, None]
+                # chord of every ray in every voxel box: (rays, voxels)
+                with np.errstate(divide="ignore", invalid="ignore"):
+                    inv = 1.0 / dirs
+                    t0 = (lo[None, :, :] - s[None, None, :]) * inv[:, None, :]
+                    t1 = (hi[None, :, :] - s[None, None, :]) * inv[:, None, :]
+                tmin = np.minimum(t0, t1)
+                tmax = np.maximum(t0, t1)
+                par = (dirs == 0)[:, None, :]
+                inside = (s[None, None, :] >= lo[None, :, :]) & (s[None, None, :] <= hi[None, :, :])
+                tmin = np.where(par, np.where(inside, -np.inf, np.inf), tmin)
+                tmax = np.where(par, np.where(inside, np.inf, -np.inf), tmax)
+                enter = np.maximum(tmin.max(axis=2), 0.0)
+                leave = tmax.min(axis=2)
+                L = np.maximum(leave - enter, 0.0)
+                out[vi, v, u] = float(np.sum(L @ mu)) / (K * K)
+    return out

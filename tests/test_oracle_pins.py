@@ -399,6 +399,35 @@ def test_supersampling_converges_to_exact_definition():
         assert errs[2] < 5e-3
 
 
+@pytest.mark.parametrize("angle_deg", [0.0, 90.0])
+def test_siddon_volume_parallel_beam_row_sums(angle_deg):
+    """SiddonK of a whole volume (Sec. II-D) in the parallel-beam limit
+    (SID 1e9 mm, SDD 2e9 mm, pitch = 2 voxels: pixel centres on voxel-centre
+    rows): every ray of pixel (u, v) runs along one row of voxels, so the
+    pixel value is the voxel size times the sum of mu along that row -- at
+    0 degrees the row along x1 with x2 index u and x3 index n3-1-v, at 90
+    degrees the row along x2 with x1 index n1-1-u."""
+    n1, n2, n3 = 5, 4, 3
+    a = (0.8, 0.9, 1.1)
+    g = synth.geometry((n1, n2, n3), a, max(n1, n2), n3, (2 * a[1] if angle_deg == 0 else 2 * a[0], 2 * a[2]),
+                       1e9, 2e9, 1)
+    g["angles_rad"] = np.array([math.radians(angle_deg)])
+    if angle_deg == 0.0:
+        g["det_cols"] = n2
+    else:
+        g["det_cols"] = n1
+    x = np.random.default_rng(3).uniform(0.0, 1.0, (n3, n2, n1))
+    for K in (1, 2, 3):
+        P = D.siddon_project(g, x, K)[0]
+        for v in range(n3):
+            for u in range(g["det_cols"]):
+                if angle_deg == 0.0:
+                    ref = a[0] * x[n3 - 1 - v, u, :].sum()
+                else:
+                    ref = a[1] * x[n3 - 1 - v, :, n1 - 1 - u].sum()
+                assert abs(P[v, u] - ref) <= 1e-7 * ref, (K, u, v, P[v, u], ref)
+
+
 def test_isocentre_voxel_cvp_beats_siddon32():
     """Sec. V-A: with no elevation (a 1x1x5 mm voxel at the isocentre), the
     32x32-ray SiddonK is worse than unrelaxed CVP from every view angle.
