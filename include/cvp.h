@@ -141,12 +141,48 @@ cvp_status cvp_project_ws(const cvp_geometry *g, const cvp_options *opts,
                           void *hip_stream);
 
 /*
+ * Reference ray-driven projector SiddonK (Sec. II-D): every pixel of every
+ * view gets the mean, over K x K rays from the source to the centres of a
+ * K x K grid of equal cells on the pixel, of the line integral of the volume,
+ * each line integral the sum of mu times the exact chord length through each
+ * voxel the ray crosses (Siddon's parametric traversal), in FP64.  As K grows
+ * this tends to the area average of the line integrals over the pixel
+ * (eq. integ), which the cutting voxel projector with CVP_SCALE_COS
+ * estimates; the paper uses K = 512 as ground truth (Sec. IV-B).  Same
+ * geometry, layouts and ownership as cvp_project; output overwritten.  Cost
+ * grows as K^2 (rays of pixels outside the projected bounding box of the
+ * volume are not traced).  Errors: CVP_E_INVALID (K outside 1..1024, NULL
+ * pointer), CVP_E_DEVICE.
+ */
+cvp_status cvp_project_siddon(const cvp_geometry *g, int32_t K, const float *d_vol, float *d_proj,
+                              void *hip_stream);
+
+/*
  * x = A^T b with the same weights (the exact adjoint of cvp_project).
  * d_proj: [n_views][rows][cols] input; d_vol: [n3][n2][n1] output,
  * overwritten.  Voxel-driven gather: every voxel is written once.
  */
 cvp_status cvp_backproject(const cvp_geometry *g, const cvp_options *opts,
                            const float *d_proj, float *d_vol, void *hip_stream);
+
+/*
+ * The operators restricted to a subset of the geometry's views: views
+ * view0, view0 + view_stride, ..., view0 + (n_views - 1) view_stride (all
+ * inside 0..n_views of the geometry - 1, else CVP_E_INVALID).  d_proj is the
+ * full [n_views][rows][cols] projection array of the geometry: the
+ * projection writes only the blocks of the chosen views (the others are left
+ * as they are), the backprojection reads only those blocks and returns their
+ * adjoint sum.  Ordered subsets of the views (OS-SART, Sec. V-E) use them.
+ * cvp_project_views takes optional scratch as cvp_project_ws (d_work NULL:
+ * none).  Results equal those of the full operators on the chosen views
+ * bitwise.
+ */
+cvp_status cvp_project_views(const cvp_geometry *g, const cvp_options *opts, const float *d_vol,
+                             float *d_proj, int32_t view0, int32_t view_stride, int32_t n_views,
+                             void *d_work, int64_t work_bytes, void *hip_stream);
+cvp_status cvp_backproject_views(const cvp_geometry *g, const cvp_options *opts, const float *d_proj,
+                                 float *d_vol, int32_t view0, int32_t view_stride, int32_t n_views,
+                                 void *hip_stream);
 
 /*
  * Batches: several independent problems (each with its own geometry) in one
@@ -223,6 +259,57 @@ cvp_status cvp_cgls_batched_iterate(const cvp_batch *b, const cvp_options *opts,
                                     float *const *d_x, float *const *d_r, float *const *d_s,
                                     float *const *d_p, float *const *d_q, void *const *d_work,
                                     void *hip_stream);
+
+/*
+ * OS-SART (the simultaneous algebraic reconstruction technique of Andersen &
+ * Kak over ordered subsets, Jiang & Wang; Sec. V-E of the paper offers it
+ * with a subset count) on the same operators.  The views are split into T
+ * interleaved subsets S_t = {t, t + T, t + 2T, ...}.  cvp_sart_setup computes
+ * the row sums R = A 1 into d_rowsum ([n_views][rows][cols]) and the column
+ * sums of every subset C_t = A_t^T 1 into d_colsum (T volumes, one after
+ * another), using d_q (projection sized) as scratch.  cvp_sart_iterate runs
+ * n_sweeps sweeps over t = 0 .. T-1 of
+ *     x <- x + lambda A_t^T ((b_t - A_t x) / R_t) / C_t
+ * (a zero denominator gives 0: pixels no voxel reaches, voxels no ray of the
+ * subset reaches), then x <- max(x, 0) if nonneg; d_q (projections) and d_z
+ * (volume) are scratch.  Caller-owned float32 device buffers, no allocation,
+ * no host synchronisation: a run of sweeps can be captured in a HIP graph.
+ * Errors: CVP_E_INVALID (T outside 1..n_views, lambda not finite and > 0,
+ * aliasing, NULL).
+ */
+cvp_status cvp_sart_setup(const cvp_geometry *g, const cvp_options *opts, int32_t n_subsets,
+                          float *d_rowsum, float *d_colsum, float *d_q, void *hip_stream);
+cvp_status cvp_sart_iterate(const cvp_geometry *g, const cvp_options *opts, int32_t n_subsets,
+                            int32_t n_sweeps, float lambda, int32_t nonneg, const float *d_b, float *d_x,
+                            const float *d_rowsum, const float *d_colsum, float *d_q, float *d_z,
+                            void *hip_stream);
+
+/*
+ * LSQR (Paige & Saunders, ACM TOMS 8, 1982; Sec. V-E names it next to CGLS):
+ * Golub-Kahan bidiagonalisation with a QR update, minimising |b - A x| over
+ * growing Krylov spaces (in exact arithmetic the iterates of CGLS).
+ *   start:   beta u = b - A x,  alpha v = A^T u,  w = v,
+ *            phibar = beta,  rhobar = alpha
+ *   iterate: beta u = A v - alpha u,  alpha v = A^T u - beta v,
+ *            rho = |(rhobar, beta)|, c = rhobar/rho, s = beta/rho,
+ *            x += (c phibar / rho) w,  w = v - (s alpha / rho) w,
+ *            rhobar = -c alpha,  phibar = s phibar
+ * Vectors: x, v, w, s (volume; s is scratch), u, q (projections; q is
+ * scratch).  Scalars on the device in d_work (cvp_lsqr_workspace_size bytes,
+ * 8-byte aligned), as doubles: [0] alpha [1] beta [2] rhobar [3] phibar
+ * [4] phi/rho [5] theta/rho [6] k (iterations done) [7] end flag (the
+ * bidiagonalisation ended; x stays) [8] |A^T (b - A x0)|; from [16]: 4096
+ * estimates of |b - A x_k|, then 4096 of |A^T (b - A x_k)| (k = 0, 1, ...),
+ * then reduction partials.  No allocation, no host sync: a run of
+ * cvp_lsqr_iterate can be captured in a HIP graph.
+ */
+cvp_status cvp_lsqr_workspace_size(int64_t n_voxels, int64_t n_pixels_total, int64_t *bytes);
+cvp_status cvp_lsqr_start(const cvp_geometry *g, const cvp_options *opts, const float *d_b, float *d_x,
+                          float *d_u, float *d_v, float *d_w, float *d_q, float *d_s, void *d_work,
+                          void *hip_stream);
+cvp_status cvp_lsqr_iterate(const cvp_geometry *g, const cvp_options *opts, int32_t n_iter, float *d_x,
+                            float *d_u, float *d_v, float *d_w, float *d_q, float *d_s, void *d_work,
+                            void *hip_stream);
 
 /* *d_result = sum_i a[i] b[i] accumulated in FP64 (device scalar), using the
  * partials area of a CGLS workspace d_work.  n >= 0. */

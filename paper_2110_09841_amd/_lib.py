@@ -92,6 +92,17 @@ def _register_extra(L):
                                      + [vp], st),
         "cvp_project_workspace_size": ([vp, ctypes.POINTER(ctypes.c_int64)], st),
         "cvp_project_ws": ([vp, ctypes.POINTER(OptionsC), vp, vp, vp, ctypes.c_int64, vp], st),
+        "cvp_project_siddon": ([vp, ctypes.c_int32, vp, vp, vp], st),
+        "cvp_project_views": ([vp, ctypes.POINTER(OptionsC), vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                               vp, ctypes.c_int64, vp], st),
+        "cvp_backproject_views": ([vp, ctypes.POINTER(OptionsC), vp, vp, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_int32, vp], st),
+        "cvp_sart_setup": ([vp, ctypes.POINTER(OptionsC), ctypes.c_int32, vp, vp, vp, vp], st),
+        "cvp_sart_iterate": ([vp, ctypes.POINTER(OptionsC), ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                              ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp], st),
+        "cvp_lsqr_workspace_size": ([ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)], st),
+        "cvp_lsqr_start": ([vp, ctypes.POINTER(OptionsC)] + [vp] * 8 + [vp], st),
+        "cvp_lsqr_iterate": ([vp, ctypes.POINTER(OptionsC), ctypes.c_int32] + [vp] * 7 + [vp], st),
         "cvp_dot": ([vp, vp, ctypes.c_int64, vp, vp, vp], st),
         "cvp_synth_ellipsoids": ([vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
                                   vp, vp], st),

@@ -14,7 +14,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libcvp.so")
 
-SOURCES = ["cvp_kernels.hip", "cvp_blas.hip", "cvp_nn.hip", "cvp_synth.hip", "cvp_capi.cpp"]
+SOURCES = ["cvp_kernels.hip", "cvp_siddon.hip", "cvp_blas.hip", "cvp_nn.hip", "cvp_synth.hip", "cvp_capi.cpp"]
 ARCH = os.environ.get("CVP_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

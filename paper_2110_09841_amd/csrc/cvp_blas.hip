@@ -189,6 +189,160 @@ residual(float *__restrict__ r, const float *__restrict__ b, const float *__rest
         r[i] = b[i] - q[i];
 }
 
+// ---------------------------------------------------------------- OS-SART
+
+__global__ void __launch_bounds__(kRedThreads)
+fill(float *__restrict__ p, int64_t n, float val)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = val;
+}
+
+// For the count views of a subset (blocks of nm pixels, view_step apart):
+// q = (b - q) / R, 0 where R = 0.
+__global__ void __launch_bounds__(kRedThreads)
+sart_residual(float *__restrict__ q, const float *__restrict__ b, const float *__restrict__ R, int64_t nm,
+              int count, int64_t view_step)
+{
+    const int64_t n = nm * count;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const int64_t j = (i / nm) * view_step + i % nm;
+        const float r = R[j];
+        q[j] = r != 0.0f ? (b[j] - q[j]) / r : 0.0f;
+    }
+}
+
+// x += lam z / C where C != 0; then x = max(x, 0) if nonneg.
+__global__ void __launch_bounds__(kRedThreads)
+sart_update(float *__restrict__ x, const float *__restrict__ z, const float *__restrict__ C, int64_t n,
+            float lam, int nonneg)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const float c = C[i];
+        float v = x[i];
+        if (c != 0.0f) v = fmaf(lam, z[i] / c, v);
+        if (nonneg) v = fmaxf(v, 0.0f);
+        x[i] = v;
+    }
+}
+
+// ---------------------------------------------------------------- LSQR
+// Scalars (FP64, device): see kLsqr* in cvp_internal.h.  Recurrences of
+// Paige & Saunders (1982), Golub-Kahan bidiagonalisation with a QR update.
+
+// y = x - sc[ci] * y with partial sums of |y|^2 (ci < 0: y = x)
+__global__ void __launch_bounds__(kRedThreads)
+axpby_norm(float *__restrict__ y, const float *__restrict__ x, int64_t n, const double *__restrict__ sc, int ci,
+           double *__restrict__ partial)
+{
+    __shared__ double sh[kRedThreads / 64];
+    const float c = ci >= 0 ? (float)sc[ci] : 0.0f;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const float v = ci >= 0 ? fmaf(-c, y[i], x[i]) : x[i];
+        y[i] = v;
+        acc += (double)v * v;
+    }
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// y *= 1 / sc[ci] (left alone where sc[ci] = 0)
+__global__ void __launch_bounds__(kRedThreads)
+scale_by_inverse(float *__restrict__ y, int64_t n, const double *__restrict__ sc, int ci)
+{
+    const double d = sc[ci];
+    if (!(d > 0.0)) return;
+    const float inv = (float)(1.0 / d);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) y[i] *= inv;
+}
+
+// v /= alpha; then start: w = v;  iteration: x += (phi/rho) w, w = v - (theta/rho) w
+__global__ void __launch_bounds__(kRedThreads)
+lsqr_vxw(float *__restrict__ v, float *__restrict__ x, float *__restrict__ w, int64_t n,
+         const double *__restrict__ sc, int init)
+{
+    const double a = sc[kLsqrAlpha];
+    const float inv = a > 0.0 ? (float)(1.0 / a) : 1.0f;
+    const float fx = (float)sc[kLsqrXStep], fw = (float)sc[kLsqrWStep];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const float vn = v[i] * inv;
+        v[i] = vn;
+        if (init) {
+            w[i] = vn;
+        } else {
+            const float wi = w[i];
+            x[i] = fmaf(fx, wi, x[i]);
+            w[i] = fmaf(-fw, wi, vn);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kRedThreads)
+lsqr_finalize(const double *__restrict__ partial, int nparts, double *__restrict__ sc, int mode)
+{
+    __shared__ double sh[kRedThreads / 64];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) acc += partial[i];
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x != 0) return;
+    const double nrm = sqrt(t);
+    double *hr = sc + kLsqrScalars;
+    double *har = hr + kCglsHistory;
+    switch (mode) {
+    case kLsqrFinBeta0:
+        sc[kLsqrBeta] = nrm;
+        sc[kLsqrPhibar] = nrm;
+        sc[kLsqrK] = 0.0;
+        sc[kLsqrBreak] = 0.0;
+        sc[kLsqrXStep] = 0.0;
+        sc[kLsqrWStep] = 0.0;
+        break;
+    case kLsqrFinAlpha0:
+        sc[kLsqrAlpha] = nrm;
+        sc[kLsqrRhobar] = nrm;
+        sc[kLsqrArnorm0] = nrm * sc[kLsqrBeta];
+        hr[0] = sc[kLsqrBeta];
+        har[0] = nrm * sc[kLsqrBeta];
+        break;
+    case kLsqrFinBeta:
+        sc[kLsqrBeta] = nrm;
+        break;
+    default: {   // kLsqrFinAlpha: alpha, then the QR step of the bidiagonal problem
+        sc[kLsqrAlpha] = nrm;
+        const double rhobar = sc[kLsqrRhobar], beta = sc[kLsqrBeta], phibar = sc[kLsqrPhibar];
+        const double rho = hypot(rhobar, beta);
+        const int k = (int)sc[kLsqrK] + 1;
+        if (rho > 0.0) {
+            const double c = rhobar / rho, sn = beta / rho;
+            sc[kLsqrXStep] = c * phibar / rho;   // phi / rho
+            sc[kLsqrWStep] = sn * nrm / rho;     // theta / rho
+            sc[kLsqrRhobar] = -c * nrm;
+            sc[kLsqrPhibar] = sn * phibar;
+            if (k < kCglsHistory) {
+                hr[k] = sn * phibar;
+                har[k] = sn * phibar * nrm * fabs(c);
+            }
+        } else {   // the bidiagonalisation has ended: x stays
+            sc[kLsqrXStep] = 0.0;
+            sc[kLsqrWStep] = 0.0;
+            sc[kLsqrBreak] = 1.0;
+            if (k < kCglsHistory) {
+                hr[k] = phibar;
+                har[k] = 0.0;
+            }
+        }
+        sc[kLsqrK] = k;
+        break;
+    }
+    }
+}
+
 }  // namespace
 
 hipError_t blas_dot(const float *a, const float *b, int64_t n, double *partials, double *sc,
@@ -218,6 +372,53 @@ hipError_t blas_update_p(float *p, const float *sv, int64_t n, const double *sc,
 hipError_t blas_residual(float *r, const float *b, const float *q, int64_t n, hipStream_t s)
 {
     hipLaunchKernelGGL(residual, dim3(kRedBlocks), dim3(kRedThreads), 0, s, r, b, q, n);
+    return hipGetLastError();
+}
+
+hipError_t blas_fill(float *p, int64_t n, float val, hipStream_t s)
+{
+    hipLaunchKernelGGL(fill, dim3(kRedBlocks), dim3(kRedThreads), 0, s, p, n, val);
+    return hipGetLastError();
+}
+
+hipError_t sart_residual_views(float *q, const float *b, const float *R, int64_t nm, int count, int64_t view_step,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL(sart_residual, dim3(kRedBlocks), dim3(kRedThreads), 0, s, q, b, R, nm, count, view_step);
+    return hipGetLastError();
+}
+
+hipError_t sart_update_x(float *x, const float *z, const float *C, int64_t n, float lam, int nonneg, hipStream_t s)
+{
+    hipLaunchKernelGGL(sart_update, dim3(kRedBlocks), dim3(kRedThreads), 0, s, x, z, C, n, lam, nonneg);
+    return hipGetLastError();
+}
+
+hipError_t lsqr_axpby_norm(float *y, const float *x, int64_t n, double *sc, int ci, int mode, hipStream_t s)
+{
+    double *part = sc + kLsqrScalars + 2 * kCglsHistory;
+    hipLaunchKernelGGL(axpby_norm, dim3(kRedBlocks), dim3(kRedThreads), 0, s, y, x, n, sc, ci, part);
+    hipLaunchKernelGGL(lsqr_finalize, dim3(1), dim3(kRedThreads), 0, s, part, kRedBlocks, sc, mode);
+    return hipGetLastError();
+}
+
+hipError_t lsqr_norm(const float *a, int64_t n, double *sc, int mode, hipStream_t s)
+{
+    double *part = sc + kLsqrScalars + 2 * kCglsHistory;
+    hipLaunchKernelGGL(dot_partials, dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, a, n, part);
+    hipLaunchKernelGGL(lsqr_finalize, dim3(1), dim3(kRedThreads), 0, s, part, kRedBlocks, sc, mode);
+    return hipGetLastError();
+}
+
+hipError_t lsqr_scale(float *y, int64_t n, const double *sc, int ci, hipStream_t s)
+{
+    hipLaunchKernelGGL(scale_by_inverse, dim3(kRedBlocks), dim3(kRedThreads), 0, s, y, n, sc, ci);
+    return hipGetLastError();
+}
+
+hipError_t lsqr_update_vxw(float *v, float *x, float *w, int64_t n, const double *sc, int init, hipStream_t s)
+{
+    hipLaunchKernelGGL(lsqr_vxw, dim3(kRedBlocks), dim3(kRedThreads), 0, s, v, x, w, n, sc, init);
     return hipGetLastError();
 }
 

@@ -19,6 +19,7 @@ namespace cvp {
 hipError_t configure_kernel_lds(size_t max_lds, size_t max_lds_batched);
 constexpr size_t kLdsBudget = 30 * 1024;   // default projection plans: five workgroups per CU (160 KB LDS; 5 x 32 KB did not fit)
 constexpr size_t kBackLdsBudget = 52 * 1024;   // backprojection windows: three workgroups per CU
+constexpr size_t kBackLdsBudgetWide = 80 * 1024;   // records of up to kPmaxWide pieces per column: two per CU
 constexpr size_t kLdsMax = 156 * 1024;      // any plan: one workgroup per CU at worst
 constexpr size_t kLdsBatchMax = kLdsMax;
 bool plan_projection(int N, int n2, int M, int nviews, int pmax, int force_u, ProjLaunch &L);
@@ -37,6 +38,7 @@ struct cvp_geometry {
     cvp::BackLaunch bl{};
     int64_t nvox = 0, npix = 0;
     double zabs = 0.0, Dmin = 0.0;   // for launch planning
+    int pmax = 4;                    // pieces per column the kernels keep (4, 8 or kPmaxWide)
 };
 
 namespace {
@@ -102,6 +104,11 @@ size_t backproject_lds_bytes(int gw, int pmax, int winCap)
 // fits one workgroup.
 bool plan_projection(int N, int n2, int M, int nviews, int pmax, int force_u, ProjLaunch &L)
 {
+    // A work item keeps at most pmax pieces per column, and a column's pieces
+    // inside a band of U detector columns are at most U; pmax = 8 with U <= 8
+    // therefore serves footprints of any width.
+    const int umax = pmax > 8 ? 8 : 32;
+    if (pmax > 8) pmax = 8;
     const size_t fixed = project_lds_bytes(0, N, n2, pmax);
     const size_t perU = project_lds_bytes(1, N, n2, pmax) - fixed;
     int U = force_u;
@@ -109,8 +116,8 @@ bool plan_projection(int N, int n2, int M, int nviews, int pmax, int force_u, Pr
         // as wide as the default budget allows; a single column may use more
         if (fixed + perU > kLdsMax) return false;
         U = fixed + perU <= kLdsBudget ? (int)((kLdsBudget - fixed) / perU) : 1;
-        U = std::max(1, std::min(U, 32));
-    } else if (U > 32 || project_lds_bytes(U, N, n2, pmax) > kLdsMax) {
+        U = std::max(1, std::min(U, umax));
+    } else if (U > umax || project_lds_bytes(U, N, n2, pmax) > kLdsMax) {
         return false;
     }
     L.U = U;
@@ -132,13 +139,17 @@ bool plan_backprojection(const DevGeom &G, int pmax, double zabs, double Dmin, i
     // (stack width, passes) by stack area; the first whose estimated window
     // fits the per-wave LDS window, else the last admissible one (its windows
     // are then read from global memory)
+    // (wide footprints: records of kPmaxWide pieces, 4-column stacks only)
     static const int cands[6][2] = {{16, 2}, {16, 1}, {8, 2}, {8, 1}, {4, 2}, {4, 1}};
+    const size_t budget = pmax > 8 ? kBackLdsBudgetWide : kBackLdsBudget;
     int gw = 0, kp = 0, cap = 0;
     for (const auto &cd : cands) {
         const int cand = cd[0], ckp = cd[1];
         if ((force_gw > 0 && cand != force_gw) || (force_kp > 0 && ckp != force_kp)) continue;
+        if (pmax > 8 && cand != 4) continue;
         const size_t rec = (size_t)back_views_per_pass(cand, pmax) * back_rec_floats(cand, pmax);
-        const int c = (int)((kBackLdsBudget / (kWaves * 4) - rec) / 4 * 4);
+        if (rec * kWaves * 4 >= budget) continue;
+        const int c = (int)((budget / (kWaves * 4) - rec) / 4 * 4);
         if (c < kBackPasses * cand * 64 || c < 1024) continue;   // the window area also parks the accumulators
         const double wu = std::hypot(cand * G.a1, G.a2) * mag / G.b1 + pmax + 2;
         const double zspan = std::hypot(cand * G.a1, G.a2);
@@ -243,8 +254,9 @@ cvp_status cvp_geometry_from_views(const cvp_geometry_desc *d, cvp_geometry **ou
     // widest projected voxel base and tallest projected row extent (pixels)
     const double wmax = std::hypot(a1, a2) * f / (b1 * (Dmin - 0.5 * std::hypot(a1, a2)));
     const int pieces = (int)std::floor(wmax) + 2;
-    if (!(Dmin > std::hypot(a1, a2)) || pieces > 8)
-        return fail(CVP_E_UNSUPPORTED, "a voxel base projects onto up to %d detector columns (max 8)", pieces);
+    if (!(Dmin > std::hypot(a1, a2)) || pieces > cvp::kPmaxWide)
+        return fail(CVP_E_UNSUPPORTED, "a voxel base projects onto up to %d detector columns (max %d)", pieces,
+                    cvp::kPmaxWide);
     const double zabs = std::max(std::fabs(x3lo), std::fabs(x3lo + n3 * a3));
     const double ymax = std::fabs(c2) + zabs * f / (b2 * Dmin) + 8.0;
     if (ymax > 8000.0)
@@ -301,6 +313,7 @@ cvp_status cvp_geometry_from_views(const cvp_geometry_desc *d, cvp_geometry **ou
     G.b1 = b1; G.b2 = b2; G.c1 = c1; G.c2 = c2; G.f = f;
     G.fb1 = f / b1; G.fb2 = f / b2; G.b2f = b2 / f;
     G.views = g->d_views;
+    G.vstride = 1;
     G.sigma = nullptr;
     G.raw_volume = 0;
     {
@@ -318,9 +331,12 @@ cvp_status cvp_geometry_from_views(const cvp_geometry_desc *d, cvp_geometry **ou
         G.wone_bound_raw = 2.0 * a1 * a2 * a3;
     }
 
-    const int pmax = pieces <= 4 ? 4 : 8;
+    // pieces per column the kernels keep: 4, 8, or (4-column backprojection
+    // stacks, projection bands of at most 8 columns) kPmaxWide
+    const int pmax = pieces <= 4 ? 4 : pieces <= 8 ? 8 : cvp::kPmaxWide;
     g->zabs = zabs;
     g->Dmin = Dmin;
+    g->pmax = pmax;
     if (!cvp::plan_projection(N, n2, M, d->n_views, pmax, 0, g->pl)) {
         cvp_geometry_destroy(g);
         return fail(CVP_E_UNSUPPORTED, "detector rows (%d) or volume rows (%d) too large for the projection LDS layout", N, n2);
@@ -355,10 +371,14 @@ cvp_status cvp_geometry_set_launch(cvp_geometry *g, const cvp_launch *in)
     const cvp::DevGeom &G = g->base;
     cvp::ProjLaunch pl{};
     cvp::BackLaunch bl{};
-    if (!cvp::plan_projection(G.N, G.n2, G.M, G.nviews, g->pl.pmax, u, pl))
+    if (!cvp::plan_projection(G.N, G.n2, G.M, G.nviews, g->pmax, u, pl)) {
+        if (g->pmax > 8 && u > 8)
+            return fail(CVP_E_UNSUPPORTED, "launch.proj_band_cols = %d: voxels span more than 8 detector columns, "
+                                           "bands are limited to 8", u);
         return fail(CVP_E_UNSUPPORTED, "launch.proj_band_cols = %d: band image of %zu bytes exceeds the LDS limit", u,
                     cvp::project_lds_bytes(u, G.N, G.n2, g->pl.pmax));
-    if (!cvp::plan_backprojection(G, g->bl.pmax, g->zabs, g->Dmin, gw, kp, bl))
+    }
+    if (!cvp::plan_backprojection(G, g->pmax, g->zabs, g->Dmin, gw, kp, bl))
         return fail(CVP_E_UNSUPPORTED, "launch.bp_stack_cols = %d, bp_passes = %d: does not fit LDS", gw, kp);
     g->pl = pl;
     g->bl = bl;
@@ -439,6 +459,18 @@ cvp_status cvp_project_ws(const cvp_geometry *g, const cvp_options *o, const flo
     return ok();
 }
 
+cvp_status cvp_project_siddon(const cvp_geometry *g, int32_t K, const float *d_vol, float *d_proj, void *stream)
+{
+    if (K < 1 || K > 1024) return fail(CVP_E_INVALID, "K = %d (must be 1..1024)", K);
+    const cvp_options o{CVP_EXACT, 0, CVP_SCALE_NONE, 0u};
+    cvp::DevGeom G;
+    cvp_status st = prepare(g, &o, d_vol, d_proj, G);
+    if (st != CVP_OK) return st;
+    hipError_t e = cvp::launch_siddon(G, K, d_vol, d_proj, (hipStream_t)stream);
+    if (e != hipSuccess) return device_fail(e, "SiddonK launch");
+    return ok();
+}
+
 cvp_status cvp_backproject(const cvp_geometry *g, const cvp_options *o, const float *d_proj,
                            float *d_vol, void *stream)
 {
@@ -447,6 +479,65 @@ cvp_status cvp_backproject(const cvp_geometry *g, const cvp_options *o, const fl
     if (st != CVP_OK) return st;
     hipError_t e = cvp::launch_backproject(G, g->bl, o->variant == CVP_EXACT, o->elevation_correction != 0,
                                            d_proj, d_vol, (hipStream_t)stream);
+    if (e != hipSuccess) return device_fail(e, "backprojection launch");
+    return ok();
+}
+
+// Views v0, v0 + stride, ..., v0 + (count - 1) stride of a geometry: the
+// view table and the projection pointer start at v0 and step by stride.
+static cvp_status view_subset(const cvp_geometry *g, int32_t view0, int32_t stride, int32_t count,
+                              cvp::DevGeom &G, int64_t &proj_offset)
+{
+    const int V = g->base.nviews;
+    if (view0 < 0 || view0 >= V) return fail(CVP_E_INVALID, "view0 = %d (must be 0..%d)", view0, V - 1);
+    if (stride < 1) return fail(CVP_E_INVALID, "view_stride = %d (must be >= 1)", stride);
+    if (count < 1 || (int64_t)view0 + (int64_t)(count - 1) * stride >= V)
+        return fail(CVP_E_INVALID, "n_views = %d: views %d + k * %d run past the last view (%d)", count, view0,
+                    stride, V - 1);
+    G.views = g->d_views + view0;
+    G.vstride = stride;
+    G.nviews = count;
+    proj_offset = (int64_t)view0 * G.N * G.M;
+    return CVP_OK;
+}
+
+cvp_status cvp_project_views(const cvp_geometry *g, const cvp_options *o, const float *d_vol, float *d_proj,
+                             int32_t view0, int32_t view_stride, int32_t n_views, void *d_work, int64_t work_bytes,
+                             void *stream)
+{
+    cvp::DevGeom G;
+    cvp_status st = prepare(g, o, d_vol, d_proj, G);
+    if (st != CVP_OK) return st;
+    int64_t off = 0;
+    st = view_subset(g, view0, view_stride, n_views, G, off);
+    if (st != CVP_OK) return st;
+    if (d_work) {
+        const int64_t need = cvp::group_max_cells(g->base) * (int64_t)sizeof(unsigned);
+        if (work_bytes < need)
+            return fail(CVP_E_INVALID, "work_bytes = %lld, need %lld (cvp_project_workspace_size)",
+                        (long long)work_bytes, (long long)need);
+        if (reinterpret_cast<uintptr_t>(d_work) & 3) return fail(CVP_E_INVALID, "work must be 4-byte aligned");
+    }
+    cvp::ProjLaunch pl{};
+    if (!cvp::plan_projection(G.N, G.n2, G.M, n_views, g->pmax, g->pl.U, pl))
+        return fail(CVP_E_UNSUPPORTED, "projection plan");
+    hipError_t e = cvp::launch_project(G, pl, o->variant == CVP_EXACT, o->elevation_correction != 0, d_vol,
+                                       d_proj + off, (unsigned *)d_work, (hipStream_t)stream);
+    if (e != hipSuccess) return device_fail(e, "projection launch");
+    return ok();
+}
+
+cvp_status cvp_backproject_views(const cvp_geometry *g, const cvp_options *o, const float *d_proj, float *d_vol,
+                                 int32_t view0, int32_t view_stride, int32_t n_views, void *stream)
+{
+    cvp::DevGeom G;
+    cvp_status st = prepare(g, o, d_proj, d_vol, G);
+    if (st != CVP_OK) return st;
+    int64_t off = 0;
+    st = view_subset(g, view0, view_stride, n_views, G, off);
+    if (st != CVP_OK) return st;
+    hipError_t e = cvp::launch_backproject(G, g->bl, o->variant == CVP_EXACT, o->elevation_correction != 0,
+                                           d_proj + off, d_vol, (hipStream_t)stream);
     if (e != hipSuccess) return device_fail(e, "backprojection launch");
     return ok();
 }
@@ -489,6 +580,9 @@ cvp_status cvp_batch_create(const cvp_geometry *const *geoms, int32_t n, cvp_bat
         if (!geoms[q]) return fail(CVP_E_INVALID, "geoms[%d] is NULL", q);
         if (geoms[q]->device != geoms[0]->device)
             return fail(CVP_E_INVALID, "geoms[%d] lives on another device", q);
+        if (geoms[q]->bl.pmax > 8)
+            return fail(CVP_E_UNSUPPORTED, "geoms[%d]: voxels project onto more than 8 detector columns "
+                                           "(batched kernels keep at most 8 pieces per column)", q);
     }
     cvp_batch *b = new (std::nothrow) cvp_batch();
     if (!b) return fail(CVP_E_NOMEM, "host allocation");
@@ -766,6 +860,145 @@ cvp_status cvp_cgls_batched_iterate(const cvp_batch *bt, const cvp_options *o, i
         if (e != hipSuccess) break;
     }
     if (e != hipSuccess) return device_fail(e, "batched cgls iterate");
+    return ok();
+}
+
+// ------------------------------------------------------------------ OS-SART
+
+static int subset_count(int V, int T, int t) { return (V - t + T - 1) / T; }
+
+cvp_status cvp_sart_setup(const cvp_geometry *g, const cvp_options *o, int32_t n_subsets, float *d_rowsum,
+                          float *d_colsum, float *d_q, void *stream)
+{
+    cvp::DevGeom G;
+    if (!d_colsum || !d_q) return fail(CVP_E_INVALID, "colsum or q is NULL");
+    cvp_status st = prepare(g, o, d_colsum, d_rowsum, G);
+    if (st != CVP_OK) return st;
+    const int V = G.nviews;
+    if (n_subsets < 1 || n_subsets > V) return fail(CVP_E_INVALID, "n_subsets = %d (must be 1..%d)", n_subsets, V);
+    if (d_q == d_rowsum) return fail(CVP_E_INVALID, "q and rowsum alias");
+    hipStream_t sm = (hipStream_t)stream;
+    const bool ex = o->variant == CVP_EXACT, ec = o->elevation_correction != 0;
+    // R = A 1 (all views), C_t = A_t^T 1 (views t, t + T, ...)
+    hipError_t e = cvp::blas_fill(d_colsum, g->nvox, 1.0f, sm);
+    if (e == hipSuccess) e = cvp::launch_project(G, g->pl, ex, ec, d_colsum, d_rowsum, nullptr, sm);
+    if (e == hipSuccess) e = cvp::blas_fill(d_q, g->npix, 1.0f, sm);
+    for (int t = 0; t < n_subsets && e == hipSuccess; ++t) {
+        cvp::DevGeom Gt = G;
+        int64_t off = 0;
+        view_subset(g, t, n_subsets, subset_count(V, n_subsets, t), Gt, off);
+        e = cvp::launch_backproject(Gt, g->bl, ex, ec, d_q + off, d_colsum + (size_t)t * g->nvox, sm);
+    }
+    if (e != hipSuccess) return device_fail(e, "sart setup");
+    return ok();
+}
+
+cvp_status cvp_sart_iterate(const cvp_geometry *g, const cvp_options *o, int32_t n_subsets, int32_t n_sweeps,
+                            float lambda, int32_t nonneg, const float *d_b, float *d_x, const float *d_rowsum,
+                            const float *d_colsum, float *d_q, float *d_z, void *stream)
+{
+    cvp::DevGeom G;
+    if (!d_b || !d_rowsum || !d_colsum || !d_q || !d_z) return fail(CVP_E_INVALID, "NULL pointer");
+    cvp_status st = prepare(g, o, d_b, d_x, G);
+    if (st != CVP_OK) return st;
+    const int V = G.nviews;
+    if (n_subsets < 1 || n_subsets > V) return fail(CVP_E_INVALID, "n_subsets = %d (must be 1..%d)", n_subsets, V);
+    if (n_sweeps < 0) return fail(CVP_E_INVALID, "n_sweeps = %d", n_sweeps);
+    if (!std::isfinite(lambda) || !(lambda > 0.0f)) return fail(CVP_E_INVALID, "lambda must be finite and > 0");
+    if (d_q == d_b || d_q == d_rowsum || d_z == d_x || (const float *)d_z == d_colsum)
+        return fail(CVP_E_INVALID, "work vectors alias inputs");
+    hipStream_t sm = (hipStream_t)stream;
+    const bool ex = o->variant == CVP_EXACT, ec = o->elevation_correction != 0;
+    const int64_t nm = (int64_t)G.N * G.M;
+    hipError_t e = hipSuccess;
+    for (int it = 0; it < n_sweeps && e == hipSuccess; ++it) {
+        for (int t = 0; t < n_subsets && e == hipSuccess; ++t) {
+            cvp::DevGeom Gt = G;
+            int64_t off = 0;
+            const int cnt = subset_count(V, n_subsets, t);
+            view_subset(g, t, n_subsets, cnt, Gt, off);
+            cvp::ProjLaunch pl{};
+            cvp::plan_projection(G.N, G.n2, G.M, cnt, g->pmax, g->pl.U, pl);
+            // q_t = A_t x (z is free: it holds the per-group maxima)
+            e = cvp::launch_project(Gt, pl, ex, ec, d_x, d_q + off, (unsigned *)d_z, sm);
+            if (e == hipSuccess)
+                e = cvp::sart_residual_views(d_q + off, d_b + off, d_rowsum + off, nm, cnt, nm * n_subsets, sm);
+            if (e == hipSuccess) e = cvp::launch_backproject(Gt, g->bl, ex, ec, d_q + off, d_z, sm);
+            if (e == hipSuccess)
+                e = cvp::sart_update_x(d_x, d_z, d_colsum + (size_t)t * g->nvox, g->nvox, lambda, nonneg != 0, sm);
+        }
+    }
+    if (e != hipSuccess) return device_fail(e, "sart iterate");
+    return ok();
+}
+
+// ------------------------------------------------------------------ LSQR
+
+cvp_status cvp_lsqr_workspace_size(int64_t n_voxels, int64_t n_pixels_total, int64_t *bytes)
+{
+    if (!bytes) return fail(CVP_E_INVALID, "bytes is NULL");
+    if (n_voxels < 0 || n_pixels_total < 0) return fail(CVP_E_INVALID, "negative size");
+    *bytes = cvp::kLsqrWorkDoubles * (int64_t)sizeof(double);
+    return ok();
+}
+
+static cvp_status lsqr_args(const cvp_geometry *g, const cvp_options *o, const void *x, const void *u,
+                            const void *v, const void *w, const void *q, const void *s, const void *work,
+                            cvp::DevGeom &G)
+{
+    const void *ptrs[7] = {x, u, v, w, q, s, work};
+    const char *names[7] = {"x", "u", "v", "w", "q", "s", "work"};
+    for (int a = 0; a < 7; ++a)
+        if (!ptrs[a]) return fail(CVP_E_INVALID, "%s is NULL", names[a]);
+    for (int a = 0; a < 7; ++a)
+        for (int b = a + 1; b < 7; ++b)
+            if (ptrs[a] == ptrs[b]) return fail(CVP_E_INVALID, "%s and %s alias", names[a], names[b]);
+    if (reinterpret_cast<uintptr_t>(work) & 7) return fail(CVP_E_INVALID, "work must be 8-byte aligned");
+    return prepare(g, o, x, const_cast<void *>(u), G);
+}
+
+cvp_status cvp_lsqr_start(const cvp_geometry *g, const cvp_options *o, const float *d_b, float *d_x, float *d_u,
+                          float *d_v, float *d_w, float *d_q, float *d_s, void *d_work, void *stream)
+{
+    cvp::DevGeom G;
+    if (!d_b) return fail(CVP_E_INVALID, "b is NULL");
+    cvp_status st = lsqr_args(g, o, d_x, d_u, d_v, d_w, d_q, d_s, d_work, G);
+    if (st != CVP_OK) return st;
+    hipStream_t sm = (hipStream_t)stream;
+    double *sc = (double *)d_work;
+    const bool ex = o->variant == CVP_EXACT, ec = o->elevation_correction != 0;
+    // beta u = b - A x;  alpha v = A^T u;  w = v
+    hipError_t e = cvp::launch_project(G, g->pl, ex, ec, d_x, d_q, (unsigned *)d_s, sm);
+    if (e == hipSuccess) e = cvp::blas_residual(d_u, d_b, d_q, g->npix, sm);
+    if (e == hipSuccess) e = cvp::lsqr_norm(d_u, g->npix, sc, cvp::kLsqrFinBeta0, sm);
+    if (e == hipSuccess) e = cvp::lsqr_scale(d_u, g->npix, sc, cvp::kLsqrBeta, sm);
+    if (e == hipSuccess) e = cvp::launch_backproject(G, g->bl, ex, ec, d_u, d_v, sm);
+    if (e == hipSuccess) e = cvp::lsqr_norm(d_v, g->nvox, sc, cvp::kLsqrFinAlpha0, sm);
+    if (e == hipSuccess) e = cvp::lsqr_update_vxw(d_v, d_x, d_w, g->nvox, sc, 1, sm);
+    if (e != hipSuccess) return device_fail(e, "lsqr start");
+    return ok();
+}
+
+cvp_status cvp_lsqr_iterate(const cvp_geometry *g, const cvp_options *o, int32_t n_iter, float *d_x, float *d_u,
+                            float *d_v, float *d_w, float *d_q, float *d_s, void *d_work, void *stream)
+{
+    cvp::DevGeom G;
+    if (n_iter < 0) return fail(CVP_E_INVALID, "n_iter = %d", n_iter);
+    cvp_status st = lsqr_args(g, o, d_x, d_u, d_v, d_w, d_q, d_s, d_work, G);
+    if (st != CVP_OK) return st;
+    hipStream_t sm = (hipStream_t)stream;
+    double *sc = (double *)d_work;
+    const bool ex = o->variant == CVP_EXACT, ec = o->elevation_correction != 0;
+    hipError_t e = hipSuccess;
+    for (int it = 0; it < n_iter && e == hipSuccess; ++it) {
+        e = cvp::launch_project(G, g->pl, ex, ec, d_v, d_q, (unsigned *)d_s, sm);                 // q = A v
+        if (e == hipSuccess) e = cvp::lsqr_axpby_norm(d_u, d_q, g->npix, sc, cvp::kLsqrAlpha, cvp::kLsqrFinBeta, sm);
+        if (e == hipSuccess) e = cvp::lsqr_scale(d_u, g->npix, sc, cvp::kLsqrBeta, sm);           // u /= beta
+        if (e == hipSuccess) e = cvp::launch_backproject(G, g->bl, ex, ec, d_u, d_s, sm);          // s = A^T u
+        if (e == hipSuccess) e = cvp::lsqr_axpby_norm(d_v, d_s, g->nvox, sc, cvp::kLsqrBeta, cvp::kLsqrFinAlpha, sm);
+        if (e == hipSuccess) e = cvp::lsqr_update_vxw(d_v, d_x, d_w, g->nvox, sc, 0, sm);       // v, x, w
+    }
+    if (e != hipSuccess) return device_fail(e, "lsqr iterate");
     return ok();
 }
 

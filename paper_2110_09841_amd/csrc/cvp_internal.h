@@ -20,6 +20,7 @@ constexpr int back_rec_floats(int gw, int pmax) { return gw * pmax * kRecFloats 
 constexpr int back_views_per_pass(int gw, int pmax) { return 64 / (gw * (pmax < 64 / gw ? pmax : 64 / gw)); }
 constexpr float kYQuantumInv = 1024.0f;
 constexpr int kBackPasses = 2;        // most 64-voxel passes per backprojection stack
+constexpr int kPmaxWide = 64;         // pieces per column of the wide-footprint backprojection
 
 // Per-view source-centred frame (Sec. II-C), FP64.  e1 and d have no x3
 // component on a circular orbit (that is what makes chi1 independent of x3,
@@ -40,7 +41,9 @@ struct DevGeom {
     double x1lo, x2lo, x3lo;   // lower corner of the volume box
     double b1, b2, c1, c2, f;
     double fb1, fb2, b2f;      // f / b1, f / b2, b2 / f
-    const ViewGeom *views;     // device, [nviews]
+    const ViewGeom *views;     // device; view q of a launch is views[q * vstride]
+    int vstride;               // view stride: a launch may cover views v0, v0 + vstride, ... (views and
+                               // the projection pointer start at v0; 1 for all views)
     const float *sigma;        // device, [N][M] pixel factors (nullptr: 1)
     int raw_volume;            // weight = cut volume (no 1/r^2)
     // Bounds on any pixel's weight sum per unit |mu| (with and without the
@@ -54,7 +57,7 @@ struct ProjLaunch {
     int nbands;
     int items;       // nbands * nviews
     int chunk;       // work-item slots per XCD (grid = 8 * chunk)
-    int pmax;        // 4 or 8
+    int pmax;        // 4 or 8 (8 with U <= 8 for wider footprints)
     size_t lds;      // dynamic LDS bytes
 };
 
@@ -65,7 +68,7 @@ struct BackLaunch {
     int nkchunks;    // ceil(n3 / (64 * kp))
     int items;
     int chunk;
-    int pmax;
+    int pmax;        // 4, 8 or kPmaxWide (then gw = 4)
     int win_cap;     // floats per wave window
     size_t lds;
 };
@@ -116,6 +119,23 @@ constexpr int kCglsHistory = 4096;
 constexpr int kCglsPartials = 1024;
 constexpr int64_t kCglsWorkDoubles = kCglsScalars + 2 * kCglsHistory + kCglsPartials;
 
+// LSQR workspace (FP64): scalars, then the |r| and |A^T r| estimate
+// histories, then the reduction partials.
+enum : int {
+    kLsqrAlpha = 0, kLsqrBeta = 1, kLsqrRhobar = 2, kLsqrPhibar = 3, kLsqrXStep = 4, kLsqrWStep = 5,
+    kLsqrK = 6, kLsqrBreak = 7, kLsqrArnorm0 = 8, kLsqrScalars = 16
+};
+enum : int { kLsqrFinBeta0 = 0, kLsqrFinAlpha0 = 1, kLsqrFinBeta = 2, kLsqrFinAlpha = 3 };
+constexpr int64_t kLsqrWorkDoubles = kLsqrScalars + 2 * kCglsHistory + kCglsPartials;
+
+hipError_t blas_fill(float *p, int64_t n, float val, hipStream_t s);
+hipError_t sart_residual_views(float *q, const float *b, const float *R, int64_t nm, int count, int64_t view_step,
+                               hipStream_t s);
+hipError_t sart_update_x(float *x, const float *z, const float *C, int64_t n, float lam, int nonneg, hipStream_t s);
+hipError_t lsqr_axpby_norm(float *y, const float *x, int64_t n, double *sc, int ci, int mode, hipStream_t s);
+hipError_t lsqr_norm(const float *a, int64_t n, double *sc, int mode, hipStream_t s);
+hipError_t lsqr_scale(float *y, int64_t n, const double *sc, int ci, hipStream_t s);
+hipError_t lsqr_update_vxw(float *v, float *x, float *w, int64_t n, const double *sc, int init, hipStream_t s);
 hipError_t blas_dot(const float *a, const float *b, int64_t n, double *partials, double *sc,
                     int mode, double *out, hipStream_t s);
 hipError_t blas_update_xr(float *x, const float *p, int64_t nv, float *r, const float *q, int64_t np,
@@ -130,6 +150,8 @@ hipError_t launch_project(const DevGeom &g, const ProjLaunch &L, bool exact, boo
                           const float *vol, float *proj, unsigned *gmax, hipStream_t stream);
 int64_t group_max_cells(const DevGeom &g);
 hipError_t launch_group_max(const DevGeom &g, const float *vol, unsigned *gmax, hipStream_t stream);
+// SiddonK reference projector: K x K rays per pixel, exact chord lengths.
+hipError_t launch_siddon(const DevGeom &g, int K, const float *vol, float *proj, hipStream_t s);
 hipError_t launch_backproject(const DevGeom &g, const BackLaunch &L, bool exact, bool ec,
                               const float *proj, float *vol, hipStream_t stream);
 

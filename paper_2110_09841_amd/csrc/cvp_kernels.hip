@@ -215,24 +215,37 @@ __device__ __forceinline__ void piece_record(const DevGeom &G, const ViewGeom &V
 
 // ------------------------------------------------------------ FP32 voxel stage
 
-// C(t): the part of the voxel's chi2 extent [Ytop, Ytop + beta] that lies
-// beyond row boundary t, s1 = Ytop - t.  With the elevation correction the
-// boundary position is averaged over the depth box, i.e. s moves uniformly
-// over [s - e, s + e] with e = |t - c2| h / D (Sec. III-B reading); the box
-// average of max(s, 0) is max(s, 0) + max(e - |s|, 0)^2 / (4e), so
-// C = [max(s0,0) - max(s1,0)] + (phi0^2 - phi1^2) / (4e).
+// Row weights.  The voxel's chi2 extent is [Ytop, Ybot] (Ybot = Ytop + beta)
+// and row v covers [t, t + 1], t = v - 1/2.  With s1 = Ytop - t and
+// s0 = Ybot - t the plain x3 share of the row is the overlap
+//   m(t) = med3(s0, 0, 1) - med3(s1, 0, 1)
+// (Sec. III-A).  With the elevation correction each row boundary moves
+// uniformly over [t - e, t + e], e = |t - c2| h / D (Sec. III-B reading); the
+// box average of max(s, 0) is max(s, 0) + max(e - |s|, 0)^2 / (4e), so the
+// row gets m(t) + Phi(t) - Phi(t + 1) with
+//   Phi(t) = (p0^2 - p1^2) / (4e),  p = max(e - |s|, 0)
+// at each boundary.  Every term is a small number computed from the face
+// offsets near that face: s1 = d + Yl and s0 = d0 + Ybl with d = Ytop_hi - t
+// and d0 = Ybot_hi - t exact (high parts on a 2^-10 grid) and Yl, Ybl the low
+// parts, so a thin sliver at either face keeps its relative precision however
+// many rows tall the voxel is, and a row the box average does not reach gets
+// exactly 0 (m = 0 and Phi = 0 at both its boundaries).
 // rho4 = 4 rho; 1/(4e) is taken of 4e + 1e-30, which only differs from 4e
 // where e = 0, and there p0 = p1 = 0.
 template <bool EC>
-__device__ __forceinline__ float cum(float s1, float beta, float tc, float rho, float rho4)
+__device__ __forceinline__ void boundary(float d, float Yl, float d0, float Ybl, float tc, float rho, float rho4,
+                                         float &s1, float &m, float &phi)
 {
-    const float s0 = s1 + beta;
-    const float plain = __builtin_amdgcn_fmed3f(s0, 0.0f, beta);   // = max(s0,0) - max(s1,0)
-    if (!EC) return plain;
-    const float p0 = fmaxf(fmaf(fabsf(tc), rho, -fabsf(s0)), 0.0f);
-    const float p1 = fmaxf(fmaf(fabsf(tc), rho, -fabsf(s1)), 0.0f);
-    const float inv4e = __builtin_amdgcn_rcpf(fmaf(fabsf(tc), rho4, 1e-30f));
-    return fmaf(fmaf(p0, p0, -(p1 * p1)), inv4e, plain);
+    s1 = d + Yl;
+    const float s0 = d0 + Ybl;
+    m = __builtin_amdgcn_fmed3f(s0, 0.0f, 1.0f) - __builtin_amdgcn_fmed3f(s1, 0.0f, 1.0f);
+    phi = 0.0f;
+    if (EC) {
+        const float p0 = fmaxf(fmaf(fabsf(tc), rho, -fabsf(s0)), 0.0f);
+        const float p1 = fmaxf(fmaf(fabsf(tc), rho, -fabsf(s1)), 0.0f);
+        const float inv4e = __builtin_amdgcn_rcpf(fmaf(fabsf(tc), rho4, 1e-30f));
+        phi = fmaf(p0, p0, -(p1 * p1)) * inv4e;
+    }
 }
 
 // Fixed-point accumulation of the projection.  A contribution w, already
@@ -309,26 +322,28 @@ __device__ __forceinline__ void row_range(float Ytop, float beta, float mfac, fl
 
 // Row weights of one voxel piece: rows [vlo, vhi] (already clipped) of the
 // unclipped range [vlo0, vhi0], added to the band column bcol.  The unclipped
-// range includes the EC margin, so at its first boundary C is exactly beta
-// and at its last exactly 0 (the box average is zero there); those two
-// evaluations are skipped unless clipping moved the boundary.  Boundaries
-// t = vlo - 1/2, vlo + 1/2, ...: d = Yh - t is exact (Yh on a 2^-10 grid) and
-// steps by 1 exactly; tc = t - c2 feeds only the box width.
+// range includes the EC margin, so Phi is exactly 0 at its first and last
+// boundaries; those two box averages are skipped unless clipping moved the
+// boundary.  Boundaries t = vlo - 1/2, vlo + 1/2, ...: d, d0 step by exactly
+// 1; tc = t - c2 feeds only the box width.  Weight of row [t, t + 1]:
+// coef (m(t) + Phi(t) - Phi(t + 1)).
 template <bool EC, bool EXACT>
-__device__ __forceinline__ void sweep_rows(int vlo0, int vhi0, int vlo, int vhi, float Yh, float Yl, float beta,
-                                           float rho, float c2f, float coef, bool raw, float zt, float r8,
-                                           float r9, unsigned long long *bcol)
+__device__ __forceinline__ void sweep_rows(int vlo0, int vhi0, int vlo, int vhi, float Yh, float Yl, float Ybh,
+                                           float Ybl, float beta, float rho, float c2f, float coef, bool raw,
+                                           float zt, float r8, float r9, unsigned long long *bcol)
 {
-    const bool ends = !EC || rho < 0.9f;         // the margin guarantees the end values
+    const bool ends = !EC || rho < 0.9f;         // the margin guarantees Phi = 0 at the ends
     const float rho4 = 4.0f * rho;
     const float tb = (float)vlo - 0.5f;
     float d = Yh - tb;
+    float d0 = Ybh - tb;
     float tc = tb - c2f;
-    float s1p = d + Yl;
-    float Cp = beta;
-    if (vlo != vlo0 || !ends) Cp = cum<EC>(s1p, beta, tc, rho, rho4);
-    auto weight = [&](float s1n, float Cn) {
-        float w = coef * (Cp - Cn);
+    float s1p, mp, phip;
+    if (vlo != vlo0 || !ends) boundary<EC>(d, Yl, d0, Ybl, tc, rho, rho4, s1p, mp, phip);
+    else boundary<false>(d, Yl, d0, Ybl, tc, rho, rho4, s1p, mp, phip);
+    float psip = mp + phip;                      // m(t) + Phi(t) of the row's top boundary
+    auto weight = [&](float s1n, float phin) {
+        float w = coef * (psip - phin);
         if (EXACT && !raw) {
             float mm = 0.5f * (fmaxf(0.0f, -s1p) + fminf(beta, -s1n));
             mm = fminf(fmaxf(mm, 0.0f), beta);
@@ -340,20 +355,24 @@ __device__ __forceinline__ void sweep_rows(int vlo0, int vhi0, int vlo, int vhi,
     unsigned long long *const last = bcol + vhi;
     for (unsigned long long *q = bcol + vlo; q < last; ++q) {
         d -= 1.0f;
+        d0 -= 1.0f;
         tc += 1.0f;
-        const float s1n = d + Yl;
-        const float Cn = cum<EC>(s1n, beta, tc, rho, rho4);
-        lds_add_fixed(q, weight(s1n, Cn));
-        Cp = Cn;
+        float s1n, mn, phin;
+        boundary<EC>(d, Yl, d0, Ybl, tc, rho, rho4, s1n, mn, phin);
+        lds_add_fixed(q, weight(s1n, phin));
+        psip = mn + phin;
         s1p = s1n;
     }
     if (vlo <= vhi) {
         d -= 1.0f;
+        d0 -= 1.0f;
         tc += 1.0f;
-        const float s1n = d + Yl;
-        float Cn = 0.0f;
-        if (vhi != vhi0 || !ends) Cn = cum<EC>(s1n, beta, tc, rho, rho4);
-        lds_add_fixed(last, weight(s1n, Cn));
+        float s1n = d + Yl, phin = 0.0f;
+        if (vhi != vhi0 || !ends) {
+            float mn;
+            boundary<EC>(d, Yl, d0, Ybl, tc, rho, rho4, s1n, mn, phin);
+        }
+        lds_add_fixed(last, weight(s1n, phin));
     }
 }
 
@@ -445,7 +464,7 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
 
     for (int idx = tid; idx < U * Npad; idx += kBlock) bins[idx] = 0ull;
 
-    const ViewGeom V = G.views[view];
+    const ViewGeom V = G.views[(size_t)view * G.vstride];
 
     // Column groups of each row j meeting the band's wedge: the chi1 range of
     // a group's base rectangle (extremes at its corners) must meet
@@ -653,8 +672,9 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
                     unsigned long long *bcol = bins + (u - u0) * Npad;
                     int vlo0, vhi0;
                     row_range_unclipped<EC>(Yh + Yl, beta, r[10], c2f, vlo0, vhi0);
-                    sweep_rows<EC, EXACT>(vlo0, vhi0, max(vlo0, 0), min(vhi0, G.N - 1), Yh, Yl, beta, rho, c2f,
-                                          coef, raw, zt, r[8], r[9], bcol);
+                    // bottom face Y(k - 1): high part Yh + bh (exact on the 2^-10 grid), low part Yl + bl
+                    sweep_rows<EC, EXACT>(vlo0, vhi0, max(vlo0, 0), min(vhi0, G.N - 1), Yh, Yl, Yh + r[4],
+                                          Yl + r[5], beta, rho, c2f, coef, raw, zt, r[8], r[9], bcol);
                 }
             }
         }
@@ -669,7 +689,7 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
         const int u = u0 + du;
         float s = finite ? (float)ldexp(fixed_to_double(bins[du * Npad + v]), -sc) : __builtin_nanf("");
         if (G.sigma) s *= G.sigma[(size_t)v * G.M + u];
-        proj[((size_t)view * G.N + v) * G.M + u] = s;
+        proj[((size_t)view * G.vstride * G.N + v) * G.M + u] = s;
     }
 }
 
@@ -782,7 +802,7 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
             const int view = vb + r * kWaves;
             float *rv = rec + r * recView;
             if (view < G.nviews)
-                build_records<EXACT, EC, PMAX, GW, LPV>(G, G.views[view], i0, j, 0, G.M - 1, rv,
+                build_records<EXACT, EC, PMAX, GW, LPV>(G, G.views[(size_t)view * G.vstride], i0, j, 0, G.M - 1, rv,
                                                         reinterpret_cast<int *>(rv + GW * PMAX * kRecFloats),
                                                         lane % LPV, lane);
         }
@@ -836,7 +856,7 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
         for (int r = 0; r < RV; ++r) {
         const int view = vb + r * kWaves;
         if (view >= G.nviews) break;
-        const ViewGeom V = G.views[view];
+        const ViewGeom V = G.views[(size_t)view * G.vstride];
         const float *recv = rec + r * recView;
         const int *npc = reinterpret_cast<const int *>(recv + GW * PMAX * kRecFloats);
         int wu0 = wb0[0], wu1 = wb0[1], wv0 = wb0[2], wv1 = wb0[3];
@@ -850,7 +870,7 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
         const int Wd = wu1 - wu0 + 1;
         const int H = wv1 - wv0 + 1;
         const int Hp = H | 1;
-        const float *pv = proj + (size_t)view * G.N * G.M;
+        const float *pv = proj + (size_t)view * G.vstride * G.N * G.M;
 
         const bool useWin = Wd * Hp <= winCap;
         if (useWin) {
@@ -890,30 +910,34 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
                 const int u = __float_as_int(r0.x);
                 const float Yh = fmaf(-kf, r1.x, r0.z);
                 const float Yl = fmaf(-kf, r1.y, r0.w);
+                const float Ybh = Yh + r1.x, Ybl = Yl + r1.y;   // bottom face Y(k - 1), exact high part
                 const float beta = r1.z, rho = r1.w, rho4 = 4.0f * r1.w;
                 // rows clipped to the detector and the window; as in the
-                // projection, C at the first boundary of the unclipped range
-                // is exactly beta
+                // projection, Phi at the first and last boundaries of the
+                // unclipped range is exactly 0
                 int vlo0, vhi0;
                 row_range_unclipped<EC>(Yh + Yl, beta, r2.z, c2f, vlo0, vhi0);
                 const bool ends = !EC || rho < 0.9f;
                 const int vlo = max(max(vlo0, 0), wv0);
                 const int vhi = kv ? min(min(vhi0, G.N - 1), wv1) : vlo - 1;
                 const float *wcol = win + (u - wu0) * Hp - wv0;
-                // boundaries as in sweep_rows: d = Yh - t exact, tc = t - c2
+                // boundaries as in sweep_rows; row weight m(t) + Phi(t) - Phi(t + 1)
                 const float tb = (float)vlo - 0.5f;
                 float d = Yh - tb;
+                float d0 = Ybh - tb;
                 float tc = tb - c2f;
-                float s1p = d + Yl;
-                float Cp = beta;
-                if (vlo != vlo0 || !ends) Cp = cum<EC>(s1p, beta, tc, rho, rho4);
-                float ap = 0.0f;          // sum of (C_v - C_v+1) [1/r^2] val_v; times coef below
+                float s1p, mp, phip;
+                if (vlo != vlo0 || !ends) boundary<EC>(d, Yl, d0, Ybl, tc, rho, rho4, s1p, mp, phip);
+                else boundary<false>(d, Yl, d0, Ybl, tc, rho, rho4, s1p, mp, phip);
+                float psip = mp + phip;
+                float ap = 0.0f;          // sum of row weight [1/r^2] val_v; times coef below
                 auto row = [&](float val) {
                     d -= 1.0f;
+                    d0 -= 1.0f;
                     tc += 1.0f;
-                    const float s1n = d + Yl;
-                    const float Cn = cum<EC>(s1n, beta, tc, rho, rho4);
-                    float w = Cp - Cn;
+                    float s1n, mn, phin;
+                    boundary<EC>(d, Yl, d0, Ybl, tc, rho, rho4, s1n, mn, phin);
+                    float w = psip - phin;
                     if (EXACT && !raw) {
                         float mm = 0.5f * (fmaxf(0.0f, -s1p) + fminf(beta, -s1n));
                         mm = fminf(fmaxf(mm, 0.0f), beta);
@@ -921,21 +945,24 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
                         w *= __builtin_amdgcn_rcpf(fmaf(zb, zb, r2.x));
                     }
                     ap = fmaf(w, val, ap);
-                    Cp = Cn;
+                    psip = mn + phin;
                     s1p = s1n;
                 };
                 if (WIN) {
                     const float *const last = wcol + vhi;
                     for (const float *q = wcol + vlo; q < last; ++q) row(*q);
                     if (vlo <= vhi) {
-                        // last row: C at the last boundary of the unclipped
-                        // range is exactly 0
+                        // last row: Phi at the last boundary of the
+                        // unclipped range is exactly 0
                         d -= 1.0f;
+                        d0 -= 1.0f;
                         tc += 1.0f;
-                        const float s1n = d + Yl;
-                        float Cn = 0.0f;
-                        if (vhi != vhi0 || !ends) Cn = cum<EC>(s1n, beta, tc, rho, rho4);
-                        float w = Cp - Cn;
+                        float s1n = d + Yl, phin = 0.0f;
+                        if (vhi != vhi0 || !ends) {
+                            float mn;
+                            boundary<EC>(d, Yl, d0, Ybl, tc, rho, rho4, s1n, mn, phin);
+                        }
+                        float w = psip - phin;
                         if (EXACT && !raw) {
                             float mm = 0.5f * (fmaxf(0.0f, -s1p) + fminf(beta, -s1n));
                             mm = fminf(fmaxf(mm, 0.0f), beta);
@@ -1122,7 +1149,12 @@ hipError_t launch_bp(const DevGeom &g, const BackLaunch &L, const float *proj, f
                      hipStream_t s)
 {
     if (L.pmax <= 4) return launch_bp_gw<EXACT, EC, 4>(g, L, proj, vol, s);
-    return launch_bp_gw<EXACT, EC, 8>(g, L, proj, vol, s);
+    if (L.pmax <= 8) return launch_bp_gw<EXACT, EC, 8>(g, L, proj, vol, s);
+    // wide footprints: 4-column stacks only
+    if (L.gw != 4) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((backproject_kernel<EXACT, EC, kPmaxWide, 4>), dim3(8 * L.chunk), dim3(kBlock), L.lds, s, g,
+                       L.ngroups, L.nkchunks, L.kp, L.items, L.chunk, L.win_cap, proj, vol);
+    return hipGetLastError();
 }
 
 template <bool EXACT, bool EC, int PMAX>
@@ -1140,6 +1172,13 @@ hipError_t set_lds_one(size_t n)
         e = hipFuncSetAttribute((const void *)backproject_kernel<EXACT, EC, PMAX, 4>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
     return e;
+}
+
+template <bool EXACT, bool EC>
+hipError_t set_lds_wide(size_t n)
+{
+    return hipFuncSetAttribute((const void *)backproject_kernel<EXACT, EC, kPmaxWide, 4>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
 }
 
 template <bool EXACT, bool EC>
@@ -1215,6 +1254,10 @@ hipError_t configure_kernel_lds(size_t max_lds, size_t max_lds_batched)
     if (e == hipSuccess) e = set_lds_one<true, false, 8>(max_lds);
     if (e == hipSuccess) e = set_lds_one<false, true, 8>(max_lds);
     if (e == hipSuccess) e = set_lds_one<false, false, 8>(max_lds);
+    if (e == hipSuccess) e = set_lds_wide<true, true>(max_lds);
+    if (e == hipSuccess) e = set_lds_wide<true, false>(max_lds);
+    if (e == hipSuccess) e = set_lds_wide<false, true>(max_lds);
+    if (e == hipSuccess) e = set_lds_wide<false, false>(max_lds);
     if (e == hipSuccess) e = set_lds_batched<true, true>(max_lds_batched);
     if (e == hipSuccess) e = set_lds_batched<true, false>(max_lds_batched);
     if (e == hipSuccess) e = set_lds_batched<false, true>(max_lds_batched);

@@ -111,6 +111,18 @@ def project(x, geom: Geometry, opts: Options = Options(), out=None):
     return out
 
 
+def project_siddon(x, geom: Geometry, K: int, out=None):
+    """Reference ray-driven projection SiddonK: the mean line integral over
+    K x K rays per pixel (cvp_project_siddon)."""
+    _check_tensor(x, geom.vol_shape, "x")
+    if out is None:
+        out = torch.empty(geom.proj_shape, dtype=torch.float32, device=x.device)
+    _check_tensor(out, geom.proj_shape, "out")
+    _lib.check(_lib.lib().cvp_project_siddon(geom.handle, int(K), ctypes.c_void_p(x.data_ptr()),
+                                             ctypes.c_void_p(out.data_ptr()), _stream()))
+    return out
+
+
 def backproject(b, geom: Geometry, opts: Options = Options(), out=None):
     """x = A^T b (overwrites ``out`` if given)."""
     _check_tensor(b, geom.proj_shape, "b")

@@ -57,7 +57,7 @@ def _create(mutate):
     ("n_views", lambda d: setattr(d, "n_views", 0), _lib.CVP_E_INVALID),
     ("angles_rad", lambda d: setattr(d, "angles_rad", None), _lib.CVP_E_INVALID),
     ("principal_px", lambda d: d.principal_px.__setitem__(0, math.inf), _lib.CVP_E_INVALID),
-    ("columns", lambda d: d.pitch_mm.__setitem__(0, 0.05), _lib.CVP_E_UNSUPPORTED),
+    ("columns", lambda d: d.pitch_mm.__setitem__(0, 0.02), _lib.CVP_E_UNSUPPORTED),   # ~120 columns per voxel
 ])
 def test_invalid_geometry_rejected(field, mutate, expect):
     st, msg = _create(mutate)

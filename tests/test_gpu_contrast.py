@@ -114,10 +114,26 @@ def test_signed_data_both_directions(gname, gfun, variant):
     opts = cvp.Options(variant=variant, ec=True)
     o = O.Options(exact=variant == "exact", ec=True)
     say("signed", gname, variant)
-    check(cvp.project(torch.from_numpy(x).cuda(), G, opts).cpu().numpy(), O.project(g, o, x), 1,
-          "%s %s signed A x" % (gname, variant))
-    check(cvp.backproject(torch.from_numpy(b).cuda(), G, opts).cpu().numpy(), O.backproject(g, o, b), 2,
-          "%s %s signed A^T b" % (gname, variant))
+    got_p = cvp.project(torch.from_numpy(x).cuda(), G, opts).cpu().numpy()
+    got_b = cvp.backproject(torch.from_numpy(b).cuda(), G, opts).cpu().numpy()
+    ref_p, ref_b = O.project(g, o, x), O.backproject(g, o, b)
+    # Signed sums cancel: an element near zero carries the FP32 rounding of
+    # terms far larger than itself.  Its error is therefore measured against
+    # the sum of the absolute contributions (the oracle applied to |x| or
+    # |b|), the scale of any floating-point sum, floored like the parity
+    # metric at 1e-3 of the largest such sum; for data of one sign this is the
+    # parity metric itself.
+    abs_p, abs_b = O.project(g, o, np.abs(x)), O.backproject(g, o, np.abs(b))
+    for got, ref, mag, what in ((got_p, ref_p, abs_p, "A x"), (got_b, ref_b, abs_b, "A^T b")):
+        e2 = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        sel = mag > 0
+        den = np.maximum(mag, FLOOR * mag.max())
+        em = float(np.max(np.abs(got - ref)[sel] / den[sel]))
+        assert np.all(got[~sel] == 0.0)
+        say("%s %s signed %s: rel L2 %.3e, max |err| / floored sum |contributions| %.3e" % (gname, variant, what, e2,
+                                                                                        em))
+        assert e2 <= REL_L2, (what, e2, em)
+        assert em <= MAX_REL, (what, e2, em)
 
 
 @pytest.mark.parametrize("variant", ["exact", "relaxed"])
