@@ -141,6 +141,23 @@ cvp_status cvp_project_ws(const cvp_geometry *g, const cvp_options *opts,
                           void *hip_stream);
 
 /*
+ * cvp_project_ws for callers that cannot allocate (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the per-group
+ * maxima live in a fixed device array of the library, CVP_NOALLOC_MAX_GROUPS
+ * 32-bit words (1 MiB) per GPU, held until the process ends.  The geometry
+ * needs n2 * ceil(n1 / 16) <= CVP_NOALLOC_MAX_GROUPS (else CVP_E_UNSUPPORTED,
+ * nothing enqueued).  The call allocates nothing; the first call on a device
+ * looks up the array's address there.  Results equal cvp_project_ws's (and
+ * cvp_project's) bitwise.  All calls on one GPU share the array: calls that
+ * overlap in time on one device (different streams, threads) race and may
+ * give wrong results; serialise them, or use cvp_project_ws with distinct
+ * work buffers.
+ */
+#define CVP_NOALLOC_MAX_GROUPS 262144
+cvp_status cvp_project_noalloc(const cvp_geometry *g, const cvp_options *opts,
+                               const float *d_vol, float *d_proj, void *hip_stream);
+
+/*
  * Reference ray-driven projector SiddonK (Sec. II-D): every pixel of every
  * view gets the mean, over K x K rays from the source to the centres of a
  * K x K grid of equal cells on the pixel, of the line integral of the volume,

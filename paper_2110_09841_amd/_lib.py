@@ -92,6 +92,7 @@ def _register_extra(L):
                                      + [vp], st),
         "cvp_project_workspace_size": ([vp, ctypes.POINTER(ctypes.c_int64)], st),
         "cvp_project_ws": ([vp, ctypes.POINTER(OptionsC), vp, vp, vp, ctypes.c_int64, vp], st),
+        "cvp_project_noalloc": ([vp, ctypes.POINTER(OptionsC), vp, vp, vp], st),
         "cvp_project_siddon": ([vp, ctypes.c_int32, vp, vp, vp], st),
         "cvp_project_views": ([vp, ctypes.POINTER(OptionsC), vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                vp, ctypes.c_int64, vp], st),

@@ -459,6 +459,26 @@ cvp_status cvp_project_ws(const cvp_geometry *g, const cvp_options *o, const flo
     return ok();
 }
 
+cvp_status cvp_project_noalloc(const cvp_geometry *g, const cvp_options *o, const float *d_vol, float *d_proj,
+                               void *stream)
+{
+    cvp::DevGeom G;
+    cvp_status st = prepare(g, o, d_vol, d_proj, G);
+    if (st != CVP_OK) return st;
+    const int64_t need = cvp::group_max_cells(g->base);
+    if (need > cvp::kStaticScratchWords)
+        return fail(CVP_E_UNSUPPORTED,
+                    "n2 * ceil(n1 / 16) = %lld exceeds the fixed scratch of %lld words (CVP_NOALLOC_MAX_GROUPS)",
+                    (long long)need, (long long)cvp::kStaticScratchWords);
+    unsigned *work = nullptr;
+    hipError_t e = cvp::static_scratch(&work);
+    if (e != hipSuccess) return device_fail(e, "scratch symbol address");
+    e = cvp::launch_project(G, g->pl, o->variant == CVP_EXACT, o->elevation_correction != 0, d_vol, d_proj, work,
+                            (hipStream_t)stream);
+    if (e != hipSuccess) return device_fail(e, "projection launch");
+    return ok();
+}
+
 cvp_status cvp_project_siddon(const cvp_geometry *g, int32_t K, const float *d_vol, float *d_proj, void *stream)
 {
     if (K < 1 || K > 1024) return fail(CVP_E_INVALID, "K = %d (must be 1..1024)", K);

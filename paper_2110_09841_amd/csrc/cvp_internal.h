@@ -150,6 +150,11 @@ hipError_t launch_project(const DevGeom &g, const ProjLaunch &L, bool exact, boo
                           const float *vol, float *proj, unsigned *gmax, hipStream_t stream);
 int64_t group_max_cells(const DevGeom &g);
 hipError_t launch_group_max(const DevGeom &g, const float *vol, unsigned *gmax, hipStream_t stream);
+// Allocation-free projection: device address (on the current device) of the
+// library's fixed scratch array for the per-group maxima, looked up once per
+// device; kStaticScratchWords words (1 MiB).
+constexpr int64_t kStaticScratchWords = int64_t(1) << 18;
+hipError_t static_scratch(unsigned **out);
 // SiddonK reference projector: K x K rays per pixel, exact chord lengths.
 hipError_t launch_siddon(const DevGeom &g, int K, const float *vol, float *proj, hipStream_t s);
 hipError_t launch_backproject(const DevGeom &g, const BackLaunch &L, bool exact, bool ec,

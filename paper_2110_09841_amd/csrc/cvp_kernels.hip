@@ -32,6 +32,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <type_traits>
 
 #include "cvp_internal.h"
@@ -1285,6 +1286,38 @@ hipError_t launch_group_max(const DevGeom &g, const float *vol, unsigned *gmax, 
     hipLaunchKernelGGL(group_max_kernel, dim3((unsigned)((cells + kWaves - 1) / kWaves)), dim3(kBlock), 0, stream,
                        g, vol, gmax);
     return hipGetLastError();
+}
+
+// Fixed device scratch of the allocation-free projection: the per-group
+// maxima table of group_max_kernel, at most kStaticScratchWords words.  Every
+// GPU the library runs on holds its own copy until the process ends; host
+// code never passes the array's name to a kernel (on the host it is only a
+// stand-in for the symbol) but the device address that hipGetSymbolAddress
+// returns for the current device.
+static __device__ __align__(256) unsigned scratch[kStaticScratchWords];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch(unsigned **out)
+{
+    *out = nullptr;
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<unsigned *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_backproject(const DevGeom &g, const BackLaunch &L, bool exact, bool ec,

@@ -73,6 +73,7 @@ def test_null_arguments():
     o = _lib.OptionsC(0, 1, 0, 0)
     assert L.cvp_project(None, ctypes.byref(o), None, None, None) == _lib.CVP_E_INVALID
     assert L.cvp_project_ws(None, ctypes.byref(o), None, None, None, 0, None) == _lib.CVP_E_INVALID
+    assert L.cvp_project_noalloc(None, ctypes.byref(o), None, None, None) == _lib.CVP_E_INVALID
     nbytes = ctypes.c_int64()
     assert L.cvp_project_workspace_size(None, ctypes.byref(nbytes)) == _lib.CVP_E_INVALID
     assert "geometry" in _lib.last_error()
