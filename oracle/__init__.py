@@ -12,7 +12,11 @@ Two parts:
   (``definition.py``: ray supersampling, exact polyhedral cut volumes,
   closed-form pixel solid angles).
 
-Geometry is passed as a plain dict with the keys of :data:`GEOM_KEYS`.
+Geometry is passed as a plain dict with the keys of :data:`GEOM_KEYS`, or,
+for a general trajectory (Sec. III-C: one camera matrix per view), with
+``matrices`` ([views][3][4], world mm -> homogeneous pixel-index coordinates)
+in place of the orbit keys; the matrices are taken apart here (RQ
+decomposition) into each view's frame and intrinsics.
 """
 import ctypes
 import os
@@ -37,7 +41,8 @@ class _Geom(ctypes.Structure):
                 ("c1", ctypes.c_double), ("c2", ctypes.c_double),
                 ("sid", ctypes.c_double), ("sdd", ctypes.c_double),
                 ("nviews", ctypes.c_int32),
-                ("angles", ctypes.POINTER(ctypes.c_double))]
+                ("angles", ctypes.POINTER(ctypes.c_double)),
+                ("frames", ctypes.POINTER(ctypes.c_double))]
 
 
 class _Opts(ctypes.Structure):
@@ -89,10 +94,11 @@ def lib():
                                         ctypes.c_int, ip, ip, dp, ctypes.c_int]
         L.orc_column_pieces.argtypes = [G, O, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                         ctypes.POINTER(_Piece), ctypes.c_int]
-        L.orc_row_length.argtypes = [G, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+        L.orc_row_length.argtypes = [G, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.orc_row_length.restype = ctypes.c_double
         L.orc_pixel_scale.argtypes = [G, ctypes.c_int, dp]
+        L.orc_pixel_scale_view.argtypes = [G, ctypes.c_int, ctypes.c_int, dp]
         L.orc_pixel_solid_angle.argtypes = [G, ctypes.c_int, ctypes.c_int]
         L.orc_pixel_solid_angle.restype = ctypes.c_double
         L.orc_project_point.argtypes = [G, ctypes.c_int, dp, dp]
@@ -108,6 +114,37 @@ def _dptr(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
+def frames_from_matrices(P, centre, tol=1e-9):
+    """Per-view frames of camera matrices P [V][3][4] (x~ = P [x; 1] in
+    homogeneous pixel-index coordinates): M = K R by RQ decomposition (K
+    upper triangular with a positive diagonal, R orthogonal), the source s =
+    -M^-1 p4, and the sign of P fixed so that the volume centre (in front of
+    the source) has positive depth.  The convention of Sec. III-A is required: rows e1
+    and d of R horizontal, e2 = (0, 0, -1) (chi2 opposite to x3), no skew.
+    Returns [V][11]: s1, s2, s3, e1x, e1y, dx, dy, f/b1, f/b2, c1, c2."""
+    from scipy.linalg import rq
+    P = np.asarray(P, dtype=np.float64)
+    out = np.zeros((len(P), 11))
+    for v, Pv in enumerate(P):
+        if Pv[2] @ np.append(centre, 1.0) < 0:
+            Pv = -Pv
+        Mv, p4 = Pv[:, :3], Pv[:, 3]
+        s = -np.linalg.solve(Mv, p4)
+        K, R = rq(Mv)
+        D = np.diag(np.sign(np.diag(K)))
+        K, R = K @ D, D @ R                 # positive diagonal of K
+        if K[2, 2] < 0:
+            raise ValueError("view %d: degenerate camera matrix" % v)
+        K = K / K[2, 2]
+        e1, e2, d = R
+        if (abs(e1[2]) > tol or abs(d[2]) > tol or abs(e2[2] + 1.0) > tol
+                or abs(K[0, 1]) > tol * K[0, 0]):
+            raise ValueError("view %d: chi1 must not depend on x3 and chi2 must run opposite to x3 "
+                             "(Sec. III-A convention)" % v)
+        out[v] = (s[0], s[1], s[2], e1[0], e1[1], d[0], d[1], K[0, 0], K[1, 1], K[0, 2], K[1, 2])
+    return out
+
+
 class Geometry:
     """Oracle-side geometry built from a plain parameter dict."""
 
@@ -117,13 +154,22 @@ class Geometry:
         a1, a2, a3 = (float(v) for v in p["voxel_mm"])
         o = p.get("vol_offset_mm", (0.0, 0.0, 0.0))
         M, N = int(p["det_cols"]), int(p["det_rows"])
-        b1, b2 = (float(v) for v in p["pitch_mm"])
-        pp = p.get("principal_px")
-        c1, c2 = ((M - 1) / 2.0, (N - 1) / 2.0) if pp is None else (float(pp[0]), float(pp[1]))
-        self.angles = np.ascontiguousarray(np.asarray(p["angles_rad"], dtype=np.float64))
+        if "matrices" in p:
+            self.frames = np.ascontiguousarray(frames_from_matrices(p["matrices"], np.asarray(o, dtype=np.float64)))
+            nv = len(self.frames)
+            self.angles = np.zeros(nv)
+            b1 = b2 = c1 = c2 = sid = sdd = 0.0      # unused: every view has its frame
+            fp = _dptr(self.frames)
+        else:
+            b1, b2 = (float(v) for v in p["pitch_mm"])
+            pp = p.get("principal_px")
+            c1, c2 = ((M - 1) / 2.0, (N - 1) / 2.0) if pp is None else (float(pp[0]), float(pp[1]))
+            self.angles = np.ascontiguousarray(np.asarray(p["angles_rad"], dtype=np.float64))
+            sid, sdd = float(p["sid_mm"]), float(p["sdd_mm"])
+            fp = ctypes.POINTER(ctypes.c_double)()
         self.c = _Geom(n1, n2, n3, a1, a2, a3, float(o[0]), float(o[1]), float(o[2]),
-                       M, N, b1, b2, c1, c2, float(p["sid_mm"]), float(p["sdd_mm"]),
-                       len(self.angles), _dptr(self.angles))
+                       M, N, b1, b2, c1, c2, sid, sdd,
+                       len(self.angles), _dptr(self.angles), fp)
         self.vol_shape = (n3, n2, n1)
         self.nviews = len(self.angles)
         self.proj_shape = (self.nviews, N, M)
@@ -201,15 +247,15 @@ def column_pieces(geom, opts: Options, view, i, j):
                  depth=arr[q].depth, h=arr[q].h) for q in range(n)]
 
 
-def row_length(geom, s3, v, depth, h, z0, z1):
+def row_length(geom, s3, v, depth, h, z0, z1, view=0):
     g = _geom(geom)
-    return lib().orc_row_length(g.ref(), s3, v, depth, h, z0, z1)
+    return lib().orc_row_length(g.ref(), view, s3, v, depth, h, z0, z1)
 
 
-def pixel_scale(geom, scaling):
+def pixel_scale(geom, scaling, view=0):
     g = _geom(geom)
     out = np.zeros(g.proj_shape[1:], np.float64)
-    lib().orc_pixel_scale(g.ref(), SCALINGS[scaling], _dptr(out))
+    lib().orc_pixel_scale_view(g.ref(), view, SCALINGS[scaling], _dptr(out))
     return out
 
 

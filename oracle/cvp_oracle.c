@@ -48,6 +48,13 @@
  *     against the paper's own implementation (the paper calls its width a
  *     heuristic and does not give it); only invariants pin it.
  *   - pixels off the detector are dropped (no renormalisation).
+ *
+ * General trajectories (Sec. III-C: per-view camera matrices, under the
+ * convention of Sec. III-A that chi2 runs opposite to x3): instead of the
+ * circular orbit, each view may come with its own frame and intrinsics
+ * (source s, horizontal e1 and d, e2 = (0,0,-1), f/b1, f/b2, principal
+ * point), taken from its projection matrix by the Python side.  Every
+ * formula above is unchanged; only the constants become per view.
  */
 #include <math.h>
 #include <stdint.h>
@@ -67,6 +74,8 @@ typedef struct {
     double sid, sdd;        /* source-isocentre, source-detector [mm] */
     int32_t nviews;
     const double *angles;   /* [nviews] rotation angles [rad] */
+    const double *frames;   /* NULL (circular orbit) or [nviews][11]: s1, s2, s3,
+                               e1x, e1y, dx, dy, f/b1, f/b2, c1, c2 */
 } orc_geom;
 
 typedef struct {
@@ -96,6 +105,15 @@ void orc_set_mutation(int m) { g_mutation = m; }
 static void view_frame(const orc_geom *g, int view, double s[3], double e1[3],
                        double e2[3], double d[3])
 {
+    if (g->frames) {
+        const double *F = g->frames + (size_t)view * 11;
+        s[0] = F[0]; s[1] = F[1]; s[2] = F[2];
+        e1[0] = F[3]; e1[1] = F[4]; e1[2] = 0.0;
+        e2[0] = 0.0; e2[1] = 0.0; e2[2] = -1.0;
+        d[0] = F[5]; d[1] = F[6]; d[2] = 0.0;
+        if (g_mutation == 1) { e1[0] = -e1[0]; e1[1] = -e1[1]; }
+        return;
+    }
     double l = g->angles[view];
     double cl = cos(l), sl = sin(l);
     s[0] = g->sid * cl; s[1] = g->sid * sl; s[2] = 0.0;
@@ -116,6 +134,25 @@ static double dot3(const double *a, const double *b)
     return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
+/* Intrinsics of a view in pixel-index units: fb1 = f/b1, fb2 = f/b2 (and its
+ * inverse b2/f), principal point (c1, c2). */
+typedef struct {
+    double fb1, fb2, ifb2, c1, c2;
+} orc_intr;
+
+static orc_intr view_intr(const orc_geom *g, int view)
+{
+    orc_intr I;
+    if (g->frames) {
+        const double *F = g->frames + (size_t)view * 11;
+        I.fb1 = F[7]; I.fb2 = F[8]; I.ifb2 = 1.0 / F[8]; I.c1 = F[9]; I.c2 = F[10];
+    } else {
+        I.fb1 = g->sdd / g->b1; I.fb2 = g->sdd / g->b2; I.ifb2 = g->b2 / g->sdd;
+        I.c1 = g->c1; I.c2 = g->c2;
+    }
+    return I;
+}
+
 /* pinhole projection of a world point onto detector pixel-index coordinates */
 void orc_project_point(const orc_geom *g, int view, const double *x, double *chi)
 {
@@ -123,8 +160,9 @@ void orc_project_point(const orc_geom *g, int view, const double *x, double *chi
     view_frame(g, view, s, e1, e2, d);
     r[0] = x[0] - s[0]; r[1] = x[1] - s[1]; r[2] = x[2] - s[2];
     double depth = dot3(d, r);
-    chi[0] = g->c1 + (g->sdd / g->b1) * dot3(e1, r) / depth;
-    chi[1] = g->c2 + (g->sdd / g->b2) * dot3(e2, r) / depth;
+    const orc_intr I = view_intr(g, view);
+    chi[0] = I.c1 + I.fb1 * dot3(e1, r) / depth;
+    chi[1] = I.c2 + I.fb2 * dot3(e2, r) / depth;
 }
 
 static void voxel_centre(const orc_geom *g, int i, int j, int k, double x[3])
@@ -203,7 +241,7 @@ int orc_column_pieces(const orc_geom *g, const orc_opts *o, int view, int i,
     double s[3], e1[3], e2[3], d[3], xc[3];
     view_frame(g, view, s, e1, e2, d);
     voxel_centre(g, i, j, 0, xc);
-    const double f = g->sdd;
+    const orc_intr I = view_intr(g, view);
 
     /* chi1 of the four base corners -> range of detector columns */
     double chimin = INFINITY, chimax = -INFINITY;
@@ -231,10 +269,10 @@ int orc_column_pieces(const orc_geom *g, const orc_opts *o, int view, int i,
         if (g_mutation == 2) th = u + 0.6;              /* wrong pixel edge */
         /* n_t in the x1x2 plane; the half-plane test on local q is
          * n_t.q + n_t.(x_c - s) */
-        double nl0 = (f / g->b1) * e1[0] - (tl - g->c1) * d[0];
-        double nl1 = (f / g->b1) * e1[1] - (tl - g->c1) * d[1];
-        double nh0 = (f / g->b1) * e1[0] - (th - g->c1) * d[0];
-        double nh1 = (f / g->b1) * e1[1] - (th - g->c1) * d[1];
+        double nl0 = I.fb1 * e1[0] - (tl - I.c1) * d[0];
+        double nl1 = I.fb1 * e1[1] - (tl - I.c1) * d[1];
+        double nh0 = I.fb1 * e1[0] - (th - I.c1) * d[0];
+        double nh1 = I.fb1 * e1[1] - (th - I.c1) * d[1];
         double p1[MAXV][2], p2[MAXV][2];
         /* chi1 >= u - 1/2 : -(n.(x-s)) <= 0 */
         int n1 = clip_halfplane((const double (*)[2])sq, 4, nl0, nl1,
@@ -278,18 +316,18 @@ int orc_column_pieces(const orc_geom *g, const orc_opts *o, int view, int i,
 
 /* x3 of the plane through the source onto the row boundary chi2 = t, at
  * depth Dp:  chi2 = c2 + (f/b2) e2.(x-s)/Dp  with e2 = (0,0,-1). */
-static double row_plane_x3(const orc_geom *g, double s3, double t, double Dp)
+static double row_plane_x3(const orc_intr *I, double s3, double t, double Dp)
 {
-    return s3 - (t - g->c2) * (g->b2 / g->sdd) * Dp;
+    return s3 - (t - I->c2) * I->ifb2 * Dp;
 }
 
 /* Sec. III-A: x3 length of [z0,z1] inside the band of row v at depth Dp. */
-static double band_length(const orc_geom *g, double s3, int v, double Dp,
+static double band_length(const orc_intr *I, double s3, int v, double Dp,
                           double z0, double z1)
 {
-    double top = row_plane_x3(g, s3, v - 0.5, Dp);
-    double bot = row_plane_x3(g, s3, v + 0.5, Dp);
-    if (g_mutation == 4) bot = row_plane_x3(g, s3, v + 0.5, Dp * 1.001);
+    double top = row_plane_x3(I, s3, v - 0.5, Dp);
+    double bot = row_plane_x3(I, s3, v + 0.5, Dp);
+    if (g_mutation == 4) bot = row_plane_x3(I, s3, v + 0.5, Dp * 1.001);
     double lo = z0 > bot ? z0 : bot;
     double hi = z1 < top ? z1 : top;
     return hi > lo ? hi - lo : 0.0;
@@ -306,10 +344,11 @@ static int cmp_double(const void *a, const void *b)
  * depth box.  The integrand is piecewise linear in Dp with kinks only where
  * a row plane passes z0 or z1, so the trapezoid rule between those kinks is
  * exact. */
-double orc_row_length(const orc_geom *g, double s3, int v, double D, double h,
+double orc_row_length(const orc_geom *g, int view, double s3, int v, double D, double h,
                       double z0, double z1)
 {
-    if (!(h > 0)) return band_length(g, s3, v, D, z0, z1);
+    const orc_intr I = view_intr(g, view);
+    if (!(h > 0)) return band_length(&I, s3, v, D, z0, z1);
     double bp[8];
     int nb = 0;
     bp[nb++] = D - h;
@@ -317,7 +356,7 @@ double orc_row_length(const orc_geom *g, double s3, int v, double D, double h,
     const double ts[2] = {v - 0.5, v + 0.5};
     const double zs[2] = {z0, z1};
     for (int a = 0; a < 2; ++a) {
-        double k = (ts[a] - g->c2) * (g->b2 / g->sdd);
+        double k = (ts[a] - I.c2) * I.ifb2;
         if (k == 0) continue;
         for (int b = 0; b < 2; ++b) {
             double Dp = (s3 - zs[b]) / k;
@@ -329,8 +368,8 @@ double orc_row_length(const orc_geom *g, double s3, int v, double D, double h,
     for (int a = 0; a + 1 < nb; ++a) {
         double w = bp[a + 1] - bp[a];
         if (w <= 0) continue;
-        acc += 0.5 * w * (band_length(g, s3, v, bp[a], z0, z1) +
-                          band_length(g, s3, v, bp[a + 1], z0, z1));
+        acc += 0.5 * w * (band_length(&I, s3, v, bp[a], z0, z1) +
+                          band_length(&I, s3, v, bp[a + 1], z0, z1));
     }
     /* mean over the box; its width as represented (bp[nb-1] - bp[0]) rather
      * than 2h keeps the quotient exact for boxes narrower than the FP64
@@ -356,6 +395,7 @@ int orc_voxel_weights(const orc_geom *g, const orc_opts *o, int view, int i,
     double s[3], e1[3], e2[3], d[3], xc[3];
     view_frame(g, view, s, e1, e2, d);
     voxel_centre(g, i, j, k, xc);
+    const orc_intr I = view_intr(g, view);
     double z0 = xc[2] - 0.5 * g->a3, z1 = xc[2] + 0.5 * g->a3;
     int n = 0;
     double volsum = 0.0;
@@ -367,7 +407,7 @@ int orc_voxel_weights(const orc_geom *g, const orc_opts *o, int view, int i,
         for (int a = 0; a < 4; ++a) {
             double Dp = pc->depth + ((a & 1) ? h : -h);
             double z = (a & 2) ? z1 : z0;
-            double chi2 = g->c2 - (g->sdd / g->b2) * (z - s[2]) / Dp;
+            double chi2 = I.c2 - I.fb2 * (z - s[2]) / Dp;
             if (chi2 < cmin) cmin = chi2;
             if (chi2 > cmax) cmax = chi2;
         }
@@ -376,13 +416,13 @@ int orc_voxel_weights(const orc_geom *g, const orc_opts *o, int view, int i,
         if (vlo < 0) vlo = 0;
         if (vhi > g->nrows - 1) vhi = g->nrows - 1;
         for (int v = vlo; v <= vhi; ++v) {
-            double len = orc_row_length(g, s[2], v, pc->depth, h, z0, z1);
+            double len = orc_row_length(g, view, s[2], v, pc->depth, h, z0, z1);
             if (g_mutation == 9) {
                 /* rows off the detector merged into its edge rows */
                 if (v == vlo)
-                    for (int vv = vlo_all; vv < vlo; ++vv) len += orc_row_length(g, s[2], vv, pc->depth, h, z0, z1);
+                    for (int vv = vlo_all; vv < vlo; ++vv) len += orc_row_length(g, view, s[2], vv, pc->depth, h, z0, z1);
                 if (v == vhi)
-                    for (int vv = vhi + 1; vv <= vhi_all; ++vv) len += orc_row_length(g, s[2], vv, pc->depth, h, z0, z1);
+                    for (int vv = vhi + 1; vv <= vhi_all; ++vv) len += orc_row_length(g, view, s[2], vv, pc->depth, h, z0, z1);
             }
             volsum += pc->area * len;
             if (!(len > 0)) continue;
@@ -395,8 +435,8 @@ int orc_voxel_weights(const orc_geom *g, const orc_opts *o, int view, int i,
                 if (o->exact) {
                     /* centroid of the piece: CM_u in x1x2, middle of the x3
                      * extent of the plain band at the centroid depth */
-                    double top = row_plane_x3(g, s[2], v - 0.5, pc->depth);
-                    double bot = row_plane_x3(g, s[2], v + 0.5, pc->depth);
+                    double top = row_plane_x3(&I, s[2], v - 0.5, pc->depth);
+                    double bot = row_plane_x3(&I, s[2], v + 0.5, pc->depth);
                     double lo = z0 > bot ? z0 : bot, hi = z1 < top ? z1 : top;
                     double zb = 0.5 * (lo + hi);
                     if (zb < z0) zb = z0;
@@ -436,36 +476,63 @@ static double tri_solid_angle(const double *A, const double *B, const double *C)
     return 2.0 * atan2(num, den);
 }
 
-/* Solid angle of pixel (u,v) seen from the source: the detector plane is at
- * distance f along the principal ray, pixel edges at (t - c) * b. */
-double orc_pixel_solid_angle(const orc_geom *g, int u, int v)
+/* Solid angle of pixel (u,v) of a view seen from the source: the detector
+ * plane is at distance f along the principal ray, pixel edges at (t - c) * b
+ * (with per-view frames: at distance 1, edges at (t - c) / (f/b)). */
+double orc_pixel_solid_angle_view(const orc_geom *g, int view, int u, int v)
 {
-    double x0 = (u - 0.5 - g->c1) * g->b1, x1 = (u + 0.5 - g->c1) * g->b1;
-    double y0 = (v - 0.5 - g->c2) * g->b2, y1 = (v + 0.5 - g->c2) * g->b2;
-    double P[4][3] = {{x0, y0, g->sdd}, {x1, y0, g->sdd}, {x1, y1, g->sdd}, {x0, y1, g->sdd}};
+    double x0, x1, y0, y1, f;
+    if (g->frames) {
+        const orc_intr I = view_intr(g, view);
+        x0 = (u - 0.5 - I.c1) / I.fb1; x1 = (u + 0.5 - I.c1) / I.fb1;
+        y0 = (v - 0.5 - I.c2) / I.fb2; y1 = (v + 0.5 - I.c2) / I.fb2;
+        f = 1.0;
+    } else {
+        x0 = (u - 0.5 - g->c1) * g->b1; x1 = (u + 0.5 - g->c1) * g->b1;
+        y0 = (v - 0.5 - g->c2) * g->b2; y1 = (v + 0.5 - g->c2) * g->b2;
+        f = g->sdd;
+    }
+    double P[4][3] = {{x0, y0, f}, {x1, y0, f}, {x1, y1, f}, {x0, y1, f}};
     return tri_solid_angle(P[0], P[1], P[2]) + tri_solid_angle(P[0], P[2], P[3]);
 }
 
-/* Sec. III-C, second phase: the factor applied to S_uv per pixel.
+double orc_pixel_solid_angle(const orc_geom *g, int u, int v)
+{
+    return orc_pixel_solid_angle_view(g, 0, u, v);
+}
+
+/* Sec. III-C, second phase: the factor applied to S_uv per pixel of a view.
  *   scaling 0: 1 / abar_uv                  (eq. cvpus)
  *   scaling 1: f^2 / (a_uv cos^3 theta_uv)  (eq. cvp), theta at the pixel centre
  *   scaling 2: 1 */
-void orc_pixel_scale(const orc_geom *g, int scaling, double *sigma)
+void orc_pixel_scale_view(const orc_geom *g, int view, int scaling, double *sigma)
 {
     for (int v = 0; v < g->nrows; ++v) {
         for (int u = 0; u < g->ncols; ++u) {
             double val = 1.0;
             if (scaling == 0) {
-                val = 1.0 / orc_pixel_solid_angle(g, u, v);
+                val = 1.0 / orc_pixel_solid_angle_view(g, view, u, v);
             } else if (scaling == 1) {
-                double X = (u - g->c1) * g->b1, Y = (v - g->c2) * g->b2;
-                double R = sqrt(X * X + Y * Y + g->sdd * g->sdd);
-                double cth = g->sdd / R;
-                val = g->sdd * g->sdd / (g->b1 * g->b2 * cth * cth * cth);
+                if (g->frames) {
+                    const orc_intr I = view_intr(g, view);
+                    double X = (u - I.c1) / I.fb1, Y = (v - I.c2) / I.fb2;
+                    double cth = 1.0 / sqrt(X * X + Y * Y + 1.0);
+                    val = I.fb1 * I.fb2 / (cth * cth * cth);
+                } else {
+                    double X = (u - g->c1) * g->b1, Y = (v - g->c2) * g->b2;
+                    double R = sqrt(X * X + Y * Y + g->sdd * g->sdd);
+                    double cth = g->sdd / R;
+                    val = g->sdd * g->sdd / (g->b1 * g->b2 * cth * cth * cth);
+                }
             }
             sigma[(size_t)v * g->ncols + u] = val;
         }
     }
+}
+
+void orc_pixel_scale(const orc_geom *g, int scaling, double *sigma)
+{
+    orc_pixel_scale_view(g, 0, scaling, sigma);
 }
 
 /* ---------------------------------------------------------- operators */
@@ -503,9 +570,10 @@ int orc_project(const orc_geom *g, const orc_opts *o, const double *x, double *b
     double *sigma = (double *)malloc(npix * sizeof(double));
     double *part = (double *)calloc((size_t)nt * npix, sizeof(double));
     if (!sigma || !part) { free(sigma); free(part); return -1; }
-    orc_pixel_scale(g, o->scaling, sigma);
+    orc_pixel_scale_view(g, view_lo, o->scaling, sigma);
     int err = 0;
     for (int view = view_lo; view < view_hi; ++view) {
+        if (g->frames && view != view_lo) orc_pixel_scale_view(g, view, o->scaling, sigma);
         memset(part, 0, (size_t)nt * npix * sizeof(double));
 #pragma omp parallel
         {
@@ -544,9 +612,11 @@ int orc_backproject_voxels(const orc_geom *g, const orc_opts *o, const double *b
                            const int64_t *idx, double *out)
 {
     const size_t npix = (size_t)g->nrows * g->ncols;
-    double *sigma = (double *)malloc(npix * sizeof(double));
+    /* pixel factors: one table, or one per view with per-view frames */
+    const int nsig = g->frames ? view_hi - view_lo : 1;
+    double *sigma = (double *)malloc((size_t)(nsig > 0 ? nsig : 1) * npix * sizeof(double));
     if (!sigma) return -1;
-    orc_pixel_scale(g, o->scaling, sigma);
+    for (int q = 0; q < nsig; ++q) orc_pixel_scale_view(g, view_lo + q, o->scaling, sigma + (size_t)q * npix);
     int err = 0;
 #pragma omp parallel
     {
@@ -562,10 +632,11 @@ int orc_backproject_voxels(const orc_geom *g, const orc_opts *o, const double *b
                 int n = orc_voxel_weights(g, o, view, i, j, k, us, vs, ws, MAXW);
                 if (n < 0) { err = 1; break; }
                 const double *bv = b + (size_t)(view - view_lo) * npix;
+                const double *sg = sigma + (g->frames ? (size_t)(view - view_lo) * npix : 0);
                 for (int p = 0; p < n; ++p) {
                     size_t pix = (size_t)vs[p] * g->ncols + us[p];
-                    double term = ws[p] * sigma[pix] * bv[pix];
-                    if (g_mutation == 6) term = ws[p] * sigma[pix] * bv[(pix + 1) % npix];
+                    double term = ws[p] * sg[pix] * bv[pix];
+                    if (g_mutation == 6) term = ws[p] * sg[pix] * bv[(pix + 1) % npix];
                     acc += term;
                 }
             }

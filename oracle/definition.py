@@ -13,12 +13,35 @@ step-by-step oracle; they share no code with it:
   paper's spherical-quadrilateral formula (Sec. II-E).
 
 Coordinates follow the same conventions as the oracle (circular orbit about
-+x3, chi2 opposite to x3), written out again here from the definitions.
++x3, chi2 opposite to x3), written out again here from the definitions.  A
+geometry with camera matrices (``matrices`` [views][3][4], Sec. III-C) is
+used through the matrices themselves: pixel boundaries are the planes
+(P_row1 - t P_row3) . [x; 1] = 0, rays run along M^-1 (chi1, chi2, 1), the
+source is -M^-1 p4 (no decomposition into frames).
 """
 import itertools
 import math
 
 import numpy as np
+
+
+def camera(geom, view):
+    """The view's camera matrix, signed so that points in front of the source
+    (the volume) have a positive third homogeneous coordinate."""
+    P = np.array(geom["matrices"][view], dtype=np.float64)
+    n = np.array(geom["vol_dims"], dtype=np.float64)
+    a = np.array(geom["voxel_mm"], dtype=np.float64)
+    o = np.array(geom.get("vol_offset_mm", (0, 0, 0)), dtype=np.float64)
+    if P[2] @ np.append(o, 1.0) < 0:
+        P = -P
+    return P
+
+
+def source(geom, view):
+    if "matrices" in geom:
+        P = camera(geom, view)
+        return -np.linalg.solve(P[:, :3], P[:, 3])
+    return frame(geom, view)[0]
 
 
 def frame(geom, view):
@@ -141,6 +164,20 @@ def _halfspaces(geom, view, ijk, u, v):
     """Rows (n, c) of the constraints n.x <= c describing voxel ijk cut by the
     ray pyramid of pixel (u, v)."""
     lo, hi = voxel_box(geom, *ijk)
+    if "matrices" in geom:
+        P = camera(geom, view)
+        H = []
+        for ax in range(3):
+            n = np.zeros(3); n[ax] = 1.0
+            H.append((n, hi[ax]))
+            H.append((-n, -lo[ax]))
+        # chi_r <= t  <=>  (P_r - t P_3) . [x; 1] <= 0 in front of the source
+        for r, lo_t, hi_t in ((0, u - 0.5, u + 0.5), (1, v - 0.5, v + 0.5)):
+            ph = P[r] - hi_t * P[2]
+            H.append((ph[:3], -ph[3]))
+            pl = -(P[r] - lo_t * P[2])
+            H.append((pl[:3], -pl[3]))
+        return H
     s, e1, e2, d = frame(geom, view)
     c1, c2 = principal(geom)
     b1, b2 = geom["pitch_mm"]
@@ -201,6 +238,15 @@ def cut_integrals(geom, view, ijk, u, v):
         tri = Delaunay(P)
     except QhullError:
         return 0.0, 0.0, 0.0
+    if "matrices" in geom:
+        s = source(geom, view)
+        i_sa = 0.0
+        for simp in tri.simplices:
+            T = P[simp]
+            tv = abs(np.linalg.det(T[1:] - T[0])) / 6.0
+            q = _TET_BARY @ T - s[None, :]
+            i_sa += tv * np.mean(1.0 / np.sum(q * q, axis=1))
+        return vol, i_sa, float("nan")
     s, e1, e2, d = frame(geom, view)
     f = float(geom["sdd_mm"])
     i_sa = 0.0
@@ -280,3 +326,21 @@ def siddon_project(geom, x, K, views=None):
                 L = np.maximum(leave - enter, 0.0)
                 out[vi, v, u] = float(np.sum(L @ mu)) / (K * K)
     return out
+
+
+def pixel_solid_angle_matrix(geom, view, u, v):
+    """Solid angle of pixel (u, v) seen from the source of a camera-matrix
+    view: the spherical quadrilateral spanned by the rays through the pixel's
+    corners, M^-1 (u +- 1/2, v +- 1/2, 1) (the paper's formula: 2 pi minus
+    the angles between consecutive great-circle planes)."""
+    P = camera(geom, view)
+    Minv = np.linalg.inv(P[:, :3])
+    t = [Minv @ np.array([u + du, v + dv, 1.0]) for du, dv in ((-0.5, -0.5), (0.5, -0.5), (0.5, 0.5), (-0.5, 0.5))]
+    t = [x / np.linalg.norm(x) for x in t]
+    acc = 0.0
+    for i in range(4):
+        a = np.cross(t[i], t[(i + 1) % 4])
+        b = np.cross(t[(i + 1) % 4], t[(i + 2) % 4])
+        c = np.dot(a, b) / (np.linalg.norm(a) * np.linalg.norm(b))
+        acc += math.acos(max(-1.0, min(1.0, c)))
+    return 2 * math.pi - acc

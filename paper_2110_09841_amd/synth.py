@@ -202,3 +202,66 @@ def philox_gaussian(n: int, seed: int) -> np.ndarray:
         z[:, 2 * h] = r * np.cos(ang)
         z[:, 2 * h + 1] = r * np.sin(ang)
     return z.reshape(-1)[:n]
+
+
+def matrix_geometry(vol_dims, voxel_mm, det_cols, det_rows, pitch_mm, sid_mm, sdd_mm, n_views, arc_deg=360.0,
+                    seed=0, wobble=True, vol_offset_mm=(0.0, 0.0, 0.0)):
+    """A general trajectory given as one camera matrix per view (world mm ->
+    homogeneous pixel-index coordinates, x~ = P [x; 1]): a circular C-arm
+    orbit with, per view and seeded, the source raised or lowered (+-2 mm),
+    the source and detector distances jittered (+-1 %), the principal point
+    shifted (+-3 px), the detector yawed about the vertical (+-1 degree,
+    so chi1 still does not depend on x3) and the pixels slightly
+    anisotropic; chi2 runs opposite to x3 (the paper's convention).
+    P = K [R | -R s] with K = [[f/b1, 0, c1], [0, f/b2, c2], [0, 0, 1]]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if np.isscalar(voxel_mm):
+        voxel_mm = (voxel_mm,) * 3
+    if np.isscalar(pitch_mm):
+        pitch_mm = (pitch_mm, pitch_mm)
+    if np.isscalar(vol_dims):
+        vol_dims = (vol_dims,) * 3
+    lam = angles(n_views, arc_deg)
+    P = np.zeros((n_views, 3, 4))
+    for v in range(n_views):
+        w = wobble
+        D = sid_mm * (1.0 + (rng.uniform(-0.01, 0.01) if w else 0.0))
+        f = sdd_mm * (1.0 + (rng.uniform(-0.01, 0.01) if w else 0.0))
+        dz = rng.uniform(-2.0, 2.0) if w else 0.0
+        yaw = math.radians(rng.uniform(-1.0, 1.0)) if w else 0.0
+        c1 = (det_cols - 1) / 2.0 + (rng.uniform(-3.0, 3.0) if w else 0.0)
+        c2 = (det_rows - 1) / 2.0 + (rng.uniform(-3.0, 3.0) if w else 0.0)
+        b1 = pitch_mm[0] * (1.0 + (rng.uniform(-0.02, 0.02) if w else 0.0))
+        b2 = pitch_mm[1]
+        cl, sl = math.cos(lam[v]), math.sin(lam[v])
+        s = np.array([D * cl, D * sl, dz])
+        cy, sy = math.cos(yaw), math.sin(yaw)
+        d = np.array([-cl * cy + sl * sy, -sl * cy - cl * sy, 0.0])
+        e1 = np.array([-d[1], d[0], 0.0])
+        R = np.array([e1, [0.0, 0.0, -1.0], d])
+        K = np.array([[f / b1, 0.0, c1], [0.0, f / b2, c2], [0.0, 0.0, 1.0]])
+        P[v, :, :3] = K @ R
+        P[v, :, 3] = -(K @ R) @ s
+    return dict(vol_dims=tuple(int(x) for x in vol_dims), voxel_mm=tuple(float(x) for x in voxel_mm),
+                vol_offset_mm=tuple(float(x) for x in vol_offset_mm), det_cols=int(det_cols),
+                det_rows=int(det_rows), matrices=P)
+
+
+def circular_matrices(p):
+    """The camera matrices of a circular geometry dict (see geometry):
+    source (D cos l, D sin l, 0), e1 = (-sin l, cos l, 0), e2 = (0, 0, -1),
+    d = (-cos l, -sin l, 0), K from f/b and the principal point."""
+    M, N = p["det_cols"], p["det_rows"]
+    pp = p.get("principal_px")
+    c1, c2 = ((M - 1) / 2.0, (N - 1) / 2.0) if pp is None else pp
+    b1, b2 = p["pitch_mm"]
+    D, f = p["sid_mm"], p["sdd_mm"]
+    K = np.array([[f / b1, 0.0, c1], [0.0, f / b2, c2], [0.0, 0.0, 1.0]])
+    out = np.zeros((len(p["angles_rad"]), 3, 4))
+    for v, l in enumerate(p["angles_rad"]):
+        cl, sl = math.cos(l), math.sin(l)
+        R = np.array([[-sl, cl, 0.0], [0.0, 0.0, -1.0], [-cl, -sl, 0.0]])
+        s = np.array([D * cl, D * sl, 0.0])
+        out[v, :, :3] = K @ R
+        out[v, :, 3] = -(K @ R) @ s
+    return out
