@@ -290,6 +290,7 @@ def batched_timing(reps=2):
     vv = 2 * sum(g.n_voxels * g.n_views for g in geoms)
     res = {"workload": "batch16_96c_320c", "problems": len(geoms), "voxel_views": vv,
            "batched_ms": times["batched"], "single_launches_ms": times["single"],
+           "batched_over_single": times["batched"] / times["single"],
            "batched_voxel_views_per_s": vv / (times["batched"] * 1e-3)}
     # CGLS on all 16 problems at once (b = the batched projections above):
     # one replay of a graph of 5 batched iterations
@@ -314,7 +315,7 @@ def network_timing(reps=5):
     """Warm-start U-Net at 128^3 (the warm-start workload's volume): forward
     pass and full training step (forward, backward, Adam), HIP events."""
     import torch
-    from paper_2110_09841_amd.unet import UNet, forward_flops
+    from paper_2110_09841_amd.unet import UNet, forward_bound_seconds, forward_flops
     shape = (128, 128, 128)
     net = UNet(shape, seed=1)
     g = torch.Generator(device="cuda").manual_seed(0)
@@ -334,9 +335,13 @@ def network_timing(reps=5):
     fwd = ev[0].elapsed_time(ev[1]) / reps
     step = ev[1].elapsed_time(ev[2]) / reps
     fl = forward_flops(shape)
-    res = {"shape": list(shape), "forward_ms": fwd, "train_step_ms": step, "forward_gflop": fl / 1e9,
-           "forward_tflops": fl / (fwd * 1e-3) / 1e12, "peak_bf16_tflops": 2500.0,
-           "train_step_tflops": 3 * fl / (step * 1e-3) / 1e12}
+    fla = forward_flops(shape, algorithmic=True)
+    bound = forward_bound_seconds(shape)
+    res = {"shape": list(shape), "forward_ms": fwd, "train_step_ms": step, "forward_gflop_executed": fl / 1e9,
+           "forward_gflop_algorithmic": fla / 1e9, "forward_tflops_algorithmic": fla / (fwd * 1e-3) / 1e12,
+           "peak_bf16_tflops": 2500.0, "forward_bound_ms": bound * 1e3,
+           "forward_over_bound": fwd / (bound * 1e3),
+           "train_step_tflops_executed": 3 * fl / (step * 1e-3) / 1e12}
     del net
     torch.cuda.empty_cache()
     return res
@@ -344,10 +349,11 @@ def network_timing(reps=5):
 
 def cgls_to_tolerance(G, opts, x_true, max_iter):
     """CGLS from zero on b = A x_true until rho = |A^T(b - A x)| / |A^T b|
-    <= 1e-3; 5 iterations per replay of a captured HIP graph (captured
-    before the timed region), so the time is counted to the first multiple
-    of 5 iterations at which rho <= 1e-3.  Time runs from the start call (r = b,
-    s = A^T b) to the replay boundary at which rho <= 1e-3 was reached."""
+    <= 1e-3, stopped on the device: the iteration that meets the tolerance
+    raises a flag and the rest of the captured 5-iteration graph (captured
+    before the timed region) does nothing, so the time counts the iterations
+    needed plus at most 4 empty ones.  Time runs from the start call (r = b,
+    s = A^T b) to the replay boundary at which the host sees the flag."""
     import torch
     from paper_2110_09841_amd import cvp
     from paper_2110_09841_amd.cgls import CGLS
@@ -357,9 +363,11 @@ def cgls_to_tolerance(G, opts, x_true, max_iter):
     it, sec, rho = solver.run(tol=1e-3, max_iter=max_iter, per_graph=5)
     res = {"tol": 1e-3, "iterations": it, "seconds": sec, "reached": bool(rho[it] <= 1e-3),
            "rho_final": float(rho[-1]), "iterations_run": len(rho) - 1, "per_graph": 5,
+           "stop": "device flag (1-iteration granularity)",
            "data": "b = A x_true (consistent), x0 = 0"}
     # one replay of a graph of 20 iterations, from a fresh start
     solver.reset(b)
+    solver.set_tolerance(0.0)
     solver.start()
     solver.capture(20)
     torch.cuda.synchronize()

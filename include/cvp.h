@@ -109,6 +109,34 @@ typedef struct cvp_geometry cvp_geometry;  /* opaque */
  */
 cvp_status cvp_geometry_from_views(const cvp_geometry_desc *desc, cvp_geometry **out);
 
+/*
+ * General trajectory (Sec. III-C: the projective geometry of each view is a
+ * camera matrix): one 3x4 matrix per view, row-major, mapping world points
+ * (mm, volume as in cvp_geometry_desc) to homogeneous detector coordinates in
+ * pixel-index units: (w chi1, w chi2, w) = P (x1, x2, x3, 1); any nonzero
+ * scale and either sign.  Supported are the views of the paper's convention
+ * (Sec. III-A): chi1 does not depend on x3 (principal ray and chi1 axis
+ * horizontal, no skew) and chi2 runs opposite to x3 -- i.e.
+ * P = K [R | -R s] with R's rows e1, (0,0,-1), d (e1, d horizontal) and
+ * K = [[f/b1, 0, c1], [0, f/b2, c2], [0, 0, 1]]; each view may have its own
+ * source position (any height), direction, distances, principal point and
+ * pixel aspect (C-arm orbits with wobble).  Views outside the convention
+ * give CVP_E_UNSUPPORTED (the message names the view); the volume must lie in
+ * front of every source by more than a voxel diagonal (else CVP_E_INVALID).
+ * Pixel factors are tabulated per view when views differ in their
+ * intrinsics.  Every operator, solver and batch accepts the result like a
+ * circular geometry.
+ */
+typedef struct {
+    int32_t vol_dims[3];        /* n1, n2, n3 */
+    double voxel_mm[3];
+    double vol_offset_mm[3];    /* centre of the volume box */
+    int32_t det_cols, det_rows;
+    int32_t n_views;
+    const double *matrices;     /* host, n_views x 12 doubles (row-major 3x4 per view); copied */
+} cvp_geometry_matrices_desc;
+cvp_status cvp_geometry_from_matrices(const cvp_geometry_matrices_desc *desc, cvp_geometry **out);
+
 /* Frees the geometry (NULL is ignored).  Not stream-ordered: the caller makes
  * sure no operator call using it is still running. */
 void cvp_geometry_destroy(cvp_geometry *g);
@@ -235,19 +263,31 @@ cvp_status cvp_backproject_batched(const cvp_batch *b, const cvp_options *opts,
  * Vectors are caller-owned device float32 buffers: x, s, p of volume size;
  * b, r, q of projection size.  The scalars stay on the device, in the
  * caller-owned workspace d_work (cvp_cgls_workspace_size bytes, 8-byte
- * aligned), laid out as doubles:
+ * aligned, zeroed once before first use), laid out as doubles:
  *   [0] gamma  [1] |q|^2  [2] alpha  [3] beta  [4] gamma0 = |A^T(b - A x0)|^2
  *   [5] |r|^2  [6] k (iterations done)  [7] breakdown flag (A p = 0 met)
- *   [8 .. 8+4095]        |s_k|^2 for k = 0..4095
- *   [4104 .. 4104+4095]  |r_k|^2 after iteration k+1
+ *   [8] stop flag  [9] gamma threshold of the stop
+ *   [10] rho_tol^2 and [11] reference gamma (0: gamma0), set by
+ *        cvp_cgls_set_tolerance (0 = never stop)  [12..15] reserved
+ *   [16 .. 16+4095]      |s_k|^2 for k = 0..4095
+ *   [4112 .. 4112+4095]  |r_k|^2 after iteration k+1
  *   then reduction partials.
  * The relative residual rho_k = sqrt(|s_k|^2 / gamma0) is read from the
- * history.  Calls enqueue kernels only (no allocation, no host sync), so a
- * run of cvp_cgls_iterate can be captured in a HIP graph.  Dot products
- * accumulate FP64 in a fixed order (bitwise reproducible).
+ * history.  Stopping on the device: with a tolerance set, cvp_cgls_start
+ * fixes the threshold rho_tol^2 * (reference gamma or gamma0) and every
+ * iteration raises the stop flag when |s_k|^2 falls to it (or at a
+ * breakdown); from then on every kernel of cvp_cgls_iterate returns at once,
+ * so x, r and s keep the iterate that met the tolerance through the rest of
+ * a captured graph, and k counts the iterations actually run.  Calls enqueue
+ * kernels only (no allocation, no host sync), so a run of cvp_cgls_iterate
+ * can be captured in a HIP graph.  Dot products accumulate FP64 in a fixed
+ * order (bitwise reproducible).
  */
 #define CVP_CGLS_HISTORY 4096
 cvp_status cvp_cgls_workspace_size(int64_t n_voxels, int64_t n_pixels_total, int64_t *bytes);
+/* rho_tol >= 0 (0: never stop), gamma_ref >= 0 (0: the run's own gamma0);
+ * takes effect at the next cvp_cgls_start (a one-thread kernel on the stream). */
+cvp_status cvp_cgls_set_tolerance(void *d_work, double rho_tol, double gamma_ref, void *hip_stream);
 cvp_status cvp_cgls_start(const cvp_geometry *g, const cvp_options *opts, const float *d_b,
                           float *d_x, float *d_r, float *d_s, float *d_p, float *d_q,
                           void *d_work, void *hip_stream);
@@ -263,8 +303,9 @@ cvp_status cvp_cgls_iterate(const cvp_geometry *g, const cvp_options *opts, int3
  * single-problem CGLS bitwise.  Arguments are host arrays of b->n device
  * pointers with the single-problem layouts (d_work[q]: cvp_cgls_workspace_size
  * bytes, 8-byte aligned); no vector or workspace may serve two problems.
- * Problems are iterated together: the caller reads each workspace's history
- * and stops when every problem is done.  Enqueues kernels only, so a run of
+ * Problems are iterated together; a problem whose stop flag is up (see
+ * cvp_cgls_set_tolerance) skips its work items and vector kernels, so the
+ * others run on alone.  Enqueues kernels only, so a run of
  * cvp_cgls_batched_iterate can be captured in a HIP graph; calls that overlap
  * in time must not share the batch object.
  */

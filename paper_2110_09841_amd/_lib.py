@@ -36,6 +36,15 @@ class GeometryDesc(ctypes.Structure):
                 ("angles_rad", ctypes.POINTER(ctypes.c_double))]
 
 
+class MatricesDesc(ctypes.Structure):
+    _fields_ = [("vol_dims", ctypes.c_int32 * 3),
+                ("voxel_mm", ctypes.c_double * 3),
+                ("vol_offset_mm", ctypes.c_double * 3),
+                ("det_cols", ctypes.c_int32), ("det_rows", ctypes.c_int32),
+                ("n_views", ctypes.c_int32),
+                ("matrices", ctypes.POINTER(ctypes.c_double))]
+
+
 class OptionsC(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("elevation_correction", ctypes.c_int32),
                 ("scaling", ctypes.c_int32), ("flags", ctypes.c_uint32)]
@@ -53,6 +62,8 @@ def lib():
     st = ctypes.c_int
     L.cvp_geometry_from_views.argtypes = [ctypes.POINTER(GeometryDesc), ctypes.POINTER(vp)]
     L.cvp_geometry_from_views.restype = st
+    L.cvp_geometry_from_matrices.argtypes = [ctypes.POINTER(MatricesDesc), ctypes.POINTER(vp)]
+    L.cvp_geometry_from_matrices.restype = st
     L.cvp_geometry_destroy.argtypes = [vp]
     L.cvp_geometry_destroy.restype = None
     for name in ("cvp_project", "cvp_backproject"):
@@ -105,6 +116,7 @@ def _register_extra(L):
         "cvp_lsqr_start": ([vp, ctypes.POINTER(OptionsC)] + [vp] * 8 + [vp], st),
         "cvp_lsqr_iterate": ([vp, ctypes.POINTER(OptionsC), ctypes.c_int32] + [vp] * 7 + [vp], st),
         "cvp_dot": ([vp, vp, ctypes.c_int64, vp, vp, vp], st),
+        "cvp_cgls_set_tolerance": ([vp, ctypes.c_double, ctypes.c_double, vp], st),
         "cvp_synth_ellipsoids": ([vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
                                   vp, vp], st),
         "cvp_synth_add_gaussian": ([vp, ctypes.c_int64, ctypes.c_float, ctypes.c_uint64, vp], st),
@@ -131,6 +143,21 @@ def last_error():
 def check(status):
     if status != CVP_OK:
         raise CVPError(status, last_error())
+
+
+def make_matrices_desc(p):
+    """MatricesDesc from a dict with vol_dims, voxel_mm, vol_offset_mm,
+    det_cols, det_rows and matrices ([views][3][4])."""
+    import numpy as np
+    m = np.ascontiguousarray(np.asarray(p["matrices"], dtype=np.float64).reshape(-1, 12))
+    d = MatricesDesc()
+    d.vol_dims[:] = [int(v) for v in p["vol_dims"]]
+    d.voxel_mm[:] = [float(v) for v in p["voxel_mm"]]
+    d.vol_offset_mm[:] = [float(v) for v in p.get("vol_offset_mm", (0.0, 0.0, 0.0))]
+    d.det_cols, d.det_rows = int(p["det_cols"]), int(p["det_rows"])
+    d.n_views = len(m)
+    d.matrices = m.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return d, m
 
 
 def make_desc(p):

@@ -14,8 +14,9 @@ import torch
 from . import _lib
 from .cvp import Batch, Geometry, Options, _check_tensor, _ptr_array, _stream
 
-N_SCALARS = 8
+N_SCALARS = 16
 HISTORY = 4096
+STOP = 8
 
 
 class CGLS:
@@ -88,6 +89,17 @@ class CGLS:
     def breakdown(self):
         return bool(self.scalars()[7] != 0.0)
 
+    def stopped(self):
+        """The device-side stop flag (tolerance met or breakdown)."""
+        return bool(self.scalars()[STOP] != 0.0)
+
+    def set_tolerance(self, tol, gamma_ref=None):
+        """Stop on the device once |s_k|^2 <= tol^2 gamma_ref (gamma_ref:
+        |s_0|^2 of the run by default); 0 never stops.  Takes effect at the
+        next start()."""
+        _lib.check(_lib.lib().cvp_cgls_set_tolerance(ctypes.c_void_p(self.work.data_ptr()), float(tol),
+                                                     float(gamma_ref or 0.0), _stream()))
+
     def reset(self, b=None, x0=None):
         """New right-hand side and/or starting point in the same buffers (a
         captured graph stays valid)."""
@@ -99,13 +111,18 @@ class CGLS:
             self.x.copy_(x0)
 
     def run(self, tol=1e-3, max_iter=400, per_graph=20, use_graph=True, gamma_ref=None, start=True):
-        """Iterate until rho_k <= tol (checked every per_graph iterations) or
-        max_iter.  rho_k = |s_k| / sqrt(gamma_ref), by default gamma_ref =
-        |s_0|^2 of this run.  Returns (iterations, seconds, rho history); time
-        counts from the start call to the replay boundary where rho <= tol."""
+        """Iterate until rho_k <= tol or max_iter.  rho_k = |s_k| /
+        sqrt(gamma_ref), by default gamma_ref = |s_0|^2 of this run.  The
+        stop is taken on the device (cvp_cgls_set_tolerance): once rho_k <=
+        tol the remaining iterations of a graph replay do nothing, so the run
+        costs the iterations it needs; the host checks the flag once per
+        replay of per_graph iterations.  Returns (iterations, seconds, rho
+        history); time counts from the start call to the replay boundary
+        where the flag is seen."""
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         if start:
+            self.set_tolerance(tol, gamma_ref)
             self.start()
         if use_graph and (self.graph is None or self.graph_iters != per_graph):
             self.capture(per_graph)
@@ -114,7 +131,7 @@ class CGLS:
             g = self.gamma_history()      # synchronises
             ref = g[0] if gamma_ref is None else gamma_ref
             rho = np.sqrt(np.maximum(g, 0.0) / ref)
-            if rho[-1] <= tol or self.breakdown() or done >= max_iter:
+            if rho[-1] <= tol or self.breakdown() or self.stopped() or done >= max_iter:
                 break
             if use_graph:
                 self.replay()
@@ -210,21 +227,37 @@ class BatchedCGLS:
     def breakdown(self):
         return [bool(float(w[7]) != 0.0) for w in self.work]
 
-    def run(self, tol=1e-3, max_iter=400, per_graph=20, use_graph=True):
+    def stopped(self):
+        return [bool(float(w[STOP]) != 0.0) for w in self.work]
+
+    def set_tolerance(self, tol, gamma_refs=None):
+        """Per-problem device-side stop (see CGLS.set_tolerance); a stopped
+        problem's work items are skipped by the batched launches."""
+        for k, w in enumerate(self.work):
+            ref = 0.0 if gamma_refs is None else float(gamma_refs[k])
+            _lib.check(_lib.lib().cvp_cgls_set_tolerance(ctypes.c_void_p(w.data_ptr()), float(tol), ref, _stream()))
+
+    def run(self, tol=1e-3, max_iter=400, per_graph=20, use_graph=True, gamma_refs=None):
         """Iterate all problems until each has rho_k <= tol (or broke down),
-        checked every per_graph iterations, or max_iter.  Returns (per-problem
+        or max_iter; each problem stops on the device when it meets the
+        tolerance (its later work items are skipped), the host checks once
+        per replay.  rho_k = |s_k| / sqrt(gamma_ref) with gamma_refs per
+        problem (default: each run's own |s_0|^2).  Returns (per-problem
         iterations to reach tol, or the last iteration if not reached;
         seconds; per-problem rho histories)."""
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        self.set_tolerance(tol, gamma_refs)
         self.start()
         if use_graph and (self.graph is None or self.graph_iters != per_graph):
             self.capture(per_graph)
         done = 0
         while True:
-            rhos = self.rho()          # synchronises
-            brk = self.breakdown()
-            if all(r[-1] <= tol or b for r, b in zip(rhos, brk)) or done >= max_iter:
+            gh = self.gamma_histories()          # synchronises
+            refs = [g[0] for g in gh] if gamma_refs is None else list(gamma_refs)
+            rhos = [np.sqrt(np.maximum(g, 0.0) / r) for g, r in zip(gh, refs)]
+            brk, stp = self.breakdown(), self.stopped()
+            if all(r[-1] <= tol or b or s for r, b, s in zip(rhos, brk, stp)) or done >= max_iter:
                 break
             if use_graph:
                 self.replay()

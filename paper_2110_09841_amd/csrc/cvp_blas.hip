@@ -29,10 +29,13 @@ __device__ __forceinline__ double block_sum(double v, double *sh)
 }
 
 // partial[b] = sum over this block's elements of a[i] * c[i] (FP64)
+__device__ __forceinline__ bool stopped(const double *stop) { return stop && *stop != 0.0; }
+
 __global__ void __launch_bounds__(kRedThreads)
 dot_partials(const float *__restrict__ a, const float *__restrict__ c, int64_t n,
-             double *__restrict__ partial)
+             double *__restrict__ partial, const double *__restrict__ stop)
 {
+    if (stopped(stop)) return;
     __shared__ double sh[kRedThreads / 64];
     double acc = 0.0;
     const int64_t n4 = n / 4;
@@ -62,10 +65,13 @@ enum : int { kFinStart = 0, kFinQQ = 1, kFinGamma = 2, kFinRR = 3, kFinDot = 4 }
 //   QQ:    alpha = gamma / |q|^2   (|q| = 0: breakdown, alpha = 0)
 //   Gamma: gamma' = |s|^2, beta = gamma'/gamma, gamma = gamma', k += 1
 //   RR:    |r|^2 into the history
+// The stop flag is raised by a breakdown or when gamma falls to the threshold
+// (tol^2 times the reference gamma, fixed at the start).
 __global__ void __launch_bounds__(kRedThreads)
 finalize(const double *__restrict__ partial, int nparts, double *__restrict__ sc, int mode,
-         double *__restrict__ out)
+         double *__restrict__ out, const double *__restrict__ stop)
 {
+    if (stopped(stop)) return;
     __shared__ double sh[kRedThreads / 64];
     double acc = 0.0;
     // fixed assignment of partials to threads and a fixed tree: deterministic
@@ -79,6 +85,8 @@ finalize(const double *__restrict__ partial, int nparts, double *__restrict__ sc
     case kFinStart:
         sc[0] = s; sc[4] = s; sc[6] = 0.0; sc[7] = 0.0;
         hist_g[0] = s;
+        sc[kCglsThr] = sc[kCglsTol2] * (sc[kCglsRef] > 0.0 ? sc[kCglsRef] : s);
+        sc[kCglsStop] = (sc[kCglsThr] > 0.0 && s <= sc[kCglsThr]) ? 1.0 : 0.0;
         break;
     case kFinQQ:
         sc[1] = s;
@@ -87,6 +95,7 @@ finalize(const double *__restrict__ partial, int nparts, double *__restrict__ sc
         } else {
             sc[2] = 0.0;
             sc[7] = 1.0;   // breakdown: A p = 0
+            sc[kCglsStop] = 1.0;
         }
         break;
     case kFinGamma: {
@@ -95,6 +104,7 @@ finalize(const double *__restrict__ partial, int nparts, double *__restrict__ sc
         sc[0] = s;
         sc[6] = k + 1;
         if (k + 1 < kCglsHistory) hist_g[k + 1] = s;
+        if (sc[kCglsThr] > 0.0 && s <= sc[kCglsThr]) sc[kCglsStop] = 1.0;
         break;
     }
     case kFinRR:
@@ -111,8 +121,9 @@ finalize(const double *__restrict__ partial, int nparts, double *__restrict__ sc
 __global__ void __launch_bounds__(kRedThreads)
 update_xr(float *__restrict__ x, const float *__restrict__ p, int64_t nv, float *__restrict__ r,
           const float *__restrict__ q, int64_t np, const double *__restrict__ sc,
-          double *__restrict__ partial)
+          double *__restrict__ partial, const double *__restrict__ stop)
 {
+    if (stopped(stop)) return;
     __shared__ double sh[kRedThreads / 64];
     const float alpha = (float)sc[2];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -159,8 +170,9 @@ update_xr(float *__restrict__ x, const float *__restrict__ p, int64_t nv, float 
 // p = s + beta p   (beta from the device scalars; copy when init != 0)
 __global__ void __launch_bounds__(kRedThreads)
 update_p(float *__restrict__ p, const float *__restrict__ s, int64_t n, const double *__restrict__ sc,
-         int init)
+         int init, const double *__restrict__ stop)
 {
+    if (stopped(stop)) return;
     const float beta = init ? 0.0f : (float)sc[3];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -346,26 +358,41 @@ lsqr_finalize(const double *__restrict__ partial, int nparts, double *__restrict
 }  // namespace
 
 hipError_t blas_dot(const float *a, const float *b, int64_t n, double *partials, double *sc,
-                    int mode, double *out, hipStream_t s)
+                    int mode, double *out, hipStream_t s, const double *stop)
 {
-    hipLaunchKernelGGL(dot_partials, dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, b, n, partials);
-    hipLaunchKernelGGL(finalize, dim3(1), dim3(kRedThreads), 0, s, partials, kRedBlocks, sc, mode, out);
+    hipLaunchKernelGGL(dot_partials, dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, b, n, partials, stop);
+    hipLaunchKernelGGL(finalize, dim3(1), dim3(kRedThreads), 0, s, partials, kRedBlocks, sc, mode, out, stop);
     return hipGetLastError();
 }
 
 hipError_t blas_update_xr(float *x, const float *p, int64_t nv, float *r, const float *q, int64_t np,
-                          double *sc, double *partials, hipStream_t s)
+                          double *sc, double *partials, hipStream_t s, const double *stop)
 {
     hipLaunchKernelGGL(update_xr, dim3(kRedBlocks), dim3(kRedThreads), 0, s, x, p, nv, r, q, np, sc,
-                       partials);
+                       partials, stop);
     hipLaunchKernelGGL(finalize, dim3(1), dim3(kRedThreads), 0, s, partials, kRedBlocks, sc,
-                       (int)kFinRR, nullptr);
+                       (int)kFinRR, nullptr, stop);
     return hipGetLastError();
 }
 
-hipError_t blas_update_p(float *p, const float *sv, int64_t n, const double *sc, int init, hipStream_t s)
+hipError_t blas_update_p(float *p, const float *sv, int64_t n, const double *sc, int init, hipStream_t s,
+                         const double *stop)
 {
-    hipLaunchKernelGGL(update_p, dim3(kRedBlocks), dim3(kRedThreads), 0, s, p, sv, n, sc, init);
+    hipLaunchKernelGGL(update_p, dim3(kRedBlocks), dim3(kRedThreads), 0, s, p, sv, n, sc, init, stop);
+    return hipGetLastError();
+}
+
+__global__ void set_tolerance(double *sc, double tol2, double ref)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        sc[kCglsTol2] = tol2;
+        sc[kCglsRef] = ref;
+    }
+}
+
+hipError_t blas_set_tolerance(double *sc, double tol2, double ref, hipStream_t s)
+{
+    hipLaunchKernelGGL(set_tolerance, dim3(1), dim3(64), 0, s, sc, tol2, ref);
     return hipGetLastError();
 }
 
@@ -405,7 +432,7 @@ hipError_t lsqr_axpby_norm(float *y, const float *x, int64_t n, double *sc, int 
 hipError_t lsqr_norm(const float *a, int64_t n, double *sc, int mode, hipStream_t s)
 {
     double *part = sc + kLsqrScalars + 2 * kCglsHistory;
-    hipLaunchKernelGGL(dot_partials, dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, a, n, part);
+    hipLaunchKernelGGL(dot_partials, dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, a, n, part, nullptr);
     hipLaunchKernelGGL(lsqr_finalize, dim3(1), dim3(kRedThreads), 0, s, part, kRedBlocks, sc, mode);
     return hipGetLastError();
 }

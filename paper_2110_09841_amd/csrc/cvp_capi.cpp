@@ -207,89 +207,136 @@ void cvp_geometry_destroy(cvp_geometry *g)
     delete g;
 }
 
-cvp_status cvp_geometry_from_views(const cvp_geometry_desc *d, cvp_geometry **out)
-{
-    if (!out) return fail(CVP_E_INVALID, "out is NULL");
-    *out = nullptr;
-    if (!d) return fail(CVP_E_INVALID, "desc is NULL");
-    for (int a = 0; a < 3; ++a) {
-        if (d->vol_dims[a] <= 0 || d->vol_dims[a] > 16384)
-            return fail(CVP_E_INVALID, "vol_dims[%d] = %d (must be 1..16384)", a, d->vol_dims[a]);
-        if (!finite_pos(d->voxel_mm[a]))
-            return fail(CVP_E_INVALID, "voxel_mm[%d] must be finite and > 0", a);
-        if (!std::isfinite(d->vol_offset_mm[a]))
-            return fail(CVP_E_INVALID, "vol_offset_mm[%d] must be finite", a);
-    }
-    if (d->det_cols <= 0 || d->det_cols > 16384) return fail(CVP_E_INVALID, "det_cols = %d (must be 1..16384)", d->det_cols);
-    if (d->det_rows <= 0 || d->det_rows > 16384) return fail(CVP_E_INVALID, "det_rows = %d (must be 1..16384)", d->det_rows);
-    if (!finite_pos(d->pitch_mm[0]) || !finite_pos(d->pitch_mm[1]))
-        return fail(CVP_E_INVALID, "pitch_mm must be finite and > 0");
-    if (!finite_pos(d->source_iso_mm)) return fail(CVP_E_INVALID, "source_iso_mm must be finite and > 0");
-    if (!std::isfinite(d->source_det_mm) || !(d->source_det_mm > d->source_iso_mm))
-        return fail(CVP_E_INVALID, "source_det_mm must exceed source_iso_mm");
-    if (d->n_views < 1) return fail(CVP_E_INVALID, "n_views = %d (must be >= 1)", d->n_views);
-    if (!d->angles_rad) return fail(CVP_E_INVALID, "angles_rad is NULL");
-    for (int v = 0; v < d->n_views; ++v)
-        if (!std::isfinite(d->angles_rad[v])) return fail(CVP_E_INVALID, "angles_rad[%d] is not finite", v);
-    double c1 = d->principal_px[0], c2 = d->principal_px[1];
-    if (std::isnan(c1)) c1 = 0.5 * (d->det_cols - 1);
-    if (std::isnan(c2)) c2 = 0.5 * (d->det_rows - 1);
-    if (!std::isfinite(c1) || !std::isfinite(c2)) return fail(CVP_E_INVALID, "principal_px must be finite or NAN");
+}  // extern "C"
 
-    const int n1 = d->vol_dims[0], n2 = d->vol_dims[1], n3 = d->vol_dims[2];
-    const double a1 = d->voxel_mm[0], a2 = d->voxel_mm[1], a3 = d->voxel_mm[2];
-    const double x1lo = d->vol_offset_mm[0] - 0.5 * n1 * a1, x2lo = d->vol_offset_mm[1] - 0.5 * n2 * a2;
-    const double x3lo = d->vol_offset_mm[2] - 0.5 * n3 * a3;
-    // farthest point of the volume box from the rotation axis (x1x2 plane)
-    double rmax = 0.0;
-    for (int c = 0; c < 4; ++c) {
-        const double x = (c & 1) ? x1lo + n1 * a1 : x1lo, y = (c & 2) ? x2lo + n2 * a2 : x2lo;
-        rmax = std::max(rmax, std::hypot(x, y));
+namespace {
+
+// Volume and detector of a geometry under construction.
+struct VolDet {
+    int n1, n2, n3, M, N;
+    double a1, a2, a3;
+    double x1lo, x2lo, x3lo;
+};
+
+cvp_status check_vol_det(const int32_t dims[3], const double vox[3], const double off[3], int cols, int rows,
+                         VolDet &vd)
+{
+    for (int a = 0; a < 3; ++a) {
+        if (dims[a] <= 0 || dims[a] > 16384)
+            return fail(CVP_E_INVALID, "vol_dims[%d] = %d (must be 1..16384)", a, dims[a]);
+        if (!finite_pos(vox[a])) return fail(CVP_E_INVALID, "voxel_mm[%d] must be finite and > 0", a);
+        if (!std::isfinite(off[a])) return fail(CVP_E_INVALID, "vol_offset_mm[%d] must be finite", a);
     }
-    const double D = d->source_iso_mm, f = d->source_det_mm;
-    if (!(D > rmax * (1.0 + 1e-9)))
-        return fail(CVP_E_INVALID, "source_iso_mm = %g must exceed the volume's distance from the axis (%g): the source would enter the volume", D, rmax);
-    const double b1 = d->pitch_mm[0], b2 = d->pitch_mm[1];
-    const double Dmin = D - rmax;
-    // widest projected voxel base and tallest projected row extent (pixels)
-    const double wmax = std::hypot(a1, a2) * f / (b1 * (Dmin - 0.5 * std::hypot(a1, a2)));
+    if (cols <= 0 || cols > 16384) return fail(CVP_E_INVALID, "det_cols = %d (must be 1..16384)", cols);
+    if (rows <= 0 || rows > 16384) return fail(CVP_E_INVALID, "det_rows = %d (must be 1..16384)", rows);
+    vd.n1 = dims[0]; vd.n2 = dims[1]; vd.n3 = dims[2];
+    vd.a1 = vox[0]; vd.a2 = vox[1]; vd.a3 = vox[2];
+    vd.x1lo = off[0] - 0.5 * vd.n1 * vd.a1;
+    vd.x2lo = off[1] - 0.5 * vd.n2 * vd.a2;
+    vd.x3lo = off[2] - 0.5 * vd.n3 * vd.a3;
+    vd.M = cols; vd.N = rows;
+    return CVP_OK;
+}
+
+// Per-pixel factors of the second phase for one view's intrinsics: 1/solid
+// angle (eq. cvpus) and f^2 / (a cos^3 theta) (eq. cvp), FP64, stored FP32.
+// Pixel edges are taken in units of f ((t - c) / (f/b)).
+void pixel_factors(const cvp::ViewGeom &V, int M, int N, float *sa, float *cs)
+{
+    for (int v = 0; v < N; ++v) {
+        const double y0 = (v - 0.5 - V.c2) / V.fb2, y1 = (v + 0.5 - V.c2) / V.fb2, yc = (v - V.c2) / V.fb2;
+        for (int u = 0; u < M; ++u) {
+            const double x0 = (u - 0.5 - V.c1) / V.fb1, x1 = (u + 0.5 - V.c1) / V.fb1, xc = (u - V.c1) / V.fb1;
+            sa[(size_t)v * M + u] = (float)(1.0 / rect_solid_angle(1.0, x0, x1, y0, y1));
+            const double R = std::sqrt(xc * xc + yc * yc + 1.0);
+            cs[(size_t)v * M + u] = (float)(V.fb1 * V.fb2 * R * R * R);
+        }
+    }
+}
+
+// Planning constants of a circular orbit (closed forms over every angle).
+struct Circular {
+    double D, f, b1, b2, c1, c2, rmax;
+};
+
+// Builds the device tables and launch plans from per-view frames.  circ:
+// the orbit's constants (then the pixel factor tables keep the orbit's own
+// formulas in mm), or nullptr for general views.
+cvp_status finish_geometry(const VolDet &vd, std::vector<cvp::ViewGeom> &views, const Circular *circ,
+                           const double *angles, cvp_geometry **out)
+{
+    const int n1 = vd.n1, n2 = vd.n2, n3 = vd.n3, M = vd.M, N = vd.N;
+    const double a1 = vd.a1, a2 = vd.a2, a3 = vd.a3, hd = std::hypot(a1, a2);
+    const int V = (int)views.size();
+    // nearest depth of the volume in front of each source, farthest distance,
+    // height range about each source, widest projected voxel base and the
+    // rows the volume reaches
+    double Dmin = 1e300, rfar = 0.0, zabs = 0.0, wmax = 0.0, ymax = 0.0, om = 0.0, fb1max = 0.0, fb2max = 0.0;
+    for (int v = 0; v < V; ++v) {
+        const cvp::ViewGeom &W = views[v];
+        double dmin_v = 1e300, z_v = 0.0;
+        for (int c = 0; c < 8; ++c) {
+            const double x = vd.x1lo + ((c & 1) ? n1 * a1 : 0.0), y = vd.x2lo + ((c & 2) ? n2 * a2 : 0.0);
+            const double z = vd.x3lo + ((c & 4) ? n3 * a3 : 0.0);
+            const double dep = W.dx * (x - W.s1) + W.dy * (y - W.s2);
+            dmin_v = std::min(dmin_v, dep);
+            z_v = std::max(z_v, std::fabs(z - W.s3));
+            rfar = std::max(rfar, std::sqrt((x - W.s1) * (x - W.s1) + (y - W.s2) * (y - W.s2) + (z - W.s3) * (z - W.s3)));
+        }
+        if (circ) dmin_v = circ->D - circ->rmax;   // every angle of the orbit
+        if (!(dmin_v > hd))
+            return fail(CVP_E_INVALID, "view %d: the volume must lie in front of the source by more than a voxel "
+                                       "diagonal (nearest depth %g mm)", v, dmin_v);
+        Dmin = std::min(Dmin, dmin_v);
+        zabs = std::max(zabs, z_v);
+        wmax = std::max(wmax, hd * W.fb1 / (dmin_v - 0.5 * hd));
+        ymax = std::max(ymax, std::fabs(W.c2) + z_v * W.fb2 / dmin_v + 8.0);
+        om = std::max(om, 1.0 / (W.fb1 * W.fb2));
+        fb1max = std::max(fb1max, W.fb1);
+        fb2max = std::max(fb2max, W.fb2);
+    }
+    if (circ) {
+        zabs = std::max(std::fabs(vd.x3lo), std::fabs(vd.x3lo + n3 * a3));
+        rfar = std::hypot(circ->D + circ->rmax, zabs);
+        const double Dm = circ->D - circ->rmax;
+        wmax = hd * circ->f / (circ->b1 * (Dm - 0.5 * hd));
+        ymax = std::fabs(circ->c2) + zabs * circ->f / (circ->b2 * Dm) + 8.0;
+        om = circ->b1 * circ->b2 / (circ->f * circ->f);
+    }
     const int pieces = (int)std::floor(wmax) + 2;
-    if (!(Dmin > std::hypot(a1, a2)) || pieces > cvp::kPmaxWide)
+    if (pieces > cvp::kPmaxWide)
         return fail(CVP_E_UNSUPPORTED, "a voxel base projects onto up to %d detector columns (max %d)", pieces,
                     cvp::kPmaxWide);
-    const double zabs = std::max(std::fabs(x3lo), std::fabs(x3lo + n3 * a3));
-    const double ymax = std::fabs(c2) + zabs * f / (b2 * Dmin) + 8.0;
     if (ymax > 8000.0)
         return fail(CVP_E_UNSUPPORTED, "the volume projects up to %.0f rows from the detector origin (max 8000)", ymax);
 
     cvp_geometry *g = new (std::nothrow) cvp_geometry();
     if (!g) return fail(CVP_E_NOMEM, "host allocation");
-    g->angles.assign(d->angles_rad, d->angles_rad + d->n_views);
+    if (angles) g->angles.assign(angles, angles + V);
     g->nvox = (int64_t)n1 * n2 * n3;
-    g->npix = (int64_t)d->n_views * d->det_rows * d->det_cols;
+    g->npix = (int64_t)V * N * M;
 
-    // per-view frames (Sec. II-C), FP64
-    std::vector<cvp::ViewGeom> views(d->n_views);
-    for (int v = 0; v < d->n_views; ++v) {
-        const double l = d->angles_rad[v], cl = std::cos(l), sl = std::sin(l);
-        cvp::ViewGeom &V = views[v];
-        V.s1 = D * cl; V.s2 = D * sl; V.s3 = 0.0;
-        V.e1x = -sl; V.e1y = cl;
-        V.dx = -cl; V.dy = -sl;
-        V.pad = 0.0;
-    }
-    // per-pixel factors of the second phase: 1/solid angle (eq. cvpus) and
-    // f^2 / (a cos^3 theta) = R^3 / (b1 b2 f) (eq. cvp); FP64, stored FP32
-    const int M = d->det_cols, N = d->det_rows;
-    std::vector<float> sig_sa((size_t)M * N), sig_cos((size_t)M * N);
-    for (int v = 0; v < N; ++v) {
-        const double y0 = (v - 0.5 - c2) * b2, y1 = (v + 0.5 - c2) * b2, yc = (v - c2) * b2;
-        for (int u = 0; u < M; ++u) {
-            const double x0 = (u - 0.5 - c1) * b1, x1 = (u + 0.5 - c1) * b1, xc = (u - c1) * b1;
-            sig_sa[(size_t)v * M + u] = (float)(1.0 / rect_solid_angle(f, x0, x1, y0, y1));
-            const double R = std::sqrt(xc * xc + yc * yc + f * f);
-            sig_cos[(size_t)v * M + u] = (float)(R * R * R / (b1 * b2 * f));
+    // pixel factor tables: one for views that share their intrinsics, else one per view
+    bool shared = true;
+    for (int v = 1; v < V && shared; ++v)
+        shared = views[v].c1 == views[0].c1 && views[v].c2 == views[0].c2 && views[v].fb1 == views[0].fb1 &&
+                 views[v].fb2 == views[0].fb2;
+    const int ntab = shared ? 1 : V;
+    std::vector<float> sig_sa((size_t)ntab * M * N), sig_cos((size_t)ntab * M * N);
+    if (circ) {
+        const double c1 = circ->c1, c2 = circ->c2, b1 = circ->b1, b2 = circ->b2, f = circ->f;
+        for (int v = 0; v < N; ++v) {
+            const double y0 = (v - 0.5 - c2) * b2, y1 = (v + 0.5 - c2) * b2, yc = (v - c2) * b2;
+            for (int u = 0; u < M; ++u) {
+                const double x0 = (u - 0.5 - c1) * b1, x1 = (u + 0.5 - c1) * b1, xc = (u - c1) * b1;
+                sig_sa[(size_t)v * M + u] = (float)(1.0 / rect_solid_angle(f, x0, x1, y0, y1));
+                const double R = std::sqrt(xc * xc + yc * yc + f * f);
+                sig_cos[(size_t)v * M + u] = (float)(R * R * R / (b1 * b2 * f));
+            }
         }
+    } else {
+        for (int t = 0; t < ntab; ++t)
+            pixel_factors(views[t], M, N, sig_sa.data() + (size_t)t * M * N, sig_cos.data() + (size_t)t * M * N);
     }
 
     hipError_t e = hipGetDevice(&g->device);
@@ -307,22 +354,27 @@ cvp_status cvp_geometry_from_views(const cvp_geometry_desc *d, cvp_geometry **ou
     if (lds_err != hipSuccess) { cvp_geometry_destroy(g); return device_fail(lds_err, "kernel LDS attribute"); }
 
     cvp::DevGeom &G = g->base;
-    G.n1 = n1; G.n2 = n2; G.n3 = n3; G.M = M; G.N = N; G.nviews = d->n_views;
+    G.n1 = n1; G.n2 = n2; G.n3 = n3; G.M = M; G.N = N; G.nviews = V;
     G.a1 = a1; G.a2 = a2; G.a3 = a3;
-    G.x1lo = x1lo; G.x2lo = x2lo; G.x3lo = x3lo;
-    G.b1 = b1; G.b2 = b2; G.c1 = c1; G.c2 = c2; G.f = f;
-    G.fb1 = f / b1; G.fb2 = f / b2; G.b2f = b2 / f;
+    G.x1lo = vd.x1lo; G.x2lo = vd.x2lo; G.x3lo = vd.x3lo;
+    // planning values (the kernels read every view's own intrinsics)
+    G.fb1 = circ ? circ->f / circ->b1 : fb1max;
+    G.fb2 = circ ? circ->f / circ->b2 : fb2max;
+    G.b2f = 1.0 / G.fb2;
+    G.c1 = views[0].c1; G.c2 = views[0].c2;
+    G.f = circ ? circ->f : 1.0;
+    G.b1 = G.f / G.fb1; G.b2 = G.f / G.fb2;
     G.views = g->d_views;
     G.vstride = 1;
     G.sigma = nullptr;
+    G.sigma_views = shared ? 0 : 1;
     G.raw_volume = 0;
     {
         // Any pixel's summed weight per unit |mu| is at most its solid angle
         // (<= b1 b2 / f^2) times the integral of r^-2 r^2 dr (or of r^2 dr for
         // raw volumes) over the source distances the volume spans; 64 covers
         // the approximations of the cut volumes with a wide margin.
-        const double om = b1 * b2 / (f * f);
-        const double r0 = Dmin, r1 = std::hypot(D + rmax, zabs);
+        const double r0 = Dmin, r1 = rfar;
         G.wsum_bound = 64.0 * om * (r1 - r0);
         G.wsum_bound_raw = 64.0 * om * (r1 * r1 * r1 - r0 * r0 * r0) / 3.0;
         // One (voxel, pixel) weight is at most the voxel's cut volume (<= a1
@@ -337,7 +389,7 @@ cvp_status cvp_geometry_from_views(const cvp_geometry_desc *d, cvp_geometry **ou
     g->zabs = zabs;
     g->Dmin = Dmin;
     g->pmax = pmax;
-    if (!cvp::plan_projection(N, n2, M, d->n_views, pmax, 0, g->pl)) {
+    if (!cvp::plan_projection(N, n2, M, V, pmax, 0, g->pl)) {
         cvp_geometry_destroy(g);
         return fail(CVP_E_UNSUPPORTED, "detector rows (%d) or volume rows (%d) too large for the projection LDS layout", N, n2);
     }
@@ -347,6 +399,132 @@ cvp_status cvp_geometry_from_views(const cvp_geometry_desc *d, cvp_geometry **ou
     }
     *out = g;
     return ok();
+}
+
+// One view from a camera matrix P (row-major 3x4, world mm -> homogeneous
+// pixel-index coordinates).  With the sign of P fixed so that the volume
+// centre has positive depth and M = P[:, :3] normalised so that its third
+// row d has unit length: d must be horizontal; c1 = M1.d, c2 = M2.d;
+// M1 - c1 d = (f/b1) e1 with e1 horizontal (no skew); M2 - c2 d = -(f/b2) x3
+// (chi2 opposite to x3, Sec. III-A); the source is -M^-1 p4.
+cvp_status view_from_matrix(const double *Pm, const double ctr[3], int v, cvp::ViewGeom &W)
+{
+    double P[3][4];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 4; ++c) P[r][c] = Pm[4 * r + c];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 4; ++c)
+            if (!std::isfinite(P[r][c])) return fail(CVP_E_INVALID, "matrices[%d] has a non-finite entry", v);
+    const double w = P[2][0] * ctr[0] + P[2][1] * ctr[1] + P[2][2] * ctr[2] + P[2][3];
+    const double sgn = w < 0.0 ? -1.0 : 1.0;
+    const double n3 = std::sqrt(P[2][0] * P[2][0] + P[2][1] * P[2][1] + P[2][2] * P[2][2]);
+    if (!(n3 > 0.0) || w == 0.0) return fail(CVP_E_INVALID, "matrices[%d]: degenerate (the volume centre has no depth)", v);
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 4; ++c) P[r][c] *= sgn / n3;
+    const double tol = 1e-9;
+    const double *d = P[2];
+    if (std::fabs(d[2]) > tol)
+        return fail(CVP_E_UNSUPPORTED, "matrices[%d]: the principal ray is not horizontal (chi1 would depend on x3, "
+                                       "Sec. III-A convention)", v);
+    const double c1 = P[0][0] * d[0] + P[0][1] * d[1] + P[0][2] * d[2];
+    const double c2 = P[1][0] * d[0] + P[1][1] * d[1] + P[1][2] * d[2];
+    const double r1[3] = {P[0][0] - c1 * d[0], P[0][1] - c1 * d[1], P[0][2] - c1 * d[2]};
+    const double r2[3] = {P[1][0] - c2 * d[0], P[1][1] - c2 * d[1], P[1][2] - c2 * d[2]};
+    const double fb1 = std::hypot(r1[0], r1[1]), fb2 = -r2[2];
+    if (!(fb1 > 0.0) || std::fabs(r1[2]) > tol * fb1)
+        return fail(CVP_E_UNSUPPORTED, "matrices[%d]: chi1 depends on x3 (skew or tilted columns; Sec. III-A "
+                                       "convention)", v);
+    if (!(fb2 > 0.0))
+        return fail(CVP_E_UNSUPPORTED, "matrices[%d]: chi2 must run opposite to x3 (Sec. III-A convention)", v);
+    if (std::hypot(r2[0], r2[1]) > tol * fb2)
+        return fail(CVP_E_UNSUPPORTED, "matrices[%d]: chi2 depends on the horizontal position at fixed depth "
+                                       "(rolled detector)", v);
+    // source: M s = -p4 (Cramer's rule)
+    const double m00 = P[0][0], m01 = P[0][1], m02 = P[0][2], m10 = P[1][0], m11 = P[1][1], m12 = P[1][2];
+    const double m20 = P[2][0], m21 = P[2][1], m22 = P[2][2];
+    const double det = m00 * (m11 * m22 - m12 * m21) - m01 * (m10 * m22 - m12 * m20) + m02 * (m10 * m21 - m11 * m20);
+    if (!(std::fabs(det) > 0.0)) return fail(CVP_E_INVALID, "matrices[%d]: singular 3x3 part", v);
+    const double b0 = -P[0][3], b1 = -P[1][3], b2 = -P[2][3];
+    W.s1 = (b0 * (m11 * m22 - m12 * m21) - m01 * (b1 * m22 - m12 * b2) + m02 * (b1 * m21 - m11 * b2)) / det;
+    W.s2 = (m00 * (b1 * m22 - m12 * b2) - b0 * (m10 * m22 - m12 * m20) + m02 * (m10 * b2 - b1 * m20)) / det;
+    W.s3 = (m00 * (m11 * b2 - b1 * m21) - m01 * (m10 * b2 - b1 * m20) + b0 * (m10 * m21 - m11 * m20)) / det;
+    W.e1x = r1[0] / fb1; W.e1y = r1[1] / fb1;
+    W.dx = d[0]; W.dy = d[1];
+    W.c1 = c1; W.c2 = c2;
+    W.fb1 = fb1; W.fb2 = fb2; W.ifb2 = 1.0 / fb2;
+    return CVP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cvp_status cvp_geometry_from_views(const cvp_geometry_desc *d, cvp_geometry **out)
+{
+    if (!out) return fail(CVP_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!d) return fail(CVP_E_INVALID, "desc is NULL");
+    VolDet vd;
+    cvp_status st = check_vol_det(d->vol_dims, d->voxel_mm, d->vol_offset_mm, d->det_cols, d->det_rows, vd);
+    if (st != CVP_OK) return st;
+    if (!finite_pos(d->pitch_mm[0]) || !finite_pos(d->pitch_mm[1]))
+        return fail(CVP_E_INVALID, "pitch_mm must be finite and > 0");
+    if (!finite_pos(d->source_iso_mm)) return fail(CVP_E_INVALID, "source_iso_mm must be finite and > 0");
+    if (!std::isfinite(d->source_det_mm) || !(d->source_det_mm > d->source_iso_mm))
+        return fail(CVP_E_INVALID, "source_det_mm must exceed source_iso_mm");
+    if (d->n_views < 1) return fail(CVP_E_INVALID, "n_views = %d (must be >= 1)", d->n_views);
+    if (!d->angles_rad) return fail(CVP_E_INVALID, "angles_rad is NULL");
+    for (int v = 0; v < d->n_views; ++v)
+        if (!std::isfinite(d->angles_rad[v])) return fail(CVP_E_INVALID, "angles_rad[%d] is not finite", v);
+    double c1 = d->principal_px[0], c2 = d->principal_px[1];
+    if (std::isnan(c1)) c1 = 0.5 * (d->det_cols - 1);
+    if (std::isnan(c2)) c2 = 0.5 * (d->det_rows - 1);
+    if (!std::isfinite(c1) || !std::isfinite(c2)) return fail(CVP_E_INVALID, "principal_px must be finite or NAN");
+
+    // farthest point of the volume box from the rotation axis (x1x2 plane)
+    double rmax = 0.0;
+    for (int c = 0; c < 4; ++c) {
+        const double x = (c & 1) ? vd.x1lo + vd.n1 * vd.a1 : vd.x1lo, y = (c & 2) ? vd.x2lo + vd.n2 * vd.a2 : vd.x2lo;
+        rmax = std::max(rmax, std::hypot(x, y));
+    }
+    const double D = d->source_iso_mm, f = d->source_det_mm;
+    if (!(D > rmax * (1.0 + 1e-9)))
+        return fail(CVP_E_INVALID, "source_iso_mm = %g must exceed the volume's distance from the axis (%g): the source would enter the volume", D, rmax);
+    const double b1 = d->pitch_mm[0], b2 = d->pitch_mm[1];
+    if (!(D - rmax > std::hypot(vd.a1, vd.a2)))
+        return fail(CVP_E_UNSUPPORTED, "the source passes within a voxel diagonal of the volume");
+
+    // per-view frames (Sec. II-C), FP64
+    std::vector<cvp::ViewGeom> views(d->n_views);
+    for (int v = 0; v < d->n_views; ++v) {
+        const double l = d->angles_rad[v], cl = std::cos(l), sl = std::sin(l);
+        cvp::ViewGeom &V = views[v];
+        V.s1 = D * cl; V.s2 = D * sl; V.s3 = 0.0;
+        V.e1x = -sl; V.e1y = cl;
+        V.dx = -cl; V.dy = -sl;
+        V.c1 = c1; V.c2 = c2;
+        V.fb1 = f / b1; V.fb2 = f / b2; V.ifb2 = b2 / f;
+    }
+    const Circular circ{D, f, b1, b2, c1, c2, rmax};
+    return finish_geometry(vd, views, &circ, d->angles_rad, out);
+}
+
+cvp_status cvp_geometry_from_matrices(const cvp_geometry_matrices_desc *d, cvp_geometry **out)
+{
+    if (!out) return fail(CVP_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!d) return fail(CVP_E_INVALID, "desc is NULL");
+    VolDet vd;
+    cvp_status st = check_vol_det(d->vol_dims, d->voxel_mm, d->vol_offset_mm, d->det_cols, d->det_rows, vd);
+    if (st != CVP_OK) return st;
+    if (d->n_views < 1) return fail(CVP_E_INVALID, "n_views = %d (must be >= 1)", d->n_views);
+    if (!d->matrices) return fail(CVP_E_INVALID, "matrices is NULL");
+    std::vector<cvp::ViewGeom> views(d->n_views);
+    for (int v = 0; v < d->n_views; ++v) {
+        st = view_from_matrix(d->matrices + (size_t)12 * v, d->vol_offset_mm, v, views[v]);
+        if (st != CVP_OK) return st;
+    }
+    return finish_geometry(vd, views, nullptr, nullptr, out);
 }
 
 cvp_status cvp_geometry_get_launch(const cvp_geometry *g, cvp_launch *out)
@@ -518,6 +696,7 @@ static cvp_status view_subset(const cvp_geometry *g, int32_t view0, int32_t stri
     G.vstride = stride;
     G.nviews = count;
     proj_offset = (int64_t)view0 * G.N * G.M;
+    if (G.sigma && G.sigma_views) G.sigma += proj_offset;
     return CVP_OK;
 }
 
@@ -569,11 +748,12 @@ struct cvp_batch {
     int device = 0;
     std::vector<const cvp_geometry *> geoms;
     cvp::BatchProblem *d_probs = nullptr;
-    cvp::BatchTable *d_ptab = nullptr, *d_btab = nullptr;
-    int *d_counter = nullptr;
+    cvp::BatchTable *d_ptab = nullptr;
+    cvp::BatchTable *d_btab[3] = {nullptr, nullptr, nullptr};   // backprojection: stack widths 16, 8, 4
+    int *d_counter = nullptr;         // [0] projection, [1 + g] backprojection group g
     std::vector<unsigned *> d_gmax;   // per problem: per-group maxima of the volume
-    size_t plds = 0, blds = 0;
-    int pgrid = 0, bgrid = 0;
+    size_t plds = 0, blds[3] = {0, 0, 0};
+    int pgrid = 0, bgrid[3] = {0, 0, 0};
 };
 
 extern "C" {
@@ -583,7 +763,8 @@ void cvp_batch_destroy(cvp_batch *b)
     if (!b) return;
     if (b->d_probs) (void)hipFree(b->d_probs);
     if (b->d_ptab) (void)hipFree(b->d_ptab);
-    if (b->d_btab) (void)hipFree(b->d_btab);
+    for (cvp::BatchTable *t : b->d_btab)
+        if (t) (void)hipFree(t);
     if (b->d_counter) (void)hipFree(b->d_counter);
     for (unsigned *t : b->d_gmax)
         if (t) (void)hipFree(t);
@@ -609,19 +790,40 @@ cvp_status cvp_batch_create(const cvp_geometry *const *geoms, int32_t n, cvp_bat
     b->n = n;
     b->device = geoms[0]->device;
     b->geoms.assign(geoms, geoms + n);
-    // every problem runs with its own single-problem plans (the batched
-    // kernels dispatch on the piece stride and stack width per item), so its
-    // results are those of its own launches; one dynamic LDS size fits all
+    // Projection: every problem keeps its own plan (the batched kernel
+    // dispatches on the piece stride per item), so its results are those of
+    // its own launches.  Backprojection: every problem keeps its own stack
+    // width (with 8-piece records), and the batch runs one persistent launch
+    // per width present; backprojection sums do not depend on the plan, so
+    // the results still equal single launches bitwise.  One dynamic LDS size
+    // fits all items of a launch.
+    static const int kGw[3] = {16, 8, 4};
+    std::vector<cvp::BackLaunch> bls(n);
+    std::vector<int> grp(n);
+    for (int q = 0; q < n; ++q) {
+        // the member's own stack width, else the next narrower one whose
+        // 8-piece records fit
+        bool planned = false;
+        for (int gi = 0; gi < 3 && !planned; ++gi) {
+            if (kGw[gi] > geoms[q]->bl.gw) continue;
+            planned = cvp::plan_backprojection(geoms[q]->base, 8, geoms[q]->zabs, geoms[q]->Dmin, kGw[gi], 0, bls[q]);
+            grp[q] = gi;
+        }
+        if (!planned) {
+            delete b;
+            return fail(CVP_E_UNSUPPORTED, "geoms[%d]: batched backprojection plan does not fit LDS", q);
+        }
+    }
     std::vector<cvp::BatchProblem> probs(n);
     std::vector<double> pcost(n), bcost(n);
     for (int q = 0; q < n; ++q) {
         const cvp_geometry *g = geoms[q];
         const cvp::ProjLaunch &pl = g->pl;
-        const cvp::BackLaunch &bl = g->bl;
+        const cvp::BackLaunch &bl = bls[q];
         cvp::BatchProblem &P = probs[q];
         P.G = g->base;
         P.U = pl.U;
-        P.pmax = bl.pmax;
+        P.pmax = pl.pmax;
         P.gw = bl.gw;
         P.kp = bl.kp;
         P.win_cap = bl.win_cap;
@@ -632,31 +834,40 @@ cvp_status cvp_batch_create(const cvp_geometry *const *geoms, int32_t n, cvp_bat
         P.in = nullptr;
         P.out = nullptr;
         P.gmax = nullptr;   // set below
+        P.stop = nullptr;   // set per call
         b->plds = std::max(b->plds, pl.lds);
-        b->blds = std::max(b->blds, bl.lds);
+        b->blds[grp[q]] = std::max(b->blds[grp[q]], bl.lds);
         pcost[q] = (double)g->nvox / pl.nbands;           // voxels per band (all k)
         bcost[q] = (double)g->base.nviews;                // views per voxel stack
     }
-    auto table = [&](const std::vector<double> &cost, bool back) {
+    // work segments of the members in `sel`, largest items first
+    auto table = [&](const std::vector<double> &cost, bool back, int sel) {
         cvp::BatchTable T{};
-        std::vector<int> ord(n);
-        for (int q = 0; q < n; ++q) ord[q] = q;
+        std::vector<int> ord;
+        for (int q = 0; q < n; ++q)
+            if (sel < 0 || grp[q] == sel) ord.push_back(q);
         std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return cost[x] > cost[y]; });
-        T.n = n;
+        T.n = (int)ord.size();
         T.start[0] = 0;
-        for (int q = 0; q < n; ++q) {
+        for (int q = 0; q < T.n; ++q) {
             T.order[q] = ord[q];
             T.start[q + 1] = T.start[q] + (back ? probs[ord[q]].bitems : probs[ord[q]].pitems);
         }
         return T;
     };
-    const cvp::BatchTable pt = table(pcost, false), bt = table(bcost, true);
+    const cvp::BatchTable pt = table(pcost, false, -1);
     int cus = 0;
     hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
     if (e == hipSuccess) e = hipMalloc((void **)&b->d_probs, n * sizeof(cvp::BatchProblem));
     if (e == hipSuccess) e = hipMalloc((void **)&b->d_ptab, sizeof(cvp::BatchTable));
-    if (e == hipSuccess) e = hipMalloc((void **)&b->d_btab, sizeof(cvp::BatchTable));
-    if (e == hipSuccess) e = hipMalloc((void **)&b->d_counter, 2 * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_counter, 4 * sizeof(int));
+    for (int gi = 0; gi < 3 && e == hipSuccess; ++gi) {
+        if (b->blds[gi] == 0) continue;   // no member with this width
+        const cvp::BatchTable bt = table(bcost, true, gi);
+        e = hipMalloc((void **)&b->d_btab[gi], sizeof(cvp::BatchTable));
+        if (e == hipSuccess) e = hipMemcpy(b->d_btab[gi], &bt, sizeof(bt), hipMemcpyHostToDevice);
+        b->bgrid[gi] = cus * cvp::batched_blocks_per_cu(true, b->blds[gi], kGw[gi]);
+    }
     b->d_gmax.assign(n, nullptr);
     for (int q = 0; q < n && e == hipSuccess; ++q) {
         e = hipMalloc((void **)&b->d_gmax[q], cvp::group_max_cells(probs[q].G) * sizeof(unsigned));
@@ -664,16 +875,14 @@ cvp_status cvp_batch_create(const cvp_geometry *const *geoms, int32_t n, cvp_bat
     }
     if (e == hipSuccess) e = hipMemcpy(b->d_probs, probs.data(), n * sizeof(cvp::BatchProblem), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b->d_ptab, &pt, sizeof(pt), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(b->d_btab, &bt, sizeof(bt), hipMemcpyHostToDevice);
     if (e != hipSuccess) { cvp_batch_destroy(b); return device_fail(e, "batch tables"); }
-    b->pgrid = cus * cvp::batched_blocks_per_cu(false, b->plds);
-    b->bgrid = cus * cvp::batched_blocks_per_cu(true, b->blds);
+    b->pgrid = cus * cvp::batched_blocks_per_cu(false, b->plds, 16);
     *out = b;
     return ok();
 }
 
 static cvp_status batched(const cvp_batch *b, const cvp_options *o, const float *const *ins,
-                          float *const *outs, void *stream, bool backward)
+                          float *const *outs, void *stream, bool backward, const double *const *stops = nullptr)
 {
     if (!b) return fail(CVP_E_INVALID, "batch is NULL");
     if (!o) return fail(CVP_E_INVALID, "options is NULL");
@@ -688,19 +897,28 @@ static cvp_status batched(const cvp_batch *b, const cvp_options *o, const float 
         io.in[q] = ins[q];
         io.out[q] = outs[q];
         io.sigma[q] = G.sigma;
+        io.stop[q] = stops ? stops[q] : nullptr;
     }
     if (!backward) {
         // per-group maxima of every volume, for the projection items' scales
         for (int q = 0; q < b->n; ++q) {
-            hipError_t e = cvp::launch_group_max(b->geoms[q]->base, ins[q], b->d_gmax[q], (hipStream_t)stream);
+            hipError_t e = cvp::launch_group_max(b->geoms[q]->base, ins[q], b->d_gmax[q], (hipStream_t)stream,
+                                                 io.stop[q]);
             if (e != hipSuccess) return device_fail(e, "batched group maxima");
         }
     }
-    hipError_t e = cvp::launch_batched(backward, b->d_probs, backward ? b->d_btab : b->d_ptab,
-                                       b->d_counter, io,
-                                       o->variant == CVP_EXACT, o->elevation_correction != 0,
-                                       backward ? b->bgrid : b->pgrid, backward ? b->blds : b->plds,
-                                       (hipStream_t)stream);
+    const bool ex = o->variant == CVP_EXACT, ec = o->elevation_correction != 0;
+    hipError_t e = hipSuccess;
+    if (!backward) {
+        e = cvp::launch_batched(false, b->d_probs, b->d_ptab, b->d_counter, io, ex, ec, b->pgrid, b->plds, 16,
+                                (hipStream_t)stream);
+    } else {
+        static const int kGw[3] = {16, 8, 4};
+        for (int gi = 0; gi < 3 && e == hipSuccess; ++gi)
+            if (b->d_btab[gi])
+                e = cvp::launch_batched(true, b->d_probs, b->d_btab[gi], b->d_counter + 1 + gi, io, ex, ec,
+                                        b->bgrid[gi], b->blds[gi], kGw[gi], (hipStream_t)stream);
+    }
     if (e != hipSuccess) return device_fail(e, "batched launch");
     return ok();
 }
@@ -773,14 +991,16 @@ cvp_status cvp_cgls_iterate(const cvp_geometry *g, const cvp_options *o, int32_t
     double *sc = (double *)d_work;
     double *part = sc + cvp::kCglsScalars + 2 * cvp::kCglsHistory;
     const bool ex = o->variant == CVP_EXACT, ec = o->elevation_correction != 0;
+    // every kernel of an iteration returns at once once the stop flag is up
+    const double *stop = sc + cvp::kCglsStop;
     hipError_t e = hipSuccess;
     for (int it = 0; it < n_iter && e == hipSuccess; ++it) {
-        e = cvp::launch_project(G, g->pl, ex, ec, d_p, d_q, (unsigned *)d_s, sm);       // q = A p (s free)
-        if (e == hipSuccess) e = cvp::blas_dot(d_q, d_q, g->npix, part, sc, 1, nullptr, sm);   // alpha
-        if (e == hipSuccess) e = cvp::blas_update_xr(d_x, d_p, g->nvox, d_r, d_q, g->npix, sc, part, sm);
-        if (e == hipSuccess) e = cvp::launch_backproject(G, g->bl, ex, ec, d_r, d_s, sm);   // s = A^T r
-        if (e == hipSuccess) e = cvp::blas_dot(d_s, d_s, g->nvox, part, sc, 2, nullptr, sm);   // beta
-        if (e == hipSuccess) e = cvp::blas_update_p(d_p, d_s, g->nvox, sc, 0, sm);           // p
+        e = cvp::launch_project(G, g->pl, ex, ec, d_p, d_q, (unsigned *)d_s, sm, stop);       // q = A p (s free)
+        if (e == hipSuccess) e = cvp::blas_dot(d_q, d_q, g->npix, part, sc, 1, nullptr, sm, stop);   // alpha
+        if (e == hipSuccess) e = cvp::blas_update_xr(d_x, d_p, g->nvox, d_r, d_q, g->npix, sc, part, sm, stop);
+        if (e == hipSuccess) e = cvp::launch_backproject(G, g->bl, ex, ec, d_r, d_s, sm, stop);   // s = A^T r
+        if (e == hipSuccess) e = cvp::blas_dot(d_s, d_s, g->nvox, part, sc, 2, nullptr, sm, stop);   // beta
+        if (e == hipSuccess) e = cvp::blas_update_p(d_p, d_s, g->nvox, sc, 0, sm, stop);           // p
     }
     if (e != hipSuccess) return device_fail(e, "cgls iterate");
     return ok();
@@ -858,24 +1078,28 @@ cvp_status cvp_cgls_batched_iterate(const cvp_batch *bt, const cvp_options *o, i
     if (st != CVP_OK) return st;
     hipStream_t sm = (hipStream_t)stream;
     const int n = bt->n;
+    // each problem's kernels and work items are skipped once its stop flag is up
+    const double *stops[cvp::kMaxBatch];
+    for (int k = 0; k < n; ++k) stops[k] = cgls_scalars(d_work[k]) + cvp::kCglsStop;
     hipError_t e = hipSuccess;
     for (int it = 0; it < n_iter; ++it) {
-        st = batched(bt, o, (const float *const *)d_p, d_q, stream, false);         // q = A p
+        st = batched(bt, o, (const float *const *)d_p, d_q, stream, false, stops);  // q = A p
         if (st != CVP_OK) return st;
         for (int k = 0; k < n && e == hipSuccess; ++k) {
             const cvp_geometry *g = bt->geoms[k];
             double *sc = cgls_scalars(d_work[k]), *part = cgls_partials(d_work[k]);
-            e = cvp::blas_dot(d_q[k], d_q[k], g->npix, part, sc, 1, nullptr, sm);        // alpha
-            if (e == hipSuccess) e = cvp::blas_update_xr(d_x[k], d_p[k], g->nvox, d_r[k], d_q[k], g->npix, sc, part, sm);
+            e = cvp::blas_dot(d_q[k], d_q[k], g->npix, part, sc, 1, nullptr, sm, stops[k]);   // alpha
+            if (e == hipSuccess)
+                e = cvp::blas_update_xr(d_x[k], d_p[k], g->nvox, d_r[k], d_q[k], g->npix, sc, part, sm, stops[k]);
         }
         if (e != hipSuccess) break;
-        st = batched(bt, o, (const float *const *)d_r, d_s, stream, true);          // s = A^T r
+        st = batched(bt, o, (const float *const *)d_r, d_s, stream, true, stops);   // s = A^T r
         if (st != CVP_OK) return st;
         for (int k = 0; k < n && e == hipSuccess; ++k) {
             const int64_t nv = bt->geoms[k]->nvox;
             double *sc = cgls_scalars(d_work[k]), *part = cgls_partials(d_work[k]);
-            e = cvp::blas_dot(d_s[k], d_s[k], nv, part, sc, 2, nullptr, sm);             // beta
-            if (e == hipSuccess) e = cvp::blas_update_p(d_p[k], d_s[k], nv, sc, 0, sm);  // p
+            e = cvp::blas_dot(d_s[k], d_s[k], nv, part, sc, 2, nullptr, sm, stops[k]);        // beta
+            if (e == hipSuccess) e = cvp::blas_update_p(d_p[k], d_s[k], nv, sc, 0, sm, stops[k]);   // p
         }
         if (e != hipSuccess) break;
     }
@@ -1019,6 +1243,17 @@ cvp_status cvp_lsqr_iterate(const cvp_geometry *g, const cvp_options *o, int32_t
         if (e == hipSuccess) e = cvp::lsqr_update_vxw(d_v, d_x, d_w, g->nvox, sc, 0, sm);       // v, x, w
     }
     if (e != hipSuccess) return device_fail(e, "lsqr iterate");
+    return ok();
+}
+
+cvp_status cvp_cgls_set_tolerance(void *d_work, double rho_tol, double gamma_ref, void *stream)
+{
+    if (!d_work) return fail(CVP_E_INVALID, "work is NULL");
+    if (reinterpret_cast<uintptr_t>(d_work) & 7) return fail(CVP_E_INVALID, "work must be 8-byte aligned");
+    if (!std::isfinite(rho_tol) || rho_tol < 0.0) return fail(CVP_E_INVALID, "rho_tol must be finite and >= 0");
+    if (!std::isfinite(gamma_ref) || gamma_ref < 0.0) return fail(CVP_E_INVALID, "gamma_ref must be finite and >= 0");
+    hipError_t e = cvp::blas_set_tolerance((double *)d_work, rho_tol * rho_tol, gamma_ref, (hipStream_t)stream);
+    if (e != hipSuccess) return device_fail(e, "cgls tolerance");
     return ok();
 }
 

@@ -22,14 +22,18 @@ constexpr float kYQuantumInv = 1024.0f;
 constexpr int kBackPasses = 2;        // most 64-voxel passes per backprojection stack
 constexpr int kPmaxWide = 64;         // pieces per column of the wide-footprint backprojection
 
-// Per-view source-centred frame (Sec. II-C), FP64.  e1 and d have no x3
-// component on a circular orbit (that is what makes chi1 independent of x3,
-// the column identity of Sec. III-A); chi2 runs along -x3.
+// Per-view source-centred frame (Sec. II-C) and intrinsics, FP64.  e1 and d
+// have no x3 component (that is what makes chi1 independent of x3, the column
+// identity of Sec. III-A); chi2 runs along -x3.  A projection matrix of the
+// view is K [R | -R s] with rows of R e1, (0,0,-1), d and
+// K = [[fb1, 0, c1], [0, fb2, c2], [0, 0, 1]] (Sec. III-C).
 struct ViewGeom {
     double s1, s2, s3;   // source position
     double e1x, e1y;     // detector chi1 axis
     double dx, dy;       // principal ray direction
-    double pad;
+    double c1, c2;       // principal point (pixel-index units)
+    double fb1, fb2;     // f / b1, f / b2
+    double ifb2;         // b2 / f
 };
 
 // Everything a kernel needs about one problem.  Passed by value.
@@ -44,7 +48,8 @@ struct DevGeom {
     const ViewGeom *views;     // device; view q of a launch is views[q * vstride]
     int vstride;               // view stride: a launch may cover views v0, v0 + vstride, ... (views and
                                // the projection pointer start at v0; 1 for all views)
-    const float *sigma;        // device, [N][M] pixel factors (nullptr: 1)
+    const float *sigma;        // device pixel factors (nullptr: 1): [N][M], or [views][N][M] if sigma_views
+    int sigma_views;           // 1: one factor table per view (views with their own intrinsics)
     int raw_volume;            // weight = cut volume (no 1/r^2)
     // Bounds on any pixel's weight sum per unit |mu| (with and without the
     // 1/r^2 factor), used to scale the projection's fixed-point sums.
@@ -80,8 +85,8 @@ struct BatchProblem {        // device table entry (one per problem)
     DevGeom G;
     int U;                   // projection band width
     int pitems;              // projection work items
-    int pmax;                // the problem's own single-problem plan: piece stride,
-    int gw;                  // backprojection stack width,
+    int pmax;                // the problem's projection piece stride (its own plan),
+    int gw;                  // the batch's backprojection stack width,
     int kp;                  // passes per stack
     int win_cap;             // and per-wave window (floats)
     int ngroups;             // backprojection column groups per row
@@ -90,6 +95,7 @@ struct BatchProblem {        // device table entry (one per problem)
     const float *in;         // set per call by batch_setup
     float *out;
     unsigned *gmax;          // the problem's per-group maxima (owned by the batch)
+    const double *stop;      // set per call: the problem's work items are skipped while *stop != 0
 };
 
 struct BatchTable {          // device: work segments, largest items first
@@ -104,17 +110,23 @@ struct BatchIO {             // per call, by value
     const float *in[kMaxBatch];
     float *out[kMaxBatch];
     const float *sigma[kMaxBatch];
+    const double *stop[kMaxBatch];   // per problem, or nullptr
 };
 
+// gw: the batch's backprojection stack width (16 or 4)
 hipError_t launch_batched(bool backward, BatchProblem *probs, const BatchTable *tab, int *counter,
-                          const BatchIO &io, bool exact, bool ec, int grid, size_t lds, hipStream_t s);
-int batched_blocks_per_cu(bool backward, size_t lds);
+                          const BatchIO &io, bool exact, bool ec, int grid, size_t lds, int gw, hipStream_t s);
+int batched_blocks_per_cu(bool backward, size_t lds, int gw);
 size_t project_lds_bytes(int U, int N, int n2, int pmax);
 size_t backproject_lds_bytes(int gw, int pmax, int winCap);
 
 // CGLS workspace (FP64): scalars, then the |s|^2 and |r|^2 histories, then the
 // reduction partials.
-constexpr int kCglsScalars = 8;      // gamma, |q|^2, alpha, beta, gamma0, |r|^2, k, breakdown
+// Scalars: [0] gamma [1] |q|^2 [2] alpha [3] beta [4] gamma0 [5] |r|^2 [6] k
+// [7] breakdown [8] stop flag [9] gamma threshold of the stop (0: none)
+// [10] tol^2 and [11] reference gamma (0: gamma0) set by cvp_cgls_set_tolerance
+constexpr int kCglsScalars = 16;
+constexpr int kCglsStop = 8, kCglsThr = 9, kCglsTol2 = 10, kCglsRef = 11;
 constexpr int kCglsHistory = 4096;
 constexpr int kCglsPartials = 1024;
 constexpr int64_t kCglsWorkDoubles = kCglsScalars + 2 * kCglsHistory + kCglsPartials;
@@ -136,20 +148,25 @@ hipError_t lsqr_axpby_norm(float *y, const float *x, int64_t n, double *sc, int 
 hipError_t lsqr_norm(const float *a, int64_t n, double *sc, int mode, hipStream_t s);
 hipError_t lsqr_scale(float *y, int64_t n, const double *sc, int ci, hipStream_t s);
 hipError_t lsqr_update_vxw(float *v, float *x, float *w, int64_t n, const double *sc, int init, hipStream_t s);
+// stop: optional device flag; a kernel returns at once while *stop != 0 (a
+// converged CGLS keeps its state through the rest of a captured graph).
 hipError_t blas_dot(const float *a, const float *b, int64_t n, double *partials, double *sc,
-                    int mode, double *out, hipStream_t s);
+                    int mode, double *out, hipStream_t s, const double *stop = nullptr);
 hipError_t blas_update_xr(float *x, const float *p, int64_t nv, float *r, const float *q, int64_t np,
-                          double *sc, double *partials, hipStream_t s);
+                          double *sc, double *partials, hipStream_t s, const double *stop = nullptr);
 hipError_t blas_update_p(float *p, const float *sv, int64_t n, const double *sc, int init,
-                         hipStream_t s);
+                         hipStream_t s, const double *stop = nullptr);
+hipError_t blas_set_tolerance(double *sc, double tol2, double ref, hipStream_t s);
 hipError_t blas_residual(float *r, const float *b, const float *q, int64_t n, hipStream_t s);
 
 // gmax: device scratch of group_max_cells(g) words for the per-group maxima
 // of |vol| (computed by the call), or nullptr (the kernel scans the wedges).
 hipError_t launch_project(const DevGeom &g, const ProjLaunch &L, bool exact, bool ec,
-                          const float *vol, float *proj, unsigned *gmax, hipStream_t stream);
+                          const float *vol, float *proj, unsigned *gmax, hipStream_t stream,
+                          const double *stop = nullptr);
 int64_t group_max_cells(const DevGeom &g);
-hipError_t launch_group_max(const DevGeom &g, const float *vol, unsigned *gmax, hipStream_t stream);
+hipError_t launch_group_max(const DevGeom &g, const float *vol, unsigned *gmax, hipStream_t stream,
+                            const double *stop = nullptr);
 // Allocation-free projection: device address (on the current device) of the
 // library's fixed scratch array for the per-group maxima, looked up once per
 // device; kStaticScratchWords words (1 MiB).
@@ -158,6 +175,6 @@ hipError_t static_scratch(unsigned **out);
 // SiddonK reference projector: K x K rays per pixel, exact chord lengths.
 hipError_t launch_siddon(const DevGeom &g, int K, const float *vol, float *proj, hipStream_t s);
 hipError_t launch_backproject(const DevGeom &g, const BackLaunch &L, bool exact, bool ec,
-                              const float *proj, float *vol, hipStream_t stream);
+                              const float *proj, float *vol, hipStream_t stream, const double *stop = nullptr);
 
 }  // namespace cvp

@@ -128,14 +128,14 @@ __device__ __forceinline__ Column make_column(const DevGeom &G, const ViewGeom &
     const double P1 = V.e1x * r1 + V.e1y * r2;
     C.Dc = V.dx * r1 + V.dy * r2;
     C.iDc = 1.0 / C.Dc;
-    const double fb = G.fb1;
-    C.chic = G.c1 + fb * P1 * C.iDc;
+    const double fb = V.fb1;
+    C.chic = V.c1 + fb * P1 * C.iDc;
     double mn = 1e300, mx = -1e300;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const double q1 = (k & 1) ? 0.5 * G.a1 : -0.5 * G.a1;
         const double q2 = (k & 2) ? 0.5 * G.a2 : -0.5 * G.a2;
-        const double ch = G.c1 + fb * (P1 + V.e1x * q1 + V.e1y * q2) / (C.Dc + V.dx * q1 + V.dy * q2);
+        const double ch = V.c1 + fb * (P1 + V.e1x * q1 + V.e1y * q2) / (C.Dc + V.dx * q1 + V.dy * q2);
         mn = fmin(mn, ch);
         mx = fmax(mx, ch);
     }
@@ -148,10 +148,10 @@ __device__ __forceinline__ Mom column_prefix(const DevGeom &G, const ViewGeom &V
                                              double t)
 {
 #pragma clang fp contract(off)
-    const double fb = G.fb1;
+    const double fb = V.fb1;
     const double inv = C.iDc;
-    const double gx = (fb * V.e1x - (t - G.c1) * V.dx) * inv;
-    const double gy = (fb * V.e1y - (t - G.c1) * V.dy) * inv;
+    const double gx = (fb * V.e1x - (t - V.c1) * V.dx) * inv;
+    const double gy = (fb * V.e1y - (t - V.c1) * V.dy) * inv;
     return halfplane_moments(0.5 * G.a1, 0.5 * G.a2, gx, gy, C.chic - t);
 }
 
@@ -183,9 +183,9 @@ __device__ __forceinline__ void piece_record(const DevGeom &G, const ViewGeom &V
     }
     const double Du = C.Dc + V.dx * cx + V.dy * cy;
     const double iDu = 1.0 / Du;
-    const double gmm = G.b2f * Du;               // x3 mm per detector row at depth Du
-    const double ig = G.fb2 * iDu;
-    const double Y0 = G.c2 - (G.x3lo + G.a3 - V.s3) * ig;
+    const double gmm = V.ifb2 * Du;              // x3 mm per detector row at depth Du
+    const double ig = V.fb2 * iDu;
+    const double Y0 = V.c2 - (G.x3lo + G.a3 - V.s3) * ig;
     const double beta = G.a3 * ig;
     const double Y0h = rint(Y0 * 1024.0) * (1.0 / 1024.0);
     const double bh = rint(beta * 1024.0) * (1.0 / 1024.0);
@@ -472,7 +472,7 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
     // [u0 - 1/2, ub + 1/2].  chi1 is monotone in x1, so the hits are
     // contiguous in the group index.  FP32 with a margin is conservative.
     {
-        const float fb = (float)(G.f / G.b1);
+        const float fb = (float)V.fb1;
         const float e1x = (float)V.e1x, e1y = (float)V.e1y, dx = (float)V.dx, dy = (float)V.dy;
         const float lo_t = u0 - 0.5f - 0.02f, hi_t = ub + 0.5f + 0.02f;
         const int rows_per = (G.n2 + kBlock - 1) / kBlock;
@@ -489,7 +489,7 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const float px = (k & 1) ? x1 : x0, py = (k & 2) ? y1 : y0;
-                    const float ch = (float)G.c1 + fb * (e1x * px + e1y * py) / (dx * px + dy * py);
+                    const float ch = (float)V.c1 + fb * (e1x * px + e1y * py) / (dx * px + dy * py);
                     mn = fminf(mn, ch);
                     mx = fmaxf(mx, ch);
                 }
@@ -527,7 +527,7 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
     }
     const int total = rowStart[G.n2];
 
-    const float c2f = (float)G.c2;
+    const float c2f = (float)V.c2;
     const float a3f = (float)G.a3;
     const float zt0 = (float)(G.x3lo + G.a3 - V.s3);   // x3 of the top of voxel 0, minus s3
     const bool raw = G.raw_volume != 0;
@@ -689,7 +689,7 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
         const int du = idx % Ub, v = idx / Ub;
         const int u = u0 + du;
         float s = finite ? (float)ldexp(fixed_to_double(bins[du * Npad + v]), -sc) : __builtin_nanf("");
-        if (G.sigma) s *= G.sigma[(size_t)v * G.M + u];
+        if (G.sigma) s *= G.sigma[((size_t)view * G.vstride * G.sigma_views * G.N + v) * G.M + u];
         proj[((size_t)view * G.vstride * G.N + v) * G.M + u] = s;
     }
 }
@@ -702,9 +702,10 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
 template <bool EXACT, bool EC, int PMAX>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5)))
 project_kernel(const DevGeom G, const int U, const int nbands, const float *__restrict__ vol,
-               float *__restrict__ proj, const unsigned *__restrict__ gmax)
+               float *__restrict__ proj, const unsigned *__restrict__ gmax, const double *__restrict__ stop)
 {
     extern __shared__ __align__(16) float smem[];
+    if (stop && *stop != 0.0) return;   // a converged solver: nothing to do
     // Workgroups go to the 8 XCDs round robin.  XCD x takes bands x, x + 8,
     // x + 16, ..., each for all views in order: the costly central bands are
     // spread over all XCDs, and the workgroups an XCD runs at a time share a
@@ -719,8 +720,10 @@ project_kernel(const DevGeom G, const int U, const int nbands, const float *__re
 // 16 q .. 16 q + 15 (< n1) of row j and all slices: one wave per (j, q),
 // lanes over k.  The projection's wedge maxima are then lookups.
 __global__ void __launch_bounds__(kBlock)
-group_max_kernel(const DevGeom G, const float *__restrict__ vol, unsigned *__restrict__ gmax)
+group_max_kernel(const DevGeom G, const float *__restrict__ vol, unsigned *__restrict__ gmax,
+                 const double *__restrict__ stop)
 {
+    if (stop && *stop != 0.0) return;
     constexpr int GW = 16;
     const int ngroups = (G.n1 + GW - 1) / GW;
     const int cell = blockIdx.x * kWaves + threadIdx.x / kWave;
@@ -780,7 +783,6 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
     float *rec = smem + wave * waveFloats;
     float *win = rec + recFloats;
 
-    const float c2f = (float)G.c2;
     const float a3f = (float)G.a3;
     const bool raw = G.raw_volume != 0;
 
@@ -818,6 +820,7 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
             if (vb + r * kWaves >= G.nviews) break;
             const float *rv = rec + r * recView;
             int *npv = reinterpret_cast<int *>(const_cast<float *>(rv) + GW * PMAX * kRecFloats);
+            const float c2f = (float)G.views[(size_t)(vb + r * kWaves) * G.vstride].c2;
             int wu0 = 1 << 30, wu1 = -1, wv0 = 1 << 30, wv1 = -1;
             const int c = lane % GW, s0 = lane / GW;
             for (int s = s0; s < PMAX; s += kWave / GW) {
@@ -858,6 +861,8 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
         const int view = vb + r * kWaves;
         if (view >= G.nviews) break;
         const ViewGeom V = G.views[(size_t)view * G.vstride];
+        const float c2f = (float)V.c2;
+        const float *sgv = G.sigma ? G.sigma + (size_t)view * G.vstride * G.sigma_views * G.N * G.M : nullptr;
         const float *recv = rec + r * recView;
         const int *npc = reinterpret_cast<const int *>(recv + GW * PMAX * kRecFloats);
         int wu0 = wb0[0], wu1 = wb0[1], wv0 = wb0[2], wv1 = wb0[3];
@@ -879,7 +884,7 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
                 const int uu = idx % Wd, vv = idx / Wd;
                 const size_t off = (size_t)(wv0 + vv) * G.M + (wu0 + uu);
                 float val = pv[off];
-                if (G.sigma) val *= G.sigma[off];
+                if (sgv) val *= sgv[off];
                 win[uu * Hp + vv] = val;
             }
         }
@@ -976,7 +981,7 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
                     for (int v = vlo; v <= vhi; ++v) {
                         const size_t off = (size_t)v * G.M + u;
                         float val = pv[off];
-                        if (G.sigma) val *= G.sigma[off];
+                        if (sgv) val *= sgv[off];
                         row(val);
                     }
                 }
@@ -1016,9 +1021,10 @@ template <bool EXACT, bool EC, int PMAX, int GW>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
 backproject_kernel(const DevGeom G, const int ngroups, const int nkchunks, const int kp, const int items,
                    const int chunk, const int winCap, const float *__restrict__ proj,
-                   float *__restrict__ vol)
+                   float *__restrict__ vol, const double *__restrict__ stop)
 {
     extern __shared__ __align__(16) float smem[];
+    if (stop && *stop != 0.0) return;
     const int item = (blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
     if (item >= items) return;
     backproject_item<EXACT, EC, PMAX, GW>(G, ngroups, nkchunks, kp, winCap, item, smem, proj, vol);
@@ -1052,6 +1058,7 @@ project_batched_kernel(const BatchProblem *__restrict__ probs, const BatchTable 
     int p, local;
     while (next_item(*T, counter, p, local)) {
         const BatchProblem &P = probs[p];
+        if (P.stop && *P.stop != 0.0) continue;
         if (P.pmax <= 4)
             project_item<EXACT, EC, 4>(P.G, P.U, local, smem, P.in, P.out, P.gmax);
         else
@@ -1059,20 +1066,14 @@ project_batched_kernel(const BatchProblem *__restrict__ probs, const BatchTable 
     }
 }
 
-// Each problem runs with its own single-problem plan (piece stride, stack
-// width, passes, window), so its items are exactly those of its own launch.
-template <bool EXACT, bool EC, int PMAX>
-__device__ __forceinline__ void backproject_batched_item(const BatchProblem &P, int local, float *smem)
-{
-    if (P.gw == 16)
-        backproject_item<EXACT, EC, PMAX, 16>(P.G, P.ngroups, P.nkchunks, P.kp, P.win_cap, local, smem, P.in, P.out);
-    else if (P.gw == 8)
-        backproject_item<EXACT, EC, PMAX, 8>(P.G, P.ngroups, P.nkchunks, P.kp, P.win_cap, local, smem, P.in, P.out);
-    else
-        backproject_item<EXACT, EC, PMAX, 4>(P.G, P.ngroups, P.nkchunks, P.kp, P.win_cap, local, smem, P.in, P.out);
-}
-
-template <bool EXACT, bool EC>
+// One persistent launch per stack width GW present in a batch, over the
+// members with that width, with records of 8 pieces per column (enough for
+// every member); each problem keeps its own passes and window.
+// Backprojection sums do not depend on the plan, so every problem's result
+// equals its own single-problem launch bitwise, and each kernel holds a
+// single variant of the gather (its registers fit like the single-problem
+// kernel's; one kernel inlining every variant spilled).
+template <bool EXACT, bool EC, int GW>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
 backproject_batched_kernel(const BatchProblem *__restrict__ probs, const BatchTable *__restrict__ T,
                            int *counter)
@@ -1081,10 +1082,8 @@ backproject_batched_kernel(const BatchProblem *__restrict__ probs, const BatchTa
     int p, local;
     while (next_item(*T, counter, p, local)) {
         const BatchProblem &P = probs[p];
-        if (P.pmax <= 4)
-            backproject_batched_item<EXACT, EC, 4>(P, local, smem);
-        else
-            backproject_batched_item<EXACT, EC, 8>(P, local, smem);
+        if (P.stop && *P.stop != 0.0) continue;
+        backproject_item<EXACT, EC, 8, GW>(P.G, P.ngroups, P.nkchunks, P.kp, P.win_cap, local, smem, P.in, P.out);
     }
 }
 
@@ -1100,6 +1099,7 @@ __global__ void batch_setup(BatchProblem *probs, const BatchIO io, int *counter)
             probs[q].out = io.out[q];
             probs[q].G.sigma = io.sigma[q];
             probs[q].G.raw_volume = io.raw;
+            probs[q].stop = io.stop[q];
         }
     }
     *counter = 0;
@@ -1107,39 +1107,39 @@ __global__ void batch_setup(BatchProblem *probs, const BatchIO io, int *counter)
 
 template <bool EXACT, bool EC>
 hipError_t launch_p(const DevGeom &g, const ProjLaunch &L, const float *vol, float *proj,
-                    unsigned *gmax, hipStream_t s)
+                    unsigned *gmax, hipStream_t s, const double *stop)
 {
     if (gmax) {
-        hipError_t e = launch_group_max(g, vol, gmax, s);
+        hipError_t e = launch_group_max(g, vol, gmax, s, stop);
         if (e != hipSuccess) return e;
     }
     const dim3 grid(8 * L.chunk), block(kBlock);
     if (L.pmax <= 4)
         hipLaunchKernelGGL((project_kernel<EXACT, EC, 4>), grid, block, L.lds, s, g, L.U, L.nbands, vol, proj,
-                           gmax);
+                           gmax, stop);
     else
         hipLaunchKernelGGL((project_kernel<EXACT, EC, 8>), grid, block, L.lds, s, g, L.U, L.nbands, vol, proj,
-                           gmax);
+                           gmax, stop);
     return hipGetLastError();
 }
 
 template <bool EXACT, bool EC, int PMAX>
 hipError_t launch_bp_gw(const DevGeom &g, const BackLaunch &L, const float *proj, float *vol,
-                        hipStream_t s)
+                        hipStream_t s, const double *stop)
 {
     const dim3 grid(8 * L.chunk), block(kBlock);
     switch (L.gw) {
     case 16:
         hipLaunchKernelGGL((backproject_kernel<EXACT, EC, PMAX, 16>), grid, block, L.lds, s, g,
-                           L.ngroups, L.nkchunks, L.kp, L.items, L.chunk, L.win_cap, proj, vol);
+                           L.ngroups, L.nkchunks, L.kp, L.items, L.chunk, L.win_cap, proj, vol, stop);
         break;
     case 8:
         hipLaunchKernelGGL((backproject_kernel<EXACT, EC, PMAX, 8>), grid, block, L.lds, s, g,
-                           L.ngroups, L.nkchunks, L.kp, L.items, L.chunk, L.win_cap, proj, vol);
+                           L.ngroups, L.nkchunks, L.kp, L.items, L.chunk, L.win_cap, proj, vol, stop);
         break;
     default:
         hipLaunchKernelGGL((backproject_kernel<EXACT, EC, PMAX, 4>), grid, block, L.lds, s, g,
-                           L.ngroups, L.nkchunks, L.kp, L.items, L.chunk, L.win_cap, proj, vol);
+                           L.ngroups, L.nkchunks, L.kp, L.items, L.chunk, L.win_cap, proj, vol, stop);
         break;
     }
     return hipGetLastError();
@@ -1147,14 +1147,14 @@ hipError_t launch_bp_gw(const DevGeom &g, const BackLaunch &L, const float *proj
 
 template <bool EXACT, bool EC>
 hipError_t launch_bp(const DevGeom &g, const BackLaunch &L, const float *proj, float *vol,
-                     hipStream_t s)
+                     hipStream_t s, const double *stop)
 {
-    if (L.pmax <= 4) return launch_bp_gw<EXACT, EC, 4>(g, L, proj, vol, s);
-    if (L.pmax <= 8) return launch_bp_gw<EXACT, EC, 8>(g, L, proj, vol, s);
+    if (L.pmax <= 4) return launch_bp_gw<EXACT, EC, 4>(g, L, proj, vol, s, stop);
+    if (L.pmax <= 8) return launch_bp_gw<EXACT, EC, 8>(g, L, proj, vol, s, stop);
     // wide footprints: 4-column stacks only
     if (L.gw != 4) return hipErrorInvalidValue;
     hipLaunchKernelGGL((backproject_kernel<EXACT, EC, kPmaxWide, 4>), dim3(8 * L.chunk), dim3(kBlock), L.lds, s, g,
-                       L.ngroups, L.nkchunks, L.kp, L.items, L.chunk, L.win_cap, proj, vol);
+                       L.ngroups, L.nkchunks, L.kp, L.items, L.chunk, L.win_cap, proj, vol, stop);
     return hipGetLastError();
 }
 
@@ -1191,9 +1191,18 @@ hipError_t launch_pb(BatchProblem *probs, const BatchTable *tab, int *counter, i
 }
 
 template <bool EXACT, bool EC>
-hipError_t launch_bb(BatchProblem *probs, const BatchTable *tab, int *counter, int grid, size_t lds, hipStream_t s)
+hipError_t launch_bb(BatchProblem *probs, const BatchTable *tab, int *counter, int grid, size_t lds, int gw,
+                     hipStream_t s)
 {
-    hipLaunchKernelGGL((backproject_batched_kernel<EXACT, EC>), dim3(grid), dim3(kBlock), lds, s, probs, tab, counter);
+    if (gw == 16)
+        hipLaunchKernelGGL((backproject_batched_kernel<EXACT, EC, 16>), dim3(grid), dim3(kBlock), lds, s, probs, tab,
+                           counter);
+    else if (gw == 8)
+        hipLaunchKernelGGL((backproject_batched_kernel<EXACT, EC, 8>), dim3(grid), dim3(kBlock), lds, s, probs, tab,
+                           counter);
+    else
+        hipLaunchKernelGGL((backproject_batched_kernel<EXACT, EC, 4>), dim3(grid), dim3(kBlock), lds, s, probs, tab,
+                           counter);
     return hipGetLastError();
 }
 
@@ -1203,7 +1212,13 @@ hipError_t set_lds_batched(size_t n)
     hipError_t e = hipFuncSetAttribute((const void *)project_batched_kernel<EXACT, EC>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
     if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)backproject_batched_kernel<EXACT, EC>,
+        e = hipFuncSetAttribute((const void *)backproject_batched_kernel<EXACT, EC, 16>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)backproject_batched_kernel<EXACT, EC, 8>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)backproject_batched_kernel<EXACT, EC, 4>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
     return e;
 }
@@ -1211,7 +1226,7 @@ hipError_t set_lds_batched(size_t n)
 }  // namespace
 
 hipError_t launch_batched(bool backward, BatchProblem *probs, const BatchTable *tab, int *counter,
-                          const BatchIO &io, bool exact, bool ec, int grid, size_t lds, hipStream_t s)
+                          const BatchIO &io, bool exact, bool ec, int grid, size_t lds, int gw, hipStream_t s)
 {
     hipLaunchKernelGGL(batch_setup, dim3(1), dim3(64), 0, s, probs, io, counter);
     hipError_t e = hipGetLastError();
@@ -1222,22 +1237,28 @@ hipError_t launch_batched(bool backward, BatchProblem *probs, const BatchTable *
         return ec ? launch_pb<false, true>(probs, tab, counter, grid, lds, s)
                   : launch_pb<false, false>(probs, tab, counter, grid, lds, s);
     }
-    if (exact) return ec ? launch_bb<true, true>(probs, tab, counter, grid, lds, s)
-                         : launch_bb<true, false>(probs, tab, counter, grid, lds, s);
-    return ec ? launch_bb<false, true>(probs, tab, counter, grid, lds, s)
-              : launch_bb<false, false>(probs, tab, counter, grid, lds, s);
+    if (exact) return ec ? launch_bb<true, true>(probs, tab, counter, grid, lds, gw, s)
+                         : launch_bb<true, false>(probs, tab, counter, grid, lds, gw, s);
+    return ec ? launch_bb<false, true>(probs, tab, counter, grid, lds, gw, s)
+              : launch_bb<false, false>(probs, tab, counter, grid, lds, gw, s);
 }
 
 // Workgroups of a persistent batched kernel that fit on one CU at this LDS size.
-int batched_blocks_per_cu(bool backward, size_t lds)
+int batched_blocks_per_cu(bool backward, size_t lds, int gw)
 {
     int nb = 0;
     hipError_t e;
     if (!backward)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)project_batched_kernel<false, true>,
                                                          kBlock, lds);
+    else if (gw == 16)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)backproject_batched_kernel<false, true, 16>,
+                                                         kBlock, lds);
+    else if (gw == 8)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)backproject_batched_kernel<false, true, 8>,
+                                                         kBlock, lds);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)backproject_batched_kernel<false, true>,
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)backproject_batched_kernel<false, true, 4>,
                                                          kBlock, lds);
     if (e != hipSuccess || nb < 1) nb = 1;
     return nb;
@@ -1267,12 +1288,12 @@ hipError_t configure_kernel_lds(size_t max_lds, size_t max_lds_batched)
 }
 
 hipError_t launch_project(const DevGeom &g, const ProjLaunch &L, bool exact, bool ec,
-                          const float *vol, float *proj, unsigned *gmax, hipStream_t stream)
+                          const float *vol, float *proj, unsigned *gmax, hipStream_t stream, const double *stop)
 {
-    if (exact) return ec ? launch_p<true, true>(g, L, vol, proj, gmax, stream)
-                         : launch_p<true, false>(g, L, vol, proj, gmax, stream);
-    return ec ? launch_p<false, true>(g, L, vol, proj, gmax, stream)
-              : launch_p<false, false>(g, L, vol, proj, gmax, stream);
+    if (exact) return ec ? launch_p<true, true>(g, L, vol, proj, gmax, stream, stop)
+                         : launch_p<true, false>(g, L, vol, proj, gmax, stream, stop);
+    return ec ? launch_p<false, true>(g, L, vol, proj, gmax, stream, stop)
+              : launch_p<false, false>(g, L, vol, proj, gmax, stream, stop);
 }
 
 int64_t group_max_cells(const DevGeom &g)
@@ -1280,11 +1301,12 @@ int64_t group_max_cells(const DevGeom &g)
     return (int64_t)g.n2 * ((g.n1 + 15) / 16);
 }
 
-hipError_t launch_group_max(const DevGeom &g, const float *vol, unsigned *gmax, hipStream_t stream)
+hipError_t launch_group_max(const DevGeom &g, const float *vol, unsigned *gmax, hipStream_t stream,
+                            const double *stop)
 {
     const int64_t cells = group_max_cells(g);
     hipLaunchKernelGGL(group_max_kernel, dim3((unsigned)((cells + kWaves - 1) / kWaves)), dim3(kBlock), 0, stream,
-                       g, vol, gmax);
+                       g, vol, gmax, stop);
     return hipGetLastError();
 }
 
@@ -1321,12 +1343,12 @@ hipError_t static_scratch(unsigned **out)
 }
 
 hipError_t launch_backproject(const DevGeom &g, const BackLaunch &L, bool exact, bool ec,
-                              const float *proj, float *vol, hipStream_t stream)
+                              const float *proj, float *vol, hipStream_t stream, const double *stop)
 {
-    if (exact) return ec ? launch_bp<true, true>(g, L, proj, vol, stream)
-                         : launch_bp<true, false>(g, L, proj, vol, stream);
-    return ec ? launch_bp<false, true>(g, L, proj, vol, stream)
-              : launch_bp<false, false>(g, L, proj, vol, stream);
+    if (exact) return ec ? launch_bp<true, true>(g, L, proj, vol, stream, stop)
+                         : launch_bp<true, false>(g, L, proj, vol, stream, stop);
+    return ec ? launch_bp<false, true>(g, L, proj, vol, stream, stop)
+              : launch_bp<false, false>(g, L, proj, vol, stream, stop);
 }
 
 }  // namespace cvp

@@ -34,19 +34,20 @@ __device__ __forceinline__ void project_point(const DevGeom &G, const ViewGeom &
 {
     const double r1 = x1 - V.s1, r2 = x2 - V.s2, r3 = x3 - V.s3;
     const double depth = V.dx * r1 + V.dy * r2;
-    chi1 = G.c1 + G.fb1 * (V.e1x * r1 + V.e1y * r2) / depth;
-    chi2 = G.c2 - G.fb2 * r3 / depth;   // e2 = (0, 0, -1)
+    chi1 = V.c1 + V.fb1 * (V.e1x * r1 + V.e1y * r2) / depth;
+    chi2 = V.c2 - V.fb2 * r3 / depth;   // e2 = (0, 0, -1)
 }
 
-// Sum of mu times the chord length along the segment s + alpha dir,
-// alpha in [0, 1] (source to detector), through the voxel grid.
+// Sum of mu times the chord length (in units of |dir|) along the half-line
+// s + alpha dir, alpha >= 0, through the voxel grid (the volume lies between
+// the source and the detector).
 __device__ double trace_ray(const DevGeom &G, const float *__restrict__ vol, const double s[3],
                             const double dir[3])
 {
     const int n[3] = {G.n1, G.n2, G.n3};
     const double a[3] = {G.a1, G.a2, G.a3};
     const double lo[3] = {G.x1lo, G.x2lo, G.x3lo};
-    double amin = 0.0, amax = 1.0;
+    double amin = 0.0, amax = INFINITY;
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
         const double hi = lo[ax] + n[ax] * a[ax];
@@ -147,9 +148,9 @@ siddon_kernel(const DevGeom G, const int K, const int LP, const float *__restric
                 const int ra = r / K, rb = r % K;
                 const double chi1 = u - 0.5 + (rb + 0.5) * inv;
                 const double chi2 = v - 0.5 + (ra + 0.5) * inv;
-                // detector point minus source: f d + (chi1 - c1) b1 e1 + (chi2 - c2) b2 e2
-                const double w1 = (chi1 - G.c1) * G.b1, w2 = (chi2 - G.c2) * G.b2;
-                const double dir[3] = {G.f * V.dx + w1 * V.e1x, G.f * V.dy + w1 * V.e1y, -w2};
+                // ray direction at unit depth: d + (chi1 - c1)/(f/b1) e1 + (chi2 - c2)/(f/b2) e2
+                const double w1 = (chi1 - V.c1) / V.fb1, w2 = (chi2 - V.c2) / V.fb2;
+                const double dir[3] = {V.dx + w1 * V.e1x, V.dy + w1 * V.e1y, -w2};
                 const double len = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
                 acc += trace_ray(G, vol, s, dir) * len;
             }

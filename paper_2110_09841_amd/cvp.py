@@ -31,21 +31,29 @@ class Options:
 
 
 class Geometry:
-    """Circular cone-beam geometry, built on the current HIP device.
+    """Cone-beam geometry, built on the current HIP device.
 
-    ``params`` is a plain dict (see ``synth.geometry``): vol_dims, voxel_mm,
-    vol_offset_mm, det_cols, det_rows, pitch_mm, principal_px, sid_mm, sdd_mm,
-    angles_rad."""
+    ``params`` is a plain dict: a circular orbit (see ``synth.geometry``:
+    vol_dims, voxel_mm, vol_offset_mm, det_cols, det_rows, pitch_mm,
+    principal_px, sid_mm, sdd_mm, angles_rad), or a general trajectory with
+    ``matrices`` ([views][3][4] camera matrices, see
+    ``synth.matrix_geometry``) in place of the orbit keys."""
 
     def __init__(self, params):
         self.params = dict(params)
-        desc, self._angles = _lib.make_desc(params)
         h = ctypes.c_void_p()
-        _lib.check(_lib.lib().cvp_geometry_from_views(ctypes.byref(desc), ctypes.byref(h)))
+        if "matrices" in params:
+            desc, self._angles = _lib.make_matrices_desc(params)
+            _lib.check(_lib.lib().cvp_geometry_from_matrices(ctypes.byref(desc), ctypes.byref(h)))
+            nv = desc.n_views
+        else:
+            desc, self._angles = _lib.make_desc(params)
+            _lib.check(_lib.lib().cvp_geometry_from_views(ctypes.byref(desc), ctypes.byref(h)))
+            nv = len(params["angles_rad"])
         self.handle = h
         n1, n2, n3 = (int(v) for v in params["vol_dims"])
         self.vol_shape = (n3, n2, n1)
-        self.proj_shape = (len(params["angles_rad"]), int(params["det_rows"]), int(params["det_cols"]))
+        self.proj_shape = (nv, int(params["det_rows"]), int(params["det_cols"]))
         self.device = torch.device("cuda", torch.cuda.current_device())
         nbytes = ctypes.c_int64()
         _lib.check(_lib.lib().cvp_project_workspace_size(h, ctypes.byref(nbytes)))

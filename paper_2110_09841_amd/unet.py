@@ -119,10 +119,28 @@ LAYERS = [("c1a", IN_CH, 16, 1), ("c1b", 16, 16, 1), ("c2a", 16, 32, 2), ("c2b",
           ("d1a", 32, 16, 1), ("d1b", 16, 16, 1)]   # name, Cin, Cout, resolution divisor
 
 
-def forward_flops(shape):
-    """Multiply-add count x 2 of one forward pass (the 3x3x3 convolutions)."""
+def forward_flops(shape, algorithmic=False):
+    """Multiply-add count x 2 of one forward pass (the 3x3x3 convolutions):
+    as executed (the two input channels padded to IN_CH) or algorithmic
+    (two input channels)."""
     n = shape[0] * shape[1] * shape[2]
-    return sum(2 * 27 * ci * co * n // (s ** 3) for _, ci, co, s in LAYERS)
+    return sum(2 * 27 * (2 if (algorithmic and name == "c1a") else ci) * co * n // (s ** 3)
+               for name, ci, co, s in LAYERS)
+
+
+def forward_bound_seconds(shape, peak_flops=2.5e15, peak_bytes=8e12):
+    """Lower bound of one forward pass: per convolution the larger of its
+    algorithmic MFMA time (BF16 peak) and its HBM time (BF16 input and output
+    activations once, weights), summed over the layers."""
+    n = shape[0] * shape[1] * shape[2]
+    t = 0.0
+    for name, ci, co, s in LAYERS:
+        v = n // (s ** 3)
+        cin = 2 if name == "c1a" else ci
+        fl = 2 * 27 * cin * co * v
+        by = 2 * v * (cin + co) + 2 * 27 * ci * co
+        t += max(fl / peak_flops, by / peak_bytes)
+    return t
 
 
 class UNet:

@@ -25,8 +25,8 @@ import numpy as np
 import torch
 
 from . import _lib, synth
-from .cgls import CGLS
-from .cvp import Geometry, Options, project
+from .cgls import CGLS, BatchedCGLS
+from .cvp import Batch, Geometry, Options, project
 from .unet import UNet
 
 HELD_OUT_SEED0 = 100000
@@ -76,6 +76,7 @@ class Pipeline:
     def iterates(self, b):
         """The first two CGLS iterates from zero (copies)."""
         self.solver.reset(b)
+        self.solver.set_tolerance(0.0)
         self.solver.start()
         self.solver.iterate(1)
         x1 = self.solver.x.clone()
@@ -139,6 +140,44 @@ class Pipeline:
                     reached_warm=bool(rhow[itw] <= tol), err_zero=err0, err_warm=errw)
 
 
+def evaluate_batched(pipe: Pipeline, net: UNet, seeds, tol=1e-3, max_iter=400, per_graph=5):
+    """The held-out phantoms of `seeds` as one batch (one geometry per
+    problem, the same trajectory): batched CGLS from zero to rho <= tol
+    against the warm start -- two batched CGLS iterations, the network on
+    each problem's iterates, then batched CGLS from x0 to the same rho (the
+    denominator |A^T b| of the zero start).  Every problem stops on the
+    device when it meets the tolerance.  Returns per-problem iterations and
+    the two wall times (the warm one including its two iterations and the
+    inference)."""
+    n = len(seeds)
+    geoms = [Geometry(pipe.params) for _ in range(n)]
+    batch = Batch(geoms)
+    xt = [pipe.phantom(s) for s in seeds]
+    bs = [pipe.measure(x, s).clone() for x, s in zip(xt, seeds)]
+    zero = BatchedCGLS(batch, pipe.opts, bs)
+    its0, t0, rhos0 = zero.run(tol=tol, max_iter=max_iter, per_graph=per_graph)
+    refs = [float(g[0]) for g in zero.gamma_histories()]
+    err0 = [float(torch.linalg.vector_norm(zero.x[q] - xt[q]) / torch.linalg.vector_norm(xt[q])) for q in range(n)]
+    warm = BatchedCGLS(batch, pipe.opts, bs)
+    warm.capture(per_graph)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    warm.set_tolerance(0.0)
+    warm.start()
+    warm.iterate(1)
+    x1 = [x.clone() for x in warm.x]
+    warm.iterate(1)
+    x0 = [net.forward(x1[q], warm.x[q]) for q in range(n)]
+    for q in range(n):
+        warm.x[q].copy_(x0[q])
+    itsw, _, rhosw = warm.run(tol=tol, max_iter=max_iter, per_graph=per_graph, gamma_refs=refs)
+    t_warm = time.perf_counter() - ts
+    errw = [float(torch.linalg.vector_norm(warm.x[q] - xt[q]) / torch.linalg.vector_norm(xt[q])) for q in range(n)]
+    return dict(seeds=list(seeds), zero_iters=its0, warm_iters=[i + 2 for i in itsw], zero_s=t0, warm_s=t_warm,
+                rho0_warm=[float(r[0]) for r in rhosw], reached_zero=[bool(r[i] <= tol) for r, i in zip(rhos0, its0)],
+                reached_warm=[bool(r[i] <= tol) for r, i in zip(rhosw, itsw)], err_zero=err0, err_warm=errw)
+
+
 def main():
     ap = argparse.ArgumentParser(description="learned CGLS warm start: train, then evaluate on held-out phantoms")
     ap.add_argument("--train", type=int, default=2000, help="training phantoms (seeds 0 .. n-1)")
@@ -151,6 +190,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-3)
     ap.add_argument("--max-iter", type=int, default=400)
     ap.add_argument("--out", default=None, help="write the JSON record here as well")
+    ap.add_argument("--batch", type=int, default=8, help="held-out phantoms per batched evaluation")
     args = ap.parse_args()
 
     def log(msg):
@@ -183,6 +223,24 @@ def main():
         v = np.array([r[key] for r in rows], dtype=np.float64)
         return {"mean": float(v.mean()), "median": float(np.median(v)), "min": float(v.min()), "max": float(v.max())}
 
+    # the same held-out phantoms through batched CGLS, args.batch at a time
+    batches = []
+    for n0 in range(0, args.eval, args.batch):
+        seeds = [HELD_OUT_SEED0 + n for n in range(n0, min(n0 + args.batch, args.eval))]
+        batches.append(evaluate_batched(pipe, net, seeds, tol=args.tol, max_iter=args.max_iter))
+        log("batched eval %d / %d: zero %.3f s, warm %.3f s" % (n0 + len(seeds), args.eval, batches[-1]["zero_s"],
+                                                             batches[-1]["warm_s"]))
+    bz = np.concatenate([b["zero_iters"] for b in batches])
+    bw = np.concatenate([b["warm_iters"] for b in batches])
+    batched_rec = {"batch": args.batch, "batches": len(batches),
+                   "zero_s": float(sum(b["zero_s"] for b in batches)),
+                   "warm_s": float(sum(b["warm_s"] for b in batches)),
+                   "zero_iters_mean": float(bz.mean()), "warm_iters_mean": float(bw.mean()),
+                   "warm_fewer_iters": int(np.sum(bw < bz)),
+                   "reached_zero": int(sum(sum(b["reached_zero"]) for b in batches)),
+                   "reached_warm": int(sum(sum(b["reached_warm"]) for b in batches)),
+                   "warm_faster_batches": int(sum(b["warm_s"] < b["zero_s"] for b in batches))}
+
     rec = {"workload": "warmstart_128c_180v", "train_phantoms": args.train, "eval_phantoms": args.eval,
            "epochs": args.epochs, "lr": args.lr, "tol": args.tol, "per_graph": pipe.per_graph,
            "target": args.target, "target_iters": args.target_iters if args.target == "cgls" else None,
@@ -192,7 +250,8 @@ def main():
            "err_zero": stat("err_zero"), "err_warm": stat("err_warm"), "rho0_warm": stat("rho0_warm"),
            "reached_zero": int(sum(r["reached_zero"] for r in rows)),
            "reached_warm": int(sum(r["reached_warm"] for r in rows)),
-           "warm_faster": int(sum(r["warm_s"] < r["zero_s"] for r in rows))}
+           "warm_faster": int(sum(r["warm_s"] < r["zero_s"] for r in rows)),
+           "batched": batched_rec}
     line = json.dumps(rec)
     print(line, flush=True)
     if args.out:

@@ -118,3 +118,50 @@ def test_batched_cgls_run_and_cgls_function():
         x, info = cvp.cgls(geoms[q], bs[q], opts, tol=1e-2, max_iter=100, per_graph=5)
         assert info["iterations"] == its[q]
         assert info["rho"][info["iterations"]] <= 1e-2 and not info["breakdown"]
+
+
+def test_device_stop_flag_single_and_batched():
+    """With a tolerance set on the device, CGLS stops at the first iteration
+    whose rho <= tol: a graph replayed past that point leaves x, r, s and the
+    counters as they were (bitwise equal to an eager run of exactly that many
+    iterations), and in a batch each problem stops at its own iteration while
+    the others run on."""
+    params = _small_batch(3)
+    geoms = [cvp.Geometry(p) for p in params]
+    opts = cvp.Options(variant="relaxed", ec=True)
+    xs = [torch.from_numpy(synth.ellipsoid_phantom(p["vol_dims"], p["voxel_mm"][0], 12, seed=500 + q)).cuda()
+          for q, p in enumerate(params)]
+    bs = [cvp.project(x, g, opts) for x, g in zip(xs, geoms)]
+    tol = 3e-2
+    stops = []
+    for q, g in enumerate(geoms):
+        s = CGLS(g, opts, bs[q])
+        s.set_tolerance(tol)
+        s.start()
+        s.capture(4)
+        for _ in range(6):
+            s.replay()
+        torch.cuda.synchronize()
+        k = int(s.scalars()[6])
+        rho = s.rho()
+        say("problem %d stopped at %d (rho %.3e)" % (q, k, rho[-1]))
+        assert s.stopped() and rho[-1] <= tol and np.all(rho[:-1] > tol), (k, rho)
+        ref = CGLS(g, opts, bs[q])
+        ref.start()
+        ref.iterate(k)
+        assert torch.equal(s.x, ref.x) and torch.equal(s.r, ref.r) and torch.equal(s.s, ref.s)
+        stops.append(k)
+    bc = cvp.BatchedCGLS(cvp.Batch(geoms), opts, bs)
+    bc.set_tolerance(tol)
+    bc.start()
+    bc.capture(4)
+    for _ in range(6):
+        bc.replay()
+    torch.cuda.synchronize()
+    for q, g in enumerate(geoms):
+        assert int(bc.work[q][6].item()) == stops[q], (q, stops)
+        ref = CGLS(g, opts, bs[q])
+        ref.start()
+        ref.iterate(stops[q])
+        assert torch.equal(bc.x[q], ref.x), q
+    assert all(bc.stopped())
