@@ -10,7 +10,10 @@ Two parts:
   ctypes: :func:`project`, :func:`backproject`, :func:`voxel_weights`, ...);
 * plain definitions that CVP approximates, used only to pin the first part
   (``definition.py``: ray supersampling, exact polyhedral cut volumes,
-  closed-form pixel solid angles).
+  closed-form pixel solid angles);
+* the solvers run on these operators (``cgls.py``, ``lsqr.py``,
+  ``sart.py``) and the TT separable-footprint projector the paper compares
+  CVP with (``tt.py``).
 
 Geometry is passed as a plain dict with the keys of :data:`GEOM_KEYS`, or,
 for a general trajectory (Sec. III-C: one camera matrix per view), with
