@@ -61,7 +61,19 @@ typedef enum {
 
 typedef enum {
     CVP_EXACT = 0,          /* r at the centroid of each cut piece */
-    CVP_RELAXED = 1         /* r at the voxel centre (speed-optimised form) */
+    CVP_RELAXED = 1,        /* r at the voxel centre (speed-optimised form) */
+    CVP_TT = 2              /* the TT separable-footprint projector the paper
+                               compares with (Sec. I, IV; Long, Fessler &
+                               Balter 2010), on the same work split (Sec. V-C):
+                               trapezoid footprints across and along the
+                               detector columns, integrated over each pixel,
+                               times the central ray's chord through the voxel.
+                               It estimates the pixel's area-averaged line
+                               integral (eq. integ), so it takes
+                               CVP_SCALE_COS, elevation_correction 0 and no
+                               flags (else CVP_E_INVALID); single-problem entry
+                               points only (the batched ones return
+                               CVP_E_UNSUPPORTED). */
 } cvp_variant;
 
 typedef enum {

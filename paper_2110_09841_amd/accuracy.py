@@ -6,14 +6,16 @@ ground truth, e_PRJ = |P_PRJ - P_S| / |P_S|, is recorded, with P_S the
 SiddonK projection for a large K (the paper uses K = 512, 262,144 rays per
 pixel).  Projectors: the cutting voxel projector in both forms with and
 without the elevation correction (flat-panel scaling, eq. cvp, the quantity
-SiddonK estimates), and SiddonK for smaller K.
+SiddonK estimates), the TT separable-footprint projector the paper compares
+with, and SiddonK for smaller K.
 
 The three arrangements (Sec. IV-B): a 1 x 1 x 5 mm voxel at the isocentre
 and a 1 mm voxel at (20, 20, 20) mm, both on a 616 x 480 detector of
 0.154 mm pixels at SID 749 / SDD 1198 mm; and a 1 mm voxel at
 (100, 150, -100) mm on a 768 x 768 detector of 1 mm pixels at SID 541 /
-SDD 949 mm.  Every projection runs in the HIP kernels (cvp_project and
-cvp_project_siddon); the errors are FP64 norms of their outputs.
+SDD 949 mm.  Every projection runs in the HIP kernels (cvp_project with
+the CVP and TT variants, cvp_project_siddon); the errors are FP64 norms of
+their outputs.
 
     python -m paper_2110_09841_amd.accuracy --views 360 --truth-k 512 --out acc.json
 """
@@ -68,6 +70,7 @@ def study(name, n_views=360, truth_k=512, siddon_ks=(1, 2, 4, 8, 16, 32, 64, 128
     for key, variant, ec in CVP_FORMS:
         P = cvp.project(x, G, cvp.Options(variant=variant, ec=ec, scaling="cos"))
         res[key] = errors_per_view(P, S)
+    res["tt"] = errors_per_view(cvp.project(x, G, cvp.TT), S)
     for K in siddon_ks:
         if K >= truth_k:
             continue
@@ -90,6 +93,11 @@ def claims(name, res):
     out["ec_lowers_worst_view_exact"] = bool(res["cvp_exact_ec"].max() <= res["cvp_exact"].max())
     out["ec_lowers_worst_view_relaxed"] = bool(res["cvp_relaxed_ec"].max() <= res["cvp_relaxed"].max())
     out["exact_better_than_relaxed_mean"] = bool(res["cvp_exact_ec"].mean() <= res["cvp_relaxed_ec"].mean())
+    if "tt" in res:
+        # more accurate than TT (Sec. I, IV-B) -- and without EC, at some
+        # views, less accurate (Sec. III-B)
+        out["cvp_exact_ec_better_than_tt_every_view"] = bool(np.all(res["cvp_exact_ec"] < res["tt"]))
+        out["cvp_exact_without_ec_worse_than_tt_at_some_view"] = bool(np.any(res["cvp_exact"] > res["tt"]))
     return out
 
 

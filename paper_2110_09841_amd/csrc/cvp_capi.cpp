@@ -39,6 +39,7 @@ struct cvp_geometry {
     int64_t nvox = 0, npix = 0;
     double zabs = 0.0, Dmin = 0.0;   // for launch planning
     int pmax = 4;                    // pieces per column the kernels keep (4, 8 or kPmaxWide)
+    double wone_tt = 0.0, wsum_tt = 0.0;   // fixed-point bounds of the TT projector's weights
 };
 
 namespace {
@@ -381,6 +382,14 @@ cvp_status finish_geometry(const VolDet &vd, std::vector<cvp::ViewGeom> &views, 
         // a2 a3) over r^2 >= Dmin^2; a factor 2 covers FP32 rounding.
         G.wone_bound = 2.0 * a1 * a2 * a3 / (Dmin * Dmin);
         G.wone_bound_raw = 2.0 * a1 * a2 * a3;
+        // TT: a weight is at most the central chord estimate, min(a1/|r1|,
+        // a2/|r2|) |r| <= sqrt(2) max(a1, a2) |r| / |r_xy|, and |r| / |r_xy|
+        // <= sec = sqrt(1 + (zabs / Dmin)^2); a pixel's sum is at most the
+        // rays' path through the volume, rfar - Dmin, times sec (the
+        // footprints integrate to the chord, 64 as above).
+        const double sec = std::sqrt(1.0 + (zabs / Dmin) * (zabs / Dmin));
+        g->wone_tt = 2.0 * std::sqrt(2.0) * std::max(a1, a2) * sec;
+        g->wsum_tt = 64.0 * (rfar - Dmin + std::hypot(std::hypot(a1, a2), a3)) * sec;
     }
 
     // pieces per column the kernels keep: 4, 8, or (4-column backprojection
@@ -571,6 +580,12 @@ cvp_status cvp_geometry_sizes(const cvp_geometry *g, int64_t *n_voxels, int64_t 
     return ok();
 }
 
+// The kernels' projector model of validated options.
+static int model_of(const cvp_options *o)
+{
+    return o->variant == CVP_TT ? cvp::kModelTT : o->variant == CVP_EXACT ? cvp::kModelExact : cvp::kModelRelaxed;
+}
+
 static cvp_status prepare(const cvp_geometry *g, const cvp_options *o, const void *in, void *outp,
                           cvp::DevGeom &G)
 {
@@ -579,8 +594,11 @@ static cvp_status prepare(const cvp_geometry *g, const cvp_options *o, const voi
     if (!in) return fail(CVP_E_INVALID, "input pointer is NULL");
     if (!outp) return fail(CVP_E_INVALID, "output pointer is NULL");
     if (in == outp) return fail(CVP_E_INVALID, "input and output alias");
-    if (o->variant != CVP_EXACT && o->variant != CVP_RELAXED)
+    if (o->variant != CVP_EXACT && o->variant != CVP_RELAXED && o->variant != CVP_TT)
         return fail(CVP_E_INVALID, "options.variant = %d", (int)o->variant);
+    if (o->variant == CVP_TT && (o->scaling != CVP_SCALE_COS || o->elevation_correction != 0 || o->flags != 0))
+        return fail(CVP_E_INVALID, "options: the TT projector estimates the area-averaged line integral and takes "
+                                   "scaling CVP_SCALE_COS, elevation_correction 0 and no flags");
     if (o->elevation_correction != 0 && o->elevation_correction != 1)
         return fail(CVP_E_INVALID, "options.elevation_correction = %d", o->elevation_correction);
     if (o->scaling != CVP_SCALE_SOLID_ANGLE && o->scaling != CVP_SCALE_COS && o->scaling != CVP_SCALE_NONE)
@@ -594,6 +612,12 @@ static cvp_status prepare(const cvp_geometry *g, const cvp_options *o, const voi
     G = g->base;
     G.sigma = o->scaling == CVP_SCALE_NONE ? nullptr : g->d_sigma[o->scaling == CVP_SCALE_COS ? 1 : 0];
     G.raw_volume = (o->flags & CVP_FLAG_RAW_VOLUME) ? 1 : 0;
+    if (o->variant == CVP_TT) {
+        // no pixel factor; the fixed-point bounds of footprint weights
+        G.sigma = nullptr;
+        G.wone_bound = g->wone_tt;
+        G.wsum_bound = g->wsum_tt;
+    }
     return CVP_OK;
 }
 
@@ -603,7 +627,7 @@ cvp_status cvp_project(const cvp_geometry *g, const cvp_options *o, const float 
     cvp::DevGeom G;
     cvp_status st = prepare(g, o, d_vol, d_proj, G);
     if (st != CVP_OK) return st;
-    hipError_t e = cvp::launch_project(G, g->pl, o->variant == CVP_EXACT, o->elevation_correction != 0,
+    hipError_t e = cvp::launch_project(G, g->pl, model_of(o), o->elevation_correction != 0,
                                        d_vol, d_proj, nullptr, (hipStream_t)stream);
     if (e != hipSuccess) return device_fail(e, "projection launch");
     return ok();
@@ -631,7 +655,7 @@ cvp_status cvp_project_ws(const cvp_geometry *g, const cvp_options *o, const flo
     if (reinterpret_cast<uintptr_t>(d_work) & 3) return fail(CVP_E_INVALID, "work must be 4-byte aligned");
     if (d_work == (const void *)d_vol || d_work == (void *)d_proj)
         return fail(CVP_E_INVALID, "work aliases the volume or the projections");
-    hipError_t e = cvp::launch_project(G, g->pl, o->variant == CVP_EXACT, o->elevation_correction != 0,
+    hipError_t e = cvp::launch_project(G, g->pl, model_of(o), o->elevation_correction != 0,
                                        d_vol, d_proj, (unsigned *)d_work, (hipStream_t)stream);
     if (e != hipSuccess) return device_fail(e, "projection launch");
     return ok();
@@ -651,7 +675,7 @@ cvp_status cvp_project_noalloc(const cvp_geometry *g, const cvp_options *o, cons
     unsigned *work = nullptr;
     hipError_t e = cvp::static_scratch(&work);
     if (e != hipSuccess) return device_fail(e, "scratch symbol address");
-    e = cvp::launch_project(G, g->pl, o->variant == CVP_EXACT, o->elevation_correction != 0, d_vol, d_proj, work,
+    e = cvp::launch_project(G, g->pl, model_of(o), o->elevation_correction != 0, d_vol, d_proj, work,
                             (hipStream_t)stream);
     if (e != hipSuccess) return device_fail(e, "projection launch");
     return ok();
@@ -675,7 +699,7 @@ cvp_status cvp_backproject(const cvp_geometry *g, const cvp_options *o, const fl
     cvp::DevGeom G;
     cvp_status st = prepare(g, o, d_proj, d_vol, G);
     if (st != CVP_OK) return st;
-    hipError_t e = cvp::launch_backproject(G, g->bl, o->variant == CVP_EXACT, o->elevation_correction != 0,
+    hipError_t e = cvp::launch_backproject(G, g->bl, model_of(o), o->elevation_correction != 0,
                                            d_proj, d_vol, (hipStream_t)stream);
     if (e != hipSuccess) return device_fail(e, "backprojection launch");
     return ok();
@@ -720,7 +744,7 @@ cvp_status cvp_project_views(const cvp_geometry *g, const cvp_options *o, const 
     cvp::ProjLaunch pl{};
     if (!cvp::plan_projection(G.N, G.n2, G.M, n_views, g->pmax, g->pl.U, pl))
         return fail(CVP_E_UNSUPPORTED, "projection plan");
-    hipError_t e = cvp::launch_project(G, pl, o->variant == CVP_EXACT, o->elevation_correction != 0, d_vol,
+    hipError_t e = cvp::launch_project(G, pl, model_of(o), o->elevation_correction != 0, d_vol,
                                        d_proj + off, (unsigned *)d_work, (hipStream_t)stream);
     if (e != hipSuccess) return device_fail(e, "projection launch");
     return ok();
@@ -735,7 +759,7 @@ cvp_status cvp_backproject_views(const cvp_geometry *g, const cvp_options *o, co
     int64_t off = 0;
     st = view_subset(g, view0, view_stride, n_views, G, off);
     if (st != CVP_OK) return st;
-    hipError_t e = cvp::launch_backproject(G, g->bl, o->variant == CVP_EXACT, o->elevation_correction != 0,
+    hipError_t e = cvp::launch_backproject(G, g->bl, model_of(o), o->elevation_correction != 0,
                                            d_proj + off, d_vol, (hipStream_t)stream);
     if (e != hipSuccess) return device_fail(e, "backprojection launch");
     return ok();
@@ -887,6 +911,7 @@ static cvp_status batched(const cvp_batch *b, const cvp_options *o, const float 
     if (!b) return fail(CVP_E_INVALID, "batch is NULL");
     if (!o) return fail(CVP_E_INVALID, "options is NULL");
     if (!ins || !outs) return fail(CVP_E_INVALID, "pointer array is NULL");
+    if (o->variant == CVP_TT) return fail(CVP_E_UNSUPPORTED, "the batched launches run the cutting voxel projector only");
     cvp::BatchIO io{};
     io.n = b->n;
     io.raw = (o->flags & CVP_FLAG_RAW_VOLUME) ? 1 : 0;
@@ -968,7 +993,8 @@ cvp_status cvp_cgls_start(const cvp_geometry *g, const cvp_options *o, const flo
     hipStream_t sm = (hipStream_t)stream;
     double *sc = (double *)d_work;
     double *part = sc + cvp::kCglsScalars + 2 * cvp::kCglsHistory;
-    const bool ex = o->variant == CVP_EXACT, ec = o->elevation_correction != 0;
+    const int ex = model_of(o);
+    const bool ec = o->elevation_correction != 0;
     // s (volume sized) is free until A^T r: it holds the projection's
     // per-group maxima
     hipError_t e = cvp::launch_project(G, g->pl, ex, ec, d_x, d_q, (unsigned *)d_s, sm);
@@ -990,7 +1016,8 @@ cvp_status cvp_cgls_iterate(const cvp_geometry *g, const cvp_options *o, int32_t
     hipStream_t sm = (hipStream_t)stream;
     double *sc = (double *)d_work;
     double *part = sc + cvp::kCglsScalars + 2 * cvp::kCglsHistory;
-    const bool ex = o->variant == CVP_EXACT, ec = o->elevation_correction != 0;
+    const int ex = model_of(o);
+    const bool ec = o->elevation_correction != 0;
     // every kernel of an iteration returns at once once the stop flag is up
     const double *stop = sc + cvp::kCglsStop;
     hipError_t e = hipSuccess;
@@ -1122,7 +1149,8 @@ cvp_status cvp_sart_setup(const cvp_geometry *g, const cvp_options *o, int32_t n
     if (n_subsets < 1 || n_subsets > V) return fail(CVP_E_INVALID, "n_subsets = %d (must be 1..%d)", n_subsets, V);
     if (d_q == d_rowsum) return fail(CVP_E_INVALID, "q and rowsum alias");
     hipStream_t sm = (hipStream_t)stream;
-    const bool ex = o->variant == CVP_EXACT, ec = o->elevation_correction != 0;
+    const int ex = model_of(o);
+    const bool ec = o->elevation_correction != 0;
     // R = A 1 (all views), C_t = A_t^T 1 (views t, t + T, ...)
     hipError_t e = cvp::blas_fill(d_colsum, g->nvox, 1.0f, sm);
     if (e == hipSuccess) e = cvp::launch_project(G, g->pl, ex, ec, d_colsum, d_rowsum, nullptr, sm);
@@ -1152,7 +1180,8 @@ cvp_status cvp_sart_iterate(const cvp_geometry *g, const cvp_options *o, int32_t
     if (d_q == d_b || d_q == d_rowsum || d_z == d_x || (const float *)d_z == d_colsum)
         return fail(CVP_E_INVALID, "work vectors alias inputs");
     hipStream_t sm = (hipStream_t)stream;
-    const bool ex = o->variant == CVP_EXACT, ec = o->elevation_correction != 0;
+    const int ex = model_of(o);
+    const bool ec = o->elevation_correction != 0;
     const int64_t nm = (int64_t)G.N * G.M;
     hipError_t e = hipSuccess;
     for (int it = 0; it < n_sweeps && e == hipSuccess; ++it) {
@@ -1210,7 +1239,8 @@ cvp_status cvp_lsqr_start(const cvp_geometry *g, const cvp_options *o, const flo
     if (st != CVP_OK) return st;
     hipStream_t sm = (hipStream_t)stream;
     double *sc = (double *)d_work;
-    const bool ex = o->variant == CVP_EXACT, ec = o->elevation_correction != 0;
+    const int ex = model_of(o);
+    const bool ec = o->elevation_correction != 0;
     // beta u = b - A x;  alpha v = A^T u;  w = v
     hipError_t e = cvp::launch_project(G, g->pl, ex, ec, d_x, d_q, (unsigned *)d_s, sm);
     if (e == hipSuccess) e = cvp::blas_residual(d_u, d_b, d_q, g->npix, sm);
@@ -1232,7 +1262,8 @@ cvp_status cvp_lsqr_iterate(const cvp_geometry *g, const cvp_options *o, int32_t
     if (st != CVP_OK) return st;
     hipStream_t sm = (hipStream_t)stream;
     double *sc = (double *)d_work;
-    const bool ex = o->variant == CVP_EXACT, ec = o->elevation_correction != 0;
+    const int ex = model_of(o);
+    const bool ec = o->elevation_correction != 0;
     hipError_t e = hipSuccess;
     for (int it = 0; it < n_iter && e == hipSuccess; ++it) {
         e = cvp::launch_project(G, g->pl, ex, ec, d_v, d_q, (unsigned *)d_s, sm);                 // q = A v

@@ -22,6 +22,13 @@ constexpr float kYQuantumInv = 1024.0f;
 constexpr int kBackPasses = 2;        // most 64-voxel passes per backprojection stack
 constexpr int kPmaxWide = 64;         // pieces per column of the wide-footprint backprojection
 
+// Projector models of launch_project / launch_backproject: the cutting voxel
+// projector with r at the voxel centre or at each cut piece's centroid, and
+// the TT separable-footprint projector on the same work split.
+constexpr int kModelRelaxed = 0;
+constexpr int kModelExact = 1;
+constexpr int kModelTT = 2;
+
 // Per-view source-centred frame (Sec. II-C) and intrinsics, FP64.  e1 and d
 // have no x3 component (that is what makes chi1 independent of x3, the column
 // identity of Sec. III-A); chi2 runs along -x3.  A projection matrix of the
@@ -161,7 +168,7 @@ hipError_t blas_residual(float *r, const float *b, const float *q, int64_t n, hi
 
 // gmax: device scratch of group_max_cells(g) words for the per-group maxima
 // of |vol| (computed by the call), or nullptr (the kernel scans the wedges).
-hipError_t launch_project(const DevGeom &g, const ProjLaunch &L, bool exact, bool ec,
+hipError_t launch_project(const DevGeom &g, const ProjLaunch &L, int model, bool ec,
                           const float *vol, float *proj, unsigned *gmax, hipStream_t stream,
                           const double *stop = nullptr);
 int64_t group_max_cells(const DevGeom &g);
@@ -174,7 +181,7 @@ constexpr int64_t kStaticScratchWords = int64_t(1) << 18;
 hipError_t static_scratch(unsigned **out);
 // SiddonK reference projector: K x K rays per pixel, exact chord lengths.
 hipError_t launch_siddon(const DevGeom &g, int K, const float *vol, float *proj, hipStream_t s);
-hipError_t launch_backproject(const DevGeom &g, const BackLaunch &L, bool exact, bool ec,
+hipError_t launch_backproject(const DevGeom &g, const BackLaunch &L, int model, bool ec,
                               const float *proj, float *vol, hipStream_t stream, const double *stop = nullptr);
 
 }  // namespace cvp

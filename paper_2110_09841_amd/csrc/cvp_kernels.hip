@@ -214,6 +214,74 @@ __device__ __forceinline__ void piece_record(const DevGeom &G, const ViewGeom &V
     rec[11] = 0.0f;
 }
 
+// Record of the TT separable footprint (the footprint projector the paper
+// compares with, Sec. I and IV: Long, Fessler & Balter 2010) of column C at
+// detector column u, in the slots of piece_record:
+//  [0] u (int bits)  [1] F1(u) min(a1/|r1|, a2/|r2|)  [2] Y0 hi  [3] Y0 lo
+//  [4] beta hi  [5] beta lo  [6] beta  [7] rho = (Df - Dn) / (Df + Dn)
+//  [8] R^2 = |r_xy|^2 of the column centre  [9] 0  [10] row margin 1.01 rho
+// F1(u) integrates over [u - 1/2, u + 1/2] the height-1 trapezoid whose
+// vertices are the sorted chi1 of the four base corners (the transaxial
+// footprint).  The axial footprint of voxel k is the trapezoid between the
+// chi2 of its top and bottom faces at the nearest (Dn) and farthest (Df)
+// depth of the base: Y(k) = Y0 - k beta is the middle of the top face's
+// ramp, Y(k) + beta that of the bottom face, and a face at Y has the ramp
+// half-width |Y - c2| rho.  The amplitude is the central ray's chord,
+// min(a1/|r1|, a2/|r2|) |r| with r = centre - s; its |r| is applied per
+// voxel.  FP64 like the rest of the column stage.
+__device__ __forceinline__ void tt_record(const DevGeom &G, const ViewGeom &V, const Column &C, int u, float *rec)
+{
+#pragma clang fp contract(off)
+    const double r1 = C.xc1 - V.s1, r2 = C.xc2 - V.s2;
+    const double P1 = V.e1x * r1 + V.e1y * r2;
+    double t[4], Dn = 1e300, Df = -1e300;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double q1 = (k & 1) ? 0.5 * G.a1 : -0.5 * G.a1;
+        const double q2 = (k & 2) ? 0.5 * G.a2 : -0.5 * G.a2;
+        const double D = C.Dc + V.dx * q1 + V.dy * q2;
+        t[k] = V.c1 + V.fb1 * (P1 + V.e1x * q1 + V.e1y * q2) / D;
+        Dn = fmin(Dn, D);
+        Df = fmax(Df, D);
+    }
+    // sort the four vertices (a five-exchange network)
+    auto cx = [&](int a, int b) {
+        const double lo = fmin(t[a], t[b]), hi = fmax(t[a], t[b]);
+        t[a] = lo;
+        t[b] = hi;
+    };
+    cx(0, 1); cx(2, 3); cx(0, 2); cx(1, 3); cx(1, 2);
+    // the trapezoid's integral up to x: rise minus fall, each a hinge
+    // smoothed over its ramp (middle m, half-width e)
+    auto hinge = [](double x, double m, double e) {
+        const double p = fmax(e - fabs(x - m), 0.0);
+        return fmax(x - m, 0.0) + (e > 0.0 ? p * p / (4.0 * e) : 0.0);
+    };
+    const double mu = 0.5 * (t[0] + t[1]), eu = 0.5 * (t[1] - t[0]);
+    const double md = 0.5 * (t[2] + t[3]), ed = 0.5 * (t[3] - t[2]);
+    const double F1 = (hinge(u + 0.5, mu, eu) - hinge(u + 0.5, md, ed)) - (hinge(u - 0.5, mu, eu) - hinge(u - 0.5, md, ed));
+    const double lphi = fmin(G.a1 / fabs(r1), G.a2 / fabs(r2));
+    const double in = 1.0 / Dn, ifar = 1.0 / Df;
+    const double ig = 0.5 * V.fb2 * (in + ifar);
+    const double Y0 = V.c2 - (G.x3lo + G.a3 - V.s3) * ig;
+    const double beta = G.a3 * ig;
+    const double Y0h = rint(Y0 * 1024.0) * (1.0 / 1024.0);
+    const double bh = rint(beta * 1024.0) * (1.0 / 1024.0);
+    const double rho = (in - ifar) / (in + ifar);
+    rec[0] = __int_as_float(u);
+    rec[1] = (float)(F1 * lphi);
+    rec[2] = (float)Y0h;
+    rec[3] = (float)(Y0 - Y0h);
+    rec[4] = (float)bh;
+    rec[5] = (float)(beta - bh);
+    rec[6] = (float)beta;
+    rec[7] = (float)rho;
+    rec[8] = (float)(r1 * r1 + r2 * r2);
+    rec[9] = 0.0f;
+    rec[10] = (float)(1.01 * rho);
+    rec[11] = 0.0f;
+}
+
 // ------------------------------------------------------------ FP32 voxel stage
 
 // Row weights.  The voxel's chi2 extent is [Ytop, Ybot] (Ybot = Ytop + beta)
@@ -246,6 +314,28 @@ __device__ __forceinline__ void boundary(float d, float Yl, float d0, float Ybl,
         const float p1 = fmaxf(fmaf(fabsf(tc), rho, -fabsf(s1)), 0.0f);
         const float inv4e = __builtin_amdgcn_rcpf(fmaf(fabsf(tc), rho4, 1e-30f));
         phi = fmaf(p0, p0, -(p1 * p1)) * inv4e;
+    }
+}
+
+// Row weights of the TT axial footprint: the trapezoid that rises over the
+// top face's ramp (middle Ytop, half-width eu) and falls over the bottom
+// face's (middle Ybot, half-width ed).  Its integral over row [t, t + 1] is
+// m(t) + Phi(t) - Phi(t + 1): m the overlap of [Ytop, Ybot] with the row as
+// in boundary, and Phi(t) = p0^2 / (4 ed) - p1^2 / (4 eu), p = max(e - |s|,
+// 0), each ramp a hinge smoothed over its width.  iu = 1 / (4 eu), id =
+// 1 / (4 ed); FULL = false gives m alone (Phi = 0 where no ramp reaches t).
+template <bool FULL>
+__device__ __forceinline__ void boundary_tt(float d, float Yl, float d0, float Ybl, float eu, float ed, float iu,
+                                            float id, float &s1, float &m, float &phi)
+{
+    s1 = d + Yl;
+    const float s0 = d0 + Ybl;
+    m = __builtin_amdgcn_fmed3f(s0, 0.0f, 1.0f) - __builtin_amdgcn_fmed3f(s1, 0.0f, 1.0f);
+    phi = 0.0f;
+    if (FULL) {
+        const float p0 = fmaxf(ed - fabsf(s0), 0.0f);
+        const float p1 = fmaxf(eu - fabsf(s1), 0.0f);
+        phi = fmaf(p0 * p0, id, -((p1 * p1) * iu));
     }
 }
 
@@ -377,6 +467,59 @@ __device__ __forceinline__ void sweep_rows(int vlo0, int vhi0, int vlo, int vhi,
     }
 }
 
+// Row weights of one TT voxel footprint, added to the band column bcol:
+// rows [vlo, vhi] (clipped) of the unclipped range [vlo0, vhi0], which
+// reaches beyond both ramps, so Phi is 0 at its first and last boundaries.
+// Yh + Yl and Ybh + Ybl: middles of the rise and of the fall (high parts on
+// the 2^-10 grid); eu, ed their half-widths.
+__device__ __forceinline__ void sweep_rows_tt(int vlo0, int vhi0, int vlo, int vhi, float Yh, float Yl, float Ybh,
+                                              float Ybl, float eu, float ed, float coef, unsigned long long *bcol)
+{
+    const float iu = __builtin_amdgcn_rcpf(fmaf(4.0f, eu, 1e-30f));
+    const float id = __builtin_amdgcn_rcpf(fmaf(4.0f, ed, 1e-30f));
+    const float tb = (float)vlo - 0.5f;
+    float d = Yh - tb;
+    float d0 = Ybh - tb;
+    float s1, mp, phip;
+    if (vlo != vlo0) boundary_tt<true>(d, Yl, d0, Ybl, eu, ed, iu, id, s1, mp, phip);
+    else boundary_tt<false>(d, Yl, d0, Ybl, eu, ed, iu, id, s1, mp, phip);
+    float psip = mp + phip;
+    unsigned long long *const last = bcol + vhi;
+    for (unsigned long long *q = bcol + vlo; q < last; ++q) {
+        d -= 1.0f;
+        d0 -= 1.0f;
+        float mn, phin;
+        boundary_tt<true>(d, Yl, d0, Ybl, eu, ed, iu, id, s1, mn, phin);
+        lds_add_fixed(q, coef * (psip - phin));
+        psip = mn + phin;
+    }
+    if (vlo <= vhi) {
+        float phin = 0.0f;
+        if (vhi != vhi0) {
+            float mn;
+            boundary_tt<true>(d - 1.0f, Yl, d0 - 1.0f, Ybl, eu, ed, iu, id, s1, mn, phin);
+        }
+        lds_add_fixed(last, coef * (psip - phin));
+    }
+}
+
+// The TT footprint of a voxel whose top-face ramp has middle Yh + Yl: the
+// half-widths |Y - c2| rho of its two faces; ramps that would overlap (a
+// voxel shorter than its ramps) meet at the crossing of the sorted
+// vertices, which moves each middle inwards by dl and narrows both ramps
+// by dl.  Outputs the middles' low parts and the half-widths.
+__device__ __forceinline__ void tt_ramps(float Yh, float Yl, float bl, float beta, float rho, float c2f,
+                                         float &Ylu, float &Ybld, float &eu, float &ed)
+{
+    const float Yt = Yh + Yl;
+    const float et = fabsf(Yt - c2f) * rho, eb = fabsf(Yt + beta - c2f) * rho;
+    const float dl = 0.5f * fmaxf(et + eb - beta, 0.0f);
+    Ylu = Yl - dl;
+    Ybld = (Yl + bl) + dl;
+    eu = et - dl;
+    ed = eb - dl;
+}
+
 // The lanes of a record pass hold consecutive pieces of a column GW lanes
 // apart, and the upper boundary u + 1/2 of piece s is the lower boundary of
 // piece s + 1: each lane computes its lower prefix (also for s = n, the
@@ -395,11 +538,16 @@ __device__ __forceinline__ Mom shfl_mom(const Mom &m, int src)
     return r;
 }
 
-template <bool EXACT, bool EC>
+template <bool EXACT, bool EC, bool TT = false>
 __device__ __forceinline__ void piece_pair_record(const DevGeom &G, const ViewGeom &V, const Column &C,
                                                   bool colok, int ufirst, int n, int s, bool last_slot,
                                                   int lane, int gw, float *rec)
 {
+    if constexpr (TT) {
+        // footprints need no polygon moments
+        if (colok && s < n) tt_record(G, V, C, ufirst + s, rec);
+        return;
+    }
     Mom lo = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (colok && s <= n) lo = column_prefix(G, V, C, (ufirst + s) - 0.5);
     Mom hi = shfl_mom(lo, lane + gw);
@@ -412,7 +560,7 @@ __device__ __forceinline__ void piece_pair_record(const DevGeom &G, const ViewGe
 // Record phase of the backprojection: LPV lanes l = (c, slot) compute the
 // pieces of columns i0 + c of row j whose detector column u lies in
 // [ulo, uhi], LPV / GW slots at a time.
-template <bool EXACT, bool EC, int PMAX, int GW, int LPV>
+template <bool EXACT, bool EC, int PMAX, int GW, int LPV, bool TT = false>
 __device__ __forceinline__ void build_records(const DevGeom &G, const ViewGeom &V, int i0, int j,
                                               int ulo, int uhi, float *rec, int *npc, int l, int lane)
 {
@@ -433,8 +581,8 @@ __device__ __forceinline__ void build_records(const DevGeom &G, const ViewGeom &
 #pragma unroll
     for (int pass = 0; pass * SLOTS < PMAX; ++pass) {
         const int s = slot + pass * SLOTS;
-        piece_pair_record<EXACT, EC>(G, V, C, colok, ufirst, n, s, slot == SLOTS - 1, lane, GW,
-                                     rec + (c * PMAX + min(s, PMAX - 1)) * kRecFloats);
+        piece_pair_record<EXACT, EC, TT>(G, V, C, colok, ufirst, n, s, slot == SLOTS - 1, lane, GW,
+                                         rec + (c * PMAX + min(s, PMAX - 1)) * kRecFloats);
     }
 }
 
@@ -442,7 +590,7 @@ __device__ __forceinline__ void build_records(const DevGeom &G, const ViewGeom &
 
 // One work item of the projection: detector-column band item / nviews of view
 // item % nviews.  smem holds the LDS layout described below.
-template <bool EXACT, bool EC, int PMAX>
+template <bool EXACT, bool EC, int PMAX, bool TT = false>
 __device__ __forceinline__ void project_item(const DevGeom &G, const int U, const int item,
                                              float *smem, const float *__restrict__ vol,
                                              float *__restrict__ proj, const unsigned *__restrict__ gmax)
@@ -629,8 +777,8 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
             }
 #pragma unroll
             for (int q = 0; q < PASSES; ++q)
-                piece_pair_record<EXACT, EC>(G, V, C, colok, ufirst, ncol, slot + 4 * q, slot == 3, lane, 16,
-                                             rq[q]);
+                piece_pair_record<EXACT, EC, TT>(G, V, C, colok, ufirst, ncol, slot + 4 * q, slot == 3, lane, 16,
+                                                 rq[q]);
         }
         if (__ballot(ncol > 0) == 0) continue;
         const bool full = vec_rows && (i0 + GW <= G.n1);
@@ -650,7 +798,9 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
                 const float m = kv ? mu[c] : 0.0f;
                 if (__ballot(m != 0.0f) == 0) continue;
                 float base = m;
-                if (!EXACT && !raw)
+                if (TT)   // the central ray's |r| (its min(a1/|r1|, a2/|r2|) is in the records)
+                    base = m * sqrtf(fmaf(zc, zc, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rq[0][8]), c))));
+                else if (!EXACT && !raw)
                     base = m * __builtin_amdgcn_rcpf(fmaf(zc, zc, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rq[0][8]), c))));
                 base = ldexpf(base, sc);
                 for (int p = 0; p < np; ++p) {
@@ -673,9 +823,16 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
                     unsigned long long *bcol = bins + (u - u0) * Npad;
                     int vlo0, vhi0;
                     row_range_unclipped<EC>(Yh + Yl, beta, r[10], c2f, vlo0, vhi0);
-                    // bottom face Y(k - 1): high part Yh + bh (exact on the 2^-10 grid), low part Yl + bl
-                    sweep_rows<EC, EXACT>(vlo0, vhi0, max(vlo0, 0), min(vhi0, G.N - 1), Yh, Yl, Yh + r[4],
-                                          Yl + r[5], beta, rho, c2f, coef, raw, zt, r[8], r[9], bcol);
+                    if constexpr (TT) {
+                        float Ylu, Ybld, eu, ed;
+                        tt_ramps(Yh, Yl, r[5], beta, rho, c2f, Ylu, Ybld, eu, ed);
+                        sweep_rows_tt(vlo0, vhi0, max(vlo0, 0), min(vhi0, G.N - 1), Yh, Ylu, Yh + r[4], Ybld, eu,
+                                      ed, coef, bcol);
+                    } else {
+                        // bottom face Y(k - 1): high part Yh + bh (exact on the 2^-10 grid), low part Yl + bl
+                        sweep_rows<EC, EXACT>(vlo0, vhi0, max(vlo0, 0), min(vhi0, G.N - 1), Yh, Yl, Yh + r[4],
+                                              Yl + r[5], beta, rho, c2f, coef, raw, zt, r[8], r[9], bcol);
+                    }
                 }
             }
         }
@@ -699,7 +856,7 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
 // SIMD); both ran about 20% faster at 512^3 x 248 views than at their
 // natural 190-220 VGPRs with 2 waves per SIMD, and the projection 3% faster
 // at 5 waves than at 4.
-template <bool EXACT, bool EC, int PMAX>
+template <bool EXACT, bool EC, int PMAX, bool TT = false>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5)))
 project_kernel(const DevGeom G, const int U, const int nbands, const float *__restrict__ vol,
                float *__restrict__ proj, const unsigned *__restrict__ gmax, const double *__restrict__ stop)
@@ -713,7 +870,7 @@ project_kernel(const DevGeom G, const int U, const int nbands, const float *__re
     const int slot = blockIdx.x >> 3;
     const int band = (blockIdx.x & 7) + 8 * (slot / G.nviews);
     if (band >= nbands) return;
-    project_item<EXACT, EC, PMAX>(G, U, band * G.nviews + slot % G.nviews, smem, vol, proj, gmax);
+    project_item<EXACT, EC, PMAX, TT>(G, U, band * G.nviews + slot % G.nviews, smem, vol, proj, gmax);
 }
 
 // gmax[j * ngroups + q] = the largest |mu| bit pattern over the columns
@@ -755,7 +912,7 @@ group_max_kernel(const DevGeom G, const float *__restrict__ vol, unsigned *__res
 // One work item of the backprojection: a stack of GW columns x 64 kp voxels
 // (kp = 1 or 2), gathered in kp 64-voxel passes that share each view's piece
 // records and detector window (with kp = 2, half their cost per voxel).
-template <bool EXACT, bool EC, int PMAX, int GW>
+template <bool EXACT, bool EC, int PMAX, int GW, bool TT = false>
 __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngroups,
                                                  const int nkchunks, const int kp, const int winCap,
                                                  const int item, float *smem,
@@ -805,7 +962,7 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
             const int view = vb + r * kWaves;
             float *rv = rec + r * recView;
             if (view < G.nviews)
-                build_records<EXACT, EC, PMAX, GW, LPV>(G, G.views[(size_t)view * G.vstride], i0, j, 0, G.M - 1, rv,
+                build_records<EXACT, EC, PMAX, GW, LPV, TT>(G, G.views[(size_t)view * G.vstride], i0, j, 0, G.M - 1, rv,
                                                         reinterpret_cast<int *>(rv + GW * PMAX * kRecFloats),
                                                         lane % LPV, lane);
         }
@@ -907,7 +1064,8 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
             if (np == 0) continue;
             const float *rc = recv + c * PMAX * kRecFloats;
             float base = 1.0f;
-            if (!EXACT && !raw) base = __builtin_amdgcn_rcpf(fmaf(zc, zc, rc[8]));
+            if (TT) base = sqrtf(fmaf(zc, zc, rc[8]));
+            else if (!EXACT && !raw) base = __builtin_amdgcn_rcpf(fmaf(zc, zc, rc[8]));
             float a = 0.0f;
             for (int p = 0; p < np; ++p) {
                 const float4 r0 = *reinterpret_cast<const float4 *>(rc + p * kRecFloats);
@@ -927,6 +1085,30 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
                 const int vlo = max(max(vlo0, 0), wv0);
                 const int vhi = kv ? min(min(vhi0, G.N - 1), wv1) : vlo - 1;
                 const float *wcol = win + (u - wu0) * Hp - wv0;
+                if constexpr (TT) {
+                    // the TT axial footprint's row integrals (Phi is exactly 0
+                    // at the ends of the unclipped range, computed or not)
+                    float Ylu, Ybld, eu, ed;
+                    tt_ramps(Yh, Yl, r1.y, beta, rho, c2f, Ylu, Ybld, eu, ed);
+                    const float iu = __builtin_amdgcn_rcpf(fmaf(4.0f, eu, 1e-30f));
+                    const float id = __builtin_amdgcn_rcpf(fmaf(4.0f, ed, 1e-30f));
+                    const float tb = (float)vlo - 0.5f;
+                    float d = Yh - tb, d0 = Ybh - tb;
+                    float s1, mp, phip;
+                    boundary_tt<true>(d, Ylu, d0, Ybld, eu, ed, iu, id, s1, mp, phip);
+                    float psip = mp + phip, ap = 0.0f;
+                    for (int v = vlo; v <= vhi; ++v) {
+                        d -= 1.0f;
+                        d0 -= 1.0f;
+                        float mn, phin;
+                        boundary_tt<true>(d, Ylu, d0, Ybld, eu, ed, iu, id, s1, mn, phin);
+                        const float val = WIN ? wcol[v] : pv[(size_t)v * G.M + u];
+                        ap = fmaf(psip - phin, val, ap);
+                        psip = mn + phin;
+                    }
+                    a = fmaf(base * r0.y, ap, a);
+                    continue;
+                }
                 // boundaries as in sweep_rows; row weight m(t) + Phi(t) - Phi(t + 1)
                 const float tb = (float)vlo - 0.5f;
                 float d = Yh - tb;
@@ -1017,7 +1199,7 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
     }
 }
 
-template <bool EXACT, bool EC, int PMAX, int GW>
+template <bool EXACT, bool EC, int PMAX, int GW, bool TT = false>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
 backproject_kernel(const DevGeom G, const int ngroups, const int nkchunks, const int kp, const int items,
                    const int chunk, const int winCap, const float *__restrict__ proj,
@@ -1027,7 +1209,7 @@ backproject_kernel(const DevGeom G, const int ngroups, const int nkchunks, const
     if (stop && *stop != 0.0) return;
     const int item = (blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
     if (item >= items) return;
-    backproject_item<EXACT, EC, PMAX, GW>(G, ngroups, nkchunks, kp, winCap, item, smem, proj, vol);
+    backproject_item<EXACT, EC, PMAX, GW, TT>(G, ngroups, nkchunks, kp, winCap, item, smem, proj, vol);
 }
 
 // ------------------------------------------------------------ batched, persistent
@@ -1105,7 +1287,7 @@ __global__ void batch_setup(BatchProblem *probs, const BatchIO io, int *counter)
     *counter = 0;
 }
 
-template <bool EXACT, bool EC>
+template <bool EXACT, bool EC, bool TT = false>
 hipError_t launch_p(const DevGeom &g, const ProjLaunch &L, const float *vol, float *proj,
                     unsigned *gmax, hipStream_t s, const double *stop)
 {
@@ -1115,70 +1297,70 @@ hipError_t launch_p(const DevGeom &g, const ProjLaunch &L, const float *vol, flo
     }
     const dim3 grid(8 * L.chunk), block(kBlock);
     if (L.pmax <= 4)
-        hipLaunchKernelGGL((project_kernel<EXACT, EC, 4>), grid, block, L.lds, s, g, L.U, L.nbands, vol, proj,
+        hipLaunchKernelGGL((project_kernel<EXACT, EC, 4, TT>), grid, block, L.lds, s, g, L.U, L.nbands, vol, proj,
                            gmax, stop);
     else
-        hipLaunchKernelGGL((project_kernel<EXACT, EC, 8>), grid, block, L.lds, s, g, L.U, L.nbands, vol, proj,
+        hipLaunchKernelGGL((project_kernel<EXACT, EC, 8, TT>), grid, block, L.lds, s, g, L.U, L.nbands, vol, proj,
                            gmax, stop);
     return hipGetLastError();
 }
 
-template <bool EXACT, bool EC, int PMAX>
+template <bool EXACT, bool EC, int PMAX, bool TT = false>
 hipError_t launch_bp_gw(const DevGeom &g, const BackLaunch &L, const float *proj, float *vol,
                         hipStream_t s, const double *stop)
 {
     const dim3 grid(8 * L.chunk), block(kBlock);
     switch (L.gw) {
     case 16:
-        hipLaunchKernelGGL((backproject_kernel<EXACT, EC, PMAX, 16>), grid, block, L.lds, s, g,
+        hipLaunchKernelGGL((backproject_kernel<EXACT, EC, PMAX, 16, TT>), grid, block, L.lds, s, g,
                            L.ngroups, L.nkchunks, L.kp, L.items, L.chunk, L.win_cap, proj, vol, stop);
         break;
     case 8:
-        hipLaunchKernelGGL((backproject_kernel<EXACT, EC, PMAX, 8>), grid, block, L.lds, s, g,
+        hipLaunchKernelGGL((backproject_kernel<EXACT, EC, PMAX, 8, TT>), grid, block, L.lds, s, g,
                            L.ngroups, L.nkchunks, L.kp, L.items, L.chunk, L.win_cap, proj, vol, stop);
         break;
     default:
-        hipLaunchKernelGGL((backproject_kernel<EXACT, EC, PMAX, 4>), grid, block, L.lds, s, g,
+        hipLaunchKernelGGL((backproject_kernel<EXACT, EC, PMAX, 4, TT>), grid, block, L.lds, s, g,
                            L.ngroups, L.nkchunks, L.kp, L.items, L.chunk, L.win_cap, proj, vol, stop);
         break;
     }
     return hipGetLastError();
 }
 
-template <bool EXACT, bool EC>
+template <bool EXACT, bool EC, bool TT = false>
 hipError_t launch_bp(const DevGeom &g, const BackLaunch &L, const float *proj, float *vol,
                      hipStream_t s, const double *stop)
 {
-    if (L.pmax <= 4) return launch_bp_gw<EXACT, EC, 4>(g, L, proj, vol, s, stop);
-    if (L.pmax <= 8) return launch_bp_gw<EXACT, EC, 8>(g, L, proj, vol, s, stop);
+    if (L.pmax <= 4) return launch_bp_gw<EXACT, EC, 4, TT>(g, L, proj, vol, s, stop);
+    if (L.pmax <= 8) return launch_bp_gw<EXACT, EC, 8, TT>(g, L, proj, vol, s, stop);
     // wide footprints: 4-column stacks only
     if (L.gw != 4) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((backproject_kernel<EXACT, EC, kPmaxWide, 4>), dim3(8 * L.chunk), dim3(kBlock), L.lds, s, g,
+    hipLaunchKernelGGL((backproject_kernel<EXACT, EC, kPmaxWide, 4, TT>), dim3(8 * L.chunk), dim3(kBlock), L.lds, s, g,
                        L.ngroups, L.nkchunks, L.kp, L.items, L.chunk, L.win_cap, proj, vol, stop);
     return hipGetLastError();
 }
 
-template <bool EXACT, bool EC, int PMAX>
+template <bool EXACT, bool EC, int PMAX, bool TT = false>
 hipError_t set_lds_one(size_t n)
 {
-    hipError_t e = hipFuncSetAttribute((const void *)project_kernel<EXACT, EC, PMAX>,
+    hipError_t e = hipFuncSetAttribute((const void *)project_kernel<EXACT, EC, PMAX, TT>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
     if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)backproject_kernel<EXACT, EC, PMAX, 16>,
+        e = hipFuncSetAttribute((const void *)backproject_kernel<EXACT, EC, PMAX, 16, TT>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
     if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)backproject_kernel<EXACT, EC, PMAX, 8>,
+        e = hipFuncSetAttribute((const void *)backproject_kernel<EXACT, EC, PMAX, 8, TT>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
     if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)backproject_kernel<EXACT, EC, PMAX, 4>,
+        e = hipFuncSetAttribute((const void *)backproject_kernel<EXACT, EC, PMAX, 4, TT>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
     return e;
 }
 
-template <bool EXACT, bool EC>
+template <bool EXACT, bool EC, bool TT = false>
 hipError_t set_lds_wide(size_t n)
 {
-    return hipFuncSetAttribute((const void *)backproject_kernel<EXACT, EC, kPmaxWide, 4>,
+    return hipFuncSetAttribute((const void *)backproject_kernel<EXACT, EC, kPmaxWide, 4, TT>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
 }
 
@@ -1280,6 +1462,9 @@ hipError_t configure_kernel_lds(size_t max_lds, size_t max_lds_batched)
     if (e == hipSuccess) e = set_lds_wide<true, false>(max_lds);
     if (e == hipSuccess) e = set_lds_wide<false, true>(max_lds);
     if (e == hipSuccess) e = set_lds_wide<false, false>(max_lds);
+    if (e == hipSuccess) e = set_lds_one<false, true, 4, true>(max_lds);
+    if (e == hipSuccess) e = set_lds_one<false, true, 8, true>(max_lds);
+    if (e == hipSuccess) e = set_lds_wide<false, true, true>(max_lds);
     if (e == hipSuccess) e = set_lds_batched<true, true>(max_lds_batched);
     if (e == hipSuccess) e = set_lds_batched<true, false>(max_lds_batched);
     if (e == hipSuccess) e = set_lds_batched<false, true>(max_lds_batched);
@@ -1287,9 +1472,12 @@ hipError_t configure_kernel_lds(size_t max_lds, size_t max_lds_batched)
     return e;
 }
 
-hipError_t launch_project(const DevGeom &g, const ProjLaunch &L, bool exact, bool ec,
+hipError_t launch_project(const DevGeom &g, const ProjLaunch &L, int model, bool ec,
                           const float *vol, float *proj, unsigned *gmax, hipStream_t stream, const double *stop)
 {
+    // TT: its ramps need the row margins of the EC instantiations
+    if (model == kModelTT) return launch_p<false, true, true>(g, L, vol, proj, gmax, stream, stop);
+    const bool exact = model == kModelExact;
     if (exact) return ec ? launch_p<true, true>(g, L, vol, proj, gmax, stream, stop)
                          : launch_p<true, false>(g, L, vol, proj, gmax, stream, stop);
     return ec ? launch_p<false, true>(g, L, vol, proj, gmax, stream, stop)
@@ -1342,9 +1530,11 @@ hipError_t static_scratch(unsigned **out)
     return hipSuccess;
 }
 
-hipError_t launch_backproject(const DevGeom &g, const BackLaunch &L, bool exact, bool ec,
+hipError_t launch_backproject(const DevGeom &g, const BackLaunch &L, int model, bool ec,
                               const float *proj, float *vol, hipStream_t stream, const double *stop)
 {
+    if (model == kModelTT) return launch_bp<false, true, true>(g, L, proj, vol, stream, stop);
+    const bool exact = model == kModelExact;
     if (exact) return ec ? launch_bp<true, true>(g, L, proj, vol, stream, stop)
                          : launch_bp<true, false>(g, L, proj, vol, stream, stop);
     return ec ? launch_bp<false, true>(g, L, proj, vol, stream, stop)

@@ -11,15 +11,17 @@ import torch
 
 from . import _lib
 
-VARIANTS = {"exact": 0, "relaxed": 1}
+VARIANTS = {"exact": 0, "relaxed": 1, "tt": 2}
 SCALINGS = {"solid_angle": 0, "cos": 1, "none": 2}
 
 
 @dataclass(frozen=True)
 class Options:
-    """variant: 'exact' (r at the cut centroid) or 'relaxed' (r at the voxel
-    centre); ec: elevation correction (Sec. III-B); scaling: 'solid_angle'
-    (eq. cvpus), 'cos' (eq. cvp) or 'none'; raw_volume: weight = cut volume."""
+    """variant: 'exact' (r at the cut centroid), 'relaxed' (r at the voxel
+    centre) or 'tt' (the TT separable-footprint projector, which takes ec
+    False and scaling 'cos': see TT); ec: elevation correction (Sec. III-B);
+    scaling: 'solid_angle' (eq. cvpus), 'cos' (eq. cvp) or 'none';
+    raw_volume: weight = cut volume."""
     variant: str = "exact"
     ec: bool = True
     scaling: str = "solid_angle"
@@ -28,6 +30,12 @@ class Options:
     def c(self):
         return _lib.OptionsC(VARIANTS[self.variant], int(bool(self.ec)), SCALINGS[self.scaling],
                              _lib.CVP_FLAG_RAW_VOLUME if self.raw_volume else 0)
+
+
+# Options of the TT separable-footprint projector (the comparator of Sec. I
+# and IV): it estimates the area-averaged line integral, the quantity of the
+# flat-panel scaling.
+TT = Options(variant="tt", ec=False, scaling="cos")
 
 
 class Geometry:

@@ -190,7 +190,8 @@ class UNet:
         _check(lib().cvp_nn_conv3d(ctypes.byref(x), _p(c.wb), _p(c.b), ctypes.byref(out), int(relu), 0, _s()))
 
     def forward(self, x1, x2):
-        """x0 = x2 + U-Net(x1, x2); x1, x2 FP32 volumes (D, H, W)."""
+        """x0 = x2 + U-Net(x1, x2); x1, x2 FP32 volumes (D, H, W).  Returns the
+        network's own output buffer, which the next forward overwrites."""
         a, L = self.a, lib()
         self.x2 = x2
         _check(L.cvp_nn_pack_input(_p(x1), _p(x2), ctypes.c_float(INPUT_SCALE), ctypes.byref(desc(a["in"])), _s()))

@@ -167,9 +167,9 @@ def evaluate_batched(pipe: Pipeline, net: UNet, seeds, tol=1e-3, max_iter=400, p
     warm.iterate(1)
     x1 = [x.clone() for x in warm.x]
     warm.iterate(1)
-    x0 = [net.forward(x1[q], warm.x[q]) for q in range(n)]
     for q in range(n):
-        warm.x[q].copy_(x0[q])
+        # forward returns the network's own output buffer: copy before the next call
+        warm.x[q].copy_(net.forward(x1[q], warm.x[q]))
     itsw, _, rhosw = warm.run(tol=tol, max_iter=max_iter, per_graph=per_graph, gamma_refs=refs)
     t_warm = time.perf_counter() - ts
     errw = [float(torch.linalg.vector_norm(warm.x[q] - xt[q]) / torch.linalg.vector_norm(xt[q])) for q in range(n)]
