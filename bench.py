@@ -8,8 +8,12 @@ backprojection A^T b, inputs resident in HBM.
 
 value = 2 * n_voxels * n_views / (t_A + t_AT)   [voxel-view updates/s]
 
-Before the timed region the autotuner picks the launch plan (projection band
-width, backprojection stack width) on random data of the same shape.  After
+Before the timed region the geometry's cut-piece records are computed once
+and cached on the device (cvp_geometry_cache_records, part of the geometry
+set-up like the pixel factor tables; its size and build time are reported,
+and one A / A^T pair without the cache is timed after the timed region for
+comparison), and the autotuner picks the launch plan (projection band width,
+backprojection stack width) on random data of the same shape.  After
 it, CGLS from zero on consistent data b = A x_true is run to
 |A^T (b - A x)| <= 1e-3 |A^T b| and its wall time reported ("cgls").
 
@@ -44,6 +48,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cgls", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the planner's default launch plan")
+    ap.add_argument("--no-record-cache", action="store_true",
+                    help="let every launch compute its own cut-piece records (no cached record table)")
     ap.add_argument("--launch", default=None, metavar="U,GW,KP",
                     help="fixed launch plan (projection band columns, backprojection stack columns and passes); "
                          "no autotuning")
@@ -224,6 +230,7 @@ def cone_timing(reps=2):
     from paper_2110_09841_amd import cvp, synth
     from paper_2110_09841_amd.autotune import autotune
     G = cvp.Geometry(synth.config_cone())
+    G.cache_records()
     vv = G.n_voxels * G.n_views
     gen = torch.Generator(device="cuda").manual_seed(6)
     x = torch.rand(G.vol_shape, generator=gen, device="cuda")
@@ -406,6 +413,14 @@ def main():
     G = cvp.Geometry(g)
     ec = not args.no_ec
     opts = cvp.Options(variant=args.variant, ec=ec)
+    record_cache = None
+    if not args.no_record_cache:
+        # the geometry's cut-piece records, computed once (geometry set-up)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nb = G.cache_records()
+        torch.cuda.synchronize()
+        record_cache = {"bytes": nb, "build_ms": 1e3 * (time.perf_counter() - t0)}
     plan = {"default": list(G.launch)}
     if args.launch:
         G.set_launch(*(int(t) for t in args.launch.split(",")))
@@ -436,6 +451,22 @@ def main():
     tB = np.array([ev[s][1].elapsed_time(ev[s][2]) for s in range(args.steps)]) * 1e-3
     vv = n1 * n2 * n3 * V
     value = 2 * vv / (tA.mean() + tB.mean())
+    if record_cache is not None:
+        # the same plan with every launch computing its own records, for comparison
+        G.cache_records(False)
+        e4 = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        cvp.project(x, G, opts, out=p_out)
+        cvp.backproject(b, G, opts, out=v_out)
+        e4[0].record()
+        cvp.project(x, G, opts, out=p_out)
+        e4[1].record()
+        cvp.backproject(b, G, opts, out=v_out)
+        e4[2].record()
+        torch.cuda.synchronize()
+        record_cache["without_cache"] = {"project_ms": e4[0].elapsed_time(e4[1]),
+                                         "backproject_ms": e4[1].elapsed_time(e4[2])}
+        G.cache_records()
+        torch.cuda.synchronize()
 
     exact = args.variant == "exact"
     counts = costmodel.estimate_counts(g)
@@ -468,6 +499,7 @@ def main():
                    "elevation_correction": ec, "scaling": "solid_angle",
                    "launch": dict(zip(("proj_band_cols", "bp_stack_cols", "bp_passes"), G.launch))},
         "autotune": plan,
+        "record_cache": record_cache,
         "project": {"ms": 1e3 * tA.mean(), "voxel_views_per_s": vv / tA.mean()},
         "backproject": {"ms": 1e3 * tB.mean(), "voxel_views_per_s": vv / tB.mean()},
         "roofline": {"bound": "alu", "kernel": name, "achieved": rdom["achieved"] / 1e12,

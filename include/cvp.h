@@ -492,6 +492,24 @@ cvp_status cvp_geometry_set_launch(cvp_geometry *g, const cvp_launch *in);
 cvp_status cvp_geometry_sizes(const cvp_geometry *g, int64_t *n_voxels,
                               int64_t *n_pixels_total);
 
+/* Cache the geometry's cut-piece records (Sec. III-A: by the column identity
+ * a voxel column's polygons H_u in one view serve every voxel of the column).
+ * enable = 1 computes, once, for every view and every voxel column (i, j)
+ * the FP64 polygon moments of its pieces (detector columns in [0, M - 1]) and
+ * keeps the resulting records on the geometry's device: n_views * n2 * n1 *
+ * (pmax * 48 + 4) bytes, pmax = 4 or 8 pieces per column (12.7 GB for 512^3
+ * voxels and 248 views).  From then on cvp_project, cvp_backproject, their
+ * _ws / _views / _noalloc variants and the solvers of the cutting voxel
+ * projector (both forms, EC on or off) read the records instead of computing
+ * them in each launch; results are bitwise the same.  The TT projector and
+ * the batched launches keep computing their own.  enable = 0 frees the table.
+ * *bytes (may be NULL) receives the table's size.  The fill is enqueued on
+ * `stream`; it allocates (hipMalloc) on the first enable only.  Call it while
+ * no other call uses the geometry.  Errors: CVP_E_INVALID (NULL geometry,
+ * enable not 0 or 1, another device current), CVP_E_UNSUPPORTED (voxels
+ * projecting onto more than 8 detector columns), CVP_E_NOMEM, CVP_E_DEVICE. */
+cvp_status cvp_geometry_cache_records(cvp_geometry *g, int32_t enable, int64_t *bytes, void *stream);
+
 /* Human-readable status name; never NULL. */
 const char *cvp_status_string(cvp_status s);
 

@@ -122,6 +122,7 @@ def _register_extra(L):
         "cvp_synth_add_gaussian": ([vp, ctypes.c_int64, ctypes.c_float, ctypes.c_uint64, vp], st),
         "cvp_geometry_get_launch": ([vp, ctypes.POINTER(LaunchC)], st),
         "cvp_geometry_set_launch": ([vp, ctypes.POINTER(LaunchC)], st),
+        "cvp_geometry_cache_records": ([vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), vp], st),
     }
     for name, (args, res) in specs.items():
         if hasattr(L, name):

@@ -40,6 +40,9 @@ struct cvp_geometry {
     double zabs = 0.0, Dmin = 0.0;   // for launch planning
     int pmax = 4;                    // pieces per column the kernels keep (4, 8 or kPmaxWide)
     double wone_tt = 0.0, wsum_tt = 0.0;   // fixed-point bounds of the TT projector's weights
+    float *d_rtab = nullptr;         // cached piece records (cvp_geometry_cache_records)
+    int *d_rtab_n = nullptr;
+    int64_t rtab_bytes = 0;
 };
 
 namespace {
@@ -205,6 +208,8 @@ void cvp_geometry_destroy(cvp_geometry *g)
     if (g->d_views) (void)hipFree(g->d_views);
     for (float *p : g->d_sigma)
         if (p) (void)hipFree(p);
+    if (g->d_rtab) (void)hipFree(g->d_rtab);
+    if (g->d_rtab_n) (void)hipFree(g->d_rtab_n);
     delete g;
 }
 
@@ -586,6 +591,46 @@ static int model_of(const cvp_options *o)
     return o->variant == CVP_TT ? cvp::kModelTT : o->variant == CVP_EXACT ? cvp::kModelExact : cvp::kModelRelaxed;
 }
 
+cvp_status cvp_geometry_cache_records(cvp_geometry *g, int32_t enable, int64_t *bytes, void *stream)
+{
+    if (!g) return fail(CVP_E_INVALID, "geometry is NULL");
+    if (enable != 0 && enable != 1) return fail(CVP_E_INVALID, "enable = %d (0 or 1)", enable);
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return device_fail(e, "hipGetDevice");
+    if (dev != g->device)
+        return fail(CVP_E_INVALID, "geometry lives on device %d but device %d is current", g->device, dev);
+    if (!enable) {
+        if (g->d_rtab) (void)hipFree(g->d_rtab);
+        if (g->d_rtab_n) (void)hipFree(g->d_rtab_n);
+        g->d_rtab = nullptr;
+        g->d_rtab_n = nullptr;
+        g->rtab_bytes = 0;
+        if (bytes) *bytes = 0;
+        return ok();
+    }
+    if (g->pmax > 8)
+        return fail(CVP_E_UNSUPPORTED, "voxels project onto more than 8 detector columns: records are not cached");
+    if (!g->d_rtab) {
+        const int64_t cols = (int64_t)g->base.nviews * g->base.n2 * g->base.n1;
+        const size_t rb = (size_t)cols * g->pmax * cvp::kRecFloats * sizeof(float);
+        const size_t nb = (size_t)cols * sizeof(int);
+        e = hipMalloc((void **)&g->d_rtab, rb);
+        if (e == hipSuccess) e = hipMalloc((void **)&g->d_rtab_n, nb);
+        if (e == hipSuccess) e = cvp::launch_record_table(g->base, g->pmax, g->d_rtab, g->d_rtab_n, (hipStream_t)stream);
+        if (e != hipSuccess) {
+            if (g->d_rtab) (void)hipFree(g->d_rtab);
+            if (g->d_rtab_n) (void)hipFree(g->d_rtab_n);
+            g->d_rtab = nullptr;
+            g->d_rtab_n = nullptr;
+            return device_fail(e, "record table");
+        }
+        g->rtab_bytes = (int64_t)(rb + nb);
+    }
+    if (bytes) *bytes = g->rtab_bytes;
+    return ok();
+}
+
 static cvp_status prepare(const cvp_geometry *g, const cvp_options *o, const void *in, void *outp,
                           cvp::DevGeom &G)
 {
@@ -617,6 +662,11 @@ static cvp_status prepare(const cvp_geometry *g, const cvp_options *o, const voi
         G.sigma = nullptr;
         G.wone_bound = g->wone_tt;
         G.wsum_bound = g->wsum_tt;
+    } else if (g->d_rtab) {
+        // the cached piece records (the same bits the kernels would compute)
+        G.rtab = g->d_rtab;
+        G.rtab_n = g->d_rtab_n;
+        G.rtab_pmax = g->pmax;
     }
     return CVP_OK;
 }
@@ -721,6 +771,11 @@ static cvp_status view_subset(const cvp_geometry *g, int32_t view0, int32_t stri
     G.nviews = count;
     proj_offset = (int64_t)view0 * G.N * G.M;
     if (G.sigma && G.sigma_views) G.sigma += proj_offset;
+    if (G.rtab) {
+        const int64_t cols = (int64_t)view0 * G.n2 * G.n1;
+        G.rtab += cols * G.rtab_pmax * cvp::kRecFloats;
+        G.rtab_n += cols;
+    }
     return CVP_OK;
 }
 

@@ -62,6 +62,14 @@ struct DevGeom {
     // 1/r^2 factor), used to scale the projection's fixed-point sums.
     double wsum_bound, wsum_bound_raw;   // a pixel's summed weight per unit |mu|
     double wone_bound, wone_bound_raw;   // one (voxel, pixel) weight per unit |mu|
+    // The geometry's cached piece records (nullptr: the kernels compute
+    // their own): rtab[((q n2 + j) n1 + i) pmax + s][kRecFloats] and the
+    // piece counts rtab_n[(q n2 + j) n1 + i] of column (i, j) in view q of
+    // the launch (q * vstride, from the launch's first view), pieces clipped
+    // to the detector columns; rtab_pmax slots per column.
+    const float *rtab;
+    const int *rtab_n;
+    int rtab_pmax;
 };
 
 struct ProjLaunch {
@@ -181,6 +189,8 @@ constexpr int64_t kStaticScratchWords = int64_t(1) << 18;
 hipError_t static_scratch(unsigned **out);
 // SiddonK reference projector: K x K rays per pixel, exact chord lengths.
 hipError_t launch_siddon(const DevGeom &g, int K, const float *vol, float *proj, hipStream_t s);
+// Fills a geometry's record table (every view, every column; pmax 4 or 8).
+hipError_t launch_record_table(const DevGeom &g, int pmax, float *rec, int *cnt, hipStream_t stream);
 hipError_t launch_backproject(const DevGeom &g, const BackLaunch &L, int model, bool ec,
                               const float *proj, float *vol, hipStream_t stream, const double *stop = nullptr);
 

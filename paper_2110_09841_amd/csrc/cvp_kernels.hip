@@ -158,10 +158,13 @@ __device__ __forceinline__ Mom column_prefix(const DevGeom &G, const ViewGeom &V
 // Record of one cut piece H_u for the FP32 voxel stage (12 floats):
 //  [0] u (int bits)  [1] W = A_u * b2 D_u / f       [2] Y0 hi   [3] Y0 lo
 //  [4] beta hi       [5] beta lo   [6] beta          [7] rho = h/D (EC)
-//  [8] R^2 (x1x2 part of r^2: cut centroid, or column centre if relaxed)
-//  [9] b2 D_u / f (mm of x3 per row)  [10] EC row margin factor  [11] unused
+//  [8] R^2 of the column centre (x1x2 part of r^2, relaxed form)
+//  [9] b2 D_u / f (mm of x3 per row)  [10] EC row margin factor
+//  [11] R^2 of the cut centroid (exact form)
 // Y(k) = Y0 - k beta is chi2 of the top face of voxel k at the centroid depth.
-// lo / hi: column_prefix at u - 1/2 and u + 1/2.
+// lo / hi: column_prefix at u - 1/2 and u + 1/2.  The record is the same for
+// every option (the kernels read the slots their form needs), so a geometry's
+// table of records serves them all.
 template <bool EXACT, bool EC>
 __device__ __forceinline__ void piece_record(const DevGeom &G, const ViewGeom &V, const Column &C,
                                              int u, const Mom &lo, const Mom &hi, float *rec)
@@ -189,14 +192,8 @@ __device__ __forceinline__ void piece_record(const DevGeom &G, const ViewGeom &V
     const double beta = G.a3 * ig;
     const double Y0h = rint(Y0 * 1024.0) * (1.0 / 1024.0);
     const double bh = rint(beta * 1024.0) * (1.0 / 1024.0);
-    double R2;
-    if (EXACT) {
-        const double p1 = C.xc1 + cx - V.s1, p2 = C.xc2 + cy - V.s2;
-        R2 = p1 * p1 + p2 * p2;
-    } else {
-        const double p1 = C.xc1 - V.s1, p2 = C.xc2 - V.s2;
-        R2 = p1 * p1 + p2 * p2;
-    }
+    const double p1 = C.xc1 + cx - V.s1, p2 = C.xc2 + cy - V.s2;   // cut centroid
+    const double q1 = C.xc1 - V.s1, q2 = C.xc2 - V.s2;             // column centre
     rec[0] = __int_as_float(u);
     rec[1] = (A > 1e-12 * G.a1 * G.a2) ? (float)(A * gmm) : 0.0f;
     rec[2] = (float)Y0h;
@@ -204,14 +201,14 @@ __device__ __forceinline__ void piece_record(const DevGeom &G, const ViewGeom &V
     rec[4] = (float)bh;
     rec[5] = (float)(beta - bh);
     rec[6] = (float)beta;
-    rec[7] = EC ? (float)(sqrt(3.0 * var) * iDu) : 0.0f;
-    rec[8] = (float)R2;
+    rec[7] = (float)(sqrt(3.0 * var) * iDu);
+    rec[8] = (float)(q1 * q1 + q2 * q2);
     rec[9] = (float)gmm;
     // EC row margin factor 1.01 rho / (1 - rho) from the FP32 rho the voxel
     // stage uses (see row_range_unclipped)
     const double rho32 = (double)rec[7];
-    rec[10] = EC ? (float)(1.01 * rho32 / fmax(1.0 - rho32, 0.05)) : 0.0f;
-    rec[11] = 0.0f;
+    rec[10] = (float)(1.01 * rho32 / fmax(1.0 - rho32, 0.05));
+    rec[11] = (float)(p1 * p1 + p2 * p2);
 }
 
 // Record of the TT separable footprint (the footprint projector the paper
@@ -586,11 +583,46 @@ __device__ __forceinline__ void build_records(const DevGeom &G, const ViewGeom &
     }
 }
 
+// A geometry's piece records, computed once: one thread per (view,
+// column), its pieces in order (detector columns clipped to [0, M - 1], at
+// most PMAX), the prefix moments of consecutive boundaries shared.  The
+// arguments and operations are those of the kernels' own record stages
+// (u + 1/2 = (u + 1) - 1/2 exactly, no contraction), so the records are the
+// same bits and the kernels that read them give the same results.
+template <int PMAX>
+__global__ void __launch_bounds__(kBlock)
+record_table_kernel(const DevGeom G, float *__restrict__ rec, int *__restrict__ cnt)
+{
+    const int64_t ncols = (int64_t)G.n1 * G.n2;
+    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= ncols * G.nviews) return;
+    const int view = (int)(idx / ncols);
+    const int rem = (int)(idx - (int64_t)view * ncols);
+    const int j = rem / G.n1, i = rem - j * G.n1;
+    const ViewGeom V = G.views[(size_t)view * G.vstride];
+    const Column C = make_column(G, V, i, j);
+    const int ufirst = max((int)floor(C.chimin + 0.5), 0);
+    const int ulast = min((int)floor(C.chimax + 0.5), G.M - 1);
+    const int n = min(max(ulast - ufirst + 1, 0), PMAX);
+    cnt[idx] = n;
+    float *out = rec + idx * PMAX * kRecFloats;
+    Mom lo = column_prefix(G, V, C, ufirst - 0.5);
+    for (int sl = 0; sl < n; ++sl) {
+        const Mom hi = column_prefix(G, V, C, (ufirst + sl) + 0.5);
+        float r[kRecFloats];
+        piece_record<false, true>(G, V, C, ufirst + sl, lo, hi, r);
+#pragma unroll
+        for (int e = 0; e < kRecFloats; e += 4)
+            *reinterpret_cast<float4 *>(out + sl * kRecFloats + e) = make_float4(r[e], r[e + 1], r[e + 2], r[e + 3]);
+        lo = hi;
+    }
+}
+
 // ------------------------------------------------------------ projection
 
 // One work item of the projection: detector-column band item / nviews of view
 // item % nviews.  smem holds the LDS layout described below.
-template <bool EXACT, bool EC, int PMAX, bool TT = false>
+template <bool EXACT, bool EC, int PMAX, bool TT = false, bool TAB = false>
 __device__ __forceinline__ void project_item(const DevGeom &G, const int U, const int item,
                                              float *smem, const float *__restrict__ vol,
                                              float *__restrict__ proj, const unsigned *__restrict__ gmax)
@@ -763,7 +795,31 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
         constexpr int PASSES = PMAX / 4;
         float rq[PASSES][kRecFloats];
         int ncol = 0;
-        {
+        if constexpr (TAB) {
+            // the geometry's records: the column's pieces that fall in the band
+            const int c = lane & 15, slot = lane >> 4;
+            const int i = i0 + c;
+            if (i < G.n1) {
+                const size_t col = ((size_t)view * G.vstride * G.n2 + j) * G.n1 + i;
+                const int nt = G.rtab_n[col];
+                const float *rc = G.rtab + col * G.rtab_pmax * kRecFloats;
+                const int uf = nt > 0 ? __float_as_int(rc[0]) : 0;
+                const int off = max(u0 - uf, 0);
+                ncol = min(max(min(nt, ub - uf + 1) - off, 0), PMAX);
+#pragma unroll
+                for (int q = 0; q < PASSES; ++q) {
+                    const int sl = slot + 4 * q;
+                    if (sl < ncol) {
+                        const float4 *r4 = reinterpret_cast<const float4 *>(rc + (off + sl) * kRecFloats);
+#pragma unroll
+                        for (int e = 0; e < kRecFloats / 4; ++e) {
+                            const float4 t4 = r4[e];
+                            rq[q][4 * e] = t4.x; rq[q][4 * e + 1] = t4.y; rq[q][4 * e + 2] = t4.z; rq[q][4 * e + 3] = t4.w;
+                        }
+                    }
+                }
+            }
+        } else {
             const int c = lane & 15, slot = lane >> 4;
             const int i = i0 + c;
             const bool colok = i < G.n1;
@@ -831,7 +887,7 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
                     } else {
                         // bottom face Y(k - 1): high part Yh + bh (exact on the 2^-10 grid), low part Yl + bl
                         sweep_rows<EC, EXACT>(vlo0, vhi0, max(vlo0, 0), min(vhi0, G.N - 1), Yh, Yl, Yh + r[4],
-                                              Yl + r[5], beta, rho, c2f, coef, raw, zt, r[8], r[9], bcol);
+                                              Yl + r[5], beta, rho, c2f, coef, raw, zt, r[11], r[9], bcol);
                     }
                 }
             }
@@ -856,7 +912,7 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
 // SIMD); both ran about 20% faster at 512^3 x 248 views than at their
 // natural 190-220 VGPRs with 2 waves per SIMD, and the projection 3% faster
 // at 5 waves than at 4.
-template <bool EXACT, bool EC, int PMAX, bool TT = false>
+template <bool EXACT, bool EC, int PMAX, bool TT = false, bool TAB = false>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5)))
 project_kernel(const DevGeom G, const int U, const int nbands, const float *__restrict__ vol,
                float *__restrict__ proj, const unsigned *__restrict__ gmax, const double *__restrict__ stop)
@@ -870,7 +926,7 @@ project_kernel(const DevGeom G, const int U, const int nbands, const float *__re
     const int slot = blockIdx.x >> 3;
     const int band = (blockIdx.x & 7) + 8 * (slot / G.nviews);
     if (band >= nbands) return;
-    project_item<EXACT, EC, PMAX, TT>(G, U, band * G.nviews + slot % G.nviews, smem, vol, proj, gmax);
+    project_item<EXACT, EC, PMAX, TT, TAB>(G, U, band * G.nviews + slot % G.nviews, smem, vol, proj, gmax);
 }
 
 // gmax[j * ngroups + q] = the largest |mu| bit pattern over the columns
@@ -912,7 +968,7 @@ group_max_kernel(const DevGeom G, const float *__restrict__ vol, unsigned *__res
 // One work item of the backprojection: a stack of GW columns x 64 kp voxels
 // (kp = 1 or 2), gathered in kp 64-voxel passes that share each view's piece
 // records and detector window (with kp = 2, half their cost per voxel).
-template <bool EXACT, bool EC, int PMAX, int GW, bool TT = false>
+template <bool EXACT, bool EC, int PMAX, int GW, bool TT = false, bool TAB = false>
 __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngroups,
                                                  const int nkchunks, const int kp, const int winCap,
                                                  const int item, float *smem,
@@ -950,14 +1006,29 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
         for (int c = 0; c < GW; ++c) acc[ps][c] = 0.0f;
 
     for (int vb = wave; vb < G.nviews; vb += kWaves * RV) {
-        // The accumulators wait in the (idle) window area while the FP64
-        // record stage, the kernel's register peak, runs.
+        if constexpr (TAB) {
+            // the geometry's records of the stack, view by view, into LDS
 #pragma unroll
-        for (int ps = 0; ps < KP; ++ps)
+            for (int r = 0; r < RV; ++r) {
+                const int view = vb + r * kWaves;
+                if (view >= G.nviews) break;
+                float *rv = rec + r * recView;
+                int *npv = reinterpret_cast<int *>(rv + GW * PMAX * kRecFloats);
+                const size_t col0 = ((size_t)view * G.vstride * G.n2 + j) * G.n1 + i0;
+                const int ncv = min(GW, G.n1 - i0);
+                const float4 *src = reinterpret_cast<const float4 *>(G.rtab + col0 * PMAX * kRecFloats);
+                for (int q4 = lane; q4 < ncv * PMAX * kRecFloats / 4; q4 += kWave)
+                    reinterpret_cast<float4 *>(rv)[q4] = src[q4];
+                if (lane < GW) npv[lane] = lane < ncv ? G.rtab_n[col0 + lane] : 0;
+            }
+        } else {
+            // The accumulators wait in the (idle) window area while the FP64
+            // record stage, the kernel's register peak, runs.
 #pragma unroll
-            for (int c = 0; c < GW; ++c) win[(ps * GW + c) * kWave + lane] = acc[ps][c];
-        wave_sync();
-        {
+            for (int ps = 0; ps < KP; ++ps)
+#pragma unroll
+                for (int c = 0; c < GW; ++c) win[(ps * GW + c) * kWave + lane] = acc[ps][c];
+            wave_sync();
             const int r = lane / LPV;
             const int view = vb + r * kWaves;
             float *rv = rec + r * recView;
@@ -1007,10 +1078,12 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
                 npv[GW] = wu0; npv[GW + 1] = wu1; npv[GW + 2] = wv0; npv[GW + 3] = wv1;
             }
         }
+        if constexpr (!TAB) {
 #pragma unroll
-        for (int ps = 0; ps < KP; ++ps)
+            for (int ps = 0; ps < KP; ++ps)
 #pragma unroll
-            for (int c = 0; c < GW; ++c) acc[ps][c] = win[(ps * GW + c) * kWave + lane];
+                for (int c = 0; c < GW; ++c) acc[ps][c] = win[(ps * GW + c) * kWave + lane];
+        }
         wave_sync();
 
 #pragma unroll 1
@@ -1130,7 +1203,7 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
                         float mm = 0.5f * (fmaxf(0.0f, -s1p) + fminf(beta, -s1n));
                         mm = fminf(fmaxf(mm, 0.0f), beta);
                         const float zb = fmaf(-mm, r2.y, zt);
-                        w *= __builtin_amdgcn_rcpf(fmaf(zb, zb, r2.x));
+                        w *= __builtin_amdgcn_rcpf(fmaf(zb, zb, r2.w));
                     }
                     ap = fmaf(w, val, ap);
                     psip = mn + phin;
@@ -1155,7 +1228,7 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
                             float mm = 0.5f * (fmaxf(0.0f, -s1p) + fminf(beta, -s1n));
                             mm = fminf(fmaxf(mm, 0.0f), beta);
                             const float zb = fmaf(-mm, r2.y, zt);
-                            w *= __builtin_amdgcn_rcpf(fmaf(zb, zb, r2.x));
+                            w *= __builtin_amdgcn_rcpf(fmaf(zb, zb, r2.w));
                         }
                         ap = fmaf(w, *last, ap);
                     }
@@ -1199,7 +1272,7 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
     }
 }
 
-template <bool EXACT, bool EC, int PMAX, int GW, bool TT = false>
+template <bool EXACT, bool EC, int PMAX, int GW, bool TT = false, bool TAB = false>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
 backproject_kernel(const DevGeom G, const int ngroups, const int nkchunks, const int kp, const int items,
                    const int chunk, const int winCap, const float *__restrict__ proj,
@@ -1209,7 +1282,7 @@ backproject_kernel(const DevGeom G, const int ngroups, const int nkchunks, const
     if (stop && *stop != 0.0) return;
     const int item = (blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
     if (item >= items) return;
-    backproject_item<EXACT, EC, PMAX, GW, TT>(G, ngroups, nkchunks, kp, winCap, item, smem, proj, vol);
+    backproject_item<EXACT, EC, PMAX, GW, TT, TAB>(G, ngroups, nkchunks, kp, winCap, item, smem, proj, vol);
 }
 
 // ------------------------------------------------------------ batched, persistent
@@ -1296,6 +1369,16 @@ hipError_t launch_p(const DevGeom &g, const ProjLaunch &L, const float *vol, flo
         if (e != hipSuccess) return e;
     }
     const dim3 grid(8 * L.chunk), block(kBlock);
+    if (!TT && g.rtab && g.rtab_pmax == (L.pmax <= 4 ? 4 : 8)) {
+        // the geometry's cached records
+        if (L.pmax <= 4)
+            hipLaunchKernelGGL((project_kernel<EXACT, EC, 4, false, true>), grid, block, L.lds, s, g, L.U, L.nbands,
+                               vol, proj, gmax, stop);
+        else
+            hipLaunchKernelGGL((project_kernel<EXACT, EC, 8, false, true>), grid, block, L.lds, s, g, L.U, L.nbands,
+                               vol, proj, gmax, stop);
+        return hipGetLastError();
+    }
     if (L.pmax <= 4)
         hipLaunchKernelGGL((project_kernel<EXACT, EC, 4, TT>), grid, block, L.lds, s, g, L.U, L.nbands, vol, proj,
                            gmax, stop);
@@ -1305,22 +1388,22 @@ hipError_t launch_p(const DevGeom &g, const ProjLaunch &L, const float *vol, flo
     return hipGetLastError();
 }
 
-template <bool EXACT, bool EC, int PMAX, bool TT = false>
+template <bool EXACT, bool EC, int PMAX, bool TT = false, bool TAB = false>
 hipError_t launch_bp_gw(const DevGeom &g, const BackLaunch &L, const float *proj, float *vol,
                         hipStream_t s, const double *stop)
 {
     const dim3 grid(8 * L.chunk), block(kBlock);
     switch (L.gw) {
     case 16:
-        hipLaunchKernelGGL((backproject_kernel<EXACT, EC, PMAX, 16, TT>), grid, block, L.lds, s, g,
+        hipLaunchKernelGGL((backproject_kernel<EXACT, EC, PMAX, 16, TT, TAB>), grid, block, L.lds, s, g,
                            L.ngroups, L.nkchunks, L.kp, L.items, L.chunk, L.win_cap, proj, vol, stop);
         break;
     case 8:
-        hipLaunchKernelGGL((backproject_kernel<EXACT, EC, PMAX, 8, TT>), grid, block, L.lds, s, g,
+        hipLaunchKernelGGL((backproject_kernel<EXACT, EC, PMAX, 8, TT, TAB>), grid, block, L.lds, s, g,
                            L.ngroups, L.nkchunks, L.kp, L.items, L.chunk, L.win_cap, proj, vol, stop);
         break;
     default:
-        hipLaunchKernelGGL((backproject_kernel<EXACT, EC, PMAX, 4, TT>), grid, block, L.lds, s, g,
+        hipLaunchKernelGGL((backproject_kernel<EXACT, EC, PMAX, 4, TT, TAB>), grid, block, L.lds, s, g,
                            L.ngroups, L.nkchunks, L.kp, L.items, L.chunk, L.win_cap, proj, vol, stop);
         break;
     }
@@ -1331,6 +1414,11 @@ template <bool EXACT, bool EC, bool TT = false>
 hipError_t launch_bp(const DevGeom &g, const BackLaunch &L, const float *proj, float *vol,
                      hipStream_t s, const double *stop)
 {
+    if (!TT && g.rtab && L.pmax <= 8 && g.rtab_pmax == (L.pmax <= 4 ? 4 : 8)) {
+        // the geometry's cached records
+        if (L.pmax <= 4) return launch_bp_gw<EXACT, EC, 4, false, true>(g, L, proj, vol, s, stop);
+        return launch_bp_gw<EXACT, EC, 8, false, true>(g, L, proj, vol, s, stop);
+    }
     if (L.pmax <= 4) return launch_bp_gw<EXACT, EC, 4, TT>(g, L, proj, vol, s, stop);
     if (L.pmax <= 8) return launch_bp_gw<EXACT, EC, 8, TT>(g, L, proj, vol, s, stop);
     // wide footprints: 4-column stacks only
@@ -1340,19 +1428,19 @@ hipError_t launch_bp(const DevGeom &g, const BackLaunch &L, const float *proj, f
     return hipGetLastError();
 }
 
-template <bool EXACT, bool EC, int PMAX, bool TT = false>
+template <bool EXACT, bool EC, int PMAX, bool TT = false, bool TAB = false>
 hipError_t set_lds_one(size_t n)
 {
-    hipError_t e = hipFuncSetAttribute((const void *)project_kernel<EXACT, EC, PMAX, TT>,
+    hipError_t e = hipFuncSetAttribute((const void *)project_kernel<EXACT, EC, PMAX, TT, TAB>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
     if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)backproject_kernel<EXACT, EC, PMAX, 16, TT>,
+        e = hipFuncSetAttribute((const void *)backproject_kernel<EXACT, EC, PMAX, 16, TT, TAB>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
     if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)backproject_kernel<EXACT, EC, PMAX, 8, TT>,
+        e = hipFuncSetAttribute((const void *)backproject_kernel<EXACT, EC, PMAX, 8, TT, TAB>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
     if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)backproject_kernel<EXACT, EC, PMAX, 4, TT>,
+        e = hipFuncSetAttribute((const void *)backproject_kernel<EXACT, EC, PMAX, 4, TT, TAB>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
     return e;
 }
@@ -1465,6 +1553,14 @@ hipError_t configure_kernel_lds(size_t max_lds, size_t max_lds_batched)
     if (e == hipSuccess) e = set_lds_one<false, true, 4, true>(max_lds);
     if (e == hipSuccess) e = set_lds_one<false, true, 8, true>(max_lds);
     if (e == hipSuccess) e = set_lds_wide<false, true, true>(max_lds);
+    if (e == hipSuccess) e = set_lds_one<true, true, 4, false, true>(max_lds);
+    if (e == hipSuccess) e = set_lds_one<true, false, 4, false, true>(max_lds);
+    if (e == hipSuccess) e = set_lds_one<false, true, 4, false, true>(max_lds);
+    if (e == hipSuccess) e = set_lds_one<false, false, 4, false, true>(max_lds);
+    if (e == hipSuccess) e = set_lds_one<true, true, 8, false, true>(max_lds);
+    if (e == hipSuccess) e = set_lds_one<true, false, 8, false, true>(max_lds);
+    if (e == hipSuccess) e = set_lds_one<false, true, 8, false, true>(max_lds);
+    if (e == hipSuccess) e = set_lds_one<false, false, 8, false, true>(max_lds);
     if (e == hipSuccess) e = set_lds_batched<true, true>(max_lds_batched);
     if (e == hipSuccess) e = set_lds_batched<true, false>(max_lds_batched);
     if (e == hipSuccess) e = set_lds_batched<false, true>(max_lds_batched);
@@ -1495,6 +1591,19 @@ hipError_t launch_group_max(const DevGeom &g, const float *vol, unsigned *gmax, 
     const int64_t cells = group_max_cells(g);
     hipLaunchKernelGGL(group_max_kernel, dim3((unsigned)((cells + kWaves - 1) / kWaves)), dim3(kBlock), 0, stream,
                        g, vol, gmax, stop);
+    return hipGetLastError();
+}
+
+hipError_t launch_record_table(const DevGeom &g, int pmax, float *rec, int *cnt, hipStream_t stream)
+{
+    const int64_t n = (int64_t)g.n1 * g.n2 * g.nviews;
+    const dim3 grid((unsigned)((n + kBlock - 1) / kBlock)), block(kBlock);
+    if (pmax == 4)
+        hipLaunchKernelGGL(record_table_kernel<4>, grid, block, 0, stream, g, rec, cnt);
+    else if (pmax == 8)
+        hipLaunchKernelGGL(record_table_kernel<8>, grid, block, 0, stream, g, rec, cnt);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

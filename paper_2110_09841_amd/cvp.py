@@ -97,6 +97,16 @@ class Geometry:
         lp = _lib.LaunchC(int(proj_band_cols), int(bp_stack_cols), int(bp_passes))
         _lib.check(_lib.lib().cvp_geometry_set_launch(self.handle, ctypes.byref(lp)))
 
+    def cache_records(self, enable=True):
+        """Compute the cut-piece records of every (view, voxel column) once
+        and keep them on the device (cvp_geometry_cache_records): the
+        cutting voxel operators then read them instead of recomputing them
+        in every launch, with bitwise the same results.  enable=False frees
+        them.  Returns the table's size in bytes (0 when freed)."""
+        nb = ctypes.c_int64()
+        _lib.check(_lib.lib().cvp_geometry_cache_records(self.handle, int(bool(enable)), ctypes.byref(nb), _stream()))
+        return int(nb.value)
+
 
 def _check_tensor(t, shape, name):
     if not isinstance(t, torch.Tensor):

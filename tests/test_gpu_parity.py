@@ -153,6 +153,7 @@ def test_cone_workload_sampled(variant):
     g = synth.config_cone()
     x, b = cone_inputs()
     G = cvp.Geometry(g)
+    G.cache_records()          # the cut-piece records bench.py caches
     rng = np.random.default_rng(1)
     idx = np.concatenate([corner_indices(256, 256, 256), rng.integers(0, 256 ** 3, size=2000)])
     o = oopts(variant, True, "solid_angle")
@@ -179,12 +180,14 @@ def carm_inputs():
 @pytest.mark.parametrize("variant", ["relaxed", "exact"])
 def test_carm_benchmark_workload_sampled(variant):
     """The benchmark workload (512^3 / 616x480 / 248 views over 200 degrees,
-    elevation correction, the launch plan bench.py times): the oracle checks
+    elevation correction, cached cut-piece records as bench.py times it):
+    the oracle checks
     eight full views of A x spread over the arc and 2000 voxels of A^T b plus
     the volume's corners, for the relaxed and the exact form."""
     g = synth.config_carm()
     x, b = carm_inputs()
     G = cvp.Geometry(g)
+    G.cache_records()          # the cut-piece records bench.py caches
     o = oopts(variant, True, "solid_angle")
     say("carm projection", variant)
     Ax = cvp.project(torch.from_numpy(x).cuda(), G, gopts(variant, True, "solid_angle")).cpu().numpy()
