@@ -108,21 +108,25 @@ def test_identity_warm_start_restarts_from_second_iterate():
 
 
 def test_trained_warm_start_beats_zero_start_in_batched_cgls():
-    """What the trained network gains: trained on 96 phantoms (the 20th CGLS
-    iterate as target), it must bring 8 held-out phantoms, run as one batch
-    through batched CGLS, to rho <= 1e-3 in fewer iterations in total than
-    batched CGLS from zero (the warm count includes its two starting
-    iterations), every problem reaching the tolerance."""
-    p = small_params()
-    pipe = Pipeline(params=p, n_ellipsoids=6, per_graph=3)
+    """What the trained network gains: trained on 400 phantoms (64^3 voxels
+    of 1 mm, 128 x 128 pixels of 1 mm, 90 views; the 20th CGLS iterate as
+    target, four epochs), it must bring 8 held-out phantoms, run as one batch
+    through batched CGLS, to rho <= 1e-3 in at least 5 % fewer iterations in
+    total than batched CGLS from zero (the warm count includes its two
+    starting iterations), every problem reaching the tolerance and none
+    taking more iterations than from zero."""
+    p = synth.geometry(64, 1.0, 128, 128, 1.0, 750.0, 1200.0, 90, 360.0)
+    pipe = Pipeline(params=p, n_ellipsoids=10, per_graph=5)
     say("warmstart gain: data")
-    data = pipe.dataset(range(96))
+    data = pipe.dataset(range(400))
     net = UNet(pipe.shape, seed=1)
     say("warmstart gain: train")
-    pipe.train(net, data, epochs=4, lr=2e-3)
+    pipe.train(net, data, epochs=4, lr=1e-3)
+    del data
     say("warmstart gain: batched evaluation")
     r = evaluate_batched(pipe, net, [100000 + n for n in range(8)], tol=1e-3, max_iter=300)
     say("zero %s (%.3f s), warm %s (%.3f s), warm rho0 %s" % (r["zero_iters"], r["zero_s"], r["warm_iters"],
                                                             r["warm_s"], ["%.3f" % v for v in r["rho0_warm"]]))
     assert all(r["reached_zero"]) and all(r["reached_warm"])
-    assert sum(r["warm_iters"]) < sum(r["zero_iters"])
+    assert all(w <= z for w, z in zip(r["warm_iters"], r["zero_iters"]))
+    assert sum(r["warm_iters"]) <= 0.95 * sum(r["zero_iters"])
