@@ -502,7 +502,10 @@ cvp_status cvp_geometry_sizes(const cvp_geometry *g, int64_t *n_voxels,
  * _ws / _views / _noalloc variants and the solvers of the cutting voxel
  * projector (both forms, EC on or off) read the records instead of computing
  * them in each launch; results are bitwise the same.  The TT projector and
- * the batched launches keep computing their own.  enable = 0 frees the table.
+ * the batched launches keep computing their own.  Without its FP64 stage the
+ * backprojection needs less LDS per workgroup, so its plan is re-derived for a
+ * smaller LDS budget (the same stack shape when it fits; likewise back when
+ * the table is freed).  enable = 0 frees the table.
  * *bytes (may be NULL) receives the table's size.  The fill is enqueued on
  * `stream`; it allocates (hipMalloc) on the first enable only.  Call it while
  * no other call uses the geometry.  Errors: CVP_E_INVALID (NULL geometry,

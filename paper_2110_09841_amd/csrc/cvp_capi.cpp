@@ -20,11 +20,12 @@ hipError_t configure_kernel_lds(size_t max_lds, size_t max_lds_batched);
 constexpr size_t kLdsBudget = 30 * 1024;   // default projection plans: five workgroups per CU (160 KB LDS; 5 x 32 KB did not fit)
 constexpr size_t kBackLdsBudget = 52 * 1024;   // backprojection windows: three workgroups per CU
 constexpr size_t kBackLdsBudgetWide = 80 * 1024;   // records of up to kPmaxWide pieces per column: two per CU
+constexpr size_t kBackLdsBudgetCached = 40 * 1024;   // cached records (no FP64 stage, ~105 VGPRs): four per CU
 constexpr size_t kLdsMax = 156 * 1024;      // any plan: one workgroup per CU at worst
 constexpr size_t kLdsBatchMax = kLdsMax;
 bool plan_projection(int N, int n2, int M, int nviews, int pmax, int force_u, ProjLaunch &L);
 bool plan_backprojection(const DevGeom &G, int pmax, double zabs, double Dmin, int force_gw,
-                         int force_kp, BackLaunch &L);
+                         int force_kp, BackLaunch &L, bool cached = false);
 }
 using cvp::kLdsBudget;
 
@@ -40,6 +41,7 @@ struct cvp_geometry {
     double zabs = 0.0, Dmin = 0.0;   // for launch planning
     int pmax = 4;                    // pieces per column the kernels keep (4, 8 or kPmaxWide)
     double wone_tt = 0.0, wsum_tt = 0.0;   // fixed-point bounds of the TT projector's weights
+    cvp::BackLaunch blc{};           // backprojection plan of the cached-record kernels
     float *d_rtab = nullptr;         // cached piece records (cvp_geometry_cache_records)
     int *d_rtab_n = nullptr;
     int64_t rtab_bytes = 0;
@@ -137,7 +139,7 @@ bool plan_projection(int N, int n2, int M, int nviews, int pmax, int force_u, Pr
 // estimated detector window fits the per-wave LDS window (force_gw > 0 and
 // force_kp > 0 fix them).
 bool plan_backprojection(const DevGeom &G, int pmax, double zabs, double Dmin, int force_gw,
-                         int force_kp, BackLaunch &L)
+                         int force_kp, BackLaunch &L, bool cached)
 {
     const double mag = G.f / Dmin;
     // (stack width, passes) by stack area; the first whose estimated window
@@ -145,7 +147,9 @@ bool plan_backprojection(const DevGeom &G, int pmax, double zabs, double Dmin, i
     // are then read from global memory)
     // (wide footprints: records of kPmaxWide pieces, 4-column stacks only)
     static const int cands[6][2] = {{16, 2}, {16, 1}, {8, 2}, {8, 1}, {4, 2}, {4, 1}};
-    const size_t budget = pmax > 8 ? kBackLdsBudgetWide : kBackLdsBudget;
+    // with cached records the kernel needs no FP64 stage and parks nothing:
+    // a smaller budget lets four workgroups share a compute unit
+    const size_t budget = pmax > 8 ? kBackLdsBudgetWide : cached ? kBackLdsBudgetCached : kBackLdsBudget;
     int gw = 0, kp = 0, cap = 0;
     for (const auto &cd : cands) {
         const int cand = cd[0], ckp = cd[1];
@@ -154,7 +158,8 @@ bool plan_backprojection(const DevGeom &G, int pmax, double zabs, double Dmin, i
         const size_t rec = (size_t)back_views_per_pass(cand, pmax) * back_rec_floats(cand, pmax);
         if (rec * kWaves * 4 >= budget) continue;
         const int c = (int)((budget / (kWaves * 4) - rec) / 4 * 4);
-        if (c < kBackPasses * cand * 64 || c < 1024) continue;   // the window area also parks the accumulators
+        if (!cached && c < kBackPasses * cand * 64) continue;   // the window area also parks the accumulators
+        if (c < 1024) continue;
         const double wu = std::hypot(cand * G.a1, G.a2) * mag / G.b1 + pmax + 2;
         const double zspan = std::hypot(cand * G.a1, G.a2);
         const double wv = 64 * ckp * G.a3 * mag / G.b2 + zabs * (G.f / G.b2) * zspan / (Dmin * Dmin) + 6;
@@ -546,8 +551,9 @@ cvp_status cvp_geometry_get_launch(const cvp_geometry *g, cvp_launch *out)
     if (!g) return fail(CVP_E_INVALID, "geometry is NULL");
     if (!out) return fail(CVP_E_INVALID, "out is NULL");
     out->proj_band_cols = g->pl.U;
-    out->bp_stack_cols = g->bl.gw;
-    out->bp_passes = g->bl.kp;
+    const cvp::BackLaunch &bl = g->d_rtab ? g->blc : g->bl;
+    out->bp_stack_cols = bl.gw;
+    out->bp_passes = bl.kp;
     return ok();
 }
 
@@ -570,10 +576,21 @@ cvp_status cvp_geometry_set_launch(cvp_geometry *g, const cvp_launch *in)
         return fail(CVP_E_UNSUPPORTED, "launch.proj_band_cols = %d: band image of %zu bytes exceeds the LDS limit", u,
                     cvp::project_lds_bytes(u, G.N, G.n2, g->pl.pmax));
     }
-    if (!cvp::plan_backprojection(G, g->pmax, g->zabs, g->Dmin, gw, kp, bl))
+    // the plan of the cutting voxel launches (cached records or not); the
+    // in-kernel plan also serves the TT projector, so it is kept valid too
+    cvp::BackLaunch blc = g->blc;
+    if (g->d_rtab) {
+        if (!cvp::plan_backprojection(G, g->pmax, g->zabs, g->Dmin, gw, kp, blc, true))
+            return fail(CVP_E_UNSUPPORTED, "launch.bp_stack_cols = %d, bp_passes = %d: does not fit LDS", gw, kp);
+        if (!cvp::plan_backprojection(G, g->pmax, g->zabs, g->Dmin, gw, kp, bl) &&
+            !cvp::plan_backprojection(G, g->pmax, g->zabs, g->Dmin, 0, 0, bl))
+            return fail(CVP_E_UNSUPPORTED, "backprojection plan");
+    } else if (!cvp::plan_backprojection(G, g->pmax, g->zabs, g->Dmin, gw, kp, bl)) {
         return fail(CVP_E_UNSUPPORTED, "launch.bp_stack_cols = %d, bp_passes = %d: does not fit LDS", gw, kp);
+    }
     g->pl = pl;
     g->bl = bl;
+    g->blc = blc;
     return ok();
 }
 
@@ -591,6 +608,24 @@ static int model_of(const cvp_options *o)
     return o->variant == CVP_TT ? cvp::kModelTT : o->variant == CVP_EXACT ? cvp::kModelExact : cvp::kModelRelaxed;
 }
 
+// The backprojection plan of the cached-record kernels: the in-kernel plan's
+// stack shape when it fits their smaller LDS budget, else their default.
+static void replan_backprojection(cvp_geometry *g)
+{
+    cvp::BackLaunch bl{};
+    if (cvp::plan_backprojection(g->base, g->pmax, g->zabs, g->Dmin, g->bl.gw, g->bl.kp, bl, true) ||
+        cvp::plan_backprojection(g->base, g->pmax, g->zabs, g->Dmin, 0, 0, bl, true))
+        g->blc = bl;
+    else
+        g->blc = g->bl;
+}
+
+// The backprojection plan of a prepared launch: cached records or not.
+static const cvp::BackLaunch &back_plan(const cvp_geometry *g, const cvp::DevGeom &G)
+{
+    return G.rtab ? g->blc : g->bl;
+}
+
 cvp_status cvp_geometry_cache_records(cvp_geometry *g, int32_t enable, int64_t *bytes, void *stream)
 {
     if (!g) return fail(CVP_E_INVALID, "geometry is NULL");
@@ -606,6 +641,7 @@ cvp_status cvp_geometry_cache_records(cvp_geometry *g, int32_t enable, int64_t *
         g->d_rtab = nullptr;
         g->d_rtab_n = nullptr;
         g->rtab_bytes = 0;
+        replan_backprojection(g);
         if (bytes) *bytes = 0;
         return ok();
     }
@@ -626,6 +662,7 @@ cvp_status cvp_geometry_cache_records(cvp_geometry *g, int32_t enable, int64_t *
             return device_fail(e, "record table");
         }
         g->rtab_bytes = (int64_t)(rb + nb);
+        replan_backprojection(g);
     }
     if (bytes) *bytes = g->rtab_bytes;
     return ok();
@@ -749,7 +786,7 @@ cvp_status cvp_backproject(const cvp_geometry *g, const cvp_options *o, const fl
     cvp::DevGeom G;
     cvp_status st = prepare(g, o, d_proj, d_vol, G);
     if (st != CVP_OK) return st;
-    hipError_t e = cvp::launch_backproject(G, g->bl, model_of(o), o->elevation_correction != 0,
+    hipError_t e = cvp::launch_backproject(G, back_plan(g, G), model_of(o), o->elevation_correction != 0,
                                            d_proj, d_vol, (hipStream_t)stream);
     if (e != hipSuccess) return device_fail(e, "backprojection launch");
     return ok();
@@ -814,7 +851,7 @@ cvp_status cvp_backproject_views(const cvp_geometry *g, const cvp_options *o, co
     int64_t off = 0;
     st = view_subset(g, view0, view_stride, n_views, G, off);
     if (st != CVP_OK) return st;
-    hipError_t e = cvp::launch_backproject(G, g->bl, model_of(o), o->elevation_correction != 0,
+    hipError_t e = cvp::launch_backproject(G, back_plan(g, G), model_of(o), o->elevation_correction != 0,
                                            d_proj + off, d_vol, (hipStream_t)stream);
     if (e != hipSuccess) return device_fail(e, "backprojection launch");
     return ok();
@@ -1054,7 +1091,7 @@ cvp_status cvp_cgls_start(const cvp_geometry *g, const cvp_options *o, const flo
     // per-group maxima
     hipError_t e = cvp::launch_project(G, g->pl, ex, ec, d_x, d_q, (unsigned *)d_s, sm);
     if (e == hipSuccess) e = cvp::blas_residual(d_r, d_b, d_q, g->npix, sm);
-    if (e == hipSuccess) e = cvp::launch_backproject(G, g->bl, ex, ec, d_r, d_s, sm);
+    if (e == hipSuccess) e = cvp::launch_backproject(G, back_plan(g, G), ex, ec, d_r, d_s, sm);
     if (e == hipSuccess) e = cvp::blas_update_p(d_p, d_s, g->nvox, sc, 1, sm);
     if (e == hipSuccess) e = cvp::blas_dot(d_s, d_s, g->nvox, part, sc, 0, nullptr, sm);
     if (e != hipSuccess) return device_fail(e, "cgls start");
@@ -1080,7 +1117,7 @@ cvp_status cvp_cgls_iterate(const cvp_geometry *g, const cvp_options *o, int32_t
         e = cvp::launch_project(G, g->pl, ex, ec, d_p, d_q, (unsigned *)d_s, sm, stop);       // q = A p (s free)
         if (e == hipSuccess) e = cvp::blas_dot(d_q, d_q, g->npix, part, sc, 1, nullptr, sm, stop);   // alpha
         if (e == hipSuccess) e = cvp::blas_update_xr(d_x, d_p, g->nvox, d_r, d_q, g->npix, sc, part, sm, stop);
-        if (e == hipSuccess) e = cvp::launch_backproject(G, g->bl, ex, ec, d_r, d_s, sm, stop);   // s = A^T r
+        if (e == hipSuccess) e = cvp::launch_backproject(G, back_plan(g, G), ex, ec, d_r, d_s, sm, stop);   // s = A^T r
         if (e == hipSuccess) e = cvp::blas_dot(d_s, d_s, g->nvox, part, sc, 2, nullptr, sm, stop);   // beta
         if (e == hipSuccess) e = cvp::blas_update_p(d_p, d_s, g->nvox, sc, 0, sm, stop);           // p
     }
@@ -1214,7 +1251,7 @@ cvp_status cvp_sart_setup(const cvp_geometry *g, const cvp_options *o, int32_t n
         cvp::DevGeom Gt = G;
         int64_t off = 0;
         view_subset(g, t, n_subsets, subset_count(V, n_subsets, t), Gt, off);
-        e = cvp::launch_backproject(Gt, g->bl, ex, ec, d_q + off, d_colsum + (size_t)t * g->nvox, sm);
+        e = cvp::launch_backproject(Gt, back_plan(g, Gt), ex, ec, d_q + off, d_colsum + (size_t)t * g->nvox, sm);
     }
     if (e != hipSuccess) return device_fail(e, "sart setup");
     return ok();
@@ -1251,7 +1288,7 @@ cvp_status cvp_sart_iterate(const cvp_geometry *g, const cvp_options *o, int32_t
             e = cvp::launch_project(Gt, pl, ex, ec, d_x, d_q + off, (unsigned *)d_z, sm);
             if (e == hipSuccess)
                 e = cvp::sart_residual_views(d_q + off, d_b + off, d_rowsum + off, nm, cnt, nm * n_subsets, sm);
-            if (e == hipSuccess) e = cvp::launch_backproject(Gt, g->bl, ex, ec, d_q + off, d_z, sm);
+            if (e == hipSuccess) e = cvp::launch_backproject(Gt, back_plan(g, Gt), ex, ec, d_q + off, d_z, sm);
             if (e == hipSuccess)
                 e = cvp::sart_update_x(d_x, d_z, d_colsum + (size_t)t * g->nvox, g->nvox, lambda, nonneg != 0, sm);
         }
@@ -1301,7 +1338,7 @@ cvp_status cvp_lsqr_start(const cvp_geometry *g, const cvp_options *o, const flo
     if (e == hipSuccess) e = cvp::blas_residual(d_u, d_b, d_q, g->npix, sm);
     if (e == hipSuccess) e = cvp::lsqr_norm(d_u, g->npix, sc, cvp::kLsqrFinBeta0, sm);
     if (e == hipSuccess) e = cvp::lsqr_scale(d_u, g->npix, sc, cvp::kLsqrBeta, sm);
-    if (e == hipSuccess) e = cvp::launch_backproject(G, g->bl, ex, ec, d_u, d_v, sm);
+    if (e == hipSuccess) e = cvp::launch_backproject(G, back_plan(g, G), ex, ec, d_u, d_v, sm);
     if (e == hipSuccess) e = cvp::lsqr_norm(d_v, g->nvox, sc, cvp::kLsqrFinAlpha0, sm);
     if (e == hipSuccess) e = cvp::lsqr_update_vxw(d_v, d_x, d_w, g->nvox, sc, 1, sm);
     if (e != hipSuccess) return device_fail(e, "lsqr start");
@@ -1324,7 +1361,7 @@ cvp_status cvp_lsqr_iterate(const cvp_geometry *g, const cvp_options *o, int32_t
         e = cvp::launch_project(G, g->pl, ex, ec, d_v, d_q, (unsigned *)d_s, sm);                 // q = A v
         if (e == hipSuccess) e = cvp::lsqr_axpby_norm(d_u, d_q, g->npix, sc, cvp::kLsqrAlpha, cvp::kLsqrFinBeta, sm);
         if (e == hipSuccess) e = cvp::lsqr_scale(d_u, g->npix, sc, cvp::kLsqrBeta, sm);           // u /= beta
-        if (e == hipSuccess) e = cvp::launch_backproject(G, g->bl, ex, ec, d_u, d_s, sm);          // s = A^T u
+        if (e == hipSuccess) e = cvp::launch_backproject(G, back_plan(g, G), ex, ec, d_u, d_s, sm);          // s = A^T u
         if (e == hipSuccess) e = cvp::lsqr_axpby_norm(d_v, d_s, g->nvox, sc, cvp::kLsqrBeta, cvp::kLsqrFinAlpha, sm);
         if (e == hipSuccess) e = cvp::lsqr_update_vxw(d_v, d_x, d_w, g->nvox, sc, 0, sm);       // v, x, w
     }

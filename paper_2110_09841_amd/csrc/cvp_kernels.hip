@@ -1369,8 +1369,9 @@ hipError_t launch_p(const DevGeom &g, const ProjLaunch &L, const float *vol, flo
         if (e != hipSuccess) return e;
     }
     const dim3 grid(8 * L.chunk), block(kBlock);
-    if (!TT && g.rtab && g.rtab_pmax == (L.pmax <= 4 ? 4 : 8)) {
+    if (!TT && g.rtab) {
         // the geometry's cached records
+        if (g.rtab_pmax != (L.pmax <= 4 ? 4 : 8)) return hipErrorInvalidValue;
         if (L.pmax <= 4)
             hipLaunchKernelGGL((project_kernel<EXACT, EC, 4, false, true>), grid, block, L.lds, s, g, L.U, L.nbands,
                                vol, proj, gmax, stop);
@@ -1414,8 +1415,9 @@ template <bool EXACT, bool EC, bool TT = false>
 hipError_t launch_bp(const DevGeom &g, const BackLaunch &L, const float *proj, float *vol,
                      hipStream_t s, const double *stop)
 {
-    if (!TT && g.rtab && L.pmax <= 8 && g.rtab_pmax == (L.pmax <= 4 ? 4 : 8)) {
-        // the geometry's cached records
+    if (!TT && g.rtab) {
+        // the geometry's cached records (the plan L was made for these kernels)
+        if (L.pmax > 8 || g.rtab_pmax != (L.pmax <= 4 ? 4 : 8)) return hipErrorInvalidValue;
         if (L.pmax <= 4) return launch_bp_gw<EXACT, EC, 4, false, true>(g, L, proj, vol, s, stop);
         return launch_bp_gw<EXACT, EC, 8, false, true>(g, L, proj, vol, s, stop);
     }
