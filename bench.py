@@ -261,12 +261,13 @@ def cone_timing(reps=2):
 
 def batched_timing(reps=2):
     """The 16-problem batch (volumes 96^3..320^3, 60..400 views): one
-    persistent launch per direction against 16 single-problem launches."""
+    persistent launch per direction against 16 single-problem launches, both
+    with every member's cut-piece records cached (and, for comparison, both
+    without)."""
     import torch
     from paper_2110_09841_amd import cvp, synth
     params = synth.config_batch()
     geoms = [cvp.Geometry(p) for p in params]
-    batch = cvp.Batch(geoms)
     opts = cvp.Options(variant="relaxed", ec=True)
     gen = torch.Generator(device="cuda").manual_seed(5)
     xs = [torch.rand(g.vol_shape, generator=gen, device="cuda") for g in geoms]
@@ -283,22 +284,34 @@ def batched_timing(reps=2):
             cvp.project(xs[q], g, opts, out=po[q])
             cvp.backproject(bs[q], g, opts, out=vo[q])
 
-    times = {}
-    for name, fn in (("batched", batched), ("single", single)):
-        fn()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
+    def timed():
+        times = {}
+        for name, fn in (("batched", batched), ("single", single)):
             fn()
-        e1.record()
-        torch.cuda.synchronize()
-        times[name] = e0.elapsed_time(e1) / reps
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            times[name] = e0.elapsed_time(e1) / reps
+        return times
+
+    batch = cvp.Batch(geoms)
+    plain = timed()
+    del batch
+    table_bytes = sum(g.cache_records() for g in geoms)
+    batch = cvp.Batch(geoms)
+    times = timed()
     vv = 2 * sum(g.n_voxels * g.n_views for g in geoms)
     res = {"workload": "batch16_96c_320c", "problems": len(geoms), "voxel_views": vv,
+           "record_cache_bytes": table_bytes,
            "batched_ms": times["batched"], "single_launches_ms": times["single"],
            "batched_over_single": times["batched"] / times["single"],
-           "batched_voxel_views_per_s": vv / (times["batched"] * 1e-3)}
+           "batched_voxel_views_per_s": vv / (times["batched"] * 1e-3),
+           "without_record_cache": {"batched_ms": plain["batched"], "single_launches_ms": plain["single"],
+                                    "batched_over_single": plain["batched"] / plain["single"]}}
     # CGLS on all 16 problems at once (b = the batched projections above):
     # one replay of a graph of 5 batched iterations
     cvp.project_batched(xs, batch, opts, outs=po)

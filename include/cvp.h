@@ -251,7 +251,10 @@ cvp_status cvp_backproject_views(const cvp_geometry *g, const cvp_options *opts,
  * backprojection).  The per-call pointer setup and the counter reset are one
  * tiny kernel on the same stream, so a batched call can be graph-captured.
  * n: 1..32 geometries on the same device; the batch keeps pointers to them
- * (they must outlive it) and owns small device tables.
+ * (they must outlive it) and owns small device tables.  When every member
+ * has cached records (cvp_geometry_cache_records) at cvp_batch_create, the
+ * batched kernels read them; a call after a member's table was freed or
+ * rebuilt returns CVP_E_INVALID.
  */
 typedef struct cvp_batch cvp_batch;   /* opaque */
 cvp_status cvp_batch_create(const cvp_geometry *const *geoms, int32_t n, cvp_batch **out);

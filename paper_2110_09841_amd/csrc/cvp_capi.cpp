@@ -870,6 +870,8 @@ struct cvp_batch {
     std::vector<unsigned *> d_gmax;   // per problem: per-group maxima of the volume
     size_t plds = 0, blds[3] = {0, 0, 0};
     int pgrid = 0, bgrid[3] = {0, 0, 0};
+    bool cached = false;                  // every member reads its geometry's cached records
+    std::vector<const float *> rtabs;     // the tables captured at creation
 };
 
 extern "C" {
@@ -906,6 +908,9 @@ cvp_status cvp_batch_create(const cvp_geometry *const *geoms, int32_t n, cvp_bat
     b->n = n;
     b->device = geoms[0]->device;
     b->geoms.assign(geoms, geoms + n);
+    // with every member's records cached the batched kernels read them too
+    b->cached = true;
+    for (int q = 0; q < n; ++q) b->cached = b->cached && geoms[q]->d_rtab != nullptr;
     // Projection: every problem keeps its own plan (the batched kernel
     // dispatches on the piece stride per item), so its results are those of
     // its own launches.  Backprojection: every problem keeps its own stack
@@ -922,7 +927,8 @@ cvp_status cvp_batch_create(const cvp_geometry *const *geoms, int32_t n, cvp_bat
         bool planned = false;
         for (int gi = 0; gi < 3 && !planned; ++gi) {
             if (kGw[gi] > geoms[q]->bl.gw) continue;
-            planned = cvp::plan_backprojection(geoms[q]->base, 8, geoms[q]->zabs, geoms[q]->Dmin, kGw[gi], 0, bls[q]);
+            planned = cvp::plan_backprojection(geoms[q]->base, 8, geoms[q]->zabs, geoms[q]->Dmin, kGw[gi], 0, bls[q],
+                                               b->cached);
             grp[q] = gi;
         }
         if (!planned) {
@@ -951,6 +957,12 @@ cvp_status cvp_batch_create(const cvp_geometry *const *geoms, int32_t n, cvp_bat
         P.out = nullptr;
         P.gmax = nullptr;   // set below
         P.stop = nullptr;   // set per call
+        if (b->cached) {
+            P.G.rtab = g->d_rtab;
+            P.G.rtab_n = g->d_rtab_n;
+            P.G.rtab_pmax = g->pmax;
+            b->rtabs.push_back(g->d_rtab);
+        }
         b->plds = std::max(b->plds, pl.lds);
         b->blds[grp[q]] = std::max(b->blds[grp[q]], bl.lds);
         pcost[q] = (double)g->nvox / pl.nbands;           // voxels per band (all k)
@@ -982,7 +994,7 @@ cvp_status cvp_batch_create(const cvp_geometry *const *geoms, int32_t n, cvp_bat
         const cvp::BatchTable bt = table(bcost, true, gi);
         e = hipMalloc((void **)&b->d_btab[gi], sizeof(cvp::BatchTable));
         if (e == hipSuccess) e = hipMemcpy(b->d_btab[gi], &bt, sizeof(bt), hipMemcpyHostToDevice);
-        b->bgrid[gi] = cus * cvp::batched_blocks_per_cu(true, b->blds[gi], kGw[gi]);
+        b->bgrid[gi] = cus * cvp::batched_blocks_per_cu(true, b->blds[gi], kGw[gi], b->cached);
     }
     b->d_gmax.assign(n, nullptr);
     for (int q = 0; q < n && e == hipSuccess; ++q) {
@@ -992,7 +1004,7 @@ cvp_status cvp_batch_create(const cvp_geometry *const *geoms, int32_t n, cvp_bat
     if (e == hipSuccess) e = hipMemcpy(b->d_probs, probs.data(), n * sizeof(cvp::BatchProblem), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b->d_ptab, &pt, sizeof(pt), hipMemcpyHostToDevice);
     if (e != hipSuccess) { cvp_batch_destroy(b); return device_fail(e, "batch tables"); }
-    b->pgrid = cus * cvp::batched_blocks_per_cu(false, b->plds, 16);
+    b->pgrid = cus * cvp::batched_blocks_per_cu(false, b->plds, 16, b->cached);
     *out = b;
     return ok();
 }
@@ -1004,6 +1016,11 @@ static cvp_status batched(const cvp_batch *b, const cvp_options *o, const float 
     if (!o) return fail(CVP_E_INVALID, "options is NULL");
     if (!ins || !outs) return fail(CVP_E_INVALID, "pointer array is NULL");
     if (o->variant == CVP_TT) return fail(CVP_E_UNSUPPORTED, "the batched launches run the cutting voxel projector only");
+    if (b->cached)
+        for (int q = 0; q < b->n; ++q)
+            if (b->geoms[q]->d_rtab != b->rtabs[q])
+                return fail(CVP_E_INVALID, "problem %d: its record table changed since cvp_batch_create "
+                                           "(keep the tables while the batch lives)", q);
     cvp::BatchIO io{};
     io.n = b->n;
     io.raw = (o->flags & CVP_FLAG_RAW_VOLUME) ? 1 : 0;
@@ -1028,13 +1045,13 @@ static cvp_status batched(const cvp_batch *b, const cvp_options *o, const float 
     hipError_t e = hipSuccess;
     if (!backward) {
         e = cvp::launch_batched(false, b->d_probs, b->d_ptab, b->d_counter, io, ex, ec, b->pgrid, b->plds, 16,
-                                (hipStream_t)stream);
+                                b->cached, (hipStream_t)stream);
     } else {
         static const int kGw[3] = {16, 8, 4};
         for (int gi = 0; gi < 3 && e == hipSuccess; ++gi)
             if (b->d_btab[gi])
                 e = cvp::launch_batched(true, b->d_probs, b->d_btab[gi], b->d_counter + 1 + gi, io, ex, ec,
-                                        b->bgrid[gi], b->blds[gi], kGw[gi], (hipStream_t)stream);
+                                        b->bgrid[gi], b->blds[gi], kGw[gi], b->cached, (hipStream_t)stream);
     }
     if (e != hipSuccess) return device_fail(e, "batched launch");
     return ok();

@@ -1016,9 +1016,20 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
                 int *npv = reinterpret_cast<int *>(rv + GW * PMAX * kRecFloats);
                 const size_t col0 = ((size_t)view * G.vstride * G.n2 + j) * G.n1 + i0;
                 const int ncv = min(GW, G.n1 - i0);
-                const float4 *src = reinterpret_cast<const float4 *>(G.rtab + col0 * PMAX * kRecFloats);
-                for (int q4 = lane; q4 < ncv * PMAX * kRecFloats / 4; q4 += kWave)
-                    reinterpret_cast<float4 *>(rv)[q4] = src[q4];
+                const int tp = G.rtab_pmax;
+                const float4 *src = reinterpret_cast<const float4 *>(G.rtab + col0 * tp * kRecFloats);
+                if (tp == PMAX) {
+                    // one contiguous block
+                    for (int q4 = lane; q4 < ncv * PMAX * kRecFloats / 4; q4 += kWave)
+                        reinterpret_cast<float4 *>(rv)[q4] = src[q4];
+                } else {
+                    // a table of tp <= PMAX slots per column (batched launches keep PMAX = 8)
+                    constexpr int F4 = kRecFloats / 4;
+                    for (int q4 = lane; q4 < ncv * tp * F4; q4 += kWave) {
+                        const int cs = q4 / F4, c = cs / tp, sl = cs - c * tp;
+                        reinterpret_cast<float4 *>(rv)[(c * PMAX + sl) * F4 + (q4 - cs * F4)] = src[q4];
+                    }
+                }
                 if (lane < GW) npv[lane] = lane < ncv ? G.rtab_n[col0 + lane] : 0;
             }
         } else {
@@ -1304,7 +1315,7 @@ __device__ __forceinline__ bool next_item(const BatchTable &T, int *counter, int
     return true;
 }
 
-template <bool EXACT, bool EC>
+template <bool EXACT, bool EC, bool TAB = false>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5)))
 project_batched_kernel(const BatchProblem *__restrict__ probs, const BatchTable *__restrict__ T,
                        int *counter)
@@ -1315,9 +1326,9 @@ project_batched_kernel(const BatchProblem *__restrict__ probs, const BatchTable 
         const BatchProblem &P = probs[p];
         if (P.stop && *P.stop != 0.0) continue;
         if (P.pmax <= 4)
-            project_item<EXACT, EC, 4>(P.G, P.U, local, smem, P.in, P.out, P.gmax);
+            project_item<EXACT, EC, 4, false, TAB>(P.G, P.U, local, smem, P.in, P.out, P.gmax);
         else
-            project_item<EXACT, EC, 8>(P.G, P.U, local, smem, P.in, P.out, P.gmax);
+            project_item<EXACT, EC, 8, false, TAB>(P.G, P.U, local, smem, P.in, P.out, P.gmax);
     }
 }
 
@@ -1328,7 +1339,7 @@ project_batched_kernel(const BatchProblem *__restrict__ probs, const BatchTable 
 // equals its own single-problem launch bitwise, and each kernel holds a
 // single variant of the gather (its registers fit like the single-problem
 // kernel's; one kernel inlining every variant spilled).
-template <bool EXACT, bool EC, int GW>
+template <bool EXACT, bool EC, int GW, bool TAB = false>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
 backproject_batched_kernel(const BatchProblem *__restrict__ probs, const BatchTable *__restrict__ T,
                            int *counter)
@@ -1338,7 +1349,8 @@ backproject_batched_kernel(const BatchProblem *__restrict__ probs, const BatchTa
     while (next_item(*T, counter, p, local)) {
         const BatchProblem &P = probs[p];
         if (P.stop && *P.stop != 0.0) continue;
-        backproject_item<EXACT, EC, 8, GW>(P.G, P.ngroups, P.nkchunks, P.kp, P.win_cap, local, smem, P.in, P.out);
+        backproject_item<EXACT, EC, 8, GW, false, TAB>(P.G, P.ngroups, P.nkchunks, P.kp, P.win_cap, local, smem, P.in,
+                                                      P.out);
     }
 }
 
@@ -1454,86 +1466,102 @@ hipError_t set_lds_wide(size_t n)
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
 }
 
-template <bool EXACT, bool EC>
+template <bool EXACT, bool EC, bool TAB>
 hipError_t launch_pb(BatchProblem *probs, const BatchTable *tab, int *counter, int grid, size_t lds,
                      hipStream_t s)
 {
-    hipLaunchKernelGGL((project_batched_kernel<EXACT, EC>), dim3(grid), dim3(kBlock), lds, s, probs, tab, counter);
+    hipLaunchKernelGGL((project_batched_kernel<EXACT, EC, TAB>), dim3(grid), dim3(kBlock), lds, s, probs, tab,
+                       counter);
     return hipGetLastError();
 }
 
-template <bool EXACT, bool EC>
+template <bool EXACT, bool EC, bool TAB>
 hipError_t launch_bb(BatchProblem *probs, const BatchTable *tab, int *counter, int grid, size_t lds, int gw,
                      hipStream_t s)
 {
     if (gw == 16)
-        hipLaunchKernelGGL((backproject_batched_kernel<EXACT, EC, 16>), dim3(grid), dim3(kBlock), lds, s, probs, tab,
-                           counter);
+        hipLaunchKernelGGL((backproject_batched_kernel<EXACT, EC, 16, TAB>), dim3(grid), dim3(kBlock), lds, s, probs,
+                           tab, counter);
     else if (gw == 8)
-        hipLaunchKernelGGL((backproject_batched_kernel<EXACT, EC, 8>), dim3(grid), dim3(kBlock), lds, s, probs, tab,
-                           counter);
+        hipLaunchKernelGGL((backproject_batched_kernel<EXACT, EC, 8, TAB>), dim3(grid), dim3(kBlock), lds, s, probs,
+                           tab, counter);
     else
-        hipLaunchKernelGGL((backproject_batched_kernel<EXACT, EC, 4>), dim3(grid), dim3(kBlock), lds, s, probs, tab,
-                           counter);
+        hipLaunchKernelGGL((backproject_batched_kernel<EXACT, EC, 4, TAB>), dim3(grid), dim3(kBlock), lds, s, probs,
+                           tab, counter);
     return hipGetLastError();
 }
 
-template <bool EXACT, bool EC>
+template <bool EXACT, bool EC, bool TAB>
 hipError_t set_lds_batched(size_t n)
 {
-    hipError_t e = hipFuncSetAttribute((const void *)project_batched_kernel<EXACT, EC>,
+    hipError_t e = hipFuncSetAttribute((const void *)project_batched_kernel<EXACT, EC, TAB>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
     if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)backproject_batched_kernel<EXACT, EC, 16>,
+        e = hipFuncSetAttribute((const void *)backproject_batched_kernel<EXACT, EC, 16, TAB>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
     if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)backproject_batched_kernel<EXACT, EC, 8>,
+        e = hipFuncSetAttribute((const void *)backproject_batched_kernel<EXACT, EC, 8, TAB>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
     if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)backproject_batched_kernel<EXACT, EC, 4>,
+        e = hipFuncSetAttribute((const void *)backproject_batched_kernel<EXACT, EC, 4, TAB>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
     return e;
+}
+
+template <bool TAB>
+hipError_t launch_batched_t(bool backward, BatchProblem *probs, const BatchTable *tab, int *counter, bool exact,
+                            bool ec, int grid, size_t lds, int gw, hipStream_t s)
+{
+    if (!backward) {
+        if (exact) return ec ? launch_pb<true, true, TAB>(probs, tab, counter, grid, lds, s)
+                             : launch_pb<true, false, TAB>(probs, tab, counter, grid, lds, s);
+        return ec ? launch_pb<false, true, TAB>(probs, tab, counter, grid, lds, s)
+                  : launch_pb<false, false, TAB>(probs, tab, counter, grid, lds, s);
+    }
+    if (exact) return ec ? launch_bb<true, true, TAB>(probs, tab, counter, grid, lds, gw, s)
+                         : launch_bb<true, false, TAB>(probs, tab, counter, grid, lds, gw, s);
+    return ec ? launch_bb<false, true, TAB>(probs, tab, counter, grid, lds, gw, s)
+              : launch_bb<false, false, TAB>(probs, tab, counter, grid, lds, gw, s);
+}
+
+template <bool TAB>
+int blocks_per_cu_t(bool backward, size_t lds, int gw)
+{
+    int nb = 0;
+    hipError_t e;
+    if (!backward)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)project_batched_kernel<false, true, TAB>,
+                                                         kBlock, lds);
+    else if (gw == 16)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, (const void *)backproject_batched_kernel<false, true, 16, TAB>, kBlock, lds);
+    else if (gw == 8)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, (const void *)backproject_batched_kernel<false, true, 8, TAB>, kBlock, lds);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, (const void *)backproject_batched_kernel<false, true, 4, TAB>, kBlock, lds);
+    if (e != hipSuccess || nb < 1) nb = 1;
+    return nb;
 }
 
 }  // namespace
 
 hipError_t launch_batched(bool backward, BatchProblem *probs, const BatchTable *tab, int *counter,
-                          const BatchIO &io, bool exact, bool ec, int grid, size_t lds, int gw, hipStream_t s)
+                          const BatchIO &io, bool exact, bool ec, int grid, size_t lds, int gw, bool cached,
+                          hipStream_t s)
 {
     hipLaunchKernelGGL(batch_setup, dim3(1), dim3(64), 0, s, probs, io, counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (!backward) {
-        if (exact) return ec ? launch_pb<true, true>(probs, tab, counter, grid, lds, s)
-                             : launch_pb<true, false>(probs, tab, counter, grid, lds, s);
-        return ec ? launch_pb<false, true>(probs, tab, counter, grid, lds, s)
-                  : launch_pb<false, false>(probs, tab, counter, grid, lds, s);
-    }
-    if (exact) return ec ? launch_bb<true, true>(probs, tab, counter, grid, lds, gw, s)
-                         : launch_bb<true, false>(probs, tab, counter, grid, lds, gw, s);
-    return ec ? launch_bb<false, true>(probs, tab, counter, grid, lds, gw, s)
-              : launch_bb<false, false>(probs, tab, counter, grid, lds, gw, s);
+    return cached ? launch_batched_t<true>(backward, probs, tab, counter, exact, ec, grid, lds, gw, s)
+                  : launch_batched_t<false>(backward, probs, tab, counter, exact, ec, grid, lds, gw, s);
 }
 
 // Workgroups of a persistent batched kernel that fit on one CU at this LDS size.
-int batched_blocks_per_cu(bool backward, size_t lds, int gw)
+int batched_blocks_per_cu(bool backward, size_t lds, int gw, bool cached)
 {
-    int nb = 0;
-    hipError_t e;
-    if (!backward)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)project_batched_kernel<false, true>,
-                                                         kBlock, lds);
-    else if (gw == 16)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)backproject_batched_kernel<false, true, 16>,
-                                                         kBlock, lds);
-    else if (gw == 8)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)backproject_batched_kernel<false, true, 8>,
-                                                         kBlock, lds);
-    else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)backproject_batched_kernel<false, true, 4>,
-                                                         kBlock, lds);
-    if (e != hipSuccess || nb < 1) nb = 1;
-    return nb;
+    return cached ? blocks_per_cu_t<true>(backward, lds, gw) : blocks_per_cu_t<false>(backward, lds, gw);
 }
 
 // Allow the dynamic LDS sizes chosen by the host (above the 64 KB default).
@@ -1563,10 +1591,14 @@ hipError_t configure_kernel_lds(size_t max_lds, size_t max_lds_batched)
     if (e == hipSuccess) e = set_lds_one<true, false, 8, false, true>(max_lds);
     if (e == hipSuccess) e = set_lds_one<false, true, 8, false, true>(max_lds);
     if (e == hipSuccess) e = set_lds_one<false, false, 8, false, true>(max_lds);
-    if (e == hipSuccess) e = set_lds_batched<true, true>(max_lds_batched);
-    if (e == hipSuccess) e = set_lds_batched<true, false>(max_lds_batched);
-    if (e == hipSuccess) e = set_lds_batched<false, true>(max_lds_batched);
-    if (e == hipSuccess) e = set_lds_batched<false, false>(max_lds_batched);
+    if (e == hipSuccess) e = set_lds_batched<true, true, false>(max_lds_batched);
+    if (e == hipSuccess) e = set_lds_batched<true, false, false>(max_lds_batched);
+    if (e == hipSuccess) e = set_lds_batched<false, true, false>(max_lds_batched);
+    if (e == hipSuccess) e = set_lds_batched<false, false, false>(max_lds_batched);
+    if (e == hipSuccess) e = set_lds_batched<true, true, true>(max_lds_batched);
+    if (e == hipSuccess) e = set_lds_batched<true, false, true>(max_lds_batched);
+    if (e == hipSuccess) e = set_lds_batched<false, true, true>(max_lds_batched);
+    if (e == hipSuccess) e = set_lds_batched<false, false, true>(max_lds_batched);
     return e;
 }
 

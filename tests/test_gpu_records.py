@@ -95,3 +95,26 @@ def test_wide_footprints_refused():
     with pytest.raises(_lib.CVPError) as ei:
         G.cache_records()
     assert ei.value.status == _lib.CVP_E_UNSUPPORTED
+
+
+def test_batch_reads_cached_records():
+    """A batch whose members all have cached records gives every member's
+    single-problem result bitwise; a member's table freed afterwards makes
+    the batch refuse to run."""
+    gs = geoms()
+    G = [cvp.Geometry(gs["pmax4"]), cvp.Geometry(gs["pmax8"])]
+    xs = [torch.from_numpy(synth.uniform_volume(g.vol_shape, seed=94 + q)).cuda() for q, g in enumerate(G)]
+    bs = [torch.from_numpy(synth.uniform_projections(g.proj_shape, seed=96 + q)).cuda() for q, g in enumerate(G)]
+    opts = cvp.Options(variant="relaxed", ec=True)
+    for g in G:
+        g.cache_records()
+    batch = cvp.Batch(G)
+    pb = cvp.project_batched(xs, batch, opts)
+    vb = cvp.backproject_batched(bs, batch, opts)
+    for q, g in enumerate(G):
+        assert torch.equal(pb[q], cvp.project(xs[q], g, opts))
+        assert torch.equal(vb[q], cvp.backproject(bs[q], g, opts))
+    G[1].cache_records(False)
+    with pytest.raises(_lib.CVPError) as ei:
+        cvp.project_batched(xs, batch, opts)
+    assert ei.value.status == _lib.CVP_E_INVALID
