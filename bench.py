@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--no-network", action="store_true", help="skip the warm-start network timing")
     ap.add_argument("--no-batched", action="store_true", help="skip the 16-problem batched timing")
     ap.add_argument("--no-cone", action="store_true", help="skip the 256^3 cone-beam timing")
+    ap.add_argument("--no-paper-benchmarks", action="store_true",
+                    help="skip the paper's two speed benchmarks (CVP and TT, one application each)")
     ap.add_argument("--cpu-baseline-full", action="store_true",
                     help="run only the full CPU-baseline plan of the oracle (minutes, no GPU)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -222,6 +224,55 @@ def measured_counters(kernel):
             "algorithmic_bytes": rec["algorithmic_bytes_per_launch"], "plan": rec.get("plan")}
 
 
+def paper_benchmarks(reps=2):
+    """The paper's two speed benchmarks (Sec. IV-A, Tables I and II) rerun on
+    synthetic data: "Long" (512 x 512 x 128 voxels of 0.5 mm, 720 views, 512 x
+    512 pixels of 1 mm, SID 541 / SDD 949) and "Pfeiffer" (256^3 voxels of
+    0.5 mm, 100 views over 198 degrees, 1280 x 960 pixels of 0.25 mm, SID 750 /
+    SDD 1000): one application of A and of A^T per projector (CVP exact and
+    relaxed with EC, and TT), timed with HIP events on uniform random data.
+    The paper's times on its GPUs (context, not targets) go beside them."""
+    import torch
+    from paper_2110_09841_amd import cvp, synth
+    setups = {
+        "long": (dict(dims=(512, 512, 128), vox=0.5, det=(512, 512), pitch=1.0, sid=541.0, sdd=949.0, views=720,
+                      arc=360.0),
+                 {"cvp": [39.3, 19.7], "cvp_relaxed": [12.3, 5.2], "tt": [101.1, 18.8]}),
+        "pfeiffer": (dict(dims=(256, 256, 256), vox=0.5, det=(1280, 960), pitch=0.25, sid=750.0, sdd=1000.0,
+                          views=100, arc=198.0),
+                     {"cvp": [22.5, 14.1], "cvp_relaxed": [7.5, 4.1], "tt": [27.6, 11.5]}),
+    }
+    out = {}
+    gen = torch.Generator(device="cuda").manual_seed(8)
+    for name, (c, paper) in setups.items():
+        G = cvp.Geometry(synth.geometry(c["dims"], c["vox"], c["det"][0], c["det"][1], c["pitch"], c["sid"], c["sdd"],
+                                        c["views"], c["arc"]))
+        x = torch.rand(G.vol_shape, generator=gen, device="cuda")
+        b = torch.rand(G.proj_shape, generator=gen, device="cuda")
+        po, vo = torch.empty_like(b), torch.empty_like(x)
+        res = {"voxel_views": G.n_voxels * G.n_views,
+               "paper_radeon_vii_s": paper}
+        for key, opts in (("cvp", cvp.Options(variant="exact", ec=True)),
+                          ("cvp_relaxed", cvp.Options(variant="relaxed", ec=True)), ("tt", cvp.TT)):
+            cvp.project(x, G, opts, out=po)
+            cvp.backproject(b, G, opts, out=vo)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            torch.cuda.synchronize()
+            ev[0].record()
+            for _ in range(reps):
+                cvp.project(x, G, opts, out=po)
+            ev[1].record()
+            for _ in range(reps):
+                cvp.backproject(b, G, opts, out=vo)
+            ev[2].record()
+            torch.cuda.synchronize()
+            res[key + "_ms"] = [ev[0].elapsed_time(ev[1]) / reps, ev[1].elapsed_time(ev[2]) / reps]
+        out[name] = res
+        del G, x, b, po, vo
+        torch.cuda.empty_cache()
+    return out
+
+
 def cone_timing(reps=2):
     """The 12-degree cone workload (256^3 voxels of 0.5 mm, 512x384 pixels
     of 0.388 mm, SID 600 / SDD 900, 360 views): A and A^T timed separately
@@ -275,18 +326,24 @@ def batched_timing(reps=2):
     po = [torch.empty(g.proj_shape, device="cuda") for g in geoms]
     vo = [torch.empty(g.vol_shape, device="cuda") for g in geoms]
 
-    def batched():
+    def batched_p():
         cvp.project_batched(xs, batch, opts, outs=po)
+
+    def batched_b():
         cvp.backproject_batched(bs, batch, opts, outs=vo)
 
-    def single():
+    def single_p():
         for q, g in enumerate(geoms):
             cvp.project(xs[q], g, opts, out=po[q])
+
+    def single_b():
+        for q, g in enumerate(geoms):
             cvp.backproject(bs[q], g, opts, out=vo[q])
 
     def timed():
         times = {}
-        for name, fn in (("batched", batched), ("single", single)):
+        for name, fn in (("batched_project", batched_p), ("batched_backproject", batched_b),
+                         ("single_project", single_p), ("single_backproject", single_b)):
             fn()
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -296,6 +353,8 @@ def batched_timing(reps=2):
             e1.record()
             torch.cuda.synchronize()
             times[name] = e0.elapsed_time(e1) / reps
+        times["batched"] = times["batched_project"] + times["batched_backproject"]
+        times["single"] = times["single_project"] + times["single_backproject"]
         return times
 
     batch = cvp.Batch(geoms)
@@ -309,6 +368,8 @@ def batched_timing(reps=2):
            "record_cache_bytes": table_bytes,
            "batched_ms": times["batched"], "single_launches_ms": times["single"],
            "batched_over_single": times["batched"] / times["single"],
+           "per_direction_ms": {k: times[k] for k in ("batched_project", "batched_backproject", "single_project",
+                                                      "single_backproject")},
            "batched_voxel_views_per_s": vv / (times["batched"] * 1e-3),
            "without_record_cache": {"batched_ms": plain["batched"], "single_launches_ms": plain["single"],
                                     "batched_over_single": plain["batched"] / plain["single"]}}
@@ -537,6 +598,8 @@ def main():
         out["batched"] = batched_timing()
     if not args.no_cone:
         out["cone"] = cone_timing()
+    if not args.no_paper_benchmarks:
+        out["paper_benchmarks"] = paper_benchmarks()
     del x, b, p_out, v_out
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:

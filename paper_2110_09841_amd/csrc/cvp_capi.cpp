@@ -865,11 +865,13 @@ struct cvp_batch {
     std::vector<const cvp_geometry *> geoms;
     cvp::BatchProblem *d_probs = nullptr;
     cvp::BatchTable *d_ptab = nullptr;
-    cvp::BatchTable *d_btab[3] = {nullptr, nullptr, nullptr};   // backprojection: stack widths 16, 8, 4
+    // backprojection groups g = 3 p + w: piece stride 4 (p = 0) or 8 (p = 1),
+    // stack width 16, 8, 4 (w = 0, 1, 2)
+    cvp::BatchTable *d_btab[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     int *d_counter = nullptr;         // [0] projection, [1 + g] backprojection group g
     std::vector<unsigned *> d_gmax;   // per problem: per-group maxima of the volume
-    size_t plds = 0, blds[3] = {0, 0, 0};
-    int pgrid = 0, bgrid[3] = {0, 0, 0};
+    size_t plds = 0, blds[6] = {0, 0, 0, 0, 0, 0};
+    int pgrid = 0, bgrid[6] = {0, 0, 0, 0, 0, 0};
     bool cached = false;                  // every member reads its geometry's cached records
     std::vector<const float *> rtabs;     // the tables captured at creation
 };
@@ -913,11 +915,11 @@ cvp_status cvp_batch_create(const cvp_geometry *const *geoms, int32_t n, cvp_bat
     for (int q = 0; q < n; ++q) b->cached = b->cached && geoms[q]->d_rtab != nullptr;
     // Projection: every problem keeps its own plan (the batched kernel
     // dispatches on the piece stride per item), so its results are those of
-    // its own launches.  Backprojection: every problem keeps its own stack
-    // width (with 8-piece records), and the batch runs one persistent launch
-    // per width present; backprojection sums do not depend on the plan, so
-    // the results still equal single launches bitwise.  One dynamic LDS size
-    // fits all items of a launch.
+    // its own launches.  Backprojection: every problem keeps its own piece
+    // stride and stack width, and the batch runs one persistent launch per
+    // (stride, width) present; backprojection sums do not depend on the plan,
+    // so the results still equal single launches bitwise.  One dynamic LDS
+    // size fits all items of a launch.
     static const int kGw[3] = {16, 8, 4};
     std::vector<cvp::BackLaunch> bls(n);
     std::vector<int> grp(n);
@@ -925,11 +927,12 @@ cvp_status cvp_batch_create(const cvp_geometry *const *geoms, int32_t n, cvp_bat
         // the member's own stack width, else the next narrower one whose
         // 8-piece records fit
         bool planned = false;
+        const int pm = geoms[q]->pmax <= 4 ? 4 : 8;
         for (int gi = 0; gi < 3 && !planned; ++gi) {
             if (kGw[gi] > geoms[q]->bl.gw) continue;
-            planned = cvp::plan_backprojection(geoms[q]->base, 8, geoms[q]->zabs, geoms[q]->Dmin, kGw[gi], 0, bls[q],
+            planned = cvp::plan_backprojection(geoms[q]->base, pm, geoms[q]->zabs, geoms[q]->Dmin, kGw[gi], 0, bls[q],
                                                b->cached);
-            grp[q] = gi;
+            grp[q] = (pm == 4 ? 0 : 3) + gi;
         }
         if (!planned) {
             delete b;
@@ -988,13 +991,13 @@ cvp_status cvp_batch_create(const cvp_geometry *const *geoms, int32_t n, cvp_bat
     hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
     if (e == hipSuccess) e = hipMalloc((void **)&b->d_probs, n * sizeof(cvp::BatchProblem));
     if (e == hipSuccess) e = hipMalloc((void **)&b->d_ptab, sizeof(cvp::BatchTable));
-    if (e == hipSuccess) e = hipMalloc((void **)&b->d_counter, 4 * sizeof(int));
-    for (int gi = 0; gi < 3 && e == hipSuccess; ++gi) {
-        if (b->blds[gi] == 0) continue;   // no member with this width
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_counter, 7 * sizeof(int));
+    for (int gi = 0; gi < 6 && e == hipSuccess; ++gi) {
+        if (b->blds[gi] == 0) continue;   // no member with this stride and width
         const cvp::BatchTable bt = table(bcost, true, gi);
         e = hipMalloc((void **)&b->d_btab[gi], sizeof(cvp::BatchTable));
         if (e == hipSuccess) e = hipMemcpy(b->d_btab[gi], &bt, sizeof(bt), hipMemcpyHostToDevice);
-        b->bgrid[gi] = cus * cvp::batched_blocks_per_cu(true, b->blds[gi], kGw[gi], b->cached);
+        b->bgrid[gi] = cus * cvp::batched_blocks_per_cu(true, b->blds[gi], kGw[gi % 3], gi < 3 ? 4 : 8, b->cached);
     }
     b->d_gmax.assign(n, nullptr);
     for (int q = 0; q < n && e == hipSuccess; ++q) {
@@ -1004,7 +1007,7 @@ cvp_status cvp_batch_create(const cvp_geometry *const *geoms, int32_t n, cvp_bat
     if (e == hipSuccess) e = hipMemcpy(b->d_probs, probs.data(), n * sizeof(cvp::BatchProblem), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b->d_ptab, &pt, sizeof(pt), hipMemcpyHostToDevice);
     if (e != hipSuccess) { cvp_batch_destroy(b); return device_fail(e, "batch tables"); }
-    b->pgrid = cus * cvp::batched_blocks_per_cu(false, b->plds, 16, b->cached);
+    b->pgrid = cus * cvp::batched_blocks_per_cu(false, b->plds, 16, 8, b->cached);
     *out = b;
     return ok();
 }
@@ -1044,14 +1047,15 @@ static cvp_status batched(const cvp_batch *b, const cvp_options *o, const float 
     const bool ex = o->variant == CVP_EXACT, ec = o->elevation_correction != 0;
     hipError_t e = hipSuccess;
     if (!backward) {
-        e = cvp::launch_batched(false, b->d_probs, b->d_ptab, b->d_counter, io, ex, ec, b->pgrid, b->plds, 16,
+        e = cvp::launch_batched(false, b->d_probs, b->d_ptab, b->d_counter, io, ex, ec, b->pgrid, b->plds, 16, 8,
                                 b->cached, (hipStream_t)stream);
     } else {
         static const int kGw[3] = {16, 8, 4};
-        for (int gi = 0; gi < 3 && e == hipSuccess; ++gi)
+        for (int gi = 0; gi < 6 && e == hipSuccess; ++gi)
             if (b->d_btab[gi])
                 e = cvp::launch_batched(true, b->d_probs, b->d_btab[gi], b->d_counter + 1 + gi, io, ex, ec,
-                                        b->bgrid[gi], b->blds[gi], kGw[gi], b->cached, (hipStream_t)stream);
+                                        b->bgrid[gi], b->blds[gi], kGw[gi % 3], gi < 3 ? 4 : 8, b->cached,
+                                        (hipStream_t)stream);
     }
     if (e != hipSuccess) return device_fail(e, "batched launch");
     return ok();

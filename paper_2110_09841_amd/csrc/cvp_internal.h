@@ -128,12 +128,12 @@ struct BatchIO {             // per call, by value
     const double *stop[kMaxBatch];   // per problem, or nullptr
 };
 
-// gw: the launch's backprojection stack width (16, 8 or 4); cached: every
-// member reads its geometry's cached records
+// gw, pmax: the backprojection launch's stack width (16, 8 or 4) and piece
+// stride (4 or 8); cached: every member reads its geometry's cached records
 hipError_t launch_batched(bool backward, BatchProblem *probs, const BatchTable *tab, int *counter,
-                          const BatchIO &io, bool exact, bool ec, int grid, size_t lds, int gw, bool cached,
+                          const BatchIO &io, bool exact, bool ec, int grid, size_t lds, int gw, int pmax, bool cached,
                           hipStream_t s);
-int batched_blocks_per_cu(bool backward, size_t lds, int gw, bool cached);
+int batched_blocks_per_cu(bool backward, size_t lds, int gw, int pmax, bool cached);
 size_t project_lds_bytes(int U, int N, int n2, int pmax);
 size_t backproject_lds_bytes(int gw, int pmax, int winCap);
 

@@ -1332,14 +1332,14 @@ project_batched_kernel(const BatchProblem *__restrict__ probs, const BatchTable 
     }
 }
 
-// One persistent launch per stack width GW present in a batch, over the
-// members with that width, with records of 8 pieces per column (enough for
-// every member); each problem keeps its own passes and window.
+// One persistent launch per (stack width GW, piece stride PMAX) present in a
+// batch, over the members with that width and stride; each problem keeps its
+// own passes and window.
 // Backprojection sums do not depend on the plan, so every problem's result
 // equals its own single-problem launch bitwise, and each kernel holds a
 // single variant of the gather (its registers fit like the single-problem
 // kernel's; one kernel inlining every variant spilled).
-template <bool EXACT, bool EC, int GW, bool TAB = false>
+template <bool EXACT, bool EC, int PMAX, int GW, bool TAB = false>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
 backproject_batched_kernel(const BatchProblem *__restrict__ probs, const BatchTable *__restrict__ T,
                            int *counter)
@@ -1349,8 +1349,8 @@ backproject_batched_kernel(const BatchProblem *__restrict__ probs, const BatchTa
     while (next_item(*T, counter, p, local)) {
         const BatchProblem &P = probs[p];
         if (P.stop && *P.stop != 0.0) continue;
-        backproject_item<EXACT, EC, 8, GW, false, TAB>(P.G, P.ngroups, P.nkchunks, P.kp, P.win_cap, local, smem, P.in,
-                                                      P.out);
+        backproject_item<EXACT, EC, PMAX, GW, false, TAB>(P.G, P.ngroups, P.nkchunks, P.kp, P.win_cap, local, smem,
+                                                         P.in, P.out);
     }
 }
 
@@ -1475,20 +1475,42 @@ hipError_t launch_pb(BatchProblem *probs, const BatchTable *tab, int *counter, i
     return hipGetLastError();
 }
 
-template <bool EXACT, bool EC, bool TAB>
-hipError_t launch_bb(BatchProblem *probs, const BatchTable *tab, int *counter, int grid, size_t lds, int gw,
-                     hipStream_t s)
+template <bool EXACT, bool EC, int PMAX, bool TAB>
+hipError_t launch_bb_p(BatchProblem *probs, const BatchTable *tab, int *counter, int grid, size_t lds, int gw,
+                       hipStream_t s)
 {
     if (gw == 16)
-        hipLaunchKernelGGL((backproject_batched_kernel<EXACT, EC, 16, TAB>), dim3(grid), dim3(kBlock), lds, s, probs,
-                           tab, counter);
+        hipLaunchKernelGGL((backproject_batched_kernel<EXACT, EC, PMAX, 16, TAB>), dim3(grid), dim3(kBlock), lds, s,
+                           probs, tab, counter);
     else if (gw == 8)
-        hipLaunchKernelGGL((backproject_batched_kernel<EXACT, EC, 8, TAB>), dim3(grid), dim3(kBlock), lds, s, probs,
-                           tab, counter);
+        hipLaunchKernelGGL((backproject_batched_kernel<EXACT, EC, PMAX, 8, TAB>), dim3(grid), dim3(kBlock), lds, s,
+                           probs, tab, counter);
     else
-        hipLaunchKernelGGL((backproject_batched_kernel<EXACT, EC, 4, TAB>), dim3(grid), dim3(kBlock), lds, s, probs,
-                           tab, counter);
+        hipLaunchKernelGGL((backproject_batched_kernel<EXACT, EC, PMAX, 4, TAB>), dim3(grid), dim3(kBlock), lds, s,
+                           probs, tab, counter);
     return hipGetLastError();
+}
+
+template <bool EXACT, bool EC, bool TAB>
+hipError_t launch_bb(BatchProblem *probs, const BatchTable *tab, int *counter, int grid, size_t lds, int gw, int pmax,
+                     hipStream_t s)
+{
+    return pmax <= 4 ? launch_bb_p<EXACT, EC, 4, TAB>(probs, tab, counter, grid, lds, gw, s)
+                     : launch_bb_p<EXACT, EC, 8, TAB>(probs, tab, counter, grid, lds, gw, s);
+}
+
+template <bool EXACT, bool EC, int PMAX, bool TAB>
+hipError_t set_lds_batched_back(size_t n)
+{
+    hipError_t e = hipFuncSetAttribute((const void *)backproject_batched_kernel<EXACT, EC, PMAX, 16, TAB>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)backproject_batched_kernel<EXACT, EC, PMAX, 8, TAB>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)backproject_batched_kernel<EXACT, EC, PMAX, 4, TAB>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
+    return e;
 }
 
 template <bool EXACT, bool EC, bool TAB>
@@ -1496,21 +1518,14 @@ hipError_t set_lds_batched(size_t n)
 {
     hipError_t e = hipFuncSetAttribute((const void *)project_batched_kernel<EXACT, EC, TAB>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)backproject_batched_kernel<EXACT, EC, 16, TAB>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)backproject_batched_kernel<EXACT, EC, 8, TAB>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)backproject_batched_kernel<EXACT, EC, 4, TAB>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
+    if (e == hipSuccess) e = set_lds_batched_back<EXACT, EC, 4, TAB>(n);
+    if (e == hipSuccess) e = set_lds_batched_back<EXACT, EC, 8, TAB>(n);
     return e;
 }
 
 template <bool TAB>
 hipError_t launch_batched_t(bool backward, BatchProblem *probs, const BatchTable *tab, int *counter, bool exact,
-                            bool ec, int grid, size_t lds, int gw, hipStream_t s)
+                            bool ec, int grid, size_t lds, int gw, int pmax, hipStream_t s)
 {
     if (!backward) {
         if (exact) return ec ? launch_pb<true, true, TAB>(probs, tab, counter, grid, lds, s)
@@ -1518,29 +1533,27 @@ hipError_t launch_batched_t(bool backward, BatchProblem *probs, const BatchTable
         return ec ? launch_pb<false, true, TAB>(probs, tab, counter, grid, lds, s)
                   : launch_pb<false, false, TAB>(probs, tab, counter, grid, lds, s);
     }
-    if (exact) return ec ? launch_bb<true, true, TAB>(probs, tab, counter, grid, lds, gw, s)
-                         : launch_bb<true, false, TAB>(probs, tab, counter, grid, lds, gw, s);
-    return ec ? launch_bb<false, true, TAB>(probs, tab, counter, grid, lds, gw, s)
-              : launch_bb<false, false, TAB>(probs, tab, counter, grid, lds, gw, s);
+    if (exact) return ec ? launch_bb<true, true, TAB>(probs, tab, counter, grid, lds, gw, pmax, s)
+                         : launch_bb<true, false, TAB>(probs, tab, counter, grid, lds, gw, pmax, s);
+    return ec ? launch_bb<false, true, TAB>(probs, tab, counter, grid, lds, gw, pmax, s)
+              : launch_bb<false, false, TAB>(probs, tab, counter, grid, lds, gw, pmax, s);
+}
+
+template <int PMAX, bool TAB>
+const void *back_batched_fn(int gw)
+{
+    if (gw == 16) return (const void *)backproject_batched_kernel<false, true, PMAX, 16, TAB>;
+    if (gw == 8) return (const void *)backproject_batched_kernel<false, true, PMAX, 8, TAB>;
+    return (const void *)backproject_batched_kernel<false, true, PMAX, 4, TAB>;
 }
 
 template <bool TAB>
-int blocks_per_cu_t(bool backward, size_t lds, int gw)
+int blocks_per_cu_t(bool backward, size_t lds, int gw, int pmax)
 {
     int nb = 0;
-    hipError_t e;
-    if (!backward)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)project_batched_kernel<false, true, TAB>,
-                                                         kBlock, lds);
-    else if (gw == 16)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &nb, (const void *)backproject_batched_kernel<false, true, 16, TAB>, kBlock, lds);
-    else if (gw == 8)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &nb, (const void *)backproject_batched_kernel<false, true, 8, TAB>, kBlock, lds);
-    else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &nb, (const void *)backproject_batched_kernel<false, true, 4, TAB>, kBlock, lds);
+    const void *fn = !backward ? (const void *)project_batched_kernel<false, true, TAB>
+                               : pmax <= 4 ? back_batched_fn<4, TAB>(gw) : back_batched_fn<8, TAB>(gw);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kBlock, lds);
     if (e != hipSuccess || nb < 1) nb = 1;
     return nb;
 }
@@ -1548,20 +1561,20 @@ int blocks_per_cu_t(bool backward, size_t lds, int gw)
 }  // namespace
 
 hipError_t launch_batched(bool backward, BatchProblem *probs, const BatchTable *tab, int *counter,
-                          const BatchIO &io, bool exact, bool ec, int grid, size_t lds, int gw, bool cached,
+                          const BatchIO &io, bool exact, bool ec, int grid, size_t lds, int gw, int pmax, bool cached,
                           hipStream_t s)
 {
     hipLaunchKernelGGL(batch_setup, dim3(1), dim3(64), 0, s, probs, io, counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return cached ? launch_batched_t<true>(backward, probs, tab, counter, exact, ec, grid, lds, gw, s)
-                  : launch_batched_t<false>(backward, probs, tab, counter, exact, ec, grid, lds, gw, s);
+    return cached ? launch_batched_t<true>(backward, probs, tab, counter, exact, ec, grid, lds, gw, pmax, s)
+                  : launch_batched_t<false>(backward, probs, tab, counter, exact, ec, grid, lds, gw, pmax, s);
 }
 
 // Workgroups of a persistent batched kernel that fit on one CU at this LDS size.
-int batched_blocks_per_cu(bool backward, size_t lds, int gw, bool cached)
+int batched_blocks_per_cu(bool backward, size_t lds, int gw, int pmax, bool cached)
 {
-    return cached ? blocks_per_cu_t<true>(backward, lds, gw) : blocks_per_cu_t<false>(backward, lds, gw);
+    return cached ? blocks_per_cu_t<true>(backward, lds, gw, pmax) : blocks_per_cu_t<false>(backward, lds, gw, pmax);
 }
 
 // Allow the dynamic LDS sizes chosen by the host (above the 64 KB default).
