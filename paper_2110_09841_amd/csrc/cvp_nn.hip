@@ -18,6 +18,7 @@
 // consecutive voxels of a lane are one 16-byte LDS read.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 namespace cvpnn {
@@ -112,6 +113,83 @@ conv3d_kernel(const Act in, const __bf16 *__restrict__ wt, const float *__restri
                     float v = acc[r][n][e] + bv;
                     if (relu) v = fmaxf(v, 0.0f);
                     out.p[(((size_t)d * out.H + h) * out.W + x) * out.stride + co] = (__bf16)v;
+                }
+            }
+        }
+    }
+}
+
+// The same convolution with the input channel count CI a compile-time power
+// of two (16, 32 or 64), for volumes whose element count fits 32 bits: a
+// lane's tap and channel follow from shifts, the tap's offsets from
+// divisions by constants, and the addresses from 32-bit voxel indices.  The
+// arithmetic (k order, MFMA sequence, epilogue) is that of conv3d_kernel, so
+// the results are the same bits.
+template <int CO, int CI>
+__global__ void __launch_bounds__(256)
+conv3d_kernel_c(const Act in, const __bf16 *__restrict__ wt, const float *__restrict__ bias, Act out, int relu,
+                int flip)
+{
+    constexpr int NT = CO / 16;
+    constexpr int KSTEPS = (27 * CI + 31) / 32;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int segs = (in.W + 63) / 64;
+    const int row = blockIdx.x * 4 + wave;           // (d, h, segment)
+    if (row >= in.D * in.H * segs) return;
+    const int seg = row % segs;
+    const int dh = row / segs;
+    const int d = dh / in.H, h = dh % in.H;
+    const int w0 = seg * 64;
+
+    f32x4 acc[4][NT];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int n = 0; n < NT; ++n) acc[r][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    const int i16 = lane & 15;
+    const int kg = lane >> 4;        // which group of 8 k within the 32
+#pragma unroll 2
+    for (int ks = 0; ks < KSTEPS; ++ks) {
+        const int k = ks * 32 + kg * 8;
+        const int tap = k / CI;
+        const int ci = k % CI;
+        const bool tv = tap < 27;
+        const int tp = flip ? 26 - tap : tap;
+        const int dz = tp / 9 - 1, dy = (tp / 3) % 3 - 1, dx = tp % 3 - 1;
+        const int z = d + dz, y = h + dy;
+        const bool zy = tv && (unsigned)z < (unsigned)in.D && (unsigned)y < (unsigned)in.H;
+        const int base = (z * in.H + y) * in.W + w0 + i16 + dx;   // voxel index of row tile 0
+        bf16x8 a[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int x = w0 + r * 16 + i16 + dx;
+            if (zy && (unsigned)x < (unsigned)in.W)
+                a[r] = *reinterpret_cast<const bf16x8 *>(in.p + (base + r * 16) * in.stride + ci);
+            else
+                a[r] = zero8();
+        }
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            const int co = n * 16 + i16;
+            bf16x8 b = tv ? *reinterpret_cast<const bf16x8 *>(wt + (tap * CO + co) * CI + ci) : zero8();
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[r][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], b, acc[r][n], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+        const int co = n * 16 + i16;
+        const float bv = bias ? bias[co] : 0.0f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int x = w0 + r * 16 + (lane >> 4) * 4 + e;
+                if (x < out.W) {
+                    float v = acc[r][n][e] + bv;
+                    if (relu) v = fmaxf(v, 0.0f);
+                    out.p[((d * out.H + h) * out.W + x) * out.stride + co] = (__bf16)v;
                 }
             }
         }
@@ -531,12 +609,29 @@ cvp_status cvp_nn_conv3d(const cvp_nn_tensor *in, const void *weight, const floa
     const dim3 grid((rows + 3) / 4), block(256);
     hipStream_t s = (hipStream_t)stream;
     const __bf16 *w = reinterpret_cast<const __bf16 *>(weight);
-    switch (out->channels) {
-    case 16: hipLaunchKernelGGL(cvpnn::conv3d_kernel<16>, grid, block, 0, s, a, w, bias, o, relu, flip); break;
-    case 32: hipLaunchKernelGGL(cvpnn::conv3d_kernel<32>, grid, block, 0, s, a, w, bias, o, relu, flip); break;
-    case 64: hipLaunchKernelGGL(cvpnn::conv3d_kernel<64>, grid, block, 0, s, a, w, bias, o, relu, flip); break;
-    default: return CVP_E_UNSUPPORTED;
+    // channel counts 16, 32, 64 and 32-bit element offsets: the specialised kernel
+    const int64_t elems = (int64_t)in->d * in->h * in->w * std::max(in->stride, out->stride);
+    const int ci = in->channels, co = out->channels;
+    const bool spec = elems < (int64_t(1) << 31) && (ci == 16 || ci == 32 || ci == 64);
+#define CONVC(CO_, CI_) hipLaunchKernelGGL((cvpnn::conv3d_kernel_c<CO_, CI_>), grid, block, 0, s, a, w, bias, o, relu, flip)
+    if (spec && co == 16 && ci == 16) CONVC(16, 16);
+    else if (spec && co == 16 && ci == 32) CONVC(16, 32);
+    else if (spec && co == 16 && ci == 64) CONVC(16, 64);
+    else if (spec && co == 32 && ci == 16) CONVC(32, 16);
+    else if (spec && co == 32 && ci == 32) CONVC(32, 32);
+    else if (spec && co == 32 && ci == 64) CONVC(32, 64);
+    else if (spec && co == 64 && ci == 16) CONVC(64, 16);
+    else if (spec && co == 64 && ci == 32) CONVC(64, 32);
+    else if (spec && co == 64 && ci == 64) CONVC(64, 64);
+    else {
+        switch (co) {
+        case 16: hipLaunchKernelGGL(cvpnn::conv3d_kernel<16>, grid, block, 0, s, a, w, bias, o, relu, flip); break;
+        case 32: hipLaunchKernelGGL(cvpnn::conv3d_kernel<32>, grid, block, 0, s, a, w, bias, o, relu, flip); break;
+        case 64: hipLaunchKernelGGL(cvpnn::conv3d_kernel<64>, grid, block, 0, s, a, w, bias, o, relu, flip); break;
+        default: return CVP_E_UNSUPPORTED;
+        }
     }
+#undef CONVC
     return st(hipGetLastError());
 }
 
