@@ -100,14 +100,14 @@ def _grid(geom):
     return (n1, n2, n3), a, lo
 
 
-def _view_weights(geom, view_geom, axial="TT"):
-    """All (voxel, pixel, weight) triples of one view, as flat arrays in
-    chunks: voxel index k*n2*n1 + j*n1 + i, pixel index v*M + u."""
-    (n1, n2, n3), a, lo = _grid(geom)
+def _weights(geom, view_geom, ii, jj, kk, axial="TT"):
+    """The (voxel, pixel, weight) triples of the voxels (ii[n], jj[n], kk[n])
+    in one view, as flat arrays in chunks: position in the voxel list, pixel
+    index v*M + u, weight."""
+    _, a, lo = _grid(geom)
     M, N = int(geom["det_cols"]), int(geom["det_rows"])
     s, e1, d, fb1, fb2, c1, c2 = view_geom
-    # columns (i, j): base corners, chi1 and depth
-    ii, jj = np.meshgrid(np.arange(n1), np.arange(n2), indexing="xy")   # [n2][n1]
+    # the voxel's column (i, j): base corners, chi1 and depth
     xc1 = lo[0] + (ii + 0.5) * a[0]
     xc2 = lo[1] + (jj + 0.5) * a[1]
     chi, dep = [], []
@@ -118,12 +118,12 @@ def _view_weights(geom, view_geom, axial="TT"):
             D = d[0] * p1 + d[1] * p2
             dep.append(D)
             chi.append(c1 + fb1 * (e1[0] * p1 + e1[1] * p2) / D)
-    chi = np.stack(chi, axis=-1)                        # [n2][n1][4], corner order
+    chi = np.stack(chi, axis=-1)                        # [n][4], corner order
     tau = chi if _MUTATION == 4 else np.sort(chi, axis=-1)
     dep = np.stack(dep, axis=-1)
     Dn, Df = dep.min(axis=-1), dep.max(axis=-1)
     Dc = d[0] * (xc1 - s[0]) + d[1] * (xc2 - s[1])
-    # amplitude: chord of the central ray (the x3 part per k below)
+    # amplitude: chord of the central ray
     r1, r2 = xc1 - s[0], xc2 - s[1]
     with np.errstate(divide="ignore"):
         if _MUTATION == 1:
@@ -131,45 +131,62 @@ def _view_weights(geom, view_geom, axial="TT"):
         else:
             lphi = np.minimum(a[0] / np.abs(r1), a[1] / np.abs(r2))
     half = 0.0 if _MUTATION == 3 else 0.5
-    # per voxel (k, j, i)
-    z0 = lo[2] + np.arange(n3) * a[2]                   # bottom face of slice k
-    z1 = z0 + a[2]
-    zc = z0 + 0.5 * a[2]
-    Z0 = (z0 - s[2])[:, None, None]
-    Z1 = (z1 - s[2])[:, None, None]
+    # the voxel's slice: bottom face z0, top face z1, centre zc
+    z0 = lo[2] + kk * a[2]
+    Z0 = z0 - s[2]
+    Z1 = Z0 + a[2]
+    zr = Z0 + 0.5 * a[2]
     if axial == "TT" and _MUTATION != 2:
-        ts = np.stack([c2 - fb2 * Z1 / Dn[None], c2 - fb2 * Z1 / Df[None],
-                       c2 - fb2 * Z0 / Dn[None], c2 - fb2 * Z0 / Df[None]], axis=-1)
-        ts = np.sort(ts, axis=-1)                       # [n3][n2][n1][4]
+        ts = np.stack([c2 - fb2 * Z1 / Dn, c2 - fb2 * Z1 / Df, c2 - fb2 * Z0 / Dn, c2 - fb2 * Z0 / Df], axis=-1)
+        ts = np.sort(ts, axis=-1)                       # [n][4]
     else:   # TR: a rectangle between the faces at the centre depth
-        top = c2 - fb2 * Z1 / Dc[None]
-        bot = c2 - fb2 * Z0 / Dc[None]
+        top = c2 - fb2 * Z1 / Dc
+        bot = c2 - fb2 * Z0 / Dc
         ts = np.stack([top, top, bot, bot], axis=-1)
-    zr = (zc - s[2])[:, None, None]
-    amp = lphi[None] * np.sqrt(r1[None] ** 2 + r2[None] ** 2 + zr ** 2)   # [n3][n2][n1]
+    amp = lphi * np.sqrt(r1 ** 2 + r2 ** 2 + zr ** 2)
 
-    ulo = np.floor(tau[..., 0] + 0.5).astype(np.int64)
-    uhi = np.floor(tau[..., 3] + 0.5).astype(np.int64)
-    vlo = np.floor(ts[..., 0] + 0.5).astype(np.int64)
-    vhi = np.floor(ts[..., 3] + 0.5).astype(np.int64)
+    ulo = np.floor(tau[:, 0] + 0.5).astype(np.int64)
+    uhi = np.floor(tau[:, 3] + 0.5).astype(np.int64)
+    vlo = np.floor(ts[:, 0] + 0.5).astype(np.int64)
+    vhi = np.floor(ts[:, 3] + 0.5).astype(np.int64)
+    if len(ii) == 0:
+        return
     nu = int((uhi - ulo).max()) + 1
     nv = int((vhi - vlo).max()) + 1
-    vox = np.arange(n1 * n2 * n3).reshape(n3, n2, n1)
+    pos = np.arange(len(ii))
+    # the axial factors of every row offset, then the transaxial ones
+    rows = []
+    for dv in range(nv):
+        v = vlo + dv
+        F2 = trapezoid_integral(ts, v - half, v + 1.0 - half)
+        rows.append((v, amp * F2, (v <= vhi) & (v >= 0) & (v < N) & (F2 != 0.0)))
     for du in range(nu):
-        u = ulo + du                                    # [n2][n1]
+        u = ulo + du
         F1 = trapezoid_integral(tau, u - half, u + 1.0 - half)
         okc = (u <= uhi) & (u >= 0) & (u < M) & (F1 != 0.0)
         if not okc.any():
             continue
-        for dv in range(nv):
-            v = vlo + dv                                # [n3][n2][n1]
-            F2 = trapezoid_integral(ts, v - half, v + 1.0 - half)
-            ok = okc[None] & (v <= vhi) & (v >= 0) & (v < N) & (F2 != 0.0)
+        for v, aF2, okv in rows:
+            ok = okc & okv
             if not ok.any():
                 continue
-            uu = np.broadcast_to(u[None], v.shape)[ok]
-            w = (amp * F1[None] * F2)[ok]
-            yield vox[ok], v[ok] * M + uu, w
+            yield pos[ok], v[ok] * M + u[ok], (aF2 * F1)[ok]
+
+
+def _view_weights(geom, view_geom, axial="TT", chunk=1 << 22):
+    """All (voxel, pixel, weight) triples of one view, voxels in chunks of
+    whole slices: voxel index k*n2*n1 + j*n1 + i, pixel index v*M + u."""
+    (n1, n2, n3), _, _ = _grid(geom)
+    per = max(1, chunk // (n1 * n2))
+    jj0, ii0 = np.divmod(np.arange(n1 * n2), n1)
+    for k0 in range(0, n3, per):
+        k1 = min(n3, k0 + per)
+        kk = np.repeat(np.arange(k0, k1), n1 * n2)
+        ii = np.tile(ii0, k1 - k0)
+        jj = np.tile(jj0, k1 - k0)
+        base = k0 * n1 * n2
+        for p, pix, w in _weights(geom, view_geom, ii, jj, kk, axial):
+            yield base + p, pix, w
 
 
 def project(geom, x, views=None, axial="TT"):
@@ -200,3 +217,20 @@ def backproject(geom, b, views=None, axial="TT"):
         for vox, pix, w in _view_weights(geom, vg[view], axial):
             acc += np.bincount(vox, weights=w * b[q][pix], minlength=n1 * n2 * n3)
     return acc.reshape(n3, n2, n1)
+
+
+def backproject_voxels(geom, b, idx, views=None, axial="TT"):
+    """(A_TT^T b) at the listed linear voxel indices (k*n2*n1 + j*n1 + i)."""
+    (n1, n2, n3), _, _ = _grid(geom)
+    M, N = int(geom["det_cols"]), int(geom["det_rows"])
+    vg = _views(geom)
+    lo, hi = (0, len(vg)) if views is None else views
+    b = np.asarray(b, dtype=np.float64).reshape(hi - lo, N * M)
+    idx = np.asarray(idx, dtype=np.int64)
+    kk, rem = np.divmod(idx, n1 * n2)
+    jj, ii = np.divmod(rem, n1)
+    out = np.zeros(len(idx))
+    for q, view in enumerate(range(lo, hi)):
+        for p, pix, w in _weights(geom, vg[view], ii, jj, kk, axial):
+            out += np.bincount(p, weights=w * b[q][pix], minlength=len(idx))
+    return out

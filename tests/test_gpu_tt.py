@@ -121,3 +121,30 @@ def test_options_checked():
     with pytest.raises(_lib.CVPError) as ei:
         cvp.project_batched([x, x.clone()], batch, cvp.TT)
     assert ei.value.status == _lib.CVP_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("name", ["pfeiffer", "long"])
+def test_paper_speed_benchmarks_sampled(name):
+    """The TT projector at the sizes the paper times it (Sec. IV-A, Tables I
+    and II; the same geometries bench.py times): the GPU computes the whole
+    operator, the oracle full views of A x and sampled voxels of A^T b."""
+    if name == "pfeiffer":
+        g = synth.geometry(256, 0.5, 1280, 960, 0.25, 750.0, 1000.0, 100, 198.0)
+        views, nvox = (61,), 1000
+    else:
+        g = synth.geometry((512, 512, 128), 0.5, 512, 512, 1.0, 541.0, 949.0, 720, 360.0)
+        views, nvox = (397,), 500
+    G = cvp.Geometry(g)
+    n3, n2, n1 = G.vol_shape
+    x = synth.uniform_volume(G.vol_shape, seed=97)
+    say("TT", name, "projection")
+    Ax = cvp.project(torch.from_numpy(x).cuda(), G, cvp.TT).cpu().numpy()
+    for v in views:
+        assert_parity(Ax[v], T.project(g, x, views=(v, v + 1))[0], "TT %s A x view %d" % (name, v))
+    del Ax
+    b = synth.uniform_projections(G.proj_shape, seed=98)
+    say("TT", name, "backprojection")
+    Atb = cvp.backproject(torch.from_numpy(b).cuda(), G, cvp.TT).cpu().numpy().ravel()
+    rng = np.random.default_rng(99)
+    idx = np.concatenate([[0, n1 - 1, n1 * n2 * n3 - 1], rng.integers(0, n1 * n2 * n3, size=nvox)])
+    assert_parity(Atb[idx], T.backproject_voxels(g, b, idx), "TT %s A^T b sampled" % name)
