@@ -839,26 +839,43 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
         if (__ballot(ncol > 0) == 0) continue;
         const bool full = vec_rows && (i0 + GW <= G.n1);
 
-        for (int kc = 0; kc < G.n3; kc += kWave) {
-            const int k = kc + lane;
-            const bool kv = k < G.n3;
-            float mu[GW];
-            load_mu(j, i0, k, full, mu);
-            const float kf = (float)k;
-            const float zt = fmaf(kf, a3f, zt0);        // top of voxel k, relative to s3
-            const float zc = zt - 0.5f * a3f;           // centre of voxel k
+        // With cached records each lane takes KP slices (k and k + 64): one
+        // broadcast of a piece record then serves 64 KP voxels.
+        constexpr int KP = TAB ? 2 : 1;
+        for (int kc = 0; kc < G.n3; kc += kWave * KP) {
+            float mu[KP][GW];
+            float kf[KP], zt[KP], zc[KP];
+            bool kv[KP];
+#pragma unroll
+            for (int h = 0; h < KP; ++h) {
+                const int k = kc + h * kWave + lane;
+                kv[h] = k < G.n3;
+                load_mu(j, i0, k, full, mu[h]);
+                kf[h] = (float)k;
+                zt[h] = fmaf(kf[h], a3f, zt0);        // top of voxel k, relative to s3
+                zc[h] = zt[h] - 0.5f * a3f;           // centre of voxel k
+            }
 #pragma unroll
             for (int c = 0; c < GW; ++c) {
                 const int np = __builtin_amdgcn_readlane(ncol, c);
                 if (np == 0) continue;
-                const float m = kv ? mu[c] : 0.0f;
-                if (__ballot(m != 0.0f) == 0) continue;
-                float base = m;
-                if (TT)   // the central ray's |r| (its min(a1/|r1|, a2/|r2|) is in the records)
-                    base = m * sqrtf(fmaf(zc, zc, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rq[0][8]), c))));
-                else if (!EXACT && !raw)
-                    base = m * __builtin_amdgcn_rcpf(fmaf(zc, zc, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rq[0][8]), c))));
-                base = ldexpf(base, sc);
+                float base[KP];
+                bool any = false;
+#pragma unroll
+                for (int h = 0; h < KP; ++h) {
+                    base[h] = kv[h] ? mu[h][c] : 0.0f;
+                    any = any || base[h] != 0.0f;
+                }
+                if (__ballot(any) == 0) continue;
+                const float r8c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rq[0][8]), c));
+#pragma unroll
+                for (int h = 0; h < KP; ++h) {
+                    if (TT)   // the central ray's |r| (its min(a1/|r1|, a2/|r2|) is in the records)
+                        base[h] = base[h] * sqrtf(fmaf(zc[h], zc[h], r8c));
+                    else if (!EXACT && !raw)
+                        base[h] = base[h] * __builtin_amdgcn_rcpf(fmaf(zc[h], zc[h], r8c));
+                    base[h] = ldexpf(base[h], sc);
+                }
                 for (int p = 0; p < np; ++p) {
                     const int src = c + 16 * (p & 3);
                     float r[kRecFloats];
@@ -872,22 +889,25 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
                             r[e] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rq[PASSES - 1][e]), src));
                     }
                     const int u = __float_as_int(r[0]);
-                    const float coef = base * r[1];
-                    const float Yh = fmaf(-kf, r[4], r[2]);
-                    const float Yl = fmaf(-kf, r[5], r[3]);
                     const float beta = r[6], rho = r[7];
                     unsigned long long *bcol = bins + (u - u0) * Npad;
-                    int vlo0, vhi0;
-                    row_range_unclipped<EC>(Yh + Yl, beta, r[10], c2f, vlo0, vhi0);
-                    if constexpr (TT) {
-                        float Ylu, Ybld, eu, ed;
-                        tt_ramps(Yh, Yl, r[5], beta, rho, c2f, Ylu, Ybld, eu, ed);
-                        sweep_rows_tt(vlo0, vhi0, max(vlo0, 0), min(vhi0, G.N - 1), Yh, Ylu, Yh + r[4], Ybld, eu,
-                                      ed, coef, bcol);
-                    } else {
-                        // bottom face Y(k - 1): high part Yh + bh (exact on the 2^-10 grid), low part Yl + bl
-                        sweep_rows<EC, EXACT>(vlo0, vhi0, max(vlo0, 0), min(vhi0, G.N - 1), Yh, Yl, Yh + r[4],
-                                              Yl + r[5], beta, rho, c2f, coef, raw, zt, r[11], r[9], bcol);
+#pragma unroll
+                    for (int h = 0; h < KP; ++h) {
+                        const float coef = base[h] * r[1];
+                        const float Yh = fmaf(-kf[h], r[4], r[2]);
+                        const float Yl = fmaf(-kf[h], r[5], r[3]);
+                        int vlo0, vhi0;
+                        row_range_unclipped<EC>(Yh + Yl, beta, r[10], c2f, vlo0, vhi0);
+                        if constexpr (TT) {
+                            float Ylu, Ybld, eu, ed;
+                            tt_ramps(Yh, Yl, r[5], beta, rho, c2f, Ylu, Ybld, eu, ed);
+                            sweep_rows_tt(vlo0, vhi0, max(vlo0, 0), min(vhi0, G.N - 1), Yh, Ylu, Yh + r[4], Ybld,
+                                          eu, ed, coef, bcol);
+                        } else {
+                            // bottom face Y(k - 1): high part Yh + bh (exact on the 2^-10 grid), low part Yl + bl
+                            sweep_rows<EC, EXACT>(vlo0, vhi0, max(vlo0, 0), min(vhi0, G.N - 1), Yh, Yl, Yh + r[4],
+                                                  Yl + r[5], beta, rho, c2f, coef, raw, zt[h], r[11], r[9], bcol);
+                        }
                     }
                 }
             }
