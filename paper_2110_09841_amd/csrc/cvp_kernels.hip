@@ -1002,7 +1002,8 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
     constexpr int KP = kBackPasses;
     const int i0 = q * GW;
     const int k0 = kch * kWave * kp;
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
     const int kmax = min(k0 + kWave * kp, G.n3) - 1;
 
     // One record pass covers RV of the wave's views (w, w + 4, ...): LPV
@@ -1130,6 +1131,11 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
         if (r > 0) {
             wu0 = npc[GW]; wu1 = npc[GW + 1]; wv0 = npc[GW + 2]; wv1 = npc[GW + 3];
         }
+        // the window bounds are the same in every lane
+        wu0 = __builtin_amdgcn_readfirstlane(wu0);
+        wu1 = __builtin_amdgcn_readfirstlane(wu1);
+        wv0 = __builtin_amdgcn_readfirstlane(wv0);
+        wv1 = __builtin_amdgcn_readfirstlane(wv1);
         if (wu1 < wu0 || wv1 < wv0) continue;
         // one spare row each side absorbs FP32 rounding of intermediate k
         wv0 = max(wv0 - 1, 0);
@@ -1151,44 +1157,56 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
         }
         wave_sync();
 
-        // the gather, with the window read from LDS (WIN) or global memory
+        // the gather, with the window read from LDS (WIN) or global memory.
+        // Each piece record is read once and serves the kp passes; a voxel's
+        // pieces are summed in piece order either way.
         auto gather = [&](auto winTag) {
         constexpr bool WIN = decltype(winTag)::value;
+        bool live[KP], kv[KP];
+        float kf[KP], zt[KP];
 #pragma unroll
         for (int ps = 0; ps < KP; ++ps) {
-        if (ps >= kp || k0 + ps * kWave >= G.n3) break;   // unused pass
-        const int k = k0 + ps * kWave + lane;
-        const bool kv = k < G.n3;
-        const float kf = (float)k;
-        const float zt = fmaf(kf, a3f, (float)(G.x3lo + G.a3 - V.s3));
-        const float zc = zt - 0.5f * a3f;
+            live[ps] = ps < kp && k0 + ps * kWave < G.n3;   // uniform
+            const int k = k0 + ps * kWave + lane;
+            kv[ps] = k < G.n3;
+            kf[ps] = (float)k;
+            zt[ps] = fmaf(kf[ps], a3f, (float)(G.x3lo + G.a3 - V.s3));
+        }
 #pragma unroll
         for (int c = 0; c < GW; ++c) {
-            const int np = npc[c];
+            const int np = __builtin_amdgcn_readfirstlane(npc[c]);
             if (np == 0) continue;
             const float *rc = recv + c * PMAX * kRecFloats;
-            float base = 1.0f;
-            if (TT) base = sqrtf(fmaf(zc, zc, rc[8]));
-            else if (!EXACT && !raw) base = __builtin_amdgcn_rcpf(fmaf(zc, zc, rc[8]));
-            float a = 0.0f;
+            float base[KP], a[KP];
+#pragma unroll
+            for (int ps = 0; ps < KP; ++ps) {
+                const float zc = zt[ps] - 0.5f * a3f;
+                base[ps] = 1.0f;
+                if (TT) base[ps] = sqrtf(fmaf(zc, zc, rc[8]));
+                else if (!EXACT && !raw) base[ps] = __builtin_amdgcn_rcpf(fmaf(zc, zc, rc[8]));
+                a[ps] = 0.0f;
+            }
             for (int p = 0; p < np; ++p) {
                 const float4 r0 = *reinterpret_cast<const float4 *>(rc + p * kRecFloats);
                 const float4 r1 = *reinterpret_cast<const float4 *>(rc + p * kRecFloats + 4);
                 const float4 r2 = *reinterpret_cast<const float4 *>(rc + p * kRecFloats + 8);
-                const int u = __float_as_int(r0.x);
-                const float Yh = fmaf(-kf, r1.x, r0.z);
-                const float Yl = fmaf(-kf, r1.y, r0.w);
-                const float Ybh = Yh + r1.x, Ybl = Yl + r1.y;   // bottom face Y(k - 1), exact high part
+                const int u = __builtin_amdgcn_readfirstlane(__float_as_int(r0.x));
                 const float beta = r1.z, rho = r1.w, rho4 = 4.0f * r1.w;
+                const bool ends = !EC || rho < 0.9f;
+                const float *wcol = win + (u - wu0) * Hp - wv0;
+#pragma unroll
+                for (int ps = 0; ps < KP; ++ps) {
+                if (!live[ps]) continue;
+                const float Yh = fmaf(-kf[ps], r1.x, r0.z);
+                const float Yl = fmaf(-kf[ps], r1.y, r0.w);
+                const float Ybh = Yh + r1.x, Ybl = Yl + r1.y;   // bottom face Y(k - 1), exact high part
                 // rows clipped to the detector and the window; as in the
                 // projection, Phi at the first and last boundaries of the
                 // unclipped range is exactly 0
                 int vlo0, vhi0;
                 row_range_unclipped<EC>(Yh + Yl, beta, r2.z, c2f, vlo0, vhi0);
-                const bool ends = !EC || rho < 0.9f;
                 const int vlo = max(max(vlo0, 0), wv0);
-                const int vhi = kv ? min(min(vhi0, G.N - 1), wv1) : vlo - 1;
-                const float *wcol = win + (u - wu0) * Hp - wv0;
+                const int vhi = kv[ps] ? min(min(vhi0, G.N - 1), wv1) : vlo - 1;
                 if constexpr (TT) {
                     // the TT axial footprint's row integrals (Phi is exactly 0
                     // at the ends of the unclipped range, computed or not)
@@ -1210,10 +1228,10 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
                         ap = fmaf(psip - phin, val, ap);
                         psip = mn + phin;
                     }
-                    a = fmaf(base * r0.y, ap, a);
-                    continue;
-                }
+                    a[ps] = fmaf(base[ps] * r0.y, ap, a[ps]);
+                } else {
                 // boundaries as in sweep_rows; row weight m(t) + Phi(t) - Phi(t + 1)
+                const float zt_ = zt[ps];
                 const float tb = (float)vlo - 0.5f;
                 float d = Yh - tb;
                 float d0 = Ybh - tb;
@@ -1233,7 +1251,7 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
                     if (EXACT && !raw) {
                         float mm = 0.5f * (fmaxf(0.0f, -s1p) + fminf(beta, -s1n));
                         mm = fminf(fmaxf(mm, 0.0f), beta);
-                        const float zb = fmaf(-mm, r2.y, zt);
+                        const float zb = fmaf(-mm, r2.y, zt_);
                         w *= __builtin_amdgcn_rcpf(fmaf(zb, zb, r2.w));
                     }
                     ap = fmaf(w, val, ap);
@@ -1258,7 +1276,7 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
                         if (EXACT && !raw) {
                             float mm = 0.5f * (fmaxf(0.0f, -s1p) + fminf(beta, -s1n));
                             mm = fminf(fmaxf(mm, 0.0f), beta);
-                            const float zb = fmaf(-mm, r2.y, zt);
+                            const float zb = fmaf(-mm, r2.y, zt_);
                             w *= __builtin_amdgcn_rcpf(fmaf(zb, zb, r2.w));
                         }
                         ap = fmaf(w, *last, ap);
@@ -1271,10 +1289,13 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
                         row(val);
                     }
                 }
-                a = fmaf(base * r0.y, ap, a);
+                a[ps] = fmaf(base[ps] * r0.y, ap, a[ps]);
+                }
+                }
             }
-            acc[ps][c] += a;
-        }
+#pragma unroll
+            for (int ps = 0; ps < KP; ++ps)
+                if (live[ps]) acc[ps][c] += a[ps];
         }
         };
         if (useWin) gather(std::true_type{});
