@@ -1003,7 +1003,7 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
     const int i0 = q * GW;
     const int k0 = kch * kWave * kp;
     const int tid = threadIdx.x, lane = tid & (kWave - 1);
-    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int wave = TAB ? __builtin_amdgcn_readfirstlane(tid / kWave) : tid / kWave;
     const int kmax = min(k0 + kWave * kp, G.n3) - 1;
 
     // One record pass covers RV of the wave's views (w, w + 4, ...): LPV
@@ -1131,11 +1131,13 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
         if (r > 0) {
             wu0 = npc[GW]; wu1 = npc[GW + 1]; wv0 = npc[GW + 2]; wv1 = npc[GW + 3];
         }
-        // the window bounds are the same in every lane
-        wu0 = __builtin_amdgcn_readfirstlane(wu0);
-        wu1 = __builtin_amdgcn_readfirstlane(wu1);
-        wv0 = __builtin_amdgcn_readfirstlane(wv0);
-        wv1 = __builtin_amdgcn_readfirstlane(wv1);
+        if constexpr (TAB) {
+            // the window bounds are the same in every lane
+            wu0 = __builtin_amdgcn_readfirstlane(wu0);
+            wu1 = __builtin_amdgcn_readfirstlane(wu1);
+            wv0 = __builtin_amdgcn_readfirstlane(wv0);
+            wv1 = __builtin_amdgcn_readfirstlane(wv1);
+        }
         if (wu1 < wu0 || wv1 < wv0) continue;
         // one spare row each side absorbs FP32 rounding of intermediate k
         wv0 = max(wv0 - 1, 0);
@@ -1158,148 +1160,196 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
         wave_sync();
 
         // the gather, with the window read from LDS (WIN) or global memory.
-        // Each piece record is read once and serves the kp passes; a voxel's
-        // pieces are summed in piece order either way.
-        auto gather = [&](auto winTag) {
+        // piece(): the row sum of one piece for one voxel (lanes over k),
+        // times the piece's coefficient by the caller.
+        auto gather = [&](auto winTag, auto npTag) {
         constexpr bool WIN = decltype(winTag)::value;
-        bool live[KP], kv[KP];
-        float kf[KP], zt[KP];
-#pragma unroll
-        for (int ps = 0; ps < KP; ++ps) {
-            live[ps] = ps < kp && k0 + ps * kWave < G.n3;   // uniform
-            const int k = k0 + ps * kWave + lane;
-            kv[ps] = k < G.n3;
-            kf[ps] = (float)k;
-            zt[ps] = fmaf(kf[ps], a3f, (float)(G.x3lo + G.a3 - V.s3));
-        }
-#pragma unroll
-        for (int c = 0; c < GW; ++c) {
-            const int np = __builtin_amdgcn_readfirstlane(npc[c]);
-            if (np == 0) continue;
-            const float *rc = recv + c * PMAX * kRecFloats;
-            float base[KP], a[KP];
-#pragma unroll
-            for (int ps = 0; ps < KP; ++ps) {
-                const float zc = zt[ps] - 0.5f * a3f;
-                base[ps] = 1.0f;
-                if (TT) base[ps] = sqrtf(fmaf(zc, zc, rc[8]));
-                else if (!EXACT && !raw) base[ps] = __builtin_amdgcn_rcpf(fmaf(zc, zc, rc[8]));
-                a[ps] = 0.0f;
-            }
-            for (int p = 0; p < np; ++p) {
-                const float4 r0 = *reinterpret_cast<const float4 *>(rc + p * kRecFloats);
-                const float4 r1 = *reinterpret_cast<const float4 *>(rc + p * kRecFloats + 4);
-                const float4 r2 = *reinterpret_cast<const float4 *>(rc + p * kRecFloats + 8);
-                const int u = __builtin_amdgcn_readfirstlane(__float_as_int(r0.x));
-                const float beta = r1.z, rho = r1.w, rho4 = 4.0f * r1.w;
-                const bool ends = !EC || rho < 0.9f;
-                const float *wcol = win + (u - wu0) * Hp - wv0;
-#pragma unroll
-                for (int ps = 0; ps < KP; ++ps) {
-                if (!live[ps]) continue;
-                const float Yh = fmaf(-kf[ps], r1.x, r0.z);
-                const float Yl = fmaf(-kf[ps], r1.y, r0.w);
-                const float Ybh = Yh + r1.x, Ybl = Yl + r1.y;   // bottom face Y(k - 1), exact high part
-                // rows clipped to the detector and the window; as in the
-                // projection, Phi at the first and last boundaries of the
-                // unclipped range is exactly 0
-                int vlo0, vhi0;
-                row_range_unclipped<EC>(Yh + Yl, beta, r2.z, c2f, vlo0, vhi0);
-                const int vlo = max(max(vlo0, 0), wv0);
-                const int vhi = kv[ps] ? min(min(vhi0, G.N - 1), wv1) : vlo - 1;
-                if constexpr (TT) {
-                    // the TT axial footprint's row integrals (Phi is exactly 0
-                    // at the ends of the unclipped range, computed or not)
-                    float Ylu, Ybld, eu, ed;
-                    tt_ramps(Yh, Yl, r1.y, beta, rho, c2f, Ylu, Ybld, eu, ed);
-                    const float iu = __builtin_amdgcn_rcpf(fmaf(4.0f, eu, 1e-30f));
-                    const float id = __builtin_amdgcn_rcpf(fmaf(4.0f, ed, 1e-30f));
-                    const float tb = (float)vlo - 0.5f;
-                    float d = Yh - tb, d0 = Ybh - tb;
-                    float s1, mp, phip;
-                    boundary_tt<true>(d, Ylu, d0, Ybld, eu, ed, iu, id, s1, mp, phip);
-                    float psip = mp + phip, ap = 0.0f;
-                    for (int v = vlo; v <= vhi; ++v) {
-                        d -= 1.0f;
-                        d0 -= 1.0f;
-                        float mn, phin;
-                        boundary_tt<true>(d, Ylu, d0, Ybld, eu, ed, iu, id, s1, mn, phin);
-                        const float val = WIN ? wcol[v] : pv[(size_t)v * G.M + u];
-                        ap = fmaf(psip - phin, val, ap);
-                        psip = mn + phin;
-                    }
-                    a[ps] = fmaf(base[ps] * r0.y, ap, a[ps]);
-                } else {
-                // boundaries as in sweep_rows; row weight m(t) + Phi(t) - Phi(t + 1)
-                const float zt_ = zt[ps];
+        constexpr int NP = decltype(npTag)::value;   // passes (a bound for the second form)
+        auto piece = [&](const float4 &r0, const float4 &r1, const float4 &r2, const int u, const float *wcol,
+                         const float kf, const float zt, const bool kv) -> float {
+            const float Yh = fmaf(-kf, r1.x, r0.z);
+            const float Yl = fmaf(-kf, r1.y, r0.w);
+            const float Ybh = Yh + r1.x, Ybl = Yl + r1.y;   // bottom face Y(k - 1), exact high part
+            const float beta = r1.z, rho = r1.w, rho4 = 4.0f * r1.w;
+            // rows clipped to the detector and the window; as in the
+            // projection, Phi at the first and last boundaries of the
+            // unclipped range is exactly 0
+            int vlo0, vhi0;
+            row_range_unclipped<EC>(Yh + Yl, beta, r2.z, c2f, vlo0, vhi0);
+            const bool ends = !EC || rho < 0.9f;
+            const int vlo = max(max(vlo0, 0), wv0);
+            const int vhi = kv ? min(min(vhi0, G.N - 1), wv1) : vlo - 1;
+            if constexpr (TT) {
+                // the TT axial footprint's row integrals (Phi is exactly 0
+                // at the ends of the unclipped range, computed or not)
+                float Ylu, Ybld, eu, ed;
+                tt_ramps(Yh, Yl, r1.y, beta, rho, c2f, Ylu, Ybld, eu, ed);
+                const float iu = __builtin_amdgcn_rcpf(fmaf(4.0f, eu, 1e-30f));
+                const float id = __builtin_amdgcn_rcpf(fmaf(4.0f, ed, 1e-30f));
                 const float tb = (float)vlo - 0.5f;
-                float d = Yh - tb;
-                float d0 = Ybh - tb;
-                float tc = tb - c2f;
-                float s1p, mp, phip;
-                if (vlo != vlo0 || !ends) boundary<EC>(d, Yl, d0, Ybl, tc, rho, rho4, s1p, mp, phip);
-                else boundary<false>(d, Yl, d0, Ybl, tc, rho, rho4, s1p, mp, phip);
-                float psip = mp + phip;
-                float ap = 0.0f;          // sum of row weight [1/r^2] val_v; times coef below
-                auto row = [&](float val) {
+                float d = Yh - tb, d0 = Ybh - tb;
+                float s1, mp, phip;
+                boundary_tt<true>(d, Ylu, d0, Ybld, eu, ed, iu, id, s1, mp, phip);
+                float psip = mp + phip, ap = 0.0f;
+                for (int v = vlo; v <= vhi; ++v) {
+                    d -= 1.0f;
+                    d0 -= 1.0f;
+                    float mn, phin;
+                    boundary_tt<true>(d, Ylu, d0, Ybld, eu, ed, iu, id, s1, mn, phin);
+                    const float val = WIN ? wcol[v] : pv[(size_t)v * G.M + u];
+                    ap = fmaf(psip - phin, val, ap);
+                    psip = mn + phin;
+                }
+                return ap;
+            }
+            // boundaries as in sweep_rows; row weight m(t) + Phi(t) - Phi(t + 1)
+            const float tb = (float)vlo - 0.5f;
+            float d = Yh - tb;
+            float d0 = Ybh - tb;
+            float tc = tb - c2f;
+            float s1p, mp, phip;
+            if (vlo != vlo0 || !ends) boundary<EC>(d, Yl, d0, Ybl, tc, rho, rho4, s1p, mp, phip);
+            else boundary<false>(d, Yl, d0, Ybl, tc, rho, rho4, s1p, mp, phip);
+            float psip = mp + phip;
+            float ap = 0.0f;          // sum of row weight [1/r^2] val_v
+            auto row = [&](float val) {
+                d -= 1.0f;
+                d0 -= 1.0f;
+                tc += 1.0f;
+                float s1n, mn, phin;
+                boundary<EC>(d, Yl, d0, Ybl, tc, rho, rho4, s1n, mn, phin);
+                float w = psip - phin;
+                if (EXACT && !raw) {
+                    float mm = 0.5f * (fmaxf(0.0f, -s1p) + fminf(beta, -s1n));
+                    mm = fminf(fmaxf(mm, 0.0f), beta);
+                    const float zb = fmaf(-mm, r2.y, zt);
+                    w *= __builtin_amdgcn_rcpf(fmaf(zb, zb, r2.w));
+                }
+                ap = fmaf(w, val, ap);
+                psip = mn + phin;
+                s1p = s1n;
+            };
+            if (WIN) {
+                const float *const last = wcol + vhi;
+                for (const float *q = wcol + vlo; q < last; ++q) row(*q);
+                if (vlo <= vhi) {
+                    // last row: Phi at the last boundary of the unclipped
+                    // range is exactly 0
                     d -= 1.0f;
                     d0 -= 1.0f;
                     tc += 1.0f;
-                    float s1n, mn, phin;
-                    boundary<EC>(d, Yl, d0, Ybl, tc, rho, rho4, s1n, mn, phin);
+                    float s1n = d + Yl, phin = 0.0f;
+                    if (vhi != vhi0 || !ends) {
+                        float mn;
+                        boundary<EC>(d, Yl, d0, Ybl, tc, rho, rho4, s1n, mn, phin);
+                    }
                     float w = psip - phin;
                     if (EXACT && !raw) {
                         float mm = 0.5f * (fmaxf(0.0f, -s1p) + fminf(beta, -s1n));
                         mm = fminf(fmaxf(mm, 0.0f), beta);
-                        const float zb = fmaf(-mm, r2.y, zt_);
+                        const float zb = fmaf(-mm, r2.y, zt);
                         w *= __builtin_amdgcn_rcpf(fmaf(zb, zb, r2.w));
                     }
-                    ap = fmaf(w, val, ap);
-                    psip = mn + phin;
-                    s1p = s1n;
-                };
-                if (WIN) {
-                    const float *const last = wcol + vhi;
-                    for (const float *q = wcol + vlo; q < last; ++q) row(*q);
-                    if (vlo <= vhi) {
-                        // last row: Phi at the last boundary of the
-                        // unclipped range is exactly 0
-                        d -= 1.0f;
-                        d0 -= 1.0f;
-                        tc += 1.0f;
-                        float s1n = d + Yl, phin = 0.0f;
-                        if (vhi != vhi0 || !ends) {
-                            float mn;
-                            boundary<EC>(d, Yl, d0, Ybl, tc, rho, rho4, s1n, mn, phin);
-                        }
-                        float w = psip - phin;
-                        if (EXACT && !raw) {
-                            float mm = 0.5f * (fmaxf(0.0f, -s1p) + fminf(beta, -s1n));
-                            mm = fminf(fmaxf(mm, 0.0f), beta);
-                            const float zb = fmaf(-mm, r2.y, zt_);
-                            w *= __builtin_amdgcn_rcpf(fmaf(zb, zb, r2.w));
-                        }
-                        ap = fmaf(w, *last, ap);
-                    }
-                } else {
-                    for (int v = vlo; v <= vhi; ++v) {
-                        const size_t off = (size_t)v * G.M + u;
-                        float val = pv[off];
-                        if (sgv) val *= sgv[off];
-                        row(val);
-                    }
+                    ap = fmaf(w, *last, ap);
                 }
-                a[ps] = fmaf(base[ps] * r0.y, ap, a[ps]);
-                }
+            } else {
+                for (int v = vlo; v <= vhi; ++v) {
+                    const size_t off = (size_t)v * G.M + u;
+                    float val = pv[off];
+                    if (sgv) val *= sgv[off];
+                    row(val);
                 }
             }
+            return ap;
+        };
+        auto record = [&](const float *rc, int p, float4 &r0, float4 &r1, float4 &r2) {
+            r0 = *reinterpret_cast<const float4 *>(rc + p * kRecFloats);
+            r1 = *reinterpret_cast<const float4 *>(rc + p * kRecFloats + 4);
+            r2 = *reinterpret_cast<const float4 *>(rc + p * kRecFloats + 8);
+        };
+        auto base_of = [&](const float *rc, float kf) {
+            const float zc = fmaf(kf, a3f, (float)(G.x3lo + G.a3 - V.s3)) - 0.5f * a3f;
+            float base = 1.0f;
+            if (TT) base = sqrtf(fmaf(zc, zc, rc[8]));
+            else if (!EXACT && !raw) base = __builtin_amdgcn_rcpf(fmaf(zc, zc, rc[8]));
+            return base;
+        };
+        if constexpr (TAB && NP > 1) {
+            // Each piece record is read once and serves the NP passes; the
+            // piece count, u and the window bounds are the same in every
+            // lane (scalar registers).  A voxel's pieces are summed in piece
+            // order, as below.  (With one pass the per-lane form below is
+            // faster.)
+            bool live[NP], kv[NP];
+            float kf[NP], zt[NP];
 #pragma unroll
-            for (int ps = 0; ps < KP; ++ps)
-                if (live[ps]) acc[ps][c] += a[ps];
+            for (int ps = 0; ps < NP; ++ps) {
+                live[ps] = k0 + ps * kWave < G.n3;   // uniform
+                const int k = k0 + ps * kWave + lane;
+                kv[ps] = k < G.n3;
+                kf[ps] = (float)k;
+                zt[ps] = fmaf(kf[ps], a3f, (float)(G.x3lo + G.a3 - V.s3));
+            }
+#pragma unroll
+            for (int c = 0; c < GW; ++c) {
+                const int np = __builtin_amdgcn_readfirstlane(npc[c]);
+                if (np == 0) continue;
+                const float *rc = recv + c * PMAX * kRecFloats;
+                float base[NP], a[NP];
+#pragma unroll
+                for (int ps = 0; ps < NP; ++ps) {
+                    base[ps] = base_of(rc, kf[ps]);
+                    a[ps] = 0.0f;
+                }
+                for (int p = 0; p < np; ++p) {
+                    float4 r0, r1, r2;
+                    record(rc, p, r0, r1, r2);
+                    const int u = __builtin_amdgcn_readfirstlane(__float_as_int(r0.x));
+                    const float *wcol = win + (u - wu0) * Hp - wv0;
+#pragma unroll
+                    for (int ps = 0; ps < NP; ++ps)
+                        if (live[ps])
+                            a[ps] = fmaf(base[ps] * r0.y, piece(r0, r1, r2, u, wcol, kf[ps], zt[ps], kv[ps]), a[ps]);
+                }
+#pragma unroll
+                for (int ps = 0; ps < NP; ++ps)
+                    if (live[ps]) acc[ps][c] += a[ps];
+            }
+        } else {
+#pragma unroll
+            for (int ps = 0; ps < NP; ++ps) {
+                if (ps >= kp || k0 + ps * kWave >= G.n3) break;   // unused pass
+                const int k = k0 + ps * kWave + lane;
+                const bool kv = k < G.n3;
+                const float kf = (float)k;
+                const float zt = fmaf(kf, a3f, (float)(G.x3lo + G.a3 - V.s3));
+#pragma unroll
+                for (int c = 0; c < GW; ++c) {
+                    const int np = npc[c];
+                    if (np == 0) continue;
+                    const float *rc = recv + c * PMAX * kRecFloats;
+                    const float base = base_of(rc, kf);
+                    float a = 0.0f;
+                    for (int p = 0; p < np; ++p) {
+                        float4 r0, r1, r2;
+                        record(rc, p, r0, r1, r2);
+                        const int u = __float_as_int(r0.x);
+                        a = fmaf(base * r0.y, piece(r0, r1, r2, u, win + (u - wu0) * Hp - wv0, kf, zt, kv), a);
+                    }
+                    acc[ps][c] += a;
+                }
+            }
         }
         };
-        if (useWin) gather(std::true_type{});
-        else gather(std::false_type{});
+        using P1 = std::integral_constant<int, 1>;
+        using P2 = std::integral_constant<int, KP>;
+        if (TAB && kp == 1) {
+            if (useWin) gather(std::true_type{}, P1{});
+            else gather(std::false_type{}, P1{});
+        } else {
+            if (useWin) gather(std::true_type{}, P2{});
+            else gather(std::false_type{}, P2{});
+        }
         wave_sync();
         }
     }
