@@ -471,6 +471,12 @@ cvp_status cvp_synth_add_gaussian(float *d_out, int64_t n, float sigma, uint64_t
  *   bp_passes       64-voxel passes per backprojection stack (1 or 2): two
  *                   passes share each view's piece records and detector
  *                   window, one keeps the window small enough for LDS.
+ *   bp_workgroups_per_cu  with cached records (cvp_geometry_cache_records):
+ *                   backprojection workgroups the LDS budget is sized for, 4
+ *                   (40 KB each) or 3 (52 KB each, larger detector windows);
+ *                   the default is 4 for 4-piece records, 3 for 8-piece ones.
+ *                   Records computed in the kernel always take 52 KB (3); it
+ *                   is reported as such.
  * cvp_geometry_get_launch reports the plan in use (the planner's default
  * after cvp_geometry_from_views).  cvp_geometry_set_launch replaces it; a zero
  * field restores the default for that field.  Errors: CVP_E_INVALID (NULL or a
@@ -486,6 +492,7 @@ typedef struct {
     int32_t proj_band_cols;
     int32_t bp_stack_cols;
     int32_t bp_passes;
+    int32_t bp_workgroups_per_cu;
 } cvp_launch;
 
 cvp_status cvp_geometry_get_launch(const cvp_geometry *g, cvp_launch *out);

@@ -62,7 +62,8 @@ def autotune(geom: Geometry, opts: Options, bands=DEFAULT_BANDS, stacks=DEFAULT_
             table = json.load(f)
         if key in table:
             rec = table[key]
-            geom.set_launch(rec["proj_band_cols"], rec["bp_stack_cols"], rec["bp_passes"])
+            geom.set_launch(rec["proj_band_cols"], rec["bp_stack_cols"], rec["bp_passes"],
+                            rec.get("bp_workgroups_per_cu", 0))
             return dict(rec, cached=True)
     g = torch.Generator(device=geom.device).manual_seed(seed)
     x = torch.rand(geom.vol_shape, generator=g, device=geom.device)
@@ -79,21 +80,25 @@ def autotune(geom: Geometry, opts: Options, bands=DEFAULT_BANDS, stacks=DEFAULT_
         p_ms[u] = _time(lambda: project(x, geom, opts, out=p_out), reps)
         if log:
             log("projection band %d: %.2f ms" % (u, p_ms[u]))
+    # with cached records the LDS budget (workgroups per CU) is a choice too
+    wpcs = (4, 3) if geom.records_cached else (0,)
     for gw in stacks:
         for kp in passes:
-            try:
-                geom.set_launch(default[0], gw, kp)
-            except _lib.CVPError:
-                continue
-            b_ms[(gw, kp)] = _time(lambda: backproject(b, geom, opts, out=v_out), reps)
-            if log:
-                log("backprojection stack %d, %d passes: %.2f ms" % (gw, kp, b_ms[(gw, kp)]))
+            for wpc in wpcs:
+                try:
+                    geom.set_launch(default[0], gw, kp, wpc)
+                except _lib.CVPError:
+                    continue
+                b_ms[(gw, kp, wpc)] = _time(lambda: backproject(b, geom, opts, out=v_out), reps)
+                if log:
+                    log("backprojection stack %d, %d passes, %d per CU: %.2f ms" % (gw, kp, wpc, b_ms[(gw, kp, wpc)]))
     best_u = min(p_ms, key=p_ms.get) if p_ms else default[0]
-    best_gw, best_kp = min(b_ms, key=b_ms.get) if b_ms else (default[1], default[2])
-    geom.set_launch(best_u, best_gw, best_kp)
-    rec = {"proj_band_cols": best_u, "bp_stack_cols": best_gw, "bp_passes": best_kp, "default": list(default),
+    best_gw, best_kp, best_wpc = min(b_ms, key=b_ms.get) if b_ms else (default[1], default[2], 0)
+    geom.set_launch(best_u, best_gw, best_kp, best_wpc)
+    rec = {"proj_band_cols": best_u, "bp_stack_cols": best_gw, "bp_passes": best_kp, "bp_workgroups_per_cu": best_wpc,
+           "default": list(default),
            "project_ms": {str(k): v for k, v in p_ms.items()},
-           "backproject_ms": {"%d/%d" % k: v for k, v in b_ms.items()}}
+           "backproject_ms": {("%d/%d/%d" % k if k[2] else "%d/%d" % k[:2]): v for k, v in b_ms.items()}}
     if cache:
         table = {}
         if os.path.exists(cache):

@@ -21,11 +21,18 @@ constexpr size_t kLdsBudget = 30 * 1024;   // default projection plans: five wor
 constexpr size_t kBackLdsBudget = 52 * 1024;   // backprojection windows: three workgroups per CU
 constexpr size_t kBackLdsBudgetWide = 80 * 1024;   // records of up to kPmaxWide pieces per column: two per CU
 constexpr size_t kBackLdsBudgetCached = 40 * 1024;   // cached records (no FP64 stage, ~105 VGPRs): four per CU
+// cached records, three per CU and larger windows: the default for 8-piece
+// records (the 16-problem batch's single launches: 450 against 348 ms at four
+// per CU); the autotuner may choose either budget for a geometry
 constexpr size_t kLdsMax = 156 * 1024;      // any plan: one workgroup per CU at worst
+// LDS the persistent batched kernels hold besides their plan's (the work-item
+// slot, one 512-byte allocation granule): their plans leave it out of the
+// budget, or four 40 KB workgroups would not fit a CU's 160 KB
+constexpr size_t kBatchStaticLds = 512;
 constexpr size_t kLdsBatchMax = kLdsMax;
 bool plan_projection(int N, int n2, int M, int nviews, int pmax, int force_u, ProjLaunch &L);
 bool plan_backprojection(const DevGeom &G, int pmax, double zabs, double Dmin, int force_gw,
-                         int force_kp, BackLaunch &L, bool cached = false);
+                         int force_kp, BackLaunch &L, bool cached = false, size_t reserve = 0, int wpc = 0);
 }
 using cvp::kLdsBudget;
 
@@ -42,6 +49,7 @@ struct cvp_geometry {
     int pmax = 4;                    // pieces per column the kernels keep (4, 8 or kPmaxWide)
     double wone_tt = 0.0, wsum_tt = 0.0;   // fixed-point bounds of the TT projector's weights
     cvp::BackLaunch blc{};           // backprojection plan of the cached-record kernels
+    int bp_wpc = 0;                  // requested workgroups per CU of that plan (0: default)
     float *d_rtab = nullptr;         // cached piece records (cvp_geometry_cache_records)
     int *d_rtab_n = nullptr;
     int64_t rtab_bytes = 0;
@@ -139,7 +147,7 @@ bool plan_projection(int N, int n2, int M, int nviews, int pmax, int force_u, Pr
 // estimated detector window fits the per-wave LDS window (force_gw > 0 and
 // force_kp > 0 fix them).
 bool plan_backprojection(const DevGeom &G, int pmax, double zabs, double Dmin, int force_gw,
-                         int force_kp, BackLaunch &L, bool cached)
+                         int force_kp, BackLaunch &L, bool cached, size_t reserve, int wpc)
 {
     const double mag = G.f / Dmin;
     // (stack width, passes) by stack area; the first whose estimated window
@@ -147,27 +155,40 @@ bool plan_backprojection(const DevGeom &G, int pmax, double zabs, double Dmin, i
     // are then read from global memory)
     // (wide footprints: records of kPmaxWide pieces, 4-column stacks only)
     static const int cands[6][2] = {{16, 2}, {16, 1}, {8, 2}, {8, 1}, {4, 2}, {4, 1}};
+    // the first candidate whose window fits the budget (true), else the last
+    // admissible one (false), gw = 0 if none is
+    auto choose = [&](size_t budget, int &gw, int &kp, int &cap) {
+        gw = kp = cap = 0;
+        for (const auto &cd : cands) {
+            const int cand = cd[0], ckp = cd[1];
+            if ((force_gw > 0 && cand != force_gw) || (force_kp > 0 && ckp != force_kp)) continue;
+            if (pmax > 8 && cand != 4) continue;
+            const size_t rec = (size_t)back_views_per_pass(cand, pmax) * back_rec_floats(cand, pmax);
+            if (rec * kWaves * 4 >= budget) continue;
+            const int c = (int)((budget / (kWaves * 4) - rec) / 4 * 4);
+            if (!cached && c < kBackPasses * cand * 64) continue;   // the window area also parks the accumulators
+            if (c < 1024) continue;
+            const double wu = std::hypot(cand * G.a1, G.a2) * mag / G.b1 + pmax + 2;
+            const double zspan = std::hypot(cand * G.a1, G.a2);
+            const double wv = 64 * ckp * G.a3 * mag / G.b2 + zabs * (G.f / G.b2) * zspan / (Dmin * Dmin) + 6;
+            gw = cand;
+            kp = ckp;
+            cap = c;
+            if (wu * ((int)wv | 1) <= c) return true;
+        }
+        return false;
+    };
     // with cached records the kernel needs no FP64 stage and parks nothing:
-    // a smaller budget lets four workgroups share a compute unit
-    const size_t budget = pmax > 8 ? kBackLdsBudgetWide : cached ? kBackLdsBudgetCached : kBackLdsBudget;
-    int gw = 0, kp = 0, cap = 0;
-    for (const auto &cd : cands) {
-        const int cand = cd[0], ckp = cd[1];
-        if ((force_gw > 0 && cand != force_gw) || (force_kp > 0 && ckp != force_kp)) continue;
-        if (pmax > 8 && cand != 4) continue;
-        const size_t rec = (size_t)back_views_per_pass(cand, pmax) * back_rec_floats(cand, pmax);
-        if (rec * kWaves * 4 >= budget) continue;
-        const int c = (int)((budget / (kWaves * 4) - rec) / 4 * 4);
-        if (!cached && c < kBackPasses * cand * 64) continue;   // the window area also parks the accumulators
-        if (c < 1024) continue;
-        const double wu = std::hypot(cand * G.a1, G.a2) * mag / G.b1 + pmax + 2;
-        const double zspan = std::hypot(cand * G.a1, G.a2);
-        const double wv = 64 * ckp * G.a3 * mag / G.b2 + zabs * (G.f / G.b2) * zspan / (Dmin * Dmin) + 6;
-        gw = cand;
-        kp = ckp;
-        cap = c;
-        if (wu * ((int)wv | 1) <= c) break;
-    }
+    // a smaller budget lets four workgroups share a compute unit (the
+    // default for 4-piece records) or a larger one keeps larger windows in
+    // LDS with three (8-piece records)
+    if (pmax > 8) wpc = 2;
+    else if (!cached) wpc = 3;
+    else if (wpc != 3 && wpc != 4) wpc = pmax > 4 ? 3 : 4;
+    const size_t budget = (pmax > 8 ? kBackLdsBudgetWide
+                           : cached && wpc == 4 ? kBackLdsBudgetCached : kBackLdsBudget) - reserve;
+    int gw, kp, cap;
+    choose(budget, gw, kp, cap);
     if (gw == 0) return false;
     L.gw = gw;
     L.kp = kp;
@@ -178,6 +199,7 @@ bool plan_backprojection(const DevGeom &G, int pmax, double zabs, double Dmin, i
     L.items = G.n2 * L.ngroups * L.nkchunks;
     L.chunk = (L.items + 7) / 8;
     L.lds = backproject_lds_bytes(gw, pmax, cap);
+    L.wpc = wpc;
     return true;
 }
 
@@ -554,6 +576,7 @@ cvp_status cvp_geometry_get_launch(const cvp_geometry *g, cvp_launch *out)
     const cvp::BackLaunch &bl = g->d_rtab ? g->blc : g->bl;
     out->bp_stack_cols = bl.gw;
     out->bp_passes = bl.kp;
+    out->bp_workgroups_per_cu = bl.wpc;
     return ok();
 }
 
@@ -566,6 +589,9 @@ cvp_status cvp_geometry_set_launch(cvp_geometry *g, const cvp_launch *in)
     if (gw != 0 && gw != 4 && gw != 8 && gw != 16)
         return fail(CVP_E_INVALID, "launch.bp_stack_cols = %d (0, 4, 8 or 16)", gw);
     if (kp < 0 || kp > cvp::kBackPasses) return fail(CVP_E_INVALID, "launch.bp_passes = %d (0, 1 or 2)", kp);
+    const int wpc = in->bp_workgroups_per_cu;
+    if (wpc != 0 && wpc != 3 && wpc != 4)
+        return fail(CVP_E_INVALID, "launch.bp_workgroups_per_cu = %d (0, 3 or 4)", wpc);
     const cvp::DevGeom &G = g->base;
     cvp::ProjLaunch pl{};
     cvp::BackLaunch bl{};
@@ -580,8 +606,9 @@ cvp_status cvp_geometry_set_launch(cvp_geometry *g, const cvp_launch *in)
     // in-kernel plan also serves the TT projector, so it is kept valid too
     cvp::BackLaunch blc = g->blc;
     if (g->d_rtab) {
-        if (!cvp::plan_backprojection(G, g->pmax, g->zabs, g->Dmin, gw, kp, blc, true))
-            return fail(CVP_E_UNSUPPORTED, "launch.bp_stack_cols = %d, bp_passes = %d: does not fit LDS", gw, kp);
+        if (!cvp::plan_backprojection(G, g->pmax, g->zabs, g->Dmin, gw, kp, blc, true, 0, wpc))
+            return fail(CVP_E_UNSUPPORTED, "launch.bp_stack_cols = %d, bp_passes = %d, bp_workgroups_per_cu = %d: "
+                                           "does not fit LDS", gw, kp, wpc);
         if (!cvp::plan_backprojection(G, g->pmax, g->zabs, g->Dmin, gw, kp, bl) &&
             !cvp::plan_backprojection(G, g->pmax, g->zabs, g->Dmin, 0, 0, bl))
             return fail(CVP_E_UNSUPPORTED, "backprojection plan");
@@ -591,6 +618,7 @@ cvp_status cvp_geometry_set_launch(cvp_geometry *g, const cvp_launch *in)
     g->pl = pl;
     g->bl = bl;
     g->blc = blc;
+    g->bp_wpc = wpc;
     return ok();
 }
 
@@ -613,8 +641,8 @@ static int model_of(const cvp_options *o)
 static void replan_backprojection(cvp_geometry *g)
 {
     cvp::BackLaunch bl{};
-    if (cvp::plan_backprojection(g->base, g->pmax, g->zabs, g->Dmin, g->bl.gw, g->bl.kp, bl, true) ||
-        cvp::plan_backprojection(g->base, g->pmax, g->zabs, g->Dmin, 0, 0, bl, true))
+    if (cvp::plan_backprojection(g->base, g->pmax, g->zabs, g->Dmin, g->bl.gw, g->bl.kp, bl, true, 0, g->bp_wpc) ||
+        cvp::plan_backprojection(g->base, g->pmax, g->zabs, g->Dmin, 0, 0, bl, true, 0, g->bp_wpc))
         g->blc = bl;
     else
         g->blc = g->bl;
@@ -931,7 +959,7 @@ cvp_status cvp_batch_create(const cvp_geometry *const *geoms, int32_t n, cvp_bat
         for (int gi = 0; gi < 3 && !planned; ++gi) {
             if (kGw[gi] > geoms[q]->bl.gw) continue;
             planned = cvp::plan_backprojection(geoms[q]->base, pm, geoms[q]->zabs, geoms[q]->Dmin, kGw[gi], 0, bls[q],
-                                               b->cached);
+                                               b->cached, cvp::kBatchStaticLds, geoms[q]->bp_wpc);
             grp[q] = (pm == 4 ? 0 : 3) + gi;
         }
         if (!planned) {

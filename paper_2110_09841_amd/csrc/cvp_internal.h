@@ -91,6 +91,7 @@ struct BackLaunch {
     int pmax;        // 4, 8 or kPmaxWide (then gw = 4)
     int win_cap;     // floats per wave window
     size_t lds;
+    int wpc;         // workgroups per CU the LDS budget was sized for
 };
 
 // Batched, persistent launches over up to kMaxBatch problems.

@@ -59,6 +59,7 @@ class Geometry:
             _lib.check(_lib.lib().cvp_geometry_from_views(ctypes.byref(desc), ctypes.byref(h)))
             nv = len(params["angles_rad"])
         self.handle = h
+        self.records_cached = False
         n1, n2, n3 = (int(v) for v in params["vol_dims"])
         self.vol_shape = (n3, n2, n1)
         self.proj_shape = (nv, int(params["det_rows"]), int(params["det_cols"]))
@@ -91,10 +92,18 @@ class Geometry:
         _lib.check(_lib.lib().cvp_geometry_get_launch(self.handle, ctypes.byref(lp)))
         return int(lp.proj_band_cols), int(lp.bp_stack_cols), int(lp.bp_passes)
 
-    def set_launch(self, proj_band_cols=0, bp_stack_cols=0, bp_passes=0):
+    @property
+    def bp_workgroups_per_cu(self):
+        """Backprojection workgroups per compute unit the plan's LDS budget
+        is sized for (3 or 4 with cached records; 3 without)."""
+        lp = _lib.LaunchC()
+        _lib.check(_lib.lib().cvp_geometry_get_launch(self.handle, ctypes.byref(lp)))
+        return int(lp.bp_workgroups_per_cu)
+
+    def set_launch(self, proj_band_cols=0, bp_stack_cols=0, bp_passes=0, bp_workgroups_per_cu=0):
         """Replace the launch plan (0 selects the planner's default for that
         field).  Raises CVPError if the plan does not fit."""
-        lp = _lib.LaunchC(int(proj_band_cols), int(bp_stack_cols), int(bp_passes))
+        lp = _lib.LaunchC(int(proj_band_cols), int(bp_stack_cols), int(bp_passes), int(bp_workgroups_per_cu))
         _lib.check(_lib.lib().cvp_geometry_set_launch(self.handle, ctypes.byref(lp)))
 
     def cache_records(self, enable=True):
@@ -105,6 +114,7 @@ class Geometry:
         them.  Returns the table's size in bytes (0 when freed)."""
         nb = ctypes.c_int64()
         _lib.check(_lib.lib().cvp_geometry_cache_records(self.handle, int(bool(enable)), ctypes.byref(nb), _stream()))
+        self.records_cached = nb.value > 0
         return int(nb.value)
 
 

@@ -60,13 +60,15 @@ def test_invalid_plans_are_rejected_and_leave_the_plan():
     g = synth.geometry(16, 1.0, 32, 3000, 0.5, 750.0, 1200.0, 2, 360.0)
     G = cvp.Geometry(g)
     before = G.launch
-    for u, gw, kp, status in ((33, 0, 0, _lib.CVP_E_INVALID), (-1, 0, 0, _lib.CVP_E_INVALID),
-                              (0, 5, 0, _lib.CVP_E_INVALID), (0, 0, 3, _lib.CVP_E_INVALID),
-                              (32, 0, 0, _lib.CVP_E_UNSUPPORTED)):
+    wpc_before = G.bp_workgroups_per_cu
+    for u, gw, kp, wpc, status in ((33, 0, 0, 0, _lib.CVP_E_INVALID), (-1, 0, 0, 0, _lib.CVP_E_INVALID),
+                                   (0, 5, 0, 0, _lib.CVP_E_INVALID), (0, 0, 3, 0, _lib.CVP_E_INVALID),
+                                   (0, 0, 0, 2, _lib.CVP_E_INVALID), (0, 0, 0, 5, _lib.CVP_E_INVALID),
+                                   (32, 0, 0, 0, _lib.CVP_E_UNSUPPORTED)):
         with pytest.raises(_lib.CVPError) as ei:
-            G.set_launch(u, gw, kp)
-        assert ei.value.status == status, (u, gw, kp, ei.value)
-        assert G.launch == before
+            G.set_launch(u, gw, kp, wpc)
+        assert ei.value.status == status, (u, gw, kp, wpc, ei.value)
+        assert G.launch == before and G.bp_workgroups_per_cu == wpc_before
 
 
 def test_autotune_sets_and_caches_a_plan(tmp_path):

@@ -2,8 +2,8 @@
 operators read the FP64 records of every (view, voxel column) that a
 one-off pass computed, instead of computing them in each launch; the
 results must be bitwise those without it -- both forms, EC on and off,
-record strides 4 and 8, view subsets, the allocation-free projection and
-CGLS -- and the TT projector, which keeps its own records, is unaffected.
+record strides 4 and 8, view subsets, either LDS budget of the
+backprojection, the allocation-free projection and CGLS -- and the TT projector, which keeps its own records, is unaffected.
 Geometries whose voxels span more than 8 columns are refused."""
 import ctypes
 
@@ -60,6 +60,15 @@ def test_cached_records_give_the_same_bits(name):
                solvers.backproject_views(b, G, 1, 3, 3, opts=opts))
         for what, r, t in zip(("A x", "A^T b", "A x (no alloc)", "A^T b (views 1, 4, 7)"), ref[variant, ec], got):
             assert torch.equal(r, t), (name, variant, ec, what)
+    # the backprojection's LDS budget (workgroups per CU) changes only the split
+    assert G.bp_workgroups_per_cu == (4 if name == "pmax4" else 3)
+    for wpc in (3, 4):
+        G.set_launch(0, 0, 0, wpc)
+        assert G.bp_workgroups_per_cu == wpc
+        for variant, ec in COMBOS[:2]:
+            opts = cvp.Options(variant=variant, ec=ec)
+            assert torch.equal(cvp.backproject(b, G, opts), ref[variant, ec][1]), (name, wpc, variant)
+    G.set_launch()
     out = torch.full(G.proj_shape, 3.0, device="cuda")
     solvers.project_views(x, G, 2, 4, 2, out, cvp.Options(variant="relaxed", ec=True))
     full = ref["relaxed", True][0]
