@@ -196,6 +196,117 @@ conv3d_kernel_c(const Act in, const __bf16 *__restrict__ wt, const float *__rest
     }
 }
 
+// The same convolution with the workgroup's input tile staged in LDS: a
+// workgroup computes 64 voxels of 4 consecutive rows h0..h0+3 of slice d (one
+// row per wave) and first copies the 66 x 6 x 3 input voxels those outputs
+// read (zeros outside the volume) into LDS, channels last, so each of the 27
+// taps' A fragments is an LDS read instead of a gather from global memory
+// (every input voxel was fetched 27 times through L1).  The k order, MFMA
+// sequence and epilogue are those of conv3d_kernel: the results are the same
+// bits.  CI = 16 or 32 (38 KB or 76 KB of LDS), CO = 16 or 32 (and 64 with
+// CI = 32).
+constexpr int kTileX = 66, kTileY = 6, kTileZ = 3;
+
+template <int CI>
+constexpr int conv_tile_bytes() { return kTileZ * kTileY * kTileX * CI * 2; }
+
+// LDS holds 4 (16 input channels) or 2 (32) workgroups per CU: the register
+// budget of that occupancy lets the scheduler keep more fragments in flight.
+template <int CO, int CI>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CI == 16 ? 4 : 2)))
+conv3d_lds_kernel(const Act in, const __bf16 *__restrict__ wt, const float *__restrict__ bias, Act out, int relu,
+                  int flip)
+{
+    constexpr int NT = CO / 16;
+    constexpr int KSTEPS = (27 * CI + 31) / 32;
+    constexpr int C8 = CI / 8;                       // 16-byte chunks per voxel
+    extern __shared__ __align__(16) unsigned char tile[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int segs = (in.W + 63) / 64, quads = (in.H + 3) / 4;
+    int blk = blockIdx.x;
+    const int seg = blk % segs;
+    blk /= segs;
+    const int h0 = (blk % quads) * 4;
+    const int d = blk / quads;
+    const int w0 = seg * 64;
+
+    // stage the input tile, voxel v = (zz, yy, xx) = (d - 1 + zz, h0 - 1 + yy,
+    // w0 - 1 + xx), as [8-channel chunk][voxel][16 bytes]: the 16 lanes of a
+    // fragment read consecutive 16-byte slots (no LDS bank conflicts)
+    constexpr int NV = kTileZ * kTileY * kTileX;
+    constexpr int NCH = NV * C8;
+    for (int idx = threadIdx.x; idx < NCH; idx += 256) {
+        const int c8 = idx / NV, v = idx % NV;
+        const int xx = v % kTileX, t = v / kTileX;
+        const int yy = t % kTileY, zz = t / kTileY;
+        const int x = w0 - 1 + xx, y = h0 - 1 + yy, z = d - 1 + zz;
+        bf16x8 val = zero8();
+        if ((unsigned)x < (unsigned)in.W && (unsigned)y < (unsigned)in.H && (unsigned)z < (unsigned)in.D)
+            val = *reinterpret_cast<const bf16x8 *>(in.p + ((z * in.H + y) * in.W + x) * in.stride + c8 * 8);
+        *reinterpret_cast<bf16x8 *>(tile + idx * 16) = val;
+    }
+    __syncthreads();
+    const int h = h0 + wave;
+    if (h >= in.H) return;                           // no barrier follows
+
+    f32x4 acc[4][NT];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int n = 0; n < NT; ++n) acc[r][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    const int i16 = lane & 15;
+    const int kg = lane >> 4;        // which group of 8 k within the 32
+    // fragments of k step ks: A from the tile, B (weights) from global memory
+    auto load = [&](int ks, bf16x8 a[4], bf16x8 b[NT]) {
+        const int k = ks * 32 + kg * 8;
+        const int tap = k / CI;
+        const int ci = k % CI;
+        const bool tv = tap < 27;
+        const int tp = flip ? 26 - tap : tap;
+        const int dz = tp / 9 - 1, dy = (tp / 3) % 3 - 1, dx = tp % 3 - 1;
+        // tile voxel of row tile 0: (dz + 1, wave + dy + 1, i16 + dx + 1)
+        const unsigned char *src =
+            tile + ((ci / 8) * NV + ((dz + 1) * kTileY + wave + dy + 1) * kTileX + i16 + dx + 1) * 16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a[r] = tv ? *reinterpret_cast<const bf16x8 *>(src + r * 16 * 16) : zero8();
+#pragma unroll
+        for (int n = 0; n < NT; ++n)
+            b[n] = tv ? *reinterpret_cast<const bf16x8 *>(wt + (tap * CO + n * 16 + i16) * CI + ci) : zero8();
+    };
+    // the k loop unrolled, with the next step's fragments loaded before this
+    // step's MFMAs (two register sets)
+    bf16x8 fa[2][4], fb[2][NT];
+    load(0, fa[0], fb[0]);
+#pragma unroll
+    for (int ks = 0; ks < KSTEPS; ++ks) {
+        const int c = ks & 1;
+        if (ks + 1 < KSTEPS) load(ks + 1, fa[c ^ 1], fb[c ^ 1]);
+#pragma unroll
+        for (int n = 0; n < NT; ++n)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                acc[r][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[c][r], fb[c][n], acc[r][n], 0, 0, 0);
+    }
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+        const int co = n * 16 + i16;
+        const float bv = bias ? bias[co] : 0.0f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int x = w0 + r * 16 + (lane >> 4) * 4 + e;
+                if (x < out.W) {
+                    float v = acc[r][n][e] + bv;
+                    if (relu) v = fmaxf(v, 0.0f);
+                    out.p[((d * out.H + h) * out.W + x) * out.stride + co] = (__bf16)v;
+                }
+            }
+        }
+    }
+}
+
 // Backward-weight partials: for the taps (dz, dy) = tap9 and all three dx,
 // and a chunk of `rows` (d, h) rows, part[chunk][tap][co][ci] =
 // sum over the chunk's voxels of dY[v][co] * X[v + off][ci].  Per 64-voxel
@@ -363,95 +474,141 @@ __global__ void channel_sum_partials(const Act a, int rows_per_chunk, float *__r
     }
 }
 
+// Elementwise kernels: one thread per 8-channel chunk of a voxel (16-byte
+// loads and stores), index I = int when the chunk count fits 31 bits.  Each
+// value is computed as in a per-channel loop, in the same order.
+template <typename I>
+__device__ __forceinline__ void chunk_coords(I i, int C8, int W, int H, int &c, int &x, int &y, int &z)
+{
+    c = (int)(i % C8) * 8;
+    I v = i / C8;
+    x = (int)(v % W);
+    v /= W;
+    y = (int)(v % H);
+    z = (int)(v / H);
+}
+
+__device__ __forceinline__ size_t voxel_at(const Act &t, int z, int y, int x)
+{
+    return (((size_t)z * t.H + y) * t.W + x) * t.stride;
+}
+
 // dY *= (Y > 0) in place (ReLU backward; Y is the post-ReLU output)
+template <typename I>
 __global__ void relu_mask(Act dy, const Act y)
 {
-    const int64_t n = (int64_t)dy.D * dy.H * dy.W * dy.C;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t v = i / dy.C;
-        const int c = (int)(i % dy.C);
-        if (!((float)y.p[v * y.stride + c] > 0.0f)) dy.p[v * dy.stride + c] = (__bf16)0.0f;
+    const int C8 = dy.C / 8;
+    const I n = (I)dy.D * dy.H * dy.W * C8;
+    for (I i = (I)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (I)gridDim.x * blockDim.x) {
+        const I v = i / C8;
+        const int c = (int)(i % C8) * 8;
+        bf16x8 g = *reinterpret_cast<const bf16x8 *>(dy.p + (size_t)v * dy.stride + c);
+        const bf16x8 q = *reinterpret_cast<const bf16x8 *>(y.p + (size_t)v * y.stride + c);
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            if (!((float)q[e] > 0.0f)) g[e] = (__bf16)0.0f;
+        *reinterpret_cast<bf16x8 *>(dy.p + (size_t)v * dy.stride + c) = g;
     }
 }
 
 // 2x2x2 average pooling: out (D/2,H/2,W/2) from in
+template <typename I>
 __global__ void avgpool2(const Act in, Act out)
 {
-    const int64_t n = (int64_t)out.D * out.H * out.W * out.C;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int c = (int)(i % out.C);
-        int64_t v = i / out.C;
-        const int x = (int)(v % out.W); v /= out.W;
-        const int y = (int)(v % out.H);
-        const int z = (int)(v / out.H);
-        float s = 0.0f;
+    const int C8 = out.C / 8;
+    const I n = (I)out.D * out.H * out.W * C8;
+    for (I i = (I)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (I)gridDim.x * blockDim.x) {
+        int c, x, y, z;
+        chunk_coords<I>(i, C8, out.W, out.H, c, x, y, z);
+        float s[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s[e] = 0.0f;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const int zz = 2 * z + (q >> 2), yy = 2 * y + ((q >> 1) & 1), xx = 2 * x + (q & 1);
-            s += (float)in.p[(((size_t)zz * in.H + yy) * in.W + xx) * in.stride + c];
+            const bf16x8 t = *reinterpret_cast<const bf16x8 *>(
+                in.p + voxel_at(in, 2 * z + (q >> 2), 2 * y + ((q >> 1) & 1), 2 * x + (q & 1)) + c);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) s[e] += (float)t[e];
         }
-        out.p[(((size_t)z * out.H + y) * out.W + x) * out.stride + c] = (__bf16)(0.125f * s);
+        bf16x8 o;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) o[e] = (__bf16)(0.125f * s[e]);
+        *reinterpret_cast<bf16x8 *>(out.p + voxel_at(out, z, y, x) + c) = o;
     }
 }
 
 // backward of avgpool2: din = dout(parent) / 8
+template <typename I>
 __global__ void avgpool2_bwd(const Act dout, Act din)
 {
-    const int64_t n = (int64_t)din.D * din.H * din.W * din.C;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int c = (int)(i % din.C);
-        int64_t v = i / din.C;
-        const int x = (int)(v % din.W); v /= din.W;
-        const int y = (int)(v % din.H);
-        const int z = (int)(v / din.H);
-        const float g = (float)dout.p[(((size_t)(z / 2) * dout.H + y / 2) * dout.W + x / 2) * dout.stride + c];
-        din.p[(((size_t)z * din.H + y) * din.W + x) * din.stride + c] = (__bf16)(0.125f * g);
+    const int C8 = din.C / 8;
+    const I n = (I)din.D * din.H * din.W * C8;
+    for (I i = (I)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (I)gridDim.x * blockDim.x) {
+        int c, x, y, z;
+        chunk_coords<I>(i, C8, din.W, din.H, c, x, y, z);
+        const bf16x8 g = *reinterpret_cast<const bf16x8 *>(dout.p + voxel_at(dout, z / 2, y / 2, x / 2) + c);
+        bf16x8 o;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) o[e] = (__bf16)(0.125f * (float)g[e]);
+        *reinterpret_cast<bf16x8 *>(din.p + voxel_at(din, z, y, x) + c) = o;
     }
 }
 
 // nearest 2x upsampling: out (2D,2H,2W) from in
+template <typename I>
 __global__ void upsample2(const Act in, Act out)
 {
-    const int64_t n = (int64_t)out.D * out.H * out.W * out.C;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int c = (int)(i % out.C);
-        int64_t v = i / out.C;
-        const int x = (int)(v % out.W); v /= out.W;
-        const int y = (int)(v % out.H);
-        const int z = (int)(v / out.H);
-        out.p[(((size_t)z * out.H + y) * out.W + x) * out.stride + c] =
-            in.p[(((size_t)(z / 2) * in.H + y / 2) * in.W + x / 2) * in.stride + c];
+    const int C8 = out.C / 8;
+    const I n = (I)out.D * out.H * out.W * C8;
+    for (I i = (I)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (I)gridDim.x * blockDim.x) {
+        int c, x, y, z;
+        chunk_coords<I>(i, C8, out.W, out.H, c, x, y, z);
+        *reinterpret_cast<bf16x8 *>(out.p + voxel_at(out, z, y, x) + c) =
+            *reinterpret_cast<const bf16x8 *>(in.p + voxel_at(in, z / 2, y / 2, x / 2) + c);
     }
 }
 
 // backward of upsample2: din = sum of the 8 children of dout
+template <typename I>
 __global__ void upsample2_bwd(const Act dout, Act din)
 {
-    const int64_t n = (int64_t)din.D * din.H * din.W * din.C;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int c = (int)(i % din.C);
-        int64_t v = i / din.C;
-        const int x = (int)(v % din.W); v /= din.W;
-        const int y = (int)(v % din.H);
-        const int z = (int)(v / din.H);
-        float s = 0.0f;
+    const int C8 = din.C / 8;
+    const I n = (I)din.D * din.H * din.W * C8;
+    for (I i = (I)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (I)gridDim.x * blockDim.x) {
+        int c, x, y, z;
+        chunk_coords<I>(i, C8, din.W, din.H, c, x, y, z);
+        float s[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s[e] = 0.0f;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const int zz = 2 * z + (q >> 2), yy = 2 * y + ((q >> 1) & 1), xx = 2 * x + (q & 1);
-            s += (float)dout.p[(((size_t)zz * dout.H + yy) * dout.W + xx) * dout.stride + c];
+            const bf16x8 t = *reinterpret_cast<const bf16x8 *>(
+                dout.p + voxel_at(dout, 2 * z + (q >> 2), 2 * y + ((q >> 1) & 1), 2 * x + (q & 1)) + c);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) s[e] += (float)t[e];
         }
-        din.p[(((size_t)z * din.H + y) * din.W + x) * din.stride + c] = (__bf16)s;
+        bf16x8 o;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) o[e] = (__bf16)s[e];
+        *reinterpret_cast<bf16x8 *>(din.p + voxel_at(din, z, y, x) + c) = o;
     }
 }
 
 // out = a + b (BF16 tensors of the same shape; slices allowed)
+template <typename I>
 __global__ void add_kernel(const Act a, const Act b, Act out)
 {
-    const int64_t n = (int64_t)out.D * out.H * out.W * out.C;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t v = i / out.C;
-        const int c = (int)(i % out.C);
-        out.p[v * out.stride + c] = (__bf16)((float)a.p[v * a.stride + c] + (float)b.p[v * b.stride + c]);
+    const int C8 = out.C / 8;
+    const I n = (I)out.D * out.H * out.W * C8;
+    for (I i = (I)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (I)gridDim.x * blockDim.x) {
+        const I v = i / C8;
+        const int c = (int)(i % C8) * 8;
+        const bf16x8 p = *reinterpret_cast<const bf16x8 *>(a.p + (size_t)v * a.stride + c);
+        const bf16x8 q = *reinterpret_cast<const bf16x8 *>(b.p + (size_t)v * b.stride + c);
+        bf16x8 o;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) o[e] = (__bf16)((float)p[e] + (float)q[e]);
+        *reinterpret_cast<bf16x8 *>(out.p + (size_t)v * out.stride + c) = o;
     }
 }
 
@@ -478,7 +635,11 @@ __global__ void head_fwd(const Act h, const float *__restrict__ w, const float *
     const int64_t n = (int64_t)h.D * h.H * h.W;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         float s = b[0];
-        for (int c = 0; c < h.C; ++c) s = fmaf(w[c], (float)h.p[v * h.stride + c], s);
+        for (int c8 = 0; c8 < h.C; c8 += 8) {
+            const bf16x8 q = *reinterpret_cast<const bf16x8 *>(h.p + v * h.stride + c8);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) s = fmaf(w[c8 + e], (float)q[e], s);
+        }
         x0[v] = x2[v] + s * inv_scale;
     }
 }
@@ -495,9 +656,17 @@ __global__ void head_bwd(const Act h, const float *__restrict__ w, const float *
     for (int c = 0; c < 17; ++c) acc[c] = 0.0f;
     for (int64_t v = v0 + threadIdx.x; v < v1; v += blockDim.x) {
         const float gv = g[v] * inv_scale;
-        for (int c = 0; c < h.C; ++c) {
-            acc[c] = fmaf((float)h.p[v * h.stride + c], gv, acc[c]);
-            dh.p[v * dh.stride + c] = (__bf16)(w[c] * gv);
+#pragma unroll
+        for (int c8 = 0; c8 < 16; c8 += 8) {
+            if (c8 >= h.C) break;
+            const bf16x8 q = *reinterpret_cast<const bf16x8 *>(h.p + v * h.stride + c8);
+            bf16x8 o;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                acc[c8 + e] = fmaf((float)q[e], gv, acc[c8 + e]);
+                o[e] = (__bf16)(w[c8 + e] * gv);
+            }
+            *reinterpret_cast<bf16x8 *>(dh.p + v * dh.stride + c8) = o;
         }
         acc[16] += gv;
     }
@@ -595,6 +764,23 @@ cvp_status st(hipError_t e) { return e == hipSuccess ? CVP_OK : CVP_E_DEVICE; }
 
 int grid_for(int64_t n) { return (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096); }
 
+// The LDS-tiled convolutions take more than the default 64 KB of dynamic LDS
+// (32 input channels: 76 KB); allowed once per process.
+hipError_t conv_lds_setup()
+{
+    static hipError_t done = [] {
+        hipError_t e = hipSuccess;
+#define ALLOW(CO_, CI_)                                                                                     \
+        if (e == hipSuccess)                                                                                \
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(cvpnn::conv3d_lds_kernel<CO_, CI_>),     \
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, cvpnn::conv_tile_bytes<CI_>());
+        ALLOW(16, 16) ALLOW(16, 32) ALLOW(32, 16) ALLOW(32, 32) ALLOW(64, 32)
+#undef ALLOW
+        return e;
+    }();
+    return done;
+}
+
 }  // namespace
 
 extern "C" {
@@ -614,14 +800,22 @@ cvp_status cvp_nn_conv3d(const cvp_nn_tensor *in, const void *weight, const floa
     const int ci = in->channels, co = out->channels;
     const bool spec = elems < (int64_t(1) << 31) && (ci == 16 || ci == 32 || ci == 64);
 #define CONVC(CO_, CI_) hipLaunchKernelGGL((cvpnn::conv3d_kernel_c<CO_, CI_>), grid, block, 0, s, a, w, bias, o, relu, flip)
-    if (spec && co == 16 && ci == 16) CONVC(16, 16);
-    else if (spec && co == 16 && ci == 32) CONVC(16, 32);
+    // 16 or 32 input channels: the LDS-tiled kernel (4 rows of a slice per workgroup)
+    const dim3 lgrid(in->d * ((in->h + 3) / 4) * ((in->w + 63) / 64));
+#define CONVL(CO_, CI_) hipLaunchKernelGGL((cvpnn::conv3d_lds_kernel<CO_, CI_>), lgrid, block, \
+                                           cvpnn::conv_tile_bytes<CI_>(), s, a, w, bias, o, relu, flip)
+    if (spec && (ci == 16 || ci == 32)) {
+        const hipError_t e = conv_lds_setup();
+        if (e != hipSuccess) return st(e);
+    }
+    if (spec && co == 16 && ci == 16) CONVL(16, 16);
+    else if (spec && co == 16 && ci == 32) CONVL(16, 32);
     else if (spec && co == 16 && ci == 64) CONVC(16, 64);
-    else if (spec && co == 32 && ci == 16) CONVC(32, 16);
-    else if (spec && co == 32 && ci == 32) CONVC(32, 32);
+    else if (spec && co == 32 && ci == 16) CONVL(32, 16);
+    else if (spec && co == 32 && ci == 32) CONVL(32, 32);
     else if (spec && co == 32 && ci == 64) CONVC(32, 64);
-    else if (spec && co == 64 && ci == 16) CONVC(64, 16);
-    else if (spec && co == 64 && ci == 32) CONVC(64, 32);
+    else if (spec && co == 64 && ci == 16) CONVC(64, 16);   // the LDS kernel's registers would spill
+    else if (spec && co == 64 && ci == 32) CONVL(64, 32);
     else if (spec && co == 64 && ci == 64) CONVC(64, 64);
     else {
         switch (co) {
@@ -632,6 +826,7 @@ cvp_status cvp_nn_conv3d(const cvp_nn_tensor *in, const void *weight, const floa
         }
     }
 #undef CONVC
+#undef CONVL
     return st(hipGetLastError());
 }
 
@@ -688,8 +883,12 @@ cvp_status cvp_nn_channel_sum(const cvp_nn_tensor *a, float *out, float *work, i
 cvp_status cvp_nn_relu_mask(const cvp_nn_tensor *dy, const cvp_nn_tensor *y, void *stream)
 {
     if (!valid(dy) || !valid(y)) return CVP_E_INVALID;
-    const int64_t n = (int64_t)dy->d * dy->h * dy->w * dy->channels;
-    hipLaunchKernelGGL(cvpnn::relu_mask, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, act(dy), act(y));
+    const int64_t n = (int64_t)dy->d * dy->h * dy->w * dy->channels / 8;
+    if (n < (int64_t(1) << 31))
+        hipLaunchKernelGGL(cvpnn::relu_mask<int>, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, act(dy), act(y));
+    else
+        hipLaunchKernelGGL(cvpnn::relu_mask<int64_t>, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, act(dy),
+                           act(y));
     return st(hipGetLastError());
 }
 
@@ -700,14 +899,22 @@ static cvp_status resample(int kind, const cvp_nn_tensor *a, const cvp_nn_tensor
     const cvp_nn_tensor *big = (kind == 0 || kind == 3) ? a : b;    // fine-resolution operand
     const cvp_nn_tensor *small = big == a ? b : a;
     if (big->d != 2 * small->d || big->h != 2 * small->h || big->w != 2 * small->w) return CVP_E_INVALID;
-    const int64_t nb = (int64_t)big->d * big->h * big->w * big->channels;
+    // 8-channel chunks of the fine and the coarse operand
+    const int64_t nb = (int64_t)big->d * big->h * big->w * big->channels / 8;
     const int64_t ns = nb / 8;
+    const bool i32 = nb < (int64_t(1) << 31);
+#define RS(K, N)                                                                                      \
+    do {                                                                                              \
+        if (i32) hipLaunchKernelGGL(cvpnn::K<int>, dim3(grid_for(N)), dim3(256), 0, s, act(a), act(b)); \
+        else hipLaunchKernelGGL(cvpnn::K<int64_t>, dim3(grid_for(N)), dim3(256), 0, s, act(a), act(b)); \
+    } while (0)
     switch (kind) {
-    case 0: hipLaunchKernelGGL(cvpnn::avgpool2, dim3(grid_for(ns)), dim3(256), 0, s, act(a), act(b)); break;
-    case 1: hipLaunchKernelGGL(cvpnn::avgpool2_bwd, dim3(grid_for(nb)), dim3(256), 0, s, act(a), act(b)); break;
-    case 2: hipLaunchKernelGGL(cvpnn::upsample2, dim3(grid_for(nb)), dim3(256), 0, s, act(a), act(b)); break;
-    default: hipLaunchKernelGGL(cvpnn::upsample2_bwd, dim3(grid_for(ns)), dim3(256), 0, s, act(a), act(b)); break;
+    case 0: RS(avgpool2, ns); break;
+    case 1: RS(avgpool2_bwd, nb); break;
+    case 2: RS(upsample2, nb); break;
+    default: RS(upsample2_bwd, ns); break;
     }
+#undef RS
     return st(hipGetLastError());
 }
 
@@ -721,8 +928,13 @@ cvp_status cvp_nn_add(const cvp_nn_tensor *a, const cvp_nn_tensor *b, const cvp_
     if (!valid(a) || !valid(b) || !valid(out) || a->channels != out->channels || b->channels != out->channels ||
         a->d != out->d || a->h != out->h || a->w != out->w || b->d != out->d || b->h != out->h || b->w != out->w)
         return CVP_E_INVALID;
-    const int64_t n = (int64_t)out->d * out->h * out->w * out->channels;
-    hipLaunchKernelGGL(cvpnn::add_kernel, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, act(a), act(b), act(out));
+    const int64_t n = (int64_t)out->d * out->h * out->w * out->channels / 8;
+    if (n < (int64_t(1) << 31))
+        hipLaunchKernelGGL(cvpnn::add_kernel<int>, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, act(a), act(b),
+                           act(out));
+    else
+        hipLaunchKernelGGL(cvpnn::add_kernel<int64_t>, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, act(a),
+                           act(b), act(out));
     return st(hipGetLastError());
 }
 
