@@ -197,23 +197,24 @@ conv3d_kernel_c(const Act in, const __bf16 *__restrict__ wt, const float *__rest
 }
 
 // The same convolution with the workgroup's input tile staged in LDS: a
-// workgroup computes 64 voxels of 4 consecutive rows h0..h0+3 of slice d (one
-// row per wave) and first copies the 66 x 6 x 3 input voxels those outputs
-// read (zeros outside the volume) into LDS, channels last, so each of the 27
+// workgroup computes 16 RX voxels (RX = 4 or 2 row tiles per wave) of 4
+// consecutive rows h0..h0+3 of slice d (one row per wave) and first copies the
+// (16 RX + 2) x 6 x 3 input voxels those outputs read (zeros outside the
+// volume) into LDS, so each of the 27
 // taps' A fragments is an LDS read instead of a gather from global memory
 // (every input voxel was fetched 27 times through L1).  The k order, MFMA
 // sequence and epilogue are those of conv3d_kernel: the results are the same
-// bits.  CI = 16 or 32 (38 KB or 76 KB of LDS), CO = 16 or 32 (and 64 with
-// CI = 32).
-constexpr int kTileX = 66, kTileY = 6, kTileZ = 3;
+// bits.  RX = 4 with 16 or 32 input channels (38 or 76 KB of LDS), RX = 2
+// with 64 (78 KB) or for rows of at most 32 voxels.
+constexpr int kTileY = 6, kTileZ = 3;
 
-template <int CI>
-constexpr int conv_tile_bytes() { return kTileZ * kTileY * kTileX * CI * 2; }
+template <int CI, int RX>
+constexpr int conv_tile_bytes() { return kTileZ * kTileY * (RX * 16 + 2) * CI * 2; }
 
 // LDS holds 4 (16 input channels) or 2 (32) workgroups per CU: the register
 // budget of that occupancy lets the scheduler keep more fragments in flight.
-template <int CO, int CI>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CI == 16 ? 4 : 2)))
+template <int CO, int CI, int RX>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(conv_tile_bytes<CI, RX>() <= 40960 ? 4 : 2)))
 conv3d_lds_kernel(const Act in, const __bf16 *__restrict__ wt, const float *__restrict__ bias, Act out, int relu,
                   int flip)
 {
@@ -222,13 +223,14 @@ conv3d_lds_kernel(const Act in, const __bf16 *__restrict__ wt, const float *__re
     constexpr int C8 = CI / 8;                       // 16-byte chunks per voxel
     extern __shared__ __align__(16) unsigned char tile[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int segs = (in.W + 63) / 64, quads = (in.H + 3) / 4;
+    constexpr int kTileX = RX * 16 + 2;
+    const int segs = (in.W + RX * 16 - 1) / (RX * 16), quads = (in.H + 3) / 4;
     int blk = blockIdx.x;
     const int seg = blk % segs;
     blk /= segs;
     const int h0 = (blk % quads) * 4;
     const int d = blk / quads;
-    const int w0 = seg * 64;
+    const int w0 = seg * RX * 16;
 
     // stage the input tile, voxel v = (zz, yy, xx) = (d - 1 + zz, h0 - 1 + yy,
     // w0 - 1 + xx), as [8-channel chunk][voxel][16 bytes]: the 16 lanes of a
@@ -249,16 +251,16 @@ conv3d_lds_kernel(const Act in, const __bf16 *__restrict__ wt, const float *__re
     const int h = h0 + wave;
     if (h >= in.H) return;                           // no barrier follows
 
-    f32x4 acc[4][NT];
+    f32x4 acc[RX][NT];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < RX; ++r)
 #pragma unroll
         for (int n = 0; n < NT; ++n) acc[r][n] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     const int i16 = lane & 15;
     const int kg = lane >> 4;        // which group of 8 k within the 32
     // fragments of k step ks: A from the tile, B (weights) from global memory
-    auto load = [&](int ks, bf16x8 a[4], bf16x8 b[NT]) {
+    auto load = [&](int ks, bf16x8 a[RX], bf16x8 b[NT]) {
         const int k = ks * 32 + kg * 8;
         const int tap = k / CI;
         const int ci = k % CI;
@@ -269,14 +271,14 @@ conv3d_lds_kernel(const Act in, const __bf16 *__restrict__ wt, const float *__re
         const unsigned char *src =
             tile + ((ci / 8) * NV + ((dz + 1) * kTileY + wave + dy + 1) * kTileX + i16 + dx + 1) * 16;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) a[r] = tv ? *reinterpret_cast<const bf16x8 *>(src + r * 16 * 16) : zero8();
+        for (int r = 0; r < RX; ++r) a[r] = tv ? *reinterpret_cast<const bf16x8 *>(src + r * 16 * 16) : zero8();
 #pragma unroll
         for (int n = 0; n < NT; ++n)
             b[n] = tv ? *reinterpret_cast<const bf16x8 *>(wt + (tap * CO + n * 16 + i16) * CI + ci) : zero8();
     };
     // the k loop unrolled, with the next step's fragments loaded before this
     // step's MFMAs (two register sets)
-    bf16x8 fa[2][4], fb[2][NT];
+    bf16x8 fa[2][RX], fb[2][NT];
     load(0, fa[0], fb[0]);
 #pragma unroll
     for (int ks = 0; ks < KSTEPS; ++ks) {
@@ -285,7 +287,7 @@ conv3d_lds_kernel(const Act in, const __bf16 *__restrict__ wt, const float *__re
 #pragma unroll
         for (int n = 0; n < NT; ++n)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+            for (int r = 0; r < RX; ++r)
                 acc[r][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[c][r], fb[c][n], acc[r][n], 0, 0, 0);
     }
 #pragma unroll
@@ -293,7 +295,7 @@ conv3d_lds_kernel(const Act in, const __bf16 *__restrict__ wt, const float *__re
         const int co = n * 16 + i16;
         const float bv = bias ? bias[co] : 0.0f;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < RX; ++r) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int x = w0 + r * 16 + (lane >> 4) * 4 + e;
@@ -765,16 +767,19 @@ cvp_status st(hipError_t e) { return e == hipSuccess ? CVP_OK : CVP_E_DEVICE; }
 int grid_for(int64_t n) { return (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096); }
 
 // The LDS-tiled convolutions take more than the default 64 KB of dynamic LDS
-// (32 input channels: 76 KB); allowed once per process.
+// (32 or 64 input channels: 76 or 78 KB); allowed once per process.
 hipError_t conv_lds_setup()
 {
     static hipError_t done = [] {
         hipError_t e = hipSuccess;
-#define ALLOW(CO_, CI_)                                                                                     \
-        if (e == hipSuccess)                                                                                \
-            e = hipFuncSetAttribute(reinterpret_cast<const void *>(cvpnn::conv3d_lds_kernel<CO_, CI_>),     \
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, cvpnn::conv_tile_bytes<CI_>());
-        ALLOW(16, 16) ALLOW(16, 32) ALLOW(32, 16) ALLOW(32, 32) ALLOW(64, 32)
+#define ALLOW(CO_, CI_, RX_)                                                                                 \
+        if (e == hipSuccess)                                                                                 \
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(cvpnn::conv3d_lds_kernel<CO_, CI_, RX_>), \
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,                              \
+                                    cvpnn::conv_tile_bytes<CI_, RX_>());
+        ALLOW(16, 16, 4) ALLOW(16, 32, 4) ALLOW(32, 16, 4) ALLOW(32, 32, 4) ALLOW(64, 32, 4)
+        ALLOW(16, 16, 2) ALLOW(16, 32, 2) ALLOW(16, 64, 2) ALLOW(32, 16, 2) ALLOW(32, 32, 2) ALLOW(32, 64, 2)
+        ALLOW(64, 32, 2) ALLOW(64, 64, 2)
 #undef ALLOW
         return e;
     }();
@@ -800,23 +805,31 @@ cvp_status cvp_nn_conv3d(const cvp_nn_tensor *in, const void *weight, const floa
     const int ci = in->channels, co = out->channels;
     const bool spec = elems < (int64_t(1) << 31) && (ci == 16 || ci == 32 || ci == 64);
 #define CONVC(CO_, CI_) hipLaunchKernelGGL((cvpnn::conv3d_kernel_c<CO_, CI_>), grid, block, 0, s, a, w, bias, o, relu, flip)
-    // 16 or 32 input channels: the LDS-tiled kernel (4 rows of a slice per workgroup)
-    const dim3 lgrid(in->d * ((in->h + 3) / 4) * ((in->w + 63) / 64));
-#define CONVL(CO_, CI_) hipLaunchKernelGGL((cvpnn::conv3d_lds_kernel<CO_, CI_>), lgrid, block, \
-                                           cvpnn::conv_tile_bytes<CI_>(), s, a, w, bias, o, relu, flip)
-    if (spec && (ci == 16 || ci == 32)) {
+    // the LDS-tiled kernel (4 rows of a slice per workgroup): 64-voxel rows
+    // with 16 or 32 input channels, 32-voxel rows with 64 or where rows are
+    // at most 32 voxels long
+    const int rx = (ci == 64 || in->w <= 32) ? 2 : 4;
+    const dim3 lgrid(in->d * ((in->h + 3) / 4) * ((in->w + rx * 16 - 1) / (rx * 16)));
+#define CONVL(CO_, CI_, RX_) hipLaunchKernelGGL((cvpnn::conv3d_lds_kernel<CO_, CI_, RX_>), lgrid, block, \
+                                                (cvpnn::conv_tile_bytes<CI_, RX_>()), s, a, w, bias, o, relu, flip)
+    if (spec) {
         const hipError_t e = conv_lds_setup();
         if (e != hipSuccess) return st(e);
     }
-    if (spec && co == 16 && ci == 16) CONVL(16, 16);
-    else if (spec && co == 16 && ci == 32) CONVL(16, 32);
-    else if (spec && co == 16 && ci == 64) CONVC(16, 64);
-    else if (spec && co == 32 && ci == 16) CONVL(32, 16);
-    else if (spec && co == 32 && ci == 32) CONVL(32, 32);
-    else if (spec && co == 32 && ci == 64) CONVC(32, 64);
-    else if (spec && co == 64 && ci == 16) CONVC(64, 16);   // the LDS kernel's registers would spill
-    else if (spec && co == 64 && ci == 32) CONVL(64, 32);
-    else if (spec && co == 64 && ci == 64) CONVC(64, 64);
+    if (spec && co == 64 && ci == 16) CONVC(64, 16);   // the LDS kernel's registers would spill
+    else if (spec && rx == 4 && co == 16 && ci == 16) CONVL(16, 16, 4);
+    else if (spec && rx == 4 && co == 16 && ci == 32) CONVL(16, 32, 4);
+    else if (spec && rx == 4 && co == 32 && ci == 16) CONVL(32, 16, 4);
+    else if (spec && rx == 4 && co == 32 && ci == 32) CONVL(32, 32, 4);
+    else if (spec && rx == 4 && co == 64 && ci == 32) CONVL(64, 32, 4);
+    else if (spec && co == 16 && ci == 16) CONVL(16, 16, 2);
+    else if (spec && co == 16 && ci == 32) CONVL(16, 32, 2);
+    else if (spec && co == 16 && ci == 64) CONVL(16, 64, 2);
+    else if (spec && co == 32 && ci == 16) CONVL(32, 16, 2);
+    else if (spec && co == 32 && ci == 32) CONVL(32, 32, 2);
+    else if (spec && co == 32 && ci == 64) CONVL(32, 64, 2);
+    else if (spec && co == 64 && ci == 32) CONVL(64, 32, 2);
+    else if (spec && co == 64 && ci == 64) CONVL(64, 64, 2);
     else {
         switch (co) {
         case 16: hipLaunchKernelGGL(cvpnn::conv3d_kernel<16>, grid, block, 0, s, a, w, bias, o, relu, flip); break;
