@@ -71,6 +71,26 @@ def test_invalid_plans_are_rejected_and_leave_the_plan():
         assert G.launch == before and G.bp_workgroups_per_cu == wpc_before
 
 
+def test_autotune_chooses_the_backprojection_budget_with_cached_records(tmp_path):
+    g = synth.config_small()
+    G = cvp.Geometry(g)
+    G.cache_records()
+    opts = cvp.Options(variant="relaxed", ec=True)
+    cache = str(tmp_path / "plans.json")
+    say("autotune, cached records")
+    rec = autotune(G, opts, bands=(8,), stacks=(16,), passes=(2,), reps=1, cache=cache)
+    assert rec["bp_workgroups_per_cu"] in (3, 4)
+    assert set(rec["backproject_ms"]) == {"16/2/4", "16/2/3"}
+    assert G.bp_workgroups_per_cu == rec["bp_workgroups_per_cu"]
+    G2 = cvp.Geometry(g)
+    G2.cache_records()
+    rec2 = autotune(G2, opts, cache=cache)
+    assert rec2["cached"] and G2.launch == G.launch and G2.bp_workgroups_per_cu == G.bp_workgroups_per_cu
+    b = torch.from_numpy(synth.uniform_projections(G.proj_shape, seed=95)).cuda()
+    G3 = cvp.Geometry(g)
+    assert torch.equal(cvp.backproject(b, G2, opts), cvp.backproject(b, G3, opts))
+
+
 def test_autotune_sets_and_caches_a_plan(tmp_path):
     g = synth.config_small()
     G = cvp.Geometry(g)
