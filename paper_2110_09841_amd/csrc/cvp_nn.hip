@@ -205,7 +205,7 @@ conv3d_kernel_c(const Act in, const __bf16 *__restrict__ wt, const float *__rest
 // (every input voxel was fetched 27 times through L1).  The k order, MFMA
 // sequence and epilogue are those of conv3d_kernel: the results are the same
 // bits.  RX = 4 with 16 or 32 input channels (38 or 76 KB of LDS), RX = 2
-// with 64 (78 KB) or for rows of at most 32 voxels.
+// with 64 (78 KB).
 constexpr int kTileY = 6, kTileZ = 3;
 
 template <int CI, int RX>
@@ -806,9 +806,9 @@ cvp_status cvp_nn_conv3d(const cvp_nn_tensor *in, const void *weight, const floa
     const bool spec = elems < (int64_t(1) << 31) && (ci == 16 || ci == 32 || ci == 64);
 #define CONVC(CO_, CI_) hipLaunchKernelGGL((cvpnn::conv3d_kernel_c<CO_, CI_>), grid, block, 0, s, a, w, bias, o, relu, flip)
     // the LDS-tiled kernel (4 rows of a slice per workgroup): 64-voxel rows
-    // with 16 or 32 input channels, 32-voxel rows with 64 or where rows are
-    // at most 32 voxels long
-    const int rx = (ci == 64 || in->w <= 32) ? 2 : 4;
+    // with 16 or 32 input channels, 32-voxel rows with 64 (a 78 KB tile; at
+    // 32^3 with 32 channels the 64-voxel rows were faster, 35 against 49 us)
+    const int rx = ci == 64 ? 2 : 4;
     const dim3 lgrid(in->d * ((in->h + 3) / 4) * ((in->w + rx * 16 - 1) / (rx * 16)));
 #define CONVL(CO_, CI_, RX_) hipLaunchKernelGGL((cvpnn::conv3d_lds_kernel<CO_, CI_, RX_>), lgrid, block, \
                                                 (cvpnn::conv_tile_bytes<CI_, RX_>()), s, a, w, bias, o, relu, flip)
