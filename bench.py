@@ -466,8 +466,7 @@ def cgls_to_tolerance(G, opts, x_true, max_iter):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md); got --gpus %d" % args.gpus)
+        print("bench.py runs on one GPU only (there is no multi-GPU path); got --gpus %d" % args.gpus)
         sys.exit(2)
     import numpy as np
     import torch

@@ -34,7 +34,7 @@ def geometry(vol_dims, voxel_mm, det_cols, det_rows, pitch_mm, sid_mm, sdd_mm,
                 angles_rad=angles(n_views, arc_deg))
 
 
-# The five workloads (volume, detector, trajectory), see the design doc.
+# The five workloads (volume, detector, trajectory).
 def config_small():
     """64^3 voxels of 1.0 mm, 96x96 pixels of 1.6 mm, SID 750 / SDD 1200,
     32 views over 360 degrees."""
