@@ -50,9 +50,9 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true", help="keep the planner's default launch plan")
     ap.add_argument("--no-record-cache", action="store_true",
                     help="let every launch compute its own cut-piece records (no cached record table)")
-    ap.add_argument("--launch", default=None, metavar="U,GW,KP[,WPC]",
+    ap.add_argument("--launch", default=None, metavar="U,GW,KP[,WPC[,SHARED]]",
                     help="fixed launch plan (projection band columns, backprojection stack columns and passes, "
-                         "and backprojection workgroups per CU); no autotuning")
+                         "backprojection workgroups per CU and one window per workgroup); no autotuning")
     ap.add_argument("--cgls-max-iter", type=int, default=200)
     ap.add_argument("--no-network", action="store_true", help="skip the warm-start network timing")
     ap.add_argument("--no-batched", action="store_true", help="skip the 16-problem batched timing")
@@ -303,7 +303,8 @@ def cone_timing(reps=2):
             e1.record()
             torch.cuda.synchronize()
             ms[name] = e0.elapsed_time(e1) / reps
-        res[variant] = {"launch": list(G.launch) + [G.bp_workgroups_per_cu], "project_ms": ms["project"],
+        res[variant] = {"launch": list(G.launch) + [G.bp_workgroups_per_cu, int(G.bp_shared_window)],
+                        "project_ms": ms["project"],
                         "backproject_ms": ms["backproject"],
                         "voxel_views_per_s": 2 * vv / ((ms["project"] + ms["backproject"]) * 1e-3)}
     del x, b, po, vo
@@ -495,13 +496,14 @@ def main():
         nb = G.cache_records()
         torch.cuda.synchronize()
         record_cache = {"bytes": nb, "build_ms": 1e3 * (time.perf_counter() - t0)}
-    plan = {"default": list(G.launch) + [G.bp_workgroups_per_cu]}
+    plan = {"default": list(G.launch) + [G.bp_workgroups_per_cu, int(G.bp_shared_window)]}
     if args.launch:
         G.set_launch(*(int(t) for t in args.launch.split(",")))
-        plan["fixed"] = list(G.launch) + [G.bp_workgroups_per_cu]
+        plan["fixed"] = list(G.launch) + [G.bp_workgroups_per_cu, int(G.bp_shared_window)]
     elif not args.no_autotune:
         rec = autotune(G, opts, reps=2)
-        plan.update(tuned=list(G.launch) + [G.bp_workgroups_per_cu], project_ms=rec["project_ms"],
+        plan.update(tuned=list(G.launch) + [G.bp_workgroups_per_cu, int(G.bp_shared_window)],
+                    project_ms=rec["project_ms"],
                     backproject_ms=rec["backproject_ms"])
     x = torch.from_numpy(x_h).cuda()
     b = torch.from_numpy(b_h).cuda()
@@ -572,8 +574,9 @@ def main():
                    "detector": [g["det_cols"], g["det_rows"]], "pitch_mm": 0.616, "views": V,
                    "arc_deg": 200, "sid_mm": 749, "sdd_mm": 1198, "variant": args.variant,
                    "elevation_correction": ec, "scaling": "solid_angle",
-                   "launch": dict(zip(("proj_band_cols", "bp_stack_cols", "bp_passes", "bp_workgroups_per_cu"),
-                                      G.launch + (G.bp_workgroups_per_cu,)))},
+                   "launch": dict(zip(("proj_band_cols", "bp_stack_cols", "bp_passes", "bp_workgroups_per_cu",
+                                       "bp_shared_window"),
+                                      G.launch + (G.bp_workgroups_per_cu, G.bp_shared_window)))},
         "autotune": plan,
         "record_cache": record_cache,
         "project": {"ms": 1e3 * tA.mean(), "voxel_views_per_s": vv / tA.mean()},

@@ -477,6 +477,13 @@ cvp_status cvp_synth_add_gaussian(float *d_out, int64_t n, float sigma, uint64_t
  *                   the default is 4 for 4-piece records, 3 for 8-piece ones.
  *                   Records computed in the kernel always take 52 KB (3); it
  *                   is reported as such.
+ *   bp_shared_window  with cached records and stacks of 8 or 16 columns: 1
+ *                   stages one detector window per workgroup (all four waves
+ *                   on one view at a time, each window four times as large
+ *                   as a wave's own: for detectors whose pixels are small
+ *                   against the voxels), 0 (the default) one per wave.  A
+ *                   request the plan cannot honour (no cached records,
+ *                   4-column stacks) is reported as 0.
  * cvp_geometry_get_launch reports the plan in use (the planner's default
  * after cvp_geometry_from_views).  cvp_geometry_set_launch replaces it; a zero
  * field restores the default for that field.  Errors: CVP_E_INVALID (NULL or a
@@ -493,6 +500,7 @@ typedef struct {
     int32_t bp_stack_cols;
     int32_t bp_passes;
     int32_t bp_workgroups_per_cu;
+    int32_t bp_shared_window;
 } cvp_launch;
 
 cvp_status cvp_geometry_get_launch(const cvp_geometry *g, cvp_launch *out);

@@ -83,7 +83,7 @@ def lib():
 
 class LaunchC(ctypes.Structure):
     _fields_ = [("proj_band_cols", ctypes.c_int32), ("bp_stack_cols", ctypes.c_int32), ("bp_passes", ctypes.c_int32),
-                ("bp_workgroups_per_cu", ctypes.c_int32)]
+                ("bp_workgroups_per_cu", ctypes.c_int32), ("bp_shared_window", ctypes.c_int32)]
 
 
 def _register_extra(L):

@@ -63,7 +63,7 @@ def autotune(geom: Geometry, opts: Options, bands=DEFAULT_BANDS, stacks=DEFAULT_
         if key in table:
             rec = table[key]
             geom.set_launch(rec["proj_band_cols"], rec["bp_stack_cols"], rec["bp_passes"],
-                            rec.get("bp_workgroups_per_cu", 0))
+                            rec.get("bp_workgroups_per_cu", 0), rec.get("bp_shared_window", False))
             return dict(rec, cached=True)
     g = torch.Generator(device=geom.device).manual_seed(seed)
     x = torch.rand(geom.vol_shape, generator=g, device=geom.device)
@@ -80,25 +80,32 @@ def autotune(geom: Geometry, opts: Options, bands=DEFAULT_BANDS, stacks=DEFAULT_
         p_ms[u] = _time(lambda: project(x, geom, opts, out=p_out), reps)
         if log:
             log("projection band %d: %.2f ms" % (u, p_ms[u]))
-    # with cached records the LDS budget (workgroups per CU) is a choice too
+    # with cached records the LDS budget (workgroups per CU) and, for stacks of
+    # 8 or 16 columns, one window per workgroup are choices too
     wpcs = (4, 3) if geom.records_cached else (0,)
     for gw in stacks:
         for kp in passes:
             for wpc in wpcs:
-                try:
-                    geom.set_launch(default[0], gw, kp, wpc)
-                except _lib.CVPError:
-                    continue
-                b_ms[(gw, kp, wpc)] = _time(lambda: backproject(b, geom, opts, out=v_out), reps)
-                if log:
-                    log("backprojection stack %d, %d passes, %d per CU: %.2f ms" % (gw, kp, wpc, b_ms[(gw, kp, wpc)]))
+                for shw in ((False, True) if geom.records_cached and gw >= 8 else (False,)):
+                    try:
+                        geom.set_launch(default[0], gw, kp, wpc, shw)
+                    except _lib.CVPError:
+                        continue
+                    b_ms[(gw, kp, wpc, shw)] = _time(lambda: backproject(b, geom, opts, out=v_out), reps)
+                    if log:
+                        log("backprojection stack %d, %d passes, %d per CU%s: %.2f ms"
+                            % (gw, kp, wpc, ", one window" if shw else "", b_ms[(gw, kp, wpc, shw)]))
     best_u = min(p_ms, key=p_ms.get) if p_ms else default[0]
-    best_gw, best_kp, best_wpc = min(b_ms, key=b_ms.get) if b_ms else (default[1], default[2], 0)
-    geom.set_launch(best_u, best_gw, best_kp, best_wpc)
+    best_gw, best_kp, best_wpc, best_shw = min(b_ms, key=b_ms.get) if b_ms else (default[1], default[2], 0, False)
+    geom.set_launch(best_u, best_gw, best_kp, best_wpc, best_shw)
+
+    def name(k):
+        s = "%d/%d/%d" % k[:3] if k[2] else "%d/%d" % k[:2]
+        return s + "/s" if k[3] else s
     rec = {"proj_band_cols": best_u, "bp_stack_cols": best_gw, "bp_passes": best_kp, "bp_workgroups_per_cu": best_wpc,
-           "default": list(default),
+           "bp_shared_window": bool(best_shw), "default": list(default),
            "project_ms": {str(k): v for k, v in p_ms.items()},
-           "backproject_ms": {("%d/%d/%d" % k if k[2] else "%d/%d" % k[:2]): v for k, v in b_ms.items()}}
+           "backproject_ms": {name(k): v for k, v in b_ms.items()}}
     if cache:
         table = {}
         if os.path.exists(cache):

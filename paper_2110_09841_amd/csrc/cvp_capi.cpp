@@ -32,7 +32,8 @@ constexpr size_t kBatchStaticLds = 512;
 constexpr size_t kLdsBatchMax = kLdsMax;
 bool plan_projection(int N, int n2, int M, int nviews, int pmax, int force_u, ProjLaunch &L);
 bool plan_backprojection(const DevGeom &G, int pmax, double zabs, double Dmin, int force_gw,
-                         int force_kp, BackLaunch &L, bool cached = false, size_t reserve = 0, int wpc = 0);
+                         int force_kp, BackLaunch &L, bool cached = false, size_t reserve = 0, int wpc = 0,
+                         bool shared_req = false);
 }
 using cvp::kLdsBudget;
 
@@ -50,6 +51,7 @@ struct cvp_geometry {
     double wone_tt = 0.0, wsum_tt = 0.0;   // fixed-point bounds of the TT projector's weights
     cvp::BackLaunch blc{};           // backprojection plan of the cached-record kernels
     int bp_wpc = 0;                  // requested workgroups per CU of that plan (0: default)
+    int bp_shared = 0;               // requested one window per workgroup in that plan
     float *d_rtab = nullptr;         // cached piece records (cvp_geometry_cache_records)
     int *d_rtab_n = nullptr;
     int64_t rtab_bytes = 0;
@@ -147,7 +149,7 @@ bool plan_projection(int N, int n2, int M, int nviews, int pmax, int force_u, Pr
 // estimated detector window fits the per-wave LDS window (force_gw > 0 and
 // force_kp > 0 fix them).
 bool plan_backprojection(const DevGeom &G, int pmax, double zabs, double Dmin, int force_gw,
-                         int force_kp, BackLaunch &L, bool cached, size_t reserve, int wpc)
+                         int force_kp, BackLaunch &L, bool cached, size_t reserve, int wpc, bool shared_req)
 {
     const double mag = G.f / Dmin;
     // (stack width, passes) by stack area; the first whose estimated window
@@ -187,8 +189,27 @@ bool plan_backprojection(const DevGeom &G, int pmax, double zabs, double Dmin, i
     else if (wpc != 3 && wpc != 4) wpc = pmax > 4 ? 3 : 4;
     const size_t budget = (pmax > 8 ? kBackLdsBudgetWide
                            : cached && wpc == 4 ? kBackLdsBudgetCached : kBackLdsBudget) - reserve;
-    int gw, kp, cap;
-    choose(budget, gw, kp, cap);
+    int gw = 0, kp = 0, cap = 0, shared = 0;
+    if (shared_req && cached && pmax <= 8) {
+        // one window per workgroup (all four waves on one view), for stacks of
+        // 8 or 16 columns: the first whose window fits it, else the last one
+        for (const auto &cd : cands) {
+            const int cand = cd[0], ckp = cd[1];
+            if ((force_gw > 0 && cand != force_gw) || (force_kp > 0 && ckp != force_kp) || cand < 8) continue;
+            const size_t rec = (size_t)((cand * pmax * kRecFloats + cand + 16 + 3) / 4 * 4) * 4;
+            if (rec + 4096 >= budget) continue;
+            const int c = (int)((budget - rec) / 4 / 4 * 4);
+            const double wu = std::hypot(cand * G.a1, G.a2) * mag / G.b1 + pmax + 2;
+            const double zspan = std::hypot(cand * G.a1, G.a2);
+            const double wv = 64 * ckp * G.a3 * mag / G.b2 + zabs * (G.f / G.b2) * zspan / (Dmin * Dmin) + 6;
+            gw = cand;
+            kp = ckp;
+            cap = c;
+            shared = 1;
+            if (wu * ((int)wv | 1) <= c) break;
+        }
+    }
+    if (!shared) choose(budget, gw, kp, cap);
     if (gw == 0) return false;
     L.gw = gw;
     L.kp = kp;
@@ -198,8 +219,10 @@ bool plan_backprojection(const DevGeom &G, int pmax, double zabs, double Dmin, i
     L.nkchunks = (G.n3 + 64 * kp - 1) / (64 * kp);
     L.items = G.n2 * L.ngroups * L.nkchunks;
     L.chunk = (L.items + 7) / 8;
-    L.lds = backproject_lds_bytes(gw, pmax, cap);
+    L.lds = shared ? (size_t)((gw * pmax * kRecFloats + gw + 16 + 3) / 4 * 4) * 4 + (size_t)cap * 4
+                   : backproject_lds_bytes(gw, pmax, cap);
     L.wpc = wpc;
+    L.shared = shared;
     return true;
 }
 
@@ -577,6 +600,7 @@ cvp_status cvp_geometry_get_launch(const cvp_geometry *g, cvp_launch *out)
     out->bp_stack_cols = bl.gw;
     out->bp_passes = bl.kp;
     out->bp_workgroups_per_cu = bl.wpc;
+    out->bp_shared_window = bl.shared;
     return ok();
 }
 
@@ -592,6 +616,8 @@ cvp_status cvp_geometry_set_launch(cvp_geometry *g, const cvp_launch *in)
     const int wpc = in->bp_workgroups_per_cu;
     if (wpc != 0 && wpc != 3 && wpc != 4)
         return fail(CVP_E_INVALID, "launch.bp_workgroups_per_cu = %d (0, 3 or 4)", wpc);
+    const int shw = in->bp_shared_window;
+    if (shw != 0 && shw != 1) return fail(CVP_E_INVALID, "launch.bp_shared_window = %d (0 or 1)", shw);
     const cvp::DevGeom &G = g->base;
     cvp::ProjLaunch pl{};
     cvp::BackLaunch bl{};
@@ -606,7 +632,7 @@ cvp_status cvp_geometry_set_launch(cvp_geometry *g, const cvp_launch *in)
     // in-kernel plan also serves the TT projector, so it is kept valid too
     cvp::BackLaunch blc = g->blc;
     if (g->d_rtab) {
-        if (!cvp::plan_backprojection(G, g->pmax, g->zabs, g->Dmin, gw, kp, blc, true, 0, wpc))
+        if (!cvp::plan_backprojection(G, g->pmax, g->zabs, g->Dmin, gw, kp, blc, true, 0, wpc, shw != 0))
             return fail(CVP_E_UNSUPPORTED, "launch.bp_stack_cols = %d, bp_passes = %d, bp_workgroups_per_cu = %d: "
                                            "does not fit LDS", gw, kp, wpc);
         if (!cvp::plan_backprojection(G, g->pmax, g->zabs, g->Dmin, gw, kp, bl) &&
@@ -619,6 +645,7 @@ cvp_status cvp_geometry_set_launch(cvp_geometry *g, const cvp_launch *in)
     g->bl = bl;
     g->blc = blc;
     g->bp_wpc = wpc;
+    g->bp_shared = shw;
     return ok();
 }
 
@@ -641,8 +668,9 @@ static int model_of(const cvp_options *o)
 static void replan_backprojection(cvp_geometry *g)
 {
     cvp::BackLaunch bl{};
-    if (cvp::plan_backprojection(g->base, g->pmax, g->zabs, g->Dmin, g->bl.gw, g->bl.kp, bl, true, 0, g->bp_wpc) ||
-        cvp::plan_backprojection(g->base, g->pmax, g->zabs, g->Dmin, 0, 0, bl, true, 0, g->bp_wpc))
+    if (cvp::plan_backprojection(g->base, g->pmax, g->zabs, g->Dmin, g->bl.gw, g->bl.kp, bl, true, 0, g->bp_wpc,
+                                 g->bp_shared != 0) ||
+        cvp::plan_backprojection(g->base, g->pmax, g->zabs, g->Dmin, 0, 0, bl, true, 0, g->bp_wpc, g->bp_shared != 0))
         g->blc = bl;
     else
         g->blc = g->bl;

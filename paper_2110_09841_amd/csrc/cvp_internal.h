@@ -92,6 +92,7 @@ struct BackLaunch {
     int win_cap;     // floats per wave window
     size_t lds;
     int wpc;         // workgroups per CU the LDS budget was sized for
+    int shared;      // 1: one detector window per workgroup (cached records only)
 };
 
 // Batched, persistent launches over up to kMaxBatch problems.

@@ -1387,6 +1387,270 @@ backproject_kernel(const DevGeom G, const int ngroups, const int nkchunks, const
     backproject_item<EXACT, EC, PMAX, GW, TT, TAB>(G, ngroups, nkchunks, kp, winCap, item, smem, proj, vol);
 }
 
+// The backprojection with one detector window per workgroup (cached records
+// only): the four waves take the same view at a time, wave w the columns
+// w GW/4 .. (w + 1) GW/4 - 1 of the stack, so the window (staged by all 256
+// threads) can be four times as large as a wave's own -- for detectors whose
+// pixels are small against the voxels, where a wave's window does not fit
+// LDS.  Each wave keeps one partial sum per view class (view mod 4), summed
+// in view order and combined as ((c0 + c1) + c2) + c3, which is the order of
+// backproject_item (wave w takes views w, w + 4, ...): the sums are the same
+// bits under either kernel.  The per-piece arithmetic is backproject_item's.
+template <bool EXACT, bool EC, int PMAX, int GW>
+__device__ __forceinline__ void backproject_shared_item(const DevGeom &G, const int ngroups, const int nkchunks,
+                                                        const int kp, const int winCap, const int item,
+                                                        float *smem, const float *__restrict__ proj,
+                                                        float *__restrict__ vol)
+{
+    constexpr int KP = kBackPasses;
+    constexpr int CPW = GW / kWaves;                 // columns per wave
+    const int kch = item % nkchunks;
+    const int t = item / nkchunks;
+    const int q = t % ngroups;
+    const int j = t / ngroups;
+    const int i0 = q * GW;
+    const int k0 = kch * kWave * kp;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int kmax = min(k0 + kWave * kp, G.n3) - 1;
+    const float a3f = (float)G.a3;
+    const bool raw = G.raw_volume != 0;
+    const int ncv = min(GW, G.n1 - i0);
+
+    // LDS: records [GW][PMAX][12], piece counts [GW], window bounds per wave
+    // [4][4], then the window
+    float *rec = smem;
+    int *npv = reinterpret_cast<int *>(rec + GW * PMAX * kRecFloats);
+    int *bnd = npv + GW;
+    float *win = rec + ((GW * PMAX * kRecFloats + GW + 16 + 3) / 4) * 4;
+
+    float acc[4][KP][CPW];
+#pragma unroll
+    for (int cl = 0; cl < 4; ++cl)
+#pragma unroll
+        for (int ps = 0; ps < KP; ++ps)
+#pragma unroll
+            for (int c = 0; c < CPW; ++c) acc[cl][ps][c] = 0.0f;
+
+    for (int view = 0; view < G.nviews; ++view) {
+        const int cl = view & 3;
+        const ViewGeom V = G.views[(size_t)view * G.vstride];
+        const float c2f = (float)V.c2;
+        // the view's records of the stack
+        {
+            const size_t col0 = ((size_t)view * G.vstride * G.n2 + j) * G.n1 + i0;
+            const int tp = G.rtab_pmax;
+            const float4 *src = reinterpret_cast<const float4 *>(G.rtab + col0 * tp * kRecFloats);
+            constexpr int F4 = kRecFloats / 4;
+            for (int q4 = tid; q4 < ncv * tp * F4; q4 += kBlock) {
+                const int cs = q4 / F4, c = cs / tp, sl = cs - c * tp;
+                reinterpret_cast<float4 *>(rec)[(c * PMAX + sl) * F4 + (q4 - cs * F4)] = src[q4];
+            }
+            if (tid < GW) npv[tid] = tid < ncv ? G.rtab_n[col0 + tid] : 0;
+        }
+        __syncthreads();
+        // the window: columns of all pieces, rows from the chunk's top voxel
+        // (smallest chi2) to its bottom voxel
+        {
+            int wu0 = 1 << 30, wu1 = -1, wv0 = 1 << 30, wv1 = -1;
+            const int c = tid % GW, sl = tid / GW;
+            if (sl < PMAX && sl < npv[c]) {
+                const float *r = rec + (c * PMAX + sl) * kRecFloats;
+                const int u = __float_as_int(r[0]);
+                const float beta = r[6], mfac = r[10];
+                const float Ytop_hi = fmaf(-(float)kmax, r[4], r[2]) + fmaf(-(float)kmax, r[5], r[3]);
+                const float Ytop_lo = fmaf(-(float)k0, r[4], r[2]) + fmaf(-(float)k0, r[5], r[3]);
+                int a, b, a2, b2;
+                row_range<EC>(Ytop_hi, beta, mfac, c2f, G.N, a, b);
+                row_range<EC>(Ytop_lo, beta, mfac, c2f, G.N, a2, b2);
+                wu0 = u;
+                wu1 = u;
+                wv0 = min(a, a2);
+                wv1 = max(b, b2);
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                wu0 = min(wu0, __shfl_xor(wu0, off));
+                wu1 = max(wu1, __shfl_xor(wu1, off));
+                wv0 = min(wv0, __shfl_xor(wv0, off));
+                wv1 = max(wv1, __shfl_xor(wv1, off));
+            }
+            if (lane == 0) {
+                bnd[wave * 4] = wu0;
+                bnd[wave * 4 + 1] = wu1;
+                bnd[wave * 4 + 2] = wv0;
+                bnd[wave * 4 + 3] = wv1;
+            }
+        }
+        __syncthreads();
+        int wu0 = bnd[0], wu1 = bnd[1], wv0 = bnd[2], wv1 = bnd[3];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) {
+            wu0 = min(wu0, bnd[w * 4]);
+            wu1 = max(wu1, bnd[w * 4 + 1]);
+            wv0 = min(wv0, bnd[w * 4 + 2]);
+            wv1 = max(wv1, bnd[w * 4 + 3]);
+        }
+        wu0 = __builtin_amdgcn_readfirstlane(wu0);
+        wu1 = __builtin_amdgcn_readfirstlane(wu1);
+        wv0 = __builtin_amdgcn_readfirstlane(wv0);
+        wv1 = __builtin_amdgcn_readfirstlane(wv1);
+        if (wu1 < wu0 || wv1 < wv0) {      // no piece in this view
+            __syncthreads();
+            continue;
+        }
+        // one spare row each side absorbs FP32 rounding of intermediate k
+        wv0 = max(wv0 - 1, 0);
+        wv1 = min(wv1 + 1, G.N - 1);
+        const int Wd = wu1 - wu0 + 1;
+        const int H = wv1 - wv0 + 1;
+        const int Hp = H | 1;
+        const float *pv = proj + (size_t)view * G.vstride * G.N * G.M;
+        const float *sgv = G.sigma ? G.sigma + (size_t)view * G.vstride * G.sigma_views * G.N * G.M : nullptr;
+        const bool useWin = Wd * Hp <= winCap;
+        if (useWin) {
+            for (int idx = tid; idx < Wd * H; idx += kBlock) {
+                const int uu = idx % Wd, vv = idx / Wd;
+                const size_t off = (size_t)(wv0 + vv) * G.M + (wu0 + uu);
+                float val = pv[off];
+                if (sgv) val *= sgv[off];
+                win[uu * Hp + vv] = val;
+            }
+        }
+        __syncthreads();
+
+        auto gather = [&](auto winTag) {
+            constexpr bool WIN = decltype(winTag)::value;
+#pragma unroll
+            for (int ps = 0; ps < KP; ++ps) {
+                if (ps >= kp || k0 + ps * kWave >= G.n3) break;   // unused pass
+                const int k = k0 + ps * kWave + lane;
+                const bool kv = k < G.n3;
+                const float kf = (float)k;
+                const float zt = fmaf(kf, a3f, (float)(G.x3lo + G.a3 - V.s3));
+                const float zc = zt - 0.5f * a3f;
+#pragma unroll
+                for (int cc = 0; cc < CPW; ++cc) {
+                    const int c = wave * CPW + cc;
+                    const int np = npv[c];
+                    if (np == 0) continue;
+                    const float *rc = rec + c * PMAX * kRecFloats;
+                    float base = 1.0f;
+                    if (!EXACT && !raw) base = __builtin_amdgcn_rcpf(fmaf(zc, zc, rc[8]));
+                    float a = 0.0f;
+                    for (int p = 0; p < np; ++p) {
+                        const float4 r0 = *reinterpret_cast<const float4 *>(rc + p * kRecFloats);
+                        const float4 r1 = *reinterpret_cast<const float4 *>(rc + p * kRecFloats + 4);
+                        const float4 r2 = *reinterpret_cast<const float4 *>(rc + p * kRecFloats + 8);
+                        const int u = __float_as_int(r0.x);
+                        const float Yh = fmaf(-kf, r1.x, r0.z);
+                        const float Yl = fmaf(-kf, r1.y, r0.w);
+                        const float Ybh = Yh + r1.x, Ybl = Yl + r1.y;
+                        const float beta = r1.z, rho = r1.w, rho4 = 4.0f * r1.w;
+                        int vlo0, vhi0;
+                        row_range_unclipped<EC>(Yh + Yl, beta, r2.z, c2f, vlo0, vhi0);
+                        const bool ends = !EC || rho < 0.9f;
+                        const int vlo = max(max(vlo0, 0), wv0);
+                        const int vhi = kv ? min(min(vhi0, G.N - 1), wv1) : vlo - 1;
+                        const float *wcol = win + (u - wu0) * Hp - wv0;
+                        const float tb = (float)vlo - 0.5f;
+                        float d = Yh - tb;
+                        float d0 = Ybh - tb;
+                        float tc = tb - c2f;
+                        float s1p, mp, phip;
+                        if (vlo != vlo0 || !ends) boundary<EC>(d, Yl, d0, Ybl, tc, rho, rho4, s1p, mp, phip);
+                        else boundary<false>(d, Yl, d0, Ybl, tc, rho, rho4, s1p, mp, phip);
+                        float psip = mp + phip;
+                        float ap = 0.0f;
+                        auto row = [&](float val) {
+                            d -= 1.0f;
+                            d0 -= 1.0f;
+                            tc += 1.0f;
+                            float s1n, mn, phin;
+                            boundary<EC>(d, Yl, d0, Ybl, tc, rho, rho4, s1n, mn, phin);
+                            float w = psip - phin;
+                            if (EXACT && !raw) {
+                                float mm = 0.5f * (fmaxf(0.0f, -s1p) + fminf(beta, -s1n));
+                                mm = fminf(fmaxf(mm, 0.0f), beta);
+                                const float zb = fmaf(-mm, r2.y, zt);
+                                w *= __builtin_amdgcn_rcpf(fmaf(zb, zb, r2.w));
+                            }
+                            ap = fmaf(w, val, ap);
+                            psip = mn + phin;
+                            s1p = s1n;
+                        };
+                        if (WIN) {
+                            const float *const last = wcol + vhi;
+                            for (const float *qq = wcol + vlo; qq < last; ++qq) row(*qq);
+                            if (vlo <= vhi) {
+                                d -= 1.0f;
+                                d0 -= 1.0f;
+                                tc += 1.0f;
+                                float s1n = d + Yl, phin = 0.0f;
+                                if (vhi != vhi0 || !ends) {
+                                    float mn;
+                                    boundary<EC>(d, Yl, d0, Ybl, tc, rho, rho4, s1n, mn, phin);
+                                }
+                                float w = psip - phin;
+                                if (EXACT && !raw) {
+                                    float mm = 0.5f * (fmaxf(0.0f, -s1p) + fminf(beta, -s1n));
+                                    mm = fminf(fmaxf(mm, 0.0f), beta);
+                                    const float zb = fmaf(-mm, r2.y, zt);
+                                    w *= __builtin_amdgcn_rcpf(fmaf(zb, zb, r2.w));
+                                }
+                                ap = fmaf(w, *last, ap);
+                            }
+                        } else {
+                            for (int v = vlo; v <= vhi; ++v) {
+                                const size_t off = (size_t)v * G.M + u;
+                                float val = pv[off];
+                                if (sgv) val *= sgv[off];
+                                row(val);
+                            }
+                        }
+                        a = fmaf(base * r0.y, ap, a);
+                    }
+                    // the partial sum of view class cl (a uniform index)
+#pragma unroll
+                    for (int ccl = 0; ccl < 4; ++ccl)
+                        if (ccl == cl) acc[ccl][ps][cc] += a;
+                }
+            }
+        };
+        if (useWin) gather(std::true_type{});
+        else gather(std::false_type{});
+        __syncthreads();                   // the next view reuses the records and the window
+    }
+
+    // ((c0 + c1) + c2) + c3 per voxel, one store each
+#pragma unroll
+    for (int ps = 0; ps < KP; ++ps) {
+        if (ps >= kp) break;
+        const int k = k0 + ps * kWave + lane;
+#pragma unroll
+        for (int cc = 0; cc < CPW; ++cc) {
+            const int i = i0 + wave * CPW + cc;
+            float sum = acc[0][ps][cc];
+#pragma unroll
+            for (int w = 1; w < 4; ++w) sum += acc[w][ps][cc];
+            if (k < G.n3 && i < G.n1) vol[((size_t)k * G.n2 + j) * G.n1 + i] = sum;
+        }
+    }
+}
+
+template <bool EXACT, bool EC, int PMAX, int GW>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
+backproject_shared_kernel(const DevGeom G, const int ngroups, const int nkchunks, const int kp, const int items,
+                          const int chunk, const int winCap, const float *__restrict__ proj,
+                          float *__restrict__ vol, const double *__restrict__ stop)
+{
+    extern __shared__ __align__(16) float smem[];
+    if (stop && *stop != 0.0) return;
+    const int item = (blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
+    if (item >= items) return;
+    backproject_shared_item<EXACT, EC, PMAX, GW>(G, ngroups, nkchunks, kp, winCap, item, smem, proj, vol);
+}
+
 // ------------------------------------------------------------ batched, persistent
 
 // Next work item of a persistent workgroup (one atomic per item) and the
@@ -1514,6 +1778,28 @@ hipError_t launch_bp_gw(const DevGeom &g, const BackLaunch &L, const float *proj
     return hipGetLastError();
 }
 
+template <bool EXACT, bool EC, int PMAX>
+hipError_t launch_bp_shared(const DevGeom &g, const BackLaunch &L, const float *proj, float *vol,
+                            hipStream_t s, const double *stop)
+{
+    const dim3 grid(8 * L.chunk), block(kBlock);
+    switch (L.gw) {
+    case 16:
+        hipLaunchKernelGGL((backproject_shared_kernel<EXACT, EC, PMAX, 16>), grid, block, L.lds, s, g, L.ngroups,
+                           L.nkchunks, L.kp, L.items, L.chunk, L.win_cap, proj, vol, stop);
+        break;
+    case 8:
+        hipLaunchKernelGGL((backproject_shared_kernel<EXACT, EC, PMAX, 8>), grid, block, L.lds, s, g, L.ngroups,
+                           L.nkchunks, L.kp, L.items, L.chunk, L.win_cap, proj, vol, stop);
+        break;
+    default:
+        hipLaunchKernelGGL((backproject_shared_kernel<EXACT, EC, PMAX, 4>), grid, block, L.lds, s, g, L.ngroups,
+                           L.nkchunks, L.kp, L.items, L.chunk, L.win_cap, proj, vol, stop);
+        break;
+    }
+    return hipGetLastError();
+}
+
 template <bool EXACT, bool EC, bool TT = false>
 hipError_t launch_bp(const DevGeom &g, const BackLaunch &L, const float *proj, float *vol,
                      hipStream_t s, const double *stop)
@@ -1521,6 +1807,10 @@ hipError_t launch_bp(const DevGeom &g, const BackLaunch &L, const float *proj, f
     if (!TT && g.rtab) {
         // the geometry's cached records (the plan L was made for these kernels)
         if (L.pmax > 8 || g.rtab_pmax != (L.pmax <= 4 ? 4 : 8)) return hipErrorInvalidValue;
+        if (L.shared) {
+            if (L.pmax <= 4) return launch_bp_shared<EXACT, EC, 4>(g, L, proj, vol, s, stop);
+            return launch_bp_shared<EXACT, EC, 8>(g, L, proj, vol, s, stop);
+        }
         if (L.pmax <= 4) return launch_bp_gw<EXACT, EC, 4, false, true>(g, L, proj, vol, s, stop);
         return launch_bp_gw<EXACT, EC, 8, false, true>(g, L, proj, vol, s, stop);
     }
@@ -1547,6 +1837,17 @@ hipError_t set_lds_one(size_t n)
     if (e == hipSuccess)
         e = hipFuncSetAttribute((const void *)backproject_kernel<EXACT, EC, PMAX, 4, TT, TAB>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
+    if constexpr (TAB && !TT) {
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void *)backproject_shared_kernel<EXACT, EC, PMAX, 16>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void *)backproject_shared_kernel<EXACT, EC, PMAX, 8>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void *)backproject_shared_kernel<EXACT, EC, PMAX, 4>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)n);
+    }
     return e;
 }
 

@@ -100,10 +100,20 @@ class Geometry:
         _lib.check(_lib.lib().cvp_geometry_get_launch(self.handle, ctypes.byref(lp)))
         return int(lp.bp_workgroups_per_cu)
 
-    def set_launch(self, proj_band_cols=0, bp_stack_cols=0, bp_passes=0, bp_workgroups_per_cu=0):
+    @property
+    def bp_shared_window(self):
+        """True when the cached-record backprojection stages one detector
+        window per workgroup instead of one per wave."""
+        lp = _lib.LaunchC()
+        _lib.check(_lib.lib().cvp_geometry_get_launch(self.handle, ctypes.byref(lp)))
+        return bool(lp.bp_shared_window)
+
+    def set_launch(self, proj_band_cols=0, bp_stack_cols=0, bp_passes=0, bp_workgroups_per_cu=0,
+                   bp_shared_window=False):
         """Replace the launch plan (0 selects the planner's default for that
         field).  Raises CVPError if the plan does not fit."""
-        lp = _lib.LaunchC(int(proj_band_cols), int(bp_stack_cols), int(bp_passes), int(bp_workgroups_per_cu))
+        lp = _lib.LaunchC(int(proj_band_cols), int(bp_stack_cols), int(bp_passes), int(bp_workgroups_per_cu),
+                          int(bool(bp_shared_window)))
         _lib.check(_lib.lib().cvp_geometry_set_launch(self.handle, ctypes.byref(lp)))
 
     def cache_records(self, enable=True):

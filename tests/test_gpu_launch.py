@@ -80,7 +80,7 @@ def test_autotune_chooses_the_backprojection_budget_with_cached_records(tmp_path
     say("autotune, cached records")
     rec = autotune(G, opts, bands=(8,), stacks=(16,), passes=(2,), reps=1, cache=cache)
     assert rec["bp_workgroups_per_cu"] in (3, 4)
-    assert set(rec["backproject_ms"]) == {"16/2/4", "16/2/3"}
+    assert set(rec["backproject_ms"]) == {"16/2/4", "16/2/3", "16/2/4/s", "16/2/3/s"}
     assert G.bp_workgroups_per_cu == rec["bp_workgroups_per_cu"]
     G2 = cvp.Geometry(g)
     G2.cache_records()

@@ -68,6 +68,21 @@ def test_cached_records_give_the_same_bits(name):
         for variant, ec in COMBOS[:2]:
             opts = cvp.Options(variant=variant, ec=ec)
             assert torch.equal(cvp.backproject(b, G, opts), ref[variant, ec][1]), (name, wpc, variant)
+    if name == "pmax8":
+        # pixels small against the voxels: one window per workgroup for 8- and
+        # 16-column stacks (4-column ones keep their own), and each wave's own
+        # windows, partly read from global memory
+        shared = []
+        for gw, kp, shw in ((8, 1, True), (16, 1, True), (4, 1, True), (8, 1, False), (4, 2, False)):
+            G.set_launch(0, gw, kp, 3, shw)
+            shared.append(G.bp_shared_window)
+            for variant, ec in COMBOS:
+                opts = cvp.Options(variant=variant, ec=ec)
+                assert torch.equal(cvp.backproject(b, G, opts), ref[variant, ec][1]), (gw, kp, variant, ec)
+            opts = cvp.Options(variant="relaxed", ec=True)
+            assert torch.equal(solvers.backproject_views(b, G, 1, 3, 3, opts=opts), ref["relaxed", True][3])
+        say("one window per workgroup:", shared)
+        assert shared == [True, True, False, False, False]
     G.set_launch()
     out = torch.full(G.proj_shape, 3.0, device="cuda")
     solvers.project_views(x, G, 2, 4, 2, out, cvp.Options(variant="relaxed", ec=True))
