@@ -230,8 +230,10 @@ def paper_benchmarks(reps=2):
     512 pixels of 1 mm, SID 541 / SDD 949) and "Pfeiffer" (256^3 voxels of
     0.5 mm, 100 views over 198 degrees, 1280 x 960 pixels of 0.25 mm, SID 750 /
     SDD 1000): one application of A and of A^T per projector (CVP exact and
-    relaxed with EC, and TT), timed with HIP events on uniform random data.
-    The paper's times on its GPUs (context, not targets) go beside them."""
+    relaxed with EC, and TT), timed with HIP events on uniform random data,
+    with the default plan; then CVP again with the cut-piece records cached
+    and the plan autotuned.  The paper's times on its GPUs (context, not
+    targets) go beside them."""
     import torch
     from paper_2110_09841_amd import cvp, synth
     setups = {
@@ -267,6 +269,27 @@ def paper_benchmarks(reps=2):
             ev[2].record()
             torch.cuda.synchronize()
             res[key + "_ms"] = [ev[0].elapsed_time(ev[1]) / reps, ev[1].elapsed_time(ev[2]) / reps]
+        # the CVP forms again with the geometry's cut-piece records cached and
+        # the plan autotuned per form (as for the other workloads)
+        from paper_2110_09841_amd.autotune import autotune
+        res["record_cache_bytes"] = G.cache_records()
+        for key, opts in (("cvp", cvp.Options(variant="exact", ec=True)),
+                          ("cvp_relaxed", cvp.Options(variant="relaxed", ec=True))):
+            autotune(G, opts, bands=(4, 6, 8, 12), reps=1)
+            cvp.project(x, G, opts, out=po)
+            cvp.backproject(b, G, opts, out=vo)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            torch.cuda.synchronize()
+            ev[0].record()
+            for _ in range(reps):
+                cvp.project(x, G, opts, out=po)
+            ev[1].record()
+            for _ in range(reps):
+                cvp.backproject(b, G, opts, out=vo)
+            ev[2].record()
+            torch.cuda.synchronize()
+            res[key + "_cached_records_ms"] = [ev[0].elapsed_time(ev[1]) / reps, ev[1].elapsed_time(ev[2]) / reps]
+            res[key + "_cached_records_launch"] = list(G.launch) + [G.bp_workgroups_per_cu, int(G.bp_shared_window)]
         out[name] = res
         del G, x, b, po, vo
         torch.cuda.empty_cache()
