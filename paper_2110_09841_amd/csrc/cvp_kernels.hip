@@ -414,9 +414,10 @@ __device__ __forceinline__ void row_range(float Ytop, float beta, float mfac, fl
 // boundaries; those two box averages are skipped unless clipping moved the
 // boundary.  Boundaries t = vlo - 1/2, vlo + 1/2, ...: d, d0 step by exactly
 // 1; tc = t - c2 feeds only the box width.  Weight of row [t, t + 1]:
-// coef (m(t) + Phi(t) - Phi(t + 1)).
+// coef (m(t) + Phi(t) - Phi(t + 1)).  The bottom face's high part is Yh + bh
+// (bh the high part of one slice's step).
 template <bool EC, bool EXACT>
-__device__ __forceinline__ void sweep_rows(int vlo0, int vhi0, int vlo, int vhi, float Yh, float Yl, float Ybh,
+__device__ __forceinline__ void sweep_rows(int vlo0, int vhi0, int vlo, int vhi, float Yh, float Yl, float bh,
                                            float Ybl, float beta, float rho, float c2f, float coef, bool raw,
                                            float zt, float r8, float r9, unsigned long long *bcol)
 {
@@ -424,7 +425,7 @@ __device__ __forceinline__ void sweep_rows(int vlo0, int vhi0, int vlo, int vhi,
     const float rho4 = 4.0f * rho;
     const float tb = (float)vlo - 0.5f;
     float d = Yh - tb;
-    float d0 = Ybh - tb;
+    float d0 = d + bh;                           // Yh + bh - tb, exact on the 2^-10 grid
     float tc = tb - c2f;
     float s1p, mp, phip;
     if (vlo != vlo0 || !ends) boundary<EC>(d, Yl, d0, Ybl, tc, rho, rho4, s1p, mp, phip);
@@ -905,7 +906,7 @@ __device__ __forceinline__ void project_item(const DevGeom &G, const int U, cons
                                           eu, ed, coef, bcol);
                         } else {
                             // bottom face Y(k - 1): high part Yh + bh (exact on the 2^-10 grid), low part Yl + bl
-                            sweep_rows<EC, EXACT>(vlo0, vhi0, max(vlo0, 0), min(vhi0, G.N - 1), Yh, Yl, Yh + r[4],
+                            sweep_rows<EC, EXACT>(vlo0, vhi0, max(vlo0, 0), min(vhi0, G.N - 1), Yh, Yl, r[4],
                                                   Yl + r[5], beta, rho, c2f, coef, raw, zt[h], r[11], r[9], bcol);
                         }
                     }
@@ -1205,7 +1206,7 @@ __device__ __forceinline__ void backproject_item(const DevGeom &G, const int ngr
             // boundaries as in sweep_rows; row weight m(t) + Phi(t) - Phi(t + 1)
             const float tb = (float)vlo - 0.5f;
             float d = Yh - tb;
-            float d0 = Ybh - tb;
+            float d0 = d + r1.x;                     // Ybh - tb, exact on the 2^-10 grid
             float tc = tb - c2f;
             float s1p, mp, phip;
             if (vlo != vlo0 || !ends) boundary<EC>(d, Yl, d0, Ybl, tc, rho, rho4, s1p, mp, phip);
@@ -1545,7 +1546,7 @@ __device__ __forceinline__ void backproject_shared_item(const DevGeom &G, const 
                         const int u = __float_as_int(r0.x);
                         const float Yh = fmaf(-kf, r1.x, r0.z);
                         const float Yl = fmaf(-kf, r1.y, r0.w);
-                        const float Ybh = Yh + r1.x, Ybl = Yl + r1.y;
+                        const float Ybl = Yl + r1.y;
                         const float beta = r1.z, rho = r1.w, rho4 = 4.0f * r1.w;
                         int vlo0, vhi0;
                         row_range_unclipped<EC>(Yh + Yl, beta, r2.z, c2f, vlo0, vhi0);
@@ -1555,7 +1556,7 @@ __device__ __forceinline__ void backproject_shared_item(const DevGeom &G, const 
                         const float *wcol = win + (u - wu0) * Hp - wv0;
                         const float tb = (float)vlo - 0.5f;
                         float d = Yh - tb;
-                        float d0 = Ybh - tb;
+                        float d0 = d + r1.x;         // Ybh - tb, exact on the 2^-10 grid
                         float tc = tb - c2f;
                         float s1p, mp, phip;
                         if (vlo != vlo0 || !ends) boundary<EC>(d, Yl, d0, Ybl, tc, rho, rho4, s1p, mp, phip);
